@@ -1,0 +1,157 @@
+"""Benchmark: ECMC events/s on one MI355X for hard disks, N = 2^20, eta = 0.708.
+
+One step = one leg (breakpoint interval) of the whole hot path: home-cell build,
+1024 chains running the event kernel to the breakpoint (reruns included),
+breakpoint reduction and write-back.  Directions alternate +x/+y.  Inputs are
+seeded synthetic lattices resident in HBM before the timed region starts.
+
+Prints ONE JSON line (see the repository's design notes for the fields).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0        # MI355X HBM3E, published
+# algorithmic bytes: per scanned cell slot 16 B fixed record (p, id) + 16 B
+# mutable record (a, t); per lifting: tag CAS 8 B, target re-read 16 B, lane
+# minima re-read 16 B, commit 24 B (t_j, t_i, a_i), tag release 4 B, log 4 B
+BYTES_PER_SLOT = 32
+BYTES_PER_EVENT = 72
+
+
+def _src_hash():
+    h = hashlib.sha256()
+    with open(os.path.join(ROOT, "paper_2004_11040_amd", "csrc", "ecmc_kernels.hip"), "rb") as f:
+        h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def _traffic(kernel_bytes_per_launch):
+    """HBM traffic per event-kernel launch from the committed rocprofv3 counter
+    summary, if it was taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", "event_kernel_N1048576_pmc.json")
+    try:
+        with open(path) as f:
+            d = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if d.get("source_sha256_16") != _src_hash():
+        return None
+    return d.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(seconds: float):
+    """The oracle, as it stands, on a bounded sample of the same workload."""
+    import oracle
+    import workloads as W
+    s = W.config(4)
+    x, y, act = s.x, s.y, s.active
+    events, t_used, legs = 0, 0.0, 0
+    while t_used < seconds and legs < 8:
+        t0 = time.perf_counter()
+        r = oracle.run(x, y, s.sigma, s.L, act, [legs % 2], s.T, log=False)
+        t_used += time.perf_counter() - t0
+        events += r.n_events
+        x, y, act = r.x, r.y, r.active
+        legs += 1
+    return {"value": events / t_used, "unit": "events/s", "cores": 1, "kind": "oracle",
+            "sample": f"first {legs} legs ({events} liftings) of the N=1048576 eta=0.708 k=1024 "
+                      f"workload, serial C global-time event queue, 1 host thread"}
+
+
+def run_form(form, steps, warmup, lanes):
+    import numpy as np
+    import torch
+
+    import paper_2004_11040_amd as pkg
+    import workloads as W
+
+    s = W.config(4)
+    flags = pkg.FP32_MIXED if form == "fp32" else pkg.FP64
+    e = pkg.Ecmc(np.stack([s.x, s.y], 1), s.sigma, s.L, flags=flags, max_chains=s.k, log_cap=1 << 12)
+    e.set_option(pkg.OPT_LANES, lanes)
+    e.set_option(pkg.OPT_KERNEL_TIMING, 1)
+    e.set_active(s.active)
+    if warmup:
+        e.run(warmup * s.T, s.T, pkg.DIR_ALTERNATE)
+    st0 = e.stats()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e.run(steps * s.T, s.T, pkg.DIR_ALTERNATE)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    st1 = e.stats()
+    d = {k: st1[k] - st0[k] for k in st1 if isinstance(st1[k], (int, float))}
+    wall = t1 - t0
+    launches = max(d["event_launches"], 1)
+    kbytes = (d["timed_slots"] * BYTES_PER_SLOT + d["timed_events"] * BYTES_PER_EVENT) / launches
+    kdur = d["event_kernel_ms"] / launches / 1e3
+    achieved = kbytes / kdur / 1e9 if kdur > 0 else 0.0
+    overlaps = e.overlaps()
+    res = {
+        "events": d["events"], "wall_s": wall, "events_per_s": d["events"] / wall,
+        "legs": d["legs"], "legs_violated": d["legs_violated"], "reruns": d["reruns"],
+        "global_legs": d["global_legs"], "slots_per_event": d["slots_scanned"] / max(d["events"], 1),
+        "kernel_ms_avg": kdur * 1e3, "kernel_bytes_per_launch": kbytes, "achieved_gbs": achieved,
+        "kernel_time_frac": d["event_kernel_ms"] / 1e3 / wall, "overlaps": overlaps,
+        "pressure_raw": 1.0 + d["sum_b"] / d["chain_time"] if d["chain_time"] else None,
+        "violation_rate_per_leg": d["legs_violated"] / max(d["legs"], 1),
+    }
+    e.close()
+    return res
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200, help="timed legs")
+    ap.add_argument("--warmup", type=int, default=4, help="untimed legs")
+    ap.add_argument("--form", choices=["fp64", "fp32", "both"], default="fp64")
+    ap.add_argument("--lanes", type=int, default=64)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+
+    forms = ["fp64", "fp32"] if args.form == "both" else [args.form]
+    results = {f: run_form(f, args.steps, args.warmup, args.lanes) for f in forms}
+    main_form = "fp32" if "fp32" in results else "fp64"
+    r = results[main_form]
+    kb = r["kernel_bytes_per_launch"]
+    roof = {"bound": "hbm", "achieved": r["achieved_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": r["achieved_gbs"] / HBM_PEAK_GBS, "traffic": _traffic(kb),
+            "kernel": "k_event<64>", "bytes_per_launch": kb, "avg_launch_ms": r["kernel_ms_avg"]}
+    line = {
+        "metric": "ECMC events/sec on 1 GPU, N=2^20 disks η=0.708: FP32-mixed vs FP64 form",
+        "value": r["events_per_s"], "unit": "events/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": r["wall_s"] / args.steps * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32+f64" if main_form == "fp32" else "f64", "data": "synthetic",
+        "config": {"workload": "hard disks N=1048576 eta=0.708, jittered 1024x1024 centred-rectangular "
+                               "lattice, k=1024 chains, legs of T=33.896 alternating +x/+y",
+                   "form": main_form, "lanes_per_chain": args.lanes, "parallelism": "1 GPU"},
+        "roofline": roof,
+        "forms": results,
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,193 @@
+/*
+ * ecmc.h -- C ABI of the MI355X (gfx950) library for multithreaded
+ * event-chain Monte Carlo of hard disks with local times.
+ *
+ * Method: Li, Todo, Maggs, Krauth, "Multithreaded event-chain Monte Carlo with
+ * local times".  Between two breakpoints h and h' (a "leg"), k active disks
+ * ("chains") move with one common velocity v (+x or +y).  Each chain advances
+ * on its own local time: it finds the next disk it would hit (time of flight
+ * tau_ij = forward distance - b_ij, b_ij = sqrt((2 sigma)^2 - dp^2), Sec. 2.2),
+ * checks the horizon condition t_i + tau_ij > t_j (Eq. 2) on the nearest disk
+ * of each of its three lanes (Sec. 3.1, the out-arrows of the constraint graph
+ * G(3)), claims the target with a compare-and-swap on its tag (Alg. 5
+ * statement 10), re-checks the target's position and local time (statement
+ * 13), and lifts (statements 14-19; Eq. 1).  A horizon violation aborts the
+ * attempt, which is undone and rerun from its breakpoint with a shorter
+ * sub-leg (restart strategy 1, Sec. 3.4); if that keeps failing, a short
+ * window runs in global-time order (Alg. 2), which cannot violate.  Without
+ * violations the liftings equal those of Alg. 2 (Lemma 2); every path
+ * evaluates each lifting from the chain's activation state with the same
+ * binary64 operations, so results are bit-identical to global-time order.
+ *
+ * Conventions
+ *  - Every function returns ECMC_OK (0) or a negative ECMC_E* code, except
+ *    ecmc_workspace_bytes (bytes, or a negative code), ecmc_last_error and
+ *    ecmc_free.  No function aborts the process.
+ *  - sigma is the disk RADIUS; disks touch at centre distance d = 2 sigma.
+ *  - The box is the periodic square [0, box)^2.
+ *  - Device memory is owned by the caller: the library never allocates device
+ *    memory.  ecmc_workspace_bytes() tells how much one context needs; the
+ *    caller passes a device buffer of at least that size to ecmc_init() and
+ *    keeps it alive until ecmc_free().
+ *  - "stream" is a hipStream_t passed as void*; every kernel of a context runs
+ *    on it.  Calls that return data to the host synchronise that stream.
+ *  - Host pointers are read or written during the call only; the caller keeps
+ *    ownership.
+ *  - A context is not thread safe; use one context per host thread.
+ */
+#ifndef ECMC_H
+#define ECMC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------- */
+#define ECMC_OK 0
+#define ECMC_EINVAL (-1)   /* bad argument or unsupported parameter set       */
+#define ECMC_EOVERLAP (-2) /* input disks overlap (closer than 2 sigma)       */
+#define ECMC_EDEVICE (-3)  /* a HIP runtime call failed                        */
+#define ECMC_ECELL (-4)    /* more disks in one cell than its 4 slots          */
+#define ECMC_EHANG (-5)    /* an event chain exceeded its iteration limit      */
+#define ECMC_ESTATE (-6)   /* call order violated (e.g. run before set_active) */
+
+/* ---- flags for ecmc_init ------------------------------------------------ */
+#define ECMC_FP64 0u        /* collision search in binary64                    */
+#define ECMC_FP32_MIXED 1u  /* collision search in binary32 on cell-relative
+                               coordinates, winners and near-ties recomputed in
+                               binary64; positions, local times and sums stay
+                               binary64 (results identical to ECMC_FP64)       */
+
+/* ---- options for ecmc_set_option --------------------------------------- */
+#define ECMC_OPT_LANES 1          /* lanes per chain: 16, 32 or 64 (default 64) */
+#define ECMC_OPT_WAIT_RETRIES 2   /* failed claims on an active target before the
+                                     chain moves up to contact (default 64)     */
+#define ECMC_OPT_MAX_SPLITS 3     /* consecutive violating attempts (each rerun
+                                     with a shorter sub-leg) before a short
+                                     window runs in global-time order (default 4) */
+#define ECMC_OPT_FORCE_GLOBAL 4   /* 1: run every leg in global-time order      */
+#define ECMC_OPT_INJECT_CHAIN 5   /* test hook: chain that reports a horizon    */
+#define ECMC_OPT_INJECT_EVENT 6   /*   violation at its given event of the next
+                                     leg attempt (-1 disables; host-forced, the
+                                     kernel still exits normally)              */
+#define ECMC_OPT_KERNEL_TIMING 7  /* 1: time every event-kernel launch with HIP
+                                     events recorded on the context's stream
+                                     (statistics event_kernel_ms / launches)    */
+#define ECMC_OPT_STRICT_ORDER 8   /* 1: add agent-scope acquire/release fences to
+                                     the completion waits that order the shared
+                                     fields (validation mode; slower)           */
+
+typedef struct ecmc_ctx ecmc_ctx;
+
+typedef struct {
+  int64_t events;          /* committed liftings (elements of L)              */
+  int64_t legs;            /* legs completed                                  */
+  int64_t legs_violated;   /* legs whose first parallel attempt violated      */
+  int64_t attempts;        /* parallel leg or sub-leg attempts launched       */
+  int64_t reruns;          /* attempts discarded because of a violation       */
+  int64_t global_legs;     /* windows run in global-time order                */
+  int64_t cas_fail;        /* lock-less lock re-checks that failed            */
+  int64_t active_waits;    /* claims that found the target active             */
+  int64_t contact_moves;   /* moves up to contact with an active target       */
+  int64_t fp32_refines;    /* binary64 recomputations of near-tie candidates  */
+  int64_t slots_scanned;   /* cell slots examined by the corridor scans        */
+  int64_t overlaps;        /* pairs closer than 2 sigma - 4 ulp(box), last check */
+  double sum_b;            /* sum of b_ij over liftings (per chain, then chains) */
+  double chain_time;       /* total chain time, k * (sum of leg lengths)       */
+  double pressure;         /* 1 + sum_b / chain_time (raw ECMC estimator)      */
+  double device_ms;        /* device time spent in ecmc_run (HIP events)       */
+  double event_kernel_ms;  /* summed duration of timed event-kernel launches   */
+  int64_t event_launches;  /* number of timed event-kernel launches            */
+  int64_t timed_events;    /* liftings committed inside the timed launches     */
+  int64_t timed_slots;     /* cell slots scanned inside the timed launches     */
+} ecmc_stats_t;
+
+/* Bytes of device workspace for a context.  n disks of radius sigma in a box of
+ * side box; cells per side (0: floor(box / (2 sigma)) reduced until the cell is
+ * at least 2 sigma wide); max_chains >= the k later passed to ecmc_set_active;
+ * log_cap = number of target ids kept per chain (a ring: the last log_cap
+ * liftings of each chain).  Negative ECMC_EINVAL for invalid sizes. */
+int64_t ecmc_workspace_bytes(int64_t n, double sigma, double box, int32_t cells,
+                             int32_t max_chains, int64_t log_cap,
+                             uint32_t flags);
+
+/* Create a context (Sec. 2.1, Alg. 1 input C_h).
+ * positions_xy: DEVICE pointer, n x 2 doubles, row-major (x0,y0,x1,y1,...),
+ *   every coordinate in [0, box).  Copied; the caller may reuse it afterwards.
+ * cells: 0 or cells per side with 2 sigma <= box/cells <= 2 sqrt(2) sigma and
+ *   cells >= 5 (each cell then holds at most 4 disks).
+ * workspace: DEVICE buffer of ws_bytes >= ecmc_workspace_bytes(...), 256-byte
+ *   aligned.  stream: hipStream_t.
+ * Errors: ECMC_EINVAL (n < 2, sigma <= 0, box <= 0, bad cells, workspace too
+ * small or misaligned, coordinates outside [0, box)), ECMC_EOVERLAP (a pair
+ * closer than 2 sigma - 4 ulp(box)), ECMC_ECELL, ECMC_EDEVICE.  On error *out
+ * is NULL. */
+int ecmc_init(ecmc_ctx **out, const double *positions_xy, int64_t n,
+              double sigma, double box, int32_t cells, uint32_t flags,
+              void *workspace, int64_t ws_bytes, int32_t max_chains,
+              int64_t log_cap, void *stream);
+
+/* Active set A_h: chain c moves disk idx[c] (HOST array of k distinct indices
+ * in [0, n)).  The active set then evolves with the liftings and persists
+ * across legs and runs (Remark on stalled spheres).  Resets the chain logs and
+ * per-chain sums.  Errors: ECMC_EINVAL (k < 1, k > max_chains, duplicates,
+ * index out of range). */
+int ecmc_set_active(ecmc_ctx *ctx, const int32_t *idx, int32_t k);
+
+/* Run chain_time / breakpoint_interval legs (that ratio must be an integer
+ * within 1e-9) of length T = breakpoint_interval each.
+ * direction: 0 +x, 1 +y, 4 alternate +x/+y (the first leg of the context is
+ * +x, and the alternation continues across calls).
+ * n_chains must equal the k given to ecmc_set_active.  T must satisfy
+ * 0 <= T <= box - 4 (box/cells) - 2 sigma.  Horizon violations are absorbed by
+ * reruns and counted in the statistics.  Synchronises the stream once per
+ * attempt (to read the violation flag).  Errors: ECMC_EINVAL, ECMC_ESTATE,
+ * ECMC_ECELL, ECMC_EHANG, ECMC_EDEVICE. */
+int ecmc_run(ecmc_ctx *ctx, int32_t n_chains, double chain_time,
+             double breakpoint_interval, int32_t direction);
+
+/* Statistics accumulated since ecmc_set_active.  Synchronises the stream. */
+int ecmc_stats(ecmc_ctx *ctx, ecmc_stats_t *out);
+
+/* Copy the current configuration to HOST memory: out_xy n x 2 doubles. */
+int ecmc_get_positions(ecmc_ctx *ctx, double *out_xy);
+
+/* Local times at the end of the last leg (HOST, n doubles; leg-relative). */
+int ecmc_get_stamps(ecmc_ctx *ctx, double *out);
+
+/* Current active set (HOST, k int32: disk of chain c). */
+int ecmc_get_active(ecmc_ctx *ctx, int32_t *out);
+
+/* Per-chain results since ecmc_set_active (HOST, k entries each; either may
+ * be NULL): sum of b_ij in the chain's lifting order, and lifting count. */
+int ecmc_get_chain_sums(ecmc_ctx *ctx, double *sum_b, int64_t *events);
+
+/* Lifting log of one chain: the target disk ids of its liftings, in order.
+ * Writes min(count, log_cap, cap) most recent entries to the HOST array
+ * targets and the chain's total lifting count to *n_out.  ECMC_EINVAL if
+ * chain is out of range or cap < min(count, log_cap). */
+int ecmc_get_log(ecmc_ctx *ctx, int32_t chain, int32_t *targets, int64_t cap,
+                 int64_t *n_out);
+
+/* Count pairs closer than 2 sigma - 4 ulp(box) in the current configuration
+ * (binary64, minimum image; zero tolerance beyond rounding of contact
+ * positions).  Writes the count to *count and into the statistics. */
+int ecmc_overlaps(ecmc_ctx *ctx, int64_t *count);
+
+/* Tuning and test options (ECMC_OPT_*).  ECMC_EINVAL for unknown keys or
+ * values. */
+int ecmc_set_option(ecmc_ctx *ctx, int32_t key, int64_t value);
+
+/* Static description of the last error on this context (never NULL). */
+const char *ecmc_last_error(const ecmc_ctx *ctx);
+
+/* Release the context (host memory only; the workspace stays the caller's).
+ * Accepts NULL. */
+void ecmc_free(ecmc_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ECMC_H */

@@ -1,0 +1,219 @@
+"""Python binding of the MI355X hard-disk event-chain Monte Carlo library.
+
+Thin ctypes marshalling over the C ABI declared in ``include/ecmc.h``; every
+step of the method runs in the HIP kernels of ``libecmc.so``.  PyTorch only
+provides the device workspace and the stream.  There is no CPU fallback: if the
+built library cannot be loaded, importing the binding's functions raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libecmc.so")
+
+OK = 0
+EINVAL, EOVERLAP, EDEVICE, ECELL, EHANG, ESTATE = -1, -2, -3, -4, -5, -6
+FP64, FP32_MIXED = 0, 1
+OPT_LANES, OPT_WAIT_RETRIES, OPT_MAX_SPLITS, OPT_FORCE_GLOBAL = 1, 2, 3, 4
+OPT_INJECT_CHAIN, OPT_INJECT_EVENT, OPT_KERNEL_TIMING, OPT_STRICT_ORDER = 5, 6, 7, 8
+DIR_X, DIR_Y, DIR_ALTERNATE = 0, 1, 4
+
+# every symbol the header declares
+EXPORTS = (
+    "ecmc_workspace_bytes", "ecmc_init", "ecmc_set_active", "ecmc_run", "ecmc_stats",
+    "ecmc_get_positions", "ecmc_get_stamps", "ecmc_get_active", "ecmc_get_chain_sums",
+    "ecmc_get_log", "ecmc_overlaps", "ecmc_set_option", "ecmc_last_error", "ecmc_free",
+)
+
+
+class EcmcError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"ecmc error {code}: {msg}")
+        self.code = code
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int64) for n in (
+        "events", "legs", "legs_violated", "attempts", "reruns", "global_legs", "cas_fail",
+        "active_waits", "contact_moves", "fp32_refines", "slots_scanned", "overlaps")] + [
+        (n, ctypes.c_double) for n in ("sum_b", "chain_time", "pressure", "device_ms",
+                                       "event_kernel_ms")] + [
+        (n, ctypes.c_int64) for n in ("event_launches", "timed_events", "timed_slots")]
+
+    def as_dict(self):
+        return {n: getattr(self, n) for n, _ in self._fields_}
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libecmc.so (raises if it is missing: there is no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is not built; run __graft_entry__.build() first")
+    lib = ctypes.CDLL(path)
+    P, I32, I64, D, U32 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_uint32
+    lib.ecmc_workspace_bytes.restype = I64
+    lib.ecmc_workspace_bytes.argtypes = [I64, D, D, I32, I32, I64, U32]
+    lib.ecmc_init.restype = ctypes.c_int
+    lib.ecmc_init.argtypes = [ctypes.POINTER(P), P, I64, D, D, I32, U32, P, I64, I32, I64, P]
+    lib.ecmc_set_active.restype = ctypes.c_int
+    lib.ecmc_set_active.argtypes = [P, P, I32]
+    lib.ecmc_run.restype = ctypes.c_int
+    lib.ecmc_run.argtypes = [P, I32, D, D, I32]
+    lib.ecmc_stats.restype = ctypes.c_int
+    lib.ecmc_stats.argtypes = [P, ctypes.POINTER(Stats)]
+    for name in ("ecmc_get_positions", "ecmc_get_stamps", "ecmc_get_active"):
+        getattr(lib, name).restype = ctypes.c_int
+        getattr(lib, name).argtypes = [P, P]
+    lib.ecmc_get_chain_sums.restype = ctypes.c_int
+    lib.ecmc_get_chain_sums.argtypes = [P, P, P]
+    lib.ecmc_get_log.restype = ctypes.c_int
+    lib.ecmc_get_log.argtypes = [P, I32, P, I64, ctypes.POINTER(I64)]
+    lib.ecmc_overlaps.restype = ctypes.c_int
+    lib.ecmc_overlaps.argtypes = [P, ctypes.POINTER(I64)]
+    lib.ecmc_set_option.restype = ctypes.c_int
+    lib.ecmc_set_option.argtypes = [P, I32, I64]
+    lib.ecmc_last_error.restype = ctypes.c_char_p
+    lib.ecmc_last_error.argtypes = [P]
+    lib.ecmc_free.restype = None
+    lib.ecmc_free.argtypes = [P]
+    _lib = lib
+    return lib
+
+
+def workspace_bytes(n, sigma, box, cells=0, max_chains=1, log_cap=1, flags=FP64) -> int:
+    return int(load_library().ecmc_workspace_bytes(int(n), float(sigma), float(box), int(cells),
+                                                   int(max_chains), int(log_cap), int(flags)))
+
+
+def _np_ptr(a):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+@dataclass
+class ChainLog:
+    count: int
+    targets: np.ndarray
+
+
+class Ecmc:
+    """One periodic box of hard disks on the current GPU.
+
+    positions: (n, 2) float64 array (host or torch tensor); copied to the GPU.
+    """
+
+    def __init__(self, positions, sigma, box, cells=0, flags=FP64, max_chains=1, log_cap=1 << 16,
+                 stream=None, device="cuda"):
+        import torch
+        self._torch = torch
+        self.lib = load_library()
+        self.n = int(positions.shape[0])
+        self.sigma, self.box, self.flags = float(sigma), float(box), int(flags)
+        self.max_chains, self.log_cap = int(max_chains), int(log_cap)
+        nbytes = self.lib.ecmc_workspace_bytes(self.n, self.sigma, self.box, int(cells),
+                                               self.max_chains, self.log_cap, self.flags)
+        if nbytes < 0:
+            raise EcmcError(int(nbytes), "invalid sizes for ecmc_workspace_bytes")
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        # torch owns the device memory; 256-byte alignment is guaranteed by its allocator
+        self.workspace = torch.empty(int(nbytes), dtype=torch.uint8, device=device)
+        pos = torch.as_tensor(np.ascontiguousarray(positions, dtype=np.float64)
+                              if not isinstance(positions, torch.Tensor) else positions,
+                              dtype=torch.float64).to(device).contiguous()
+        self._ctx = ctypes.c_void_p()
+        rc = self.lib.ecmc_init(ctypes.byref(self._ctx), ctypes.c_void_p(pos.data_ptr()), self.n,
+                                self.sigma, self.box, int(cells), self.flags,
+                                ctypes.c_void_p(self.workspace.data_ptr()), int(nbytes),
+                                self.max_chains, self.log_cap,
+                                ctypes.c_void_p(self.stream.cuda_stream))
+        if rc != OK:
+            raise EcmcError(rc, {EOVERLAP: "input disks overlap", EINVAL: "invalid argument"}.get(
+                rc, "ecmc_init failed"))
+        self.k = 0
+
+    # -- helpers -------------------------------------------------------------
+    def _check(self, rc):
+        if rc != OK:
+            msg = self.lib.ecmc_last_error(self._ctx)
+            raise EcmcError(rc, msg.decode() if msg else "")
+
+    def close(self):
+        if getattr(self, "_ctx", None) and self._ctx.value:
+            self.lib.ecmc_free(self._ctx)
+            self._ctx = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- API -----------------------------------------------------------------
+    def set_active(self, idx):
+        a = np.ascontiguousarray(idx, dtype=np.int32)
+        self._check(self.lib.ecmc_set_active(self._ctx, _np_ptr(a), a.shape[0]))
+        self.k = int(a.shape[0])
+
+    def run(self, chain_time, breakpoint_interval, direction=DIR_ALTERNATE, n_chains=None):
+        self._check(self.lib.ecmc_run(self._ctx, self.k if n_chains is None else int(n_chains),
+                                      float(chain_time), float(breakpoint_interval), int(direction)))
+
+    def run_legs(self, n_legs, T, direction=DIR_ALTERNATE):
+        self.run(n_legs * T, T, direction)
+
+    def set_option(self, key, value):
+        self._check(self.lib.ecmc_set_option(self._ctx, int(key), int(value)))
+
+    def stats(self) -> dict:
+        s = Stats()
+        self._check(self.lib.ecmc_stats(self._ctx, ctypes.byref(s)))
+        return s.as_dict()
+
+    def positions(self) -> np.ndarray:
+        out = np.empty((self.n, 2), np.float64)
+        self._check(self.lib.ecmc_get_positions(self._ctx, _np_ptr(out)))
+        return out
+
+    def stamps(self) -> np.ndarray:
+        out = np.empty(self.n, np.float64)
+        self._check(self.lib.ecmc_get_stamps(self._ctx, _np_ptr(out)))
+        return out
+
+    def active(self) -> np.ndarray:
+        out = np.empty(self.k, np.int32)
+        self._check(self.lib.ecmc_get_active(self._ctx, _np_ptr(out)))
+        return out
+
+    def chain_sums(self):
+        sb = np.empty(self.k, np.float64)
+        ev = np.empty(self.k, np.int64)
+        self._check(self.lib.ecmc_get_chain_sums(self._ctx, _np_ptr(sb), _np_ptr(ev)))
+        return sb, ev
+
+    def log(self, chain) -> ChainLog:
+        """Target disk ids of the chain's liftings (the most recent log_cap)."""
+        n = ctypes.c_int64(0)
+        rc = self.lib.ecmc_get_log(self._ctx, int(chain), None, 0, ctypes.byref(n))
+        count = int(n.value)
+        keep = min(count, self.log_cap)
+        if keep == 0:
+            self._check(rc)
+            return ChainLog(count, np.empty(0, np.int32))
+        buf = np.empty(keep, np.int32)
+        self._check(self.lib.ecmc_get_log(self._ctx, int(chain), _np_ptr(buf), keep,
+                                          ctypes.byref(n)))
+        return ChainLog(count, buf)
+
+    def overlaps(self) -> int:
+        c = ctypes.c_int64(0)
+        self._check(self.lib.ecmc_overlaps(self._ctx, ctypes.byref(c)))
+        return int(c.value)

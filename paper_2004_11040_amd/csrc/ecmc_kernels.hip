@@ -1,0 +1,1716 @@
+// ecmc_kernels.hip -- gfx950 kernels for multithreaded hard-disk event-chain
+// Monte Carlo with local times (Li, Todo, Maggs, Krauth; Sec. 2.3-2.4, Alg. 5
+// and Alg. 6), and the host-side implementation of the C ABI in
+// include/ecmc.h.
+//
+// Data layout in HBM (one context = one periodic box of N disks):
+//   canonical arrays, disk-id order:  X[N], Y[N], STAMP[N] (binary64),
+//                                     ACTIVE[kmax] (disk of chain c)
+//   per-leg home-cell slots, S = nc*nc*4 (row-major cells, 4 slots per cell):
+//     MUT[S]  {a, t}       16 B  position along v and local time (mutable)
+//     CST[S]  {p, id, -}   16 B  perpendicular position and disk id (fixed for
+//                                the leg; id = -1 for an empty slot)
+//     TAG[S]  u32          STATIC, STALLED, or the chain that owns the disk
+//     M32[S]  {a-a0, p-p0} 8 B  binary32 cell-relative mirror (FP32-mixed form)
+//   per chain: slot of its disk, counters, sum of b, log ring, violation flag.
+//
+// During a leg a disk's record never leaves the slot of the cell it occupied at
+// the breakpoint ("home cell").  Along v positions only grow, p never changes,
+// and two disks closer than 2 sigma in p cannot pass each other (Sec. 3.1), so
+// walking home columns forward from the moving disk's home column finds every
+// disk it can hit; a column whose disks are all farther than the best time of
+// flight found so far ends the walk.
+//
+// Memory ordering (gfx950: one agent made of 8 XCDs, each with its own L2).
+// Every field that chains share (slot positions and local times, tags) is
+// accessed only with agent-scope atomic operations, which the AMDGPU memory
+// model makes coherent per location across the whole device.  Ordering between
+// different locations is obtained from completion waits (s_waitcnt vmcnt(0)):
+//   writer: data stores, wait until they completed, then the tag store;
+//   reader: a claim (compare-and-swap) or a load completes before the loads
+//           that depend on it are issued.
+// Agent-scope release/acquire fences would give the same order formally, but
+// they write back / invalidate a whole L2 and are serialized across the device
+// (measured ~7 ns each, i.e. ~7 us per fence with 1024 waves in flight).  The
+// completion-wait protocol was validated on gfx950 with a cross-XCD
+// message-passing litmus test (0 reordered observations in 1.2e8, against
+// 0.5 % without the waits) and is re-checked by ecmc_selftest_ordering().
+// A chain claims its target with a compare-and-swap on the target's tag; after
+// the claim it re-reads the target's position and local time and the local
+// times of the other lane minima, so the re-check of Alg. 5 statement 13 and
+// the horizon test use data no older than the claim.  The commit writes the
+// target's local time, the moving disk's local time and then its position
+// (statements 14-16; local time before position, Remark on memory order),
+// waits for completion, and releases the moving disk's tag (statement 17).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <limits>
+#include <new>
+#include <vector>
+
+#include "../../include/ecmc.h"
+
+namespace {
+
+constexpr uint32_t TAG_STATIC = 0xFFFFFFFFu;
+constexpr uint32_t TAG_STALLED = 0xFFFFFFFEu;
+constexpr uint32_t TAG_PAUSED = 0xFFFFFFFDu;  // active, waiting for the next sub-leg
+constexpr int CAP = 4;          // disks per cell (rigorous for cell width < 2 sqrt(2) sigma)
+constexpr int ROWS = 3;         // rows of cells covering the corridor |dp| < 2 sigma
+constexpr int NCNT = 6;         // per-chain counters
+enum { C_EVENTS = 0, C_CASFAIL, C_WAITS, C_MOVES, C_REFINES, C_SCANNED };
+constexpr double STOP_MARGIN = 1e-7;  // slack in the column lower bound (>> rounding)
+
+struct MutRec {
+  double a, t;
+};
+struct CstRec {
+  double p;
+  int32_t id;
+  int32_t pad;
+};
+
+struct Ctl {
+  unsigned long long tstar_bits;  // min over violating chains of their local time
+  int32_t abort;                  // a chain flagged a violation in this attempt
+  int32_t error;                  // ECMC_E* raised by a kernel
+  unsigned long long overlaps;
+  int32_t inject_chain, inject_event;
+  int32_t pad[2];
+  long long delta_events, delta_slots;  // work of the last attempt (all chains)
+};
+
+struct Geo {
+  double L, halfL, d, d2, sigma, c, inv_c;
+  int32_t nc;
+  int32_t mmax;  // largest column offset a scan may reach
+};
+
+struct Dev {
+  double *X, *Y, *STAMP;
+  int32_t *ACTIVE, *SLOT_OF, *CELL_CNT;
+  MutRec *MUT;
+  CstRec *CST;
+  uint32_t *TAG;
+  float2 *M32;
+  int32_t *CH_SLOT;
+  long long *CNT_W, *CNT_C;  // working / committed counters [k][NCNT]
+  double *SUMB_W, *SUMB_C;
+  long long *LOGLEN_W, *LOGLEN_C;
+  int32_t *LOG;
+  double *FLAG;
+  // global-order candidates
+  double *GC_TAU, *GC_B;
+  int32_t *GC_SLOT;
+  // first-touch undo of an attempt: original records of the slots it modified
+  MutRec *MUT_SNAP;
+  float2 *M32_SNAP;
+  uint32_t *EPOCH;
+  int32_t *CH_SLOT_SNAP;
+  // chain references (activation position and local time) and their copies
+  double *CH_A, *CH_T, *CH_A_SNAP, *CH_T_SNAP;
+  Ctl *ctl;
+  int64_t n;
+  int32_t k;
+  int64_t log_cap;
+};
+
+struct LegP {
+  int32_t dir;     // 0: v = +x, 1: v = +y
+  int32_t final;   // 1: tend is the leg's breakpoint h' (stall); 0: intermediate (pause)
+  double h;        // start of this attempt (leg-relative time)
+  double tend;     // end of this attempt
+  uint32_t epoch;  // attempt number (first-touch undo marker)
+  int32_t strict;  // 1: add the formal agent-scope acquire/release fences
+};
+
+// Save a slot's record before its first modification in this attempt.  Only
+// the chain that owns the slot (holds its tag) modifies it, so one writer at a
+// time; ownership moves between chains on different XCDs, so the marker and
+// the saved copy are agent-scope atomics like every other shared field (they
+// are ordered before the tag release that hands the slot over).
+__device__ __forceinline__ void save_first_touch(const Dev &D, int sl, double a, double t, uint32_t epoch) {
+  if (__hip_atomic_load(&D.EPOCH[sl], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != epoch) {
+    __hip_atomic_store(&D.MUT_SNAP[sl].a, a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(&D.MUT_SNAP[sl].t, t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (D.M32) {
+      const float mx = __hip_atomic_load(&D.M32[sl].x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      const float my = __hip_atomic_load(&D.M32[sl].y, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(&D.M32_SNAP[sl].x, mx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(&D.M32_SNAP[sl].y, my, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __hip_atomic_store(&D.EPOCH[sl], epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+// ------------------------------------------------------------------------
+// agent-scope atomic helpers
+// ------------------------------------------------------------------------
+__device__ __forceinline__ double ld_a(const double *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_a(double *p, double v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+// wait until every memory operation this wave issued has completed
+// (s_waitcnt vmcnt(0); expcnt and lgkmcnt left at their maximum)
+__device__ __forceinline__ void wait_mem() { __builtin_amdgcn_s_waitcnt(0x0F70); }
+// publish: earlier stores complete before the tag store is issued
+__device__ __forceinline__ void st_rel(uint32_t *p, uint32_t v) {
+  wait_mem();
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void fence_rel() { wait_mem(); }
+__device__ __forceinline__ void fence_acq() { wait_mem(); }
+// validation mode: the formal agent-scope fences on top of the waits
+__device__ __forceinline__ void strict_rel(int on) {
+  if (on) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+}
+__device__ __forceinline__ void strict_acq(int on) {
+  if (on) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+}
+
+// ------------------------------------------------------------------------
+// Canonical binary64 event arithmetic (identical operation order wherever a
+// time of flight or a move is evaluated; no contraction: -ffp-contract=off).
+// ------------------------------------------------------------------------
+__device__ __forceinline__ double min_image(double dp, const Geo &g) {
+  if (dp > g.halfL) return dp - g.L;
+  if (dp < -g.halfL) return dp + g.L;
+  return dp;
+}
+// time of flight from (ai,pi) to (aj,pj) moving forward; +inf outside corridor
+__device__ __forceinline__ double tof(double ai, double pi, double aj, double pj, const Geo &g,
+                                      double &b, double &dp) {
+  dp = min_image(pj - pi, g);
+  double dp2 = dp * dp;
+  if (!(dp2 < g.d2)) return INFINITY;
+  double da = aj - ai;
+  if (da < 0.0) da = da + g.L;
+  b = sqrt(g.d2 - dp2);
+  double tau = da - b;
+  if (tau < 0.0) tau = 0.0;
+  return tau;
+}
+__device__ __forceinline__ double fwd_move(double a, double dist, const Geo &g) {
+  double r = a + dist;
+  if (r >= g.L) r = r - g.L;
+  return r;
+}
+__device__ __forceinline__ bool key_less(double t1, int i1, double t2, int i2) {
+  return t1 < t2 || (t1 == t2 && i1 < i2);
+}
+// lane of the corridor: 0 |dp| < sigma, 1 sigma <= dp, 2 dp <= -sigma
+__device__ __forceinline__ int lane_class(double dp, const Geo &g) {
+  if (fabs(dp) < g.sigma) return 0;
+  return dp > 0.0 ? 1 : 2;
+}
+
+// ------------------------------------------------------------------------
+// generic fill (graph-safe replacement for memset)
+// ------------------------------------------------------------------------
+template <typename T>
+__global__ void k_fill(T *p, T v, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (; i < n; i += stride) p[i] = v;
+}
+
+// ------------------------------------------------------------------------
+// a1: home-cell build.  Bin every disk by its (a, p) at the breakpoint.
+// ------------------------------------------------------------------------
+__global__ void k_bin(Dev D, Geo g, int32_t dir) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= D.n) return;
+  double a = dir ? D.Y[i] : D.X[i];
+  double p = dir ? D.X[i] : D.Y[i];
+  int col = (int)(a * g.inv_c), row = (int)(p * g.inv_c);
+  col = col < 0 ? 0 : (col >= g.nc ? g.nc - 1 : col);
+  row = row < 0 ? 0 : (row >= g.nc ? g.nc - 1 : row);
+  int cell = row * g.nc + col;
+  int r = atomicAdd(&D.CELL_CNT[cell], 1);
+  if (r < CAP) {
+    D.CST[(int64_t)cell * CAP + r].id = (int32_t)i;
+  } else {
+    atomicExch(&D.ctl->error, ECMC_ECELL);
+  }
+}
+
+// One thread per cell: order the cell's disks by id (deterministic layout) and
+// write their slot records.
+__global__ void k_cellfill(Dev D, Geo g, int32_t dir) {
+  int64_t cell = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t ncell = (int64_t)g.nc * g.nc;
+  if (cell >= ncell) return;
+  int cnt = D.CELL_CNT[cell];
+  cnt = cnt > CAP ? CAP : cnt;
+  int ids[CAP];
+  for (int q = 0; q < CAP; ++q) ids[q] = q < cnt ? D.CST[cell * CAP + q].id : 0x7fffffff;
+  for (int q = 1; q < CAP; ++q)  // insertion sort of <= 4 ids
+    for (int r = q; r > 0 && ids[r] < ids[r - 1]; --r) {
+      int tmp = ids[r];
+      ids[r] = ids[r - 1];
+      ids[r - 1] = tmp;
+    }
+  int row = (int)(cell / g.nc), col = (int)(cell % g.nc);
+  double a0 = col * g.c, p0 = row * g.c;
+  for (int q = 0; q < CAP; ++q) {
+    int64_t s = cell * CAP + q;
+    if (q < cnt) {
+      int i = ids[q];
+      double a = dir ? D.Y[i] : D.X[i];
+      double p = dir ? D.X[i] : D.Y[i];
+      CstRec cr;
+      cr.p = p;
+      cr.id = i;
+      cr.pad = 0;
+      D.CST[s] = cr;
+      MutRec mr;
+      mr.a = a;
+      mr.t = D.STAMP[i];
+      D.MUT[s] = mr;
+      D.TAG[s] = TAG_STATIC;
+      D.SLOT_OF[i] = (int32_t)s;
+      if (D.M32) D.M32[s] = make_float2((float)(a - a0), (float)(p - p0));
+    } else {
+      CstRec cr;
+      cr.p = 0.0;
+      cr.id = -1;
+      cr.pad = 0;
+      D.CST[s] = cr;
+      MutRec mr;
+      mr.a = 0.0;
+      mr.t = 0.0;
+      D.MUT[s] = mr;
+      D.TAG[s] = TAG_STATIC;
+      if (D.M32) D.M32[s] = make_float2(0.f, 0.f);
+    }
+  }
+}
+
+// Once per leg, after the home-cell build: attach each chain to its disk's slot.
+__global__ void k_chains_leg(Dev D, int64_t nslots) {
+  int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= D.k) return;
+  if (D.ctl->error) return;  // a failed build leaves SLOT_OF unusable
+  int s = D.SLOT_OF[D.ACTIVE[c]];
+  if (s < 0 || s >= nslots || D.CST[s].id != D.ACTIVE[c]) {
+    atomicExch(&D.ctl->error, ECMC_ECELL);
+    return;
+  }
+  D.CH_SLOT[c] = s;
+  D.CH_A[c] = D.MUT[s].a;
+  D.CH_T[c] = D.MUT[s].t;
+}
+
+// Before every attempt: tag each chain's disk, keep a copy of the chain slots,
+// reset working counters from the committed ones (a discarded attempt leaves
+// no trace).
+__global__ void k_chains_attempt(Dev D) {
+  int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= D.k) return;
+  if (D.ctl->error) return;
+  const int s = D.CH_SLOT[c];
+  D.CH_SLOT_SNAP[c] = s;
+  D.CH_A_SNAP[c] = D.CH_A[c];
+  D.CH_T_SNAP[c] = D.CH_T[c];
+  D.TAG[s] = (uint32_t)c;
+  for (int q = 0; q < NCNT; ++q) D.CNT_W[c * NCNT + q] = D.CNT_C[c * NCNT + q];
+  D.SUMB_W[c] = D.SUMB_C[c];
+  D.LOGLEN_W[c] = D.LOGLEN_C[c];
+  D.FLAG[c] = INFINITY;
+}
+
+// After a violating attempt: put back every slot it modified, free the tags.
+__global__ void k_restore(Dev D, int64_t nslots, uint32_t epoch) {
+  int64_t sl = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (sl < nslots) {
+    if (D.EPOCH[sl] == epoch) {
+      D.MUT[sl] = D.MUT_SNAP[sl];
+      if (D.M32) D.M32[sl] = D.M32_SNAP[sl];
+    }
+    // tags: only chains own disks between attempts; they are set again below
+    if (D.TAG[sl] != TAG_STATIC) D.TAG[sl] = TAG_STATIC;
+  }
+  if (sl < D.k) {
+    D.CH_SLOT[sl] = D.CH_SLOT_SNAP[sl];
+    D.CH_A[sl] = D.CH_A_SNAP[sl];
+    D.CH_T[sl] = D.CH_T_SNAP[sl];
+  }
+}
+
+__global__ void k_ctl_reset(Dev D) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    D.ctl->tstar_bits = 0x7FF0000000000000ull;  // +inf
+    D.ctl->abort = 0;
+  }
+}
+
+// ------------------------------------------------------------------------
+// a3-a7: the event kernel.  One chain per group of G lanes (G = 64: one
+// wavefront per chain).  Each iteration is one attempt at one event of Alg. 5
+// (statements 1-19) for the group's chain; a wait on an active target is a
+// retry in the next iteration, never a spin inside the iteration.
+// ------------------------------------------------------------------------
+template <int G>
+struct Win {
+  static constexpr int M = (G == 16) ? 4 : 5;  // columns per pass
+  static constexpr int NS = ROWS * CAP * M;   // slots per pass
+  static constexpr int SPL = (NS + G - 1) / G;
+};
+
+template <int G>
+__device__ __forceinline__ void grp_min(double &tau, int &id) {
+#pragma unroll
+  for (int off = G / 2; off > 0; off >>= 1) {
+    double t2 = __shfl_xor(tau, off, G);
+    int i2 = __shfl_xor(id, off, G);
+    if (key_less(t2, i2, tau, id)) {
+      tau = t2;
+      id = i2;
+    }
+  }
+}
+
+template <int G>
+__device__ __forceinline__ int grp_owner(bool mine, int lane) {
+  unsigned long long m = __ballot(mine);
+  if constexpr (G == 64) {
+    return m ? (__ffsll((long long)m) - 1) : 0;
+  } else {
+    const int base = (__lane_id() / G) * G;
+    m &= ((1ull << G) - 1ull) << base;
+    return m ? (__ffsll((long long)m) - 1 - base) : 0;
+  }
+}
+
+// Per-lane candidates: the nearest disk in each of the three lanes of the
+// corridor (the horizon set) with its record; the target is the smallest of
+// the three.
+struct Cand {
+  double tau[3], t[3], a[3], b[3], p[3];
+  int id[3], slot[3];
+};
+
+template <int G>
+__device__ __forceinline__ void flag_violation(const Dev &D, int c, double t, int lane) {
+  if (lane == 0) {
+    D.FLAG[c] = t;
+    atomicMin(&D.ctl->tstar_bits, (unsigned long long)__double_as_longlong(t));
+    __hip_atomic_store(&D.ctl->abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+// Event arithmetic always starts from the chain's reference: the position a and
+// local time t its disk had when the chain activated it (the lazy form of
+// Alg. 2, the same operands the global-time order uses).  The reference lives
+// in registers and in CH_A/CH_T between attempts.  What other chains see in
+// the disk's slot is a published point of the same trajectory: the reference
+// itself, a move up to contact, or, at a breakpoint, the point reached there
+// (stall at h', or pause at an intermediate breakpoint: the disk then looks
+// exactly like a stalled one to the others, t = breakpoint).
+template <int G>
+__global__ void __launch_bounds__(256) k_event(Dev D, Geo g, LegP lp, int32_t wait_retries,
+                                               long long iter_cap) {
+  const int lane = threadIdx.x & (G - 1);
+  const int c = (int)(((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G);
+  if (c >= D.k) return;  // whole groups leave together
+  if (D.ctl->error) return;
+  using W = Win<G>;
+
+  int s = D.CH_SLOT[c];
+  double a = D.CH_A[c];  // reference position of the chain's disk
+  double t = D.CH_T[c];  // reference local time
+  double p = D.CST[s].p;
+  double t_pub = ld_a(&D.MUT[s].t);  // published point
+  if (lane == 0) save_first_touch(D, s, ld_a(&D.MUT[s].a), t_pub, lp.epoch);
+  long long cnt[NCNT];
+  for (int q = 0; q < NCNT; ++q) cnt[q] = D.CNT_W[c * NCNT + q];
+  double sumb = D.SUMB_W[c];
+  long long loglen = D.LOGLEN_W[c];
+  const long long ev_start = cnt[C_EVENTS];
+  long long lane_scanned = 0;
+  const int inj_ev = (D.ctl->inject_chain == c) ? D.ctl->inject_event : -1;
+  int retries = 0;
+  const double tend = lp.tend, h = lp.h;
+
+  for (long long it = 0;; ++it) {
+    // the abort word (another chain saw a violation) is read with the scan's
+    // loads and tested after them
+    int ab = 0;
+    if (lane == 0) ab = __hip_atomic_load(&D.ctl->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (it >= iter_cap) {
+      if (lane == 0) {
+        atomicExch(&D.ctl->error, ECMC_EHANG);
+        __hip_atomic_store(&D.ctl->abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+      break;
+    }
+    if (inj_ev >= 0 && cnt[C_EVENTS] - ev_start == inj_ev) {  // test hook
+      flag_violation<G>(D, c, t, lane);
+      break;
+    }
+
+    // ---- statements 1-9: corridor scan over home columns ----
+    const int cell0 = s >> 2;
+    const int row0 = cell0 / g.nc, col0 = cell0 - row0 * g.nc;
+    double u = a - col0 * g.c;  // distance from the home column's trailing edge
+    if (u < 0.0) u = u + g.L;
+    const double trem = tend - t;
+
+    Cand bl;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      bl.tau[q] = INFINITY;
+      bl.t[q] = bl.a[q] = bl.b[q] = bl.p[q] = 0.0;
+      bl.id[q] = 0x7fffffff;
+      bl.slot[q] = -1;
+    }
+    double gt[3];
+    int gi[3];
+    int scanned = 0;
+    for (int m0 = 0;; m0 += W::M) {
+#pragma unroll
+      for (int r = 0; r < W::SPL; ++r) {
+        const int w = lane + r * G;
+        if (w < W::NS) {
+          const int mc = m0 + w / (ROWS * CAP);
+          const int rem = w % (ROWS * CAP);
+          if (mc <= g.mmax) {
+            int col = col0 + mc;
+            if (col >= g.nc) col -= g.nc;
+            int row = row0 + rem / CAP - 1;
+            row = row < 0 ? row + g.nc : (row >= g.nc ? row - g.nc : row);
+            const int sl = ((row * g.nc + col) << 2) + (rem % CAP);
+            const CstRec cr = D.CST[sl];
+            const double aj = ld_a(&D.MUT[sl].a);
+            const double tj = ld_a(&D.MUT[sl].t);
+            if (cr.id >= 0 && sl != s) {
+              ++scanned;
+              double b, dp;
+              const double tau = tof(a, p, aj, cr.p, g, b, dp);
+              // a disk that came to rest behind the moving disk before this
+              // attempt began (its stamp <= h) is not ahead of it
+              const bool behind = (t + tau < tj) && (tj <= h);
+              if (tau < INFINITY && !behind) {
+                const int cls = lane_class(dp, g);
+#pragma unroll
+                for (int q = 0; q < 3; ++q) {  // unrolled: no dynamic indexing
+                  if (q == cls && key_less(tau, cr.id, bl.tau[q], bl.id[q])) {
+                    bl.tau[q] = tau;
+                    bl.id[q] = cr.id;
+                    bl.slot[q] = sl;
+                    bl.t[q] = tj;
+                    bl.a[q] = aj;
+                    bl.b[q] = b;
+                    bl.p[q] = cr.p;
+                  }
+                }
+              }
+            }
+          }
+        }
+      }
+      // group minima per lane-class
+      double lim = 0.0;
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        gt[q] = bl.tau[q];
+        gi[q] = bl.id[q];
+        grp_min<G>(gt[q], gi[q]);
+        const double lq = gt[q] < trem ? gt[q] : trem;
+        lim = lq > lim ? lq : lim;
+      }
+      const int mnext = m0 + W::M;
+      if (mnext > g.mmax) break;
+      const double lb = mnext * g.c - u - g.d - STOP_MARGIN;
+      if (lb > lim) break;
+    }
+    lane_scanned += scanned;
+    ab = __shfl(ab, 0, G);
+    if (ab) break;
+
+    // broadcast the records of the minima
+    double gtj[3], gaj[3], gbj[3], gpj[3];
+    int gsl[3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      const int own = grp_owner<G>(bl.tau[q] == gt[q] && bl.id[q] == gi[q] && gt[q] < INFINITY, lane);
+      gtj[q] = __shfl(bl.t[q], own, G);
+      gaj[q] = __shfl(bl.a[q], own, G);
+      gbj[q] = __shfl(bl.b[q], own, G);
+      gpj[q] = __shfl(bl.p[q], own, G);
+      gsl[q] = __shfl(bl.slot[q], own, G);
+    }
+    int tc = 0;
+    if (key_less(gt[1], gi[1], gt[tc], gi[tc])) tc = 1;
+    if (key_less(gt[2], gi[2], gt[tc], gi[tc])) tc = 2;
+    const double tau = gt[tc];
+    const int ts = gsl[tc];
+
+    // ---- statement 5: horizon condition on the lane minima (scanned times) ----
+    bool viol = false;
+#pragma unroll
+    for (int q = 0; q < 3; ++q)
+      if (gt[q] < trem && t + gt[q] < gtj[q]) viol = true;
+    if (viol) {
+      flag_violation<G>(D, c, t, lane);
+      break;
+    }
+
+    // ---- no admissible lifting before the breakpoint: stall (statements
+    // 21-24) or pause; both publish the point reached at the breakpoint ----
+    if (!(tau < trem)) {
+      const double an = fwd_move(a, trem, g);
+      if (lane == 0) {
+        st_a(&D.MUT[s].t, tend);
+        fence_rel();
+        strict_rel(lp.strict);
+        st_a(&D.MUT[s].a, an);
+        strict_rel(lp.strict);
+        st_rel(&D.TAG[s], lp.final ? TAG_STALLED : TAG_PAUSED);
+      }
+      if (lp.final) {
+        a = an;
+        t = tend;
+      }
+      break;
+    }
+
+    // ---- statement 10: claim the target ----
+    int won = 0;
+    uint32_t old = TAG_STATIC;
+    double aj2 = 0.0, tj2 = 0.0, tcls[3] = {0.0, 0.0, 0.0};
+    if (lane == 0) {
+      won = __hip_atomic_compare_exchange_strong(&D.TAG[ts], &old, (uint32_t)c, __ATOMIC_RELAXED,
+                                                 __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                ? 1
+                : 0;
+      fence_acq();
+      strict_acq(lp.strict);
+      if (won) {
+        // statement 13 (extended to the local time): reads issued after the claim completed
+        aj2 = ld_a(&D.MUT[ts].a);
+        tj2 = ld_a(&D.MUT[ts].t);
+#pragma unroll
+        for (int q = 0; q < 3; ++q) tcls[q] = (gt[q] < trem) ? ld_a(&D.MUT[gsl[q]].t) : 0.0;
+      }
+    }
+    won = __shfl(won, 0, G);
+    if (!won) {
+      old = __shfl(old, 0, G);
+      if (old == TAG_STALLED || old == TAG_PAUSED) {
+        // it sits where it is at the breakpoint with t = breakpoint, and this
+        // chain would reach it earlier: a horizon violation
+        flag_violation<G>(D, c, t, lane);
+        break;
+      }
+      // the target is active on another chain: retry; after wait_retries
+      // failed claims publish a move up to contact with it (Remark on necklaces)
+      cnt[C_WAITS] += (lane == 0);
+      if (++retries >= wait_retries) {
+        retries = 0;
+        const double tn = t + tau;
+        if (tn > t_pub) {
+          int bad = 0;
+          if (lane == 0) {
+            fence_acq();
+            strict_acq(lp.strict);
+#pragma unroll
+            for (int q = 0; q < 3; ++q)
+              if (gt[q] < trem && t + gt[q] < ld_a(&D.MUT[gsl[q]].t)) bad = 1;
+          }
+          bad = __shfl(bad, 0, G);
+          if (bad) {
+            flag_violation<G>(D, c, t, lane);
+            break;
+          }
+          const double an = fwd_move(a, tau, g);
+          if (lane == 0) {
+            st_a(&D.MUT[s].t, tn);
+            fence_rel();
+            strict_rel(lp.strict);
+            st_a(&D.MUT[s].a, an);
+          }
+          t_pub = tn;
+          cnt[C_MOVES] += (lane == 0);
+        }
+      }
+      __builtin_amdgcn_s_sleep(4);
+      continue;
+    }
+    aj2 = __shfl(aj2, 0, G);
+    tj2 = __shfl(tj2, 0, G);
+#pragma unroll
+    for (int q = 0; q < 3; ++q) tcls[q] = __shfl(tcls[q], 0, G);
+    // statement 13: the target must not have moved (nor been stamped) since the scan
+    if (aj2 != gaj[tc] || tj2 != gtj[tc]) {
+      if (lane == 0) {
+        strict_rel(lp.strict);
+        st_rel(&D.TAG[ts], TAG_STATIC);  // statement 20
+      }
+      cnt[C_CASFAIL] += (lane == 0);
+      continue;
+    }
+    // statement 5 again with local times read after the claim
+#pragma unroll
+    for (int q = 0; q < 3; ++q)
+      if (gt[q] < trem && t + gt[q] < tcls[q]) viol = true;
+    if (viol) {
+      if (lane == 0) st_rel(&D.TAG[ts], TAG_STATIC);
+      flag_violation<G>(D, c, t, lane);
+      break;
+    }
+
+    // ---- statements 14-19: commit the lifting ----
+    const double tn = t + tau;
+    const double an = fwd_move(a, tau, g);
+    if (lane == 0) {
+      save_first_touch(D, ts, aj2, tj2, lp.epoch);
+      st_a(&D.MUT[ts].t, tn);  // 14: t_j
+      st_a(&D.MUT[s].t, tn);   // 15: t_i
+      fence_rel();
+      strict_rel(lp.strict);
+      st_a(&D.MUT[s].a, an);   // 16: x_i
+      if (D.M32) {
+        const int cc = (s >> 2) % g.nc;
+        __hip_atomic_store(&D.M32[s].x, (float)(an - cc * g.c), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+      strict_rel(lp.strict);
+      st_rel(&D.TAG[s], TAG_STATIC);  // 17: release i
+      D.LOG[(int64_t)c * D.log_cap + (loglen % D.log_cap)] = gi[tc];
+    }
+    ++loglen;
+    cnt[C_EVENTS] += 1;
+    sumb = sumb + gbj[tc];
+    s = ts;  // 19: continue with j
+    a = aj2;
+    p = gpj[tc];
+    t = tn;
+    t_pub = tn;
+    retries = 0;
+  }
+  // group-wide sum of per-lane scan counts
+  long long sc = lane_scanned;
+#pragma unroll
+  for (int off = G / 2; off > 0; off >>= 1) sc += __shfl_xor(sc, off, G);
+  if (lane == 0) {
+    cnt[C_SCANNED] += sc;
+    for (int q = 0; q < NCNT; ++q) D.CNT_W[c * NCNT + q] = cnt[q];
+    D.SUMB_W[c] = sumb;
+    D.LOGLEN_W[c] = loglen;
+    D.CH_SLOT[c] = s;
+    D.CH_A[c] = a;
+    D.CH_T[c] = t;
+  }
+}
+
+// ------------------------------------------------------------------------
+// a8: breakpoint.  If the attempt finished without a violation, write the
+// slot records back to the canonical arrays and commit per-chain results.
+// ------------------------------------------------------------------------
+__global__ void k_writeback(Dev D, Geo g, int32_t dir) {
+  if (D.ctl->error) return;
+  int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s < D.k) D.ACTIVE[s] = D.CST[D.CH_SLOT[s]].id;
+  int64_t ns = (int64_t)g.nc * g.nc * CAP;
+  if (s >= ns) return;
+  const int id = D.CST[s].id;
+  if (id < 0) return;
+  const MutRec m = D.MUT[s];
+  if (dir)
+    D.Y[id] = m.a;
+  else
+    D.X[id] = m.a;
+  D.STAMP[id] = m.t;
+}
+
+// Work done by the last attempt, summed over chains (one block).
+__global__ void k_count_delta(Dev D) {
+  __shared__ long long se[256], ss[256];
+  long long e = 0, sl = 0;
+  for (int c = threadIdx.x; c < D.k; c += blockDim.x) {
+    e += D.CNT_W[c * NCNT + C_EVENTS] - D.CNT_C[c * NCNT + C_EVENTS];
+    sl += D.CNT_W[c * NCNT + C_SCANNED] - D.CNT_C[c * NCNT + C_SCANNED];
+  }
+  se[threadIdx.x] = e;
+  ss[threadIdx.x] = sl;
+  __syncthreads();
+  for (int off = blockDim.x / 2; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) {
+      se[threadIdx.x] += se[threadIdx.x + off];
+      ss[threadIdx.x] += ss[threadIdx.x + off];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    D.ctl->delta_events = se[0];
+    D.ctl->delta_slots = ss[0];
+  }
+}
+
+__global__ void k_chains_commit(Dev D) {
+  if (D.ctl->abort || D.ctl->error) return;
+  int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= D.k) return;
+  for (int q = 0; q < NCNT; ++q) D.CNT_C[c * NCNT + q] = D.CNT_W[c * NCNT + q];
+  D.SUMB_C[c] = D.SUMB_W[c];
+  D.LOGLEN_C[c] = D.LOGLEN_W[c];
+}
+
+// ------------------------------------------------------------------------
+// Fallback: one leg (or its remainder) in global-time order, Alg. 2, on one
+// workgroup.  Each chain keeps its minimum (tau, target); the block picks the
+// smallest event time, commits it, and refreshes exactly the minima the
+// lifting can change.  Cannot violate a horizon; slow, used only when reruns
+// with shorter breakpoints keep failing.
+// ------------------------------------------------------------------------
+__device__ void g_scan(const Dev &D, const Geo &g, int s, double a, double p, double tc,
+                       double tnow, double bound, double &btau, int &bslot, double &bb) {
+  btau = INFINITY;
+  bslot = -1;
+  bb = 0.0;
+  int bid = 0x7fffffff;
+  const int cell0 = s >> 2;
+  const int row0 = cell0 / g.nc, col0 = cell0 - row0 * g.nc;
+  double u = a - col0 * g.c;
+  if (u < 0.0) u = u + g.L;
+  for (int mc = 0; mc <= g.mmax; ++mc) {
+    if (mc > 0) {
+      const double lim = btau < bound ? btau : bound;
+      if (mc * g.c - u - g.d - STOP_MARGIN > lim) break;
+    }
+    int col = col0 + mc;
+    if (col >= g.nc) col -= g.nc;
+    for (int dr = -1; dr <= 1; ++dr) {
+      int row = row0 + dr;
+      row = row < 0 ? row + g.nc : (row >= g.nc ? row - g.nc : row);
+      for (int q = 0; q < CAP; ++q) {
+        const int sl = ((row * g.nc + col) << 2) + q;
+        const int id = D.CST[sl].id;
+        if (id < 0 || sl == s || D.TAG[sl] != TAG_STATIC) continue;
+        double b, dp;
+        const double tau = tof(a, p, D.MUT[sl].a, D.CST[sl].p, g, b, dp);
+        if (!(tau < bound) || tc + tau < tnow) continue;
+        if (key_less(tau, id, btau, bid)) {
+          btau = tau;
+          bid = id;
+          bslot = sl;
+          bb = b;
+        }
+      }
+    }
+  }
+}
+
+__global__ void __launch_bounds__(1024) k_global(Dev D, Geo g, LegP lp) {
+  if (D.ctl->error) return;
+  __shared__ double red_e[1024];
+  __shared__ int red_c[1024];
+  __shared__ int s_w, s_old, s_new;
+  __shared__ double s_e;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const double tend = lp.tend;
+  // initial minima at global time h (disks that came to rest behind a moving
+  // disk before h are not ahead of it).  Chains act from their references.
+  for (int c = tid; c < D.k; c += nt) {
+    const int s = D.CH_SLOT[c];
+    const double tc0 = D.CH_T[c];
+    double bt, bb;
+    int bs;
+    g_scan(D, g, s, D.CH_A[c], D.CST[s].p, tc0, tc0 > lp.h ? tc0 : lp.h, tend - tc0, bt, bs, bb);
+    D.GC_TAU[c] = bt;
+    D.GC_SLOT[c] = bs;
+    D.GC_B[c] = bb;
+  }
+  __syncthreads();
+  for (;;) {
+    double be = INFINITY;
+    int bc = 0x7fffffff;
+    for (int c = tid; c < D.k; c += nt) {
+      const double tcc = D.CH_T[c];
+      const double tau = D.GC_TAU[c];
+      if (!(tau < tend - tcc)) continue;
+      const double e = tcc + tau;
+      if (e < be || (e == be && c < bc)) {
+        be = e;
+        bc = c;
+      }
+    }
+    red_e[tid] = be;
+    red_c[tid] = bc;
+    __syncthreads();
+    for (int off = nt / 2; off > 0; off >>= 1) {
+      if (tid < off) {
+        const double e2 = red_e[tid + off];
+        const int c2 = red_c[tid + off];
+        if (e2 < red_e[tid] || (e2 == red_e[tid] && c2 < red_c[tid])) {
+          red_e[tid] = e2;
+          red_c[tid] = c2;
+        }
+      }
+      __syncthreads();
+    }
+    if (red_c[0] == 0x7fffffff) break;  // no lifting before tend
+    if (tid == 0) {
+      const int w = red_c[0];
+      const int s = D.CH_SLOT[w];
+      const int ts = D.GC_SLOT[w];
+      const double tau = D.GC_TAU[w];
+      const double tn = D.CH_T[w] + tau;
+      const double an = fwd_move(D.CH_A[w], tau, g);
+      MutRec mi;
+      mi.a = an;
+      mi.t = tn;
+      D.MUT[s] = mi;
+      D.MUT[ts].t = tn;
+      if (D.M32) D.M32[s].x = (float)(an - ((s >> 2) % g.nc) * g.c);
+      D.TAG[s] = TAG_STATIC;
+      D.TAG[ts] = (uint32_t)w;
+      const long long len = D.LOGLEN_W[w];
+      D.LOG[(int64_t)w * D.log_cap + (len % D.log_cap)] = D.CST[ts].id;
+      D.LOGLEN_W[w] = len + 1;
+      D.CNT_W[w * NCNT + C_EVENTS] += 1;
+      D.SUMB_W[w] = D.SUMB_W[w] + D.GC_B[w];
+      D.CH_SLOT[w] = ts;
+      D.CH_A[w] = D.MUT[ts].a;
+      D.CH_T[w] = tn;
+      s_w = w;
+      s_old = s;
+      s_new = ts;
+      s_e = tn;
+    }
+    __threadfence_block();
+    __syncthreads();
+    const int w = s_w, si = s_old, sj = s_new;
+    const double e = s_e;
+    for (int c = tid; c < D.k; c += nt) {
+      const int s = D.CH_SLOT[c];
+      const double tcc = D.CH_T[c];
+      const double bound = tend - tcc;
+      if (c == w || D.GC_SLOT[c] == sj) {
+        double bt, bb;
+        int bs;
+        g_scan(D, g, s, D.CH_A[c], D.CST[s].p, tcc, e, bound, bt, bs, bb);
+        D.GC_TAU[c] = bt;
+        D.GC_SLOT[c] = bs;
+        D.GC_B[c] = bb;
+      } else {
+        double b, dp;
+        const double tau = tof(D.CH_A[c], D.CST[s].p, D.MUT[si].a, D.CST[si].p, g, b, dp);
+        const int oid = D.GC_SLOT[c] >= 0 ? D.CST[D.GC_SLOT[c]].id : 0x7fffffff;
+        if (tau < bound && !(tcc + tau < e) && key_less(tau, D.CST[si].id, D.GC_TAU[c], oid)) {
+          D.GC_TAU[c] = tau;
+          D.GC_SLOT[c] = si;
+          D.GC_B[c] = b;
+        }
+      }
+    }
+    __threadfence_block();
+    __syncthreads();
+  }
+  // breakpoint: every chain publishes the point reached there; at h' it stalls
+  for (int c = tid; c < D.k; c += nt) {
+    const int s = D.CH_SLOT[c];
+    const double tcc = D.CH_T[c];
+    const double an = fwd_move(D.CH_A[c], tend - tcc, g);
+    MutRec m;
+    m.a = an;
+    m.t = tend;
+    D.MUT[s] = m;
+    D.TAG[s] = lp.final ? TAG_STALLED : TAG_PAUSED;
+    if (lp.final) {
+      D.CH_A[c] = an;
+      D.CH_T[c] = tend;
+    }
+  }
+}
+
+// ------------------------------------------------------------------------
+// a9: overlap check on the canonical positions, using a +x home-cell build.
+// ------------------------------------------------------------------------
+__global__ void k_overlap(Dev D, Geo g, double lim2) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= D.n) return;
+  const int s = D.SLOT_OF[i];
+  const int cell = s >> 2;
+  const int row0 = cell / g.nc, col0 = cell - row0 * g.nc;
+  const double xi = D.X[i], yi = D.Y[i];
+  unsigned long long cnt = 0;
+  for (int dr = -1; dr <= 1; ++dr)
+    for (int dc = -1; dc <= 1; ++dc) {
+      int row = row0 + dr, col = col0 + dc;
+      row = row < 0 ? row + g.nc : (row >= g.nc ? row - g.nc : row);
+      col = col < 0 ? col + g.nc : (col >= g.nc ? col - g.nc : col);
+      for (int q = 0; q < CAP; ++q) {
+        const int j = D.CST[((row * g.nc + col) << 2) + q].id;
+        if (j <= (int)i) continue;
+        const double dx = min_image(D.X[j] - xi, g), dy = min_image(D.Y[j] - yi, g);
+        if (dx * dx + dy * dy < lim2) ++cnt;
+      }
+    }
+  if (cnt) atomicAdd(&D.ctl->overlaps, cnt);
+}
+
+// coordinates must lie in [0, L)
+__global__ void k_check_range(Dev D, double L) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= D.n) return;
+  const double x = D.X[i], y = D.Y[i];
+  if (!(x >= 0.0 && x < L && y >= 0.0 && y < L)) atomicExch(&D.ctl->error, ECMC_EINVAL);
+}
+
+// split interleaved (x,y) into the canonical arrays
+__global__ void k_split_xy(Dev D, const double *xy) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= D.n) return;
+  D.X[i] = xy[2 * i];
+  D.Y[i] = xy[2 * i + 1];
+}
+
+__global__ void k_join_xy(Dev D, double *xy) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= D.n) return;
+  xy[2 * i] = D.X[i];
+  xy[2 * i + 1] = D.Y[i];
+}
+
+}  // namespace
+
+// ==========================================================================
+// Host side
+// ==========================================================================
+struct ecmc_ctx {
+  Dev D;
+  Geo g;
+  hipStream_t stream;
+  uint32_t flags;
+  int32_t kmax;
+  int64_t log_cap;
+  int32_t lanes = 64;
+  int32_t wait_retries = 64;
+  int32_t max_splits = 4;     // consecutive failed attempts before a global-order window
+  double sub_frac = 1.0;      // current sub-leg length as a fraction of the leg (adaptive)
+  uint32_t epoch = 0;
+  int32_t force_global = 0;
+  int32_t inject_chain = -1, inject_event = -1;
+  int64_t leg_counter = 0;
+  bool active_set = false;
+  int32_t kernel_timing = 0;
+  int32_t strict_order = 0;
+  double event_kernel_ms = 0.0;
+  int64_t event_launches = 0, timed_events = 0, timed_slots = 0;
+  hipEvent_t kev0, kev1;
+  bool kevents_ok = false;
+  // host-side statistics
+  int64_t legs = 0, legs_violated = 0, attempts = 0, reruns = 0, global_legs = 0;
+  double chain_time = 0.0;
+  double device_ms = 0.0;
+  int64_t last_overlaps = 0;
+  const char *err = "no error";
+  hipEvent_t ev0, ev1;
+  bool events_ok = false;
+};
+
+namespace {
+
+constexpr int64_t ALIGN = 256;
+int64_t align_up(int64_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
+
+struct Layout {
+  int64_t off[40];
+  int64_t total;
+};
+
+int32_t default_cells(double sigma, double box) {
+  const double d = 2.0 * sigma;
+  int64_t nc = (int64_t)std::floor(box / d);
+  while (nc > 1 && box / (double)nc < d * (1.0 + 1e-9)) --nc;
+  if (nc > 46340) nc = 46340;
+  return (int32_t)nc;
+}
+
+bool cells_ok(double sigma, double box, int32_t nc) {
+  const double d = 2.0 * sigma;
+  if (nc < 5 || nc > 46340) return false;
+  const double c = box / (double)nc;
+  return c >= d * (1.0 + 1e-9) && c <= std::sqrt(2.0) * d;
+}
+
+// workspace layout; order matters only for alignment
+Layout make_layout(int64_t n, int32_t nc, int32_t kmax, int64_t log_cap, uint32_t flags) {
+  Layout L;
+  int64_t S = (int64_t)nc * nc * CAP;
+  int64_t sizes[] = {
+      n * 8,                  // 0 X
+      n * 8,                  // 1 Y
+      n * 8,                  // 2 STAMP
+      (int64_t)kmax * 4,      // 3 ACTIVE
+      n * 4,                  // 4 SLOT_OF
+      (int64_t)nc * nc * 4,   // 5 CELL_CNT
+      S * 16,                 // 6 MUT
+      S * 16,                 // 7 CST
+      S * 4,                  // 8 TAG
+      (flags & ECMC_FP32_MIXED) ? S * 8 : 0,  // 9 M32
+      (int64_t)kmax * 4,      // 10 CH_SLOT
+      (int64_t)kmax * NCNT * 8,  // 11 CNT_W
+      (int64_t)kmax * NCNT * 8,  // 12 CNT_C
+      (int64_t)kmax * 8,      // 13 SUMB_W
+      (int64_t)kmax * 8,      // 14 SUMB_C
+      (int64_t)kmax * 8,      // 15 LOGLEN_W
+      (int64_t)kmax * 8,      // 16 LOGLEN_C
+      (int64_t)kmax * log_cap * 4,  // 17 LOG
+      (int64_t)kmax * 8,      // 18 FLAG
+      (int64_t)kmax * 8,      // 19 GC_TAU
+      (int64_t)kmax * 8,      // 20 GC_B
+      (int64_t)kmax * 4,      // 21 GC_SLOT
+      (int64_t)sizeof(Ctl),   // 22 ctl
+      n * 16,                 // 23 staging for interleaved xy readback
+      S * 16,                 // 24 MUT_SNAP
+      (flags & ECMC_FP32_MIXED) ? S * 8 : 0,  // 25 M32_SNAP
+      S * 4,                  // 26 EPOCH
+      (int64_t)kmax * 4,      // 27 CH_SLOT_SNAP
+      (int64_t)kmax * 8,      // 28 CH_A
+      (int64_t)kmax * 8,      // 29 CH_T
+      (int64_t)kmax * 8,      // 30 CH_A_SNAP
+      (int64_t)kmax * 8,      // 31 CH_T_SNAP
+  };
+  int64_t o = 0;
+  int nsz = (int)(sizeof(sizes) / sizeof(sizes[0]));
+  for (int q = 0; q < nsz; ++q) {
+    L.off[q] = o;
+    o += align_up(sizes[q]);
+  }
+  L.total = o;
+  return L;
+}
+
+#define HIPCHK(expr)                          \
+  do {                                        \
+    if ((expr) != hipSuccess) {               \
+      ctx->err = "HIP runtime call failed: " #expr; \
+      return ECMC_EDEVICE;                    \
+    }                                         \
+  } while (0)
+
+inline unsigned blocks_for(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+template <typename T>
+int fill(ecmc_ctx *ctx, T *p, T v, int64_t n) {
+  if (n <= 0) return ECMC_OK;
+  unsigned nb = blocks_for(n, 256);
+  if (nb > 65535u * 16u) nb = 65535u * 16u;
+  k_fill<T><<<nb, 256, 0, ctx->stream>>>(p, v, n);
+  HIPCHK(hipGetLastError());
+  return ECMC_OK;
+}
+
+int read_ctl(ecmc_ctx *ctx, Ctl *h) {
+  HIPCHK(hipMemcpyAsync(h, ctx->D.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  return ECMC_OK;
+}
+
+// a1: build home cells for direction dir from the canonical arrays
+int build_cells(ecmc_ctx *ctx, int dir) {
+  Dev &D = ctx->D;
+  int rc = fill<int32_t>(ctx, D.CELL_CNT, 0, (int64_t)ctx->g.nc * ctx->g.nc);
+  if (rc) return rc;
+  k_bin<<<blocks_for(D.n, 256), 256, 0, ctx->stream>>>(D, ctx->g, dir);
+  HIPCHK(hipGetLastError());
+  k_cellfill<<<blocks_for((int64_t)ctx->g.nc * ctx->g.nc, 256), 256, 0, ctx->stream>>>(D, ctx->g, dir);
+  HIPCHK(hipGetLastError());
+  return ECMC_OK;
+}
+
+// Every chain's group must be resident at once: a chain that never started
+// would keep its disk tagged active and others would wait on it.
+template <int G>
+int check_resident(ecmc_ctx *ctx, unsigned nb) {
+  int dev = 0, ncu = 0, per_cu = 0;
+  HIPCHK(hipGetDevice(&dev));
+  HIPCHK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+  HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_event<G>, 256, 0));
+  if ((int64_t)per_cu * ncu < (int64_t)nb) {
+    ctx->err = "too many chains for one resident launch at this lane count";
+    return ECMC_EINVAL;
+  }
+  return ECMC_OK;
+}
+
+int launch_event(ecmc_ctx *ctx, LegP lp) {
+  Dev &D = ctx->D;
+  // attempts per chain before the kernel gives up (a leg needs a few hundred)
+  const long long cap = 1ll << 24;
+  const int G = ctx->lanes;
+  const int64_t threads = (int64_t)D.k * G;
+  const unsigned nb = blocks_for(threads, 256);
+  int rc = G == 64 ? check_resident<64>(ctx, nb)
+                   : (G == 32 ? check_resident<32>(ctx, nb) : check_resident<16>(ctx, nb));
+  if (rc) return rc;
+  if (G == 64)
+    k_event<64><<<nb, 256, 0, ctx->stream>>>(D, ctx->g, lp, ctx->wait_retries, cap);
+  else if (G == 32)
+    k_event<32><<<nb, 256, 0, ctx->stream>>>(D, ctx->g, lp, ctx->wait_retries, cap);
+  else
+    k_event<16><<<nb, 256, 0, ctx->stream>>>(D, ctx->g, lp, ctx->wait_retries, cap);
+  HIPCHK(hipGetLastError());
+  return ECMC_OK;
+}
+
+// One attempt over [h, tend) of the current leg (home cells already built).
+// On a violation every slot the attempt modified is put back.
+int attempt(ecmc_ctx *ctx, int dir, double h, double tend, bool final, bool global, bool *violated,
+            double *tstar) {
+  Dev &D = ctx->D;
+  const int64_t S = (int64_t)ctx->g.nc * ctx->g.nc * CAP;
+  k_ctl_reset<<<1, 1, 0, ctx->stream>>>(D);
+  HIPCHK(hipGetLastError());
+  k_chains_attempt<<<blocks_for(D.k, 256), 256, 0, ctx->stream>>>(D);
+  HIPCHK(hipGetLastError());
+  LegP lp;
+  lp.dir = dir;
+  lp.final = final ? 1 : 0;
+  lp.h = h;
+  lp.tend = tend;
+  lp.strict = ctx->strict_order;
+  lp.epoch = ++ctx->epoch;
+  if (lp.epoch == 0) lp.epoch = ++ctx->epoch;  // 0 marks "never touched"
+  const bool timed = !global && ctx->kernel_timing && ctx->kevents_ok;
+  int rc;
+  if (global) {
+    k_global<<<1, 1024, 0, ctx->stream>>>(D, ctx->g, lp);
+    HIPCHK(hipGetLastError());
+  } else {
+    if (timed) HIPCHK(hipEventRecord(ctx->kev0, ctx->stream));
+    rc = launch_event(ctx, lp);
+    if (rc) return rc;
+    if (timed) HIPCHK(hipEventRecord(ctx->kev1, ctx->stream));
+  }
+  k_count_delta<<<1, 256, 0, ctx->stream>>>(D);
+  HIPCHK(hipGetLastError());
+  k_chains_commit<<<blocks_for(D.k, 256), 256, 0, ctx->stream>>>(D);
+  HIPCHK(hipGetLastError());
+  Ctl hc;
+  rc = read_ctl(ctx, &hc);
+  if (rc) return rc;
+  ctx->attempts += global ? 0 : 1;
+  if (hc.error) {
+    ctx->err = hc.error == ECMC_ECELL ? "a cell received more than 4 disks"
+                                      : (hc.error == ECMC_EHANG ? "event chain iteration limit reached"
+                                                                : "device error");
+    return hc.error;
+  }
+  *violated = hc.abort != 0;
+  if (timed) {
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, ctx->kev0, ctx->kev1));
+    ctx->event_kernel_ms += ms;
+    ctx->event_launches += 1;
+    ctx->timed_events += hc.delta_events;  // work done inside the timed launch
+    ctx->timed_slots += hc.delta_slots;
+  }
+  double ts;
+  std::memcpy(&ts, &hc.tstar_bits, 8);
+  *tstar = ts;
+  if (global && *violated) {
+    ctx->err = "global-time order reported a violation";
+    return ECMC_EDEVICE;
+  }
+  if (*violated) {
+    k_restore<<<blocks_for(S, 256), 256, 0, ctx->stream>>>(D, S, lp.epoch);
+    HIPCHK(hipGetLastError());
+  }
+  return ECMC_OK;
+}
+
+int set_inject(ecmc_ctx *ctx, int32_t chain, int32_t ev) {
+  Ctl h;
+  HIPCHK(hipMemcpyAsync(&h, ctx->D.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  h.inject_chain = chain;
+  h.inject_event = ev;
+  HIPCHK(hipMemcpyAsync(ctx->D.ctl, &h, sizeof(Ctl), hipMemcpyHostToDevice, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  return ECMC_OK;
+}
+
+// One leg [0, T] in direction dir.  The home cells are built once; the leg is
+// then run as a sequence of attempts [h, h + dt) ("sub-legs": extra
+// breakpoints in the same direction, at which chains pause without moving, so
+// results do not depend on where they fall).  A violating attempt is undone
+// and rerun with a shorter sub-leg, taking the earliest violation time t* as
+// its end when it lies inside (restart strategy 1, Sec. 3.4; Remark on partial
+// validation); successful attempts let the sub-leg grow back.  After
+// max_splits consecutive failures a short window runs in global-time order
+// (Alg. 2), which cannot violate.
+int run_leg(ecmc_ctx *ctx, int dir, double T) {
+  Dev &D = ctx->D;
+  int rc = fill<double>(ctx, D.STAMP, 0.0, D.n);  // Alg. 1: local times start at h
+  if (rc) return rc;
+  rc = build_cells(ctx, dir);
+  if (rc) return rc;
+  k_chains_leg<<<blocks_for(D.k, 256), 256, 0, ctx->stream>>>(D, (int64_t)ctx->g.nc * ctx->g.nc * CAP);
+  HIPCHK(hipGetLastError());
+  bool v;
+  double ts;
+  const double dt_min = T / 4096.0;
+  double h = 0.0;
+  int fails = 0;
+  bool first = true;
+  double frac = ctx->sub_frac;
+  while (h < T) {
+    if (ctx->force_global) {
+      rc = attempt(ctx, dir, h, T, true, true, &v, &ts);
+      if (rc) return rc;
+      ctx->global_legs++;
+      break;
+    }
+    double dt = frac * T;
+    if (dt < dt_min) dt = dt_min;
+    double tend = h + dt;
+    if (tend >= T * (1.0 - 1e-12)) tend = T;
+    const bool final = tend >= T;
+    bool violated = false;
+    double tstar = INFINITY;
+    rc = attempt(ctx, dir, h, tend, final, false, &violated, &tstar);
+    if (rc) return rc;
+    if (ctx->inject_chain >= 0) {  // the hook fires on one attempt only
+      ctx->inject_chain = -1;
+      rc = set_inject(ctx, -1, -1);
+      if (rc) return rc;
+    }
+    if (!violated) {
+      h = tend;
+      fails = 0;
+      frac = std::min(1.0, frac * 1.5);
+      continue;
+    }
+    if (first) ctx->legs_violated++;
+    first = false;
+    ctx->reruns++;
+    ++fails;
+    double shrink = 0.5 * (tend - h);
+    if (tstar > h && tstar - h < shrink) shrink = tstar - h;
+    frac = std::max(shrink / T, dt_min / T);
+    if (fails > ctx->max_splits) {
+      // a short window in global-time order guarantees progress
+      double gend = h + std::max(shrink, dt_min);
+      if (gend >= T * (1.0 - 1e-12)) gend = T;
+      rc = attempt(ctx, dir, h, gend, gend >= T, true, &v, &ts);
+      if (rc) return rc;
+      ctx->global_legs++;
+      h = gend;
+      fails = 0;
+    }
+  }
+  ctx->sub_frac = frac;
+  const int64_t S = (int64_t)ctx->g.nc * ctx->g.nc * CAP;
+  k_writeback<<<blocks_for(S, 256), 256, 0, ctx->stream>>>(D, ctx->g, dir);
+  HIPCHK(hipGetLastError());
+  return ECMC_OK;
+}
+
+}  // namespace
+
+// ==========================================================================
+// C ABI
+// ==========================================================================
+extern "C" {
+
+int64_t ecmc_workspace_bytes(int64_t n, double sigma, double box, int32_t cells, int32_t max_chains,
+                             int64_t log_cap, uint32_t flags) {
+  if (n < 2 || n > (1ll << 30) || !(sigma > 0.0) || !(box > 0.0) || max_chains < 1 ||
+      max_chains > (1 << 24) || log_cap < 1 || (flags & ~1u))
+    return ECMC_EINVAL;
+  const int32_t nc = cells == 0 ? default_cells(sigma, box) : cells;
+  if (!cells_ok(sigma, box, nc)) return ECMC_EINVAL;
+  if ((int64_t)nc * nc * CAP < n) return ECMC_EINVAL;
+  return make_layout(n, nc, max_chains, log_cap, flags).total;
+}
+
+int ecmc_init(ecmc_ctx **out, const double *positions_xy, int64_t n, double sigma, double box,
+              int32_t cells, uint32_t flags, void *workspace, int64_t ws_bytes, int32_t max_chains,
+              int64_t log_cap, void *stream) {
+  if (!out) return ECMC_EINVAL;
+  *out = nullptr;
+  const int64_t need = ecmc_workspace_bytes(n, sigma, box, cells, max_chains, log_cap, flags);
+  if (need < 0 || !positions_xy || !workspace || ws_bytes < need ||
+      ((uintptr_t)workspace % ALIGN) != 0)
+    return ECMC_EINVAL;
+  ecmc_ctx *ctx = new (std::nothrow) ecmc_ctx();
+  if (!ctx) return ECMC_EINVAL;
+  ctx->stream = (hipStream_t)stream;
+  ctx->flags = flags;
+  ctx->kmax = max_chains;
+  ctx->log_cap = log_cap;
+  const int32_t nc = cells == 0 ? default_cells(sigma, box) : cells;
+  Geo &g = ctx->g;
+  g.L = box;
+  g.halfL = 0.5 * box;
+  g.sigma = sigma;
+  g.d = 2.0 * sigma;
+  g.d2 = g.d * g.d;
+  g.nc = nc;
+  g.c = box / (double)nc;
+  g.inv_c = 1.0 / g.c;
+  g.mmax = nc - 3;
+  Layout Lo = make_layout(n, nc, max_chains, log_cap, flags);
+  char *b = (char *)workspace;
+  Dev &D = ctx->D;
+  D.X = (double *)(b + Lo.off[0]);
+  D.Y = (double *)(b + Lo.off[1]);
+  D.STAMP = (double *)(b + Lo.off[2]);
+  D.ACTIVE = (int32_t *)(b + Lo.off[3]);
+  D.SLOT_OF = (int32_t *)(b + Lo.off[4]);
+  D.CELL_CNT = (int32_t *)(b + Lo.off[5]);
+  D.MUT = (MutRec *)(b + Lo.off[6]);
+  D.CST = (CstRec *)(b + Lo.off[7]);
+  D.TAG = (uint32_t *)(b + Lo.off[8]);
+  D.M32 = (flags & ECMC_FP32_MIXED) ? (float2 *)(b + Lo.off[9]) : nullptr;
+  D.CH_SLOT = (int32_t *)(b + Lo.off[10]);
+  D.CNT_W = (long long *)(b + Lo.off[11]);
+  D.CNT_C = (long long *)(b + Lo.off[12]);
+  D.SUMB_W = (double *)(b + Lo.off[13]);
+  D.SUMB_C = (double *)(b + Lo.off[14]);
+  D.LOGLEN_W = (long long *)(b + Lo.off[15]);
+  D.LOGLEN_C = (long long *)(b + Lo.off[16]);
+  D.LOG = (int32_t *)(b + Lo.off[17]);
+  D.FLAG = (double *)(b + Lo.off[18]);
+  D.GC_TAU = (double *)(b + Lo.off[19]);
+  D.GC_B = (double *)(b + Lo.off[20]);
+  D.GC_SLOT = (int32_t *)(b + Lo.off[21]);
+  D.ctl = (Ctl *)(b + Lo.off[22]);
+  D.MUT_SNAP = (MutRec *)(b + Lo.off[24]);
+  D.M32_SNAP = (flags & ECMC_FP32_MIXED) ? (float2 *)(b + Lo.off[25]) : nullptr;
+  D.EPOCH = (uint32_t *)(b + Lo.off[26]);
+  D.CH_SLOT_SNAP = (int32_t *)(b + Lo.off[27]);
+  D.CH_A = (double *)(b + Lo.off[28]);
+  D.CH_T = (double *)(b + Lo.off[29]);
+  D.CH_A_SNAP = (double *)(b + Lo.off[30]);
+  D.CH_T_SNAP = (double *)(b + Lo.off[31]);
+  D.n = n;
+  D.k = 0;
+  D.log_cap = log_cap;
+  int rc = ECMC_OK;
+  do {
+    Ctl h;
+    std::memset(&h, 0, sizeof(h));
+    h.inject_chain = -1;
+    h.inject_event = -1;
+    if (hipMemcpyAsync(D.ctl, &h, sizeof(Ctl), hipMemcpyHostToDevice, ctx->stream) != hipSuccess) {
+      rc = ECMC_EDEVICE;
+      break;
+    }
+    if (fill<uint32_t>(ctx, D.EPOCH, 0u, (int64_t)nc * nc * CAP) != ECMC_OK) {
+      rc = ECMC_EDEVICE;
+      break;
+    }
+    k_split_xy<<<blocks_for(n, 256), 256, 0, ctx->stream>>>(D, positions_xy);
+    k_check_range<<<blocks_for(n, 256), 256, 0, ctx->stream>>>(D, box);
+    if (hipGetLastError() != hipSuccess) {
+      rc = ECMC_EDEVICE;
+      break;
+    }
+    Ctl hc;
+    rc = read_ctl(ctx, &hc);
+    if (rc) break;
+    if (hc.error) {
+      ctx->err = "coordinates outside [0, box)";
+      rc = ECMC_EINVAL;
+      break;
+    }
+    int64_t ov = 0;
+    rc = ecmc_overlaps(ctx, &ov);
+    if (rc) break;
+    if (ov) {
+      rc = ECMC_EOVERLAP;
+      break;
+    }
+    if (hipEventCreate(&ctx->ev0) == hipSuccess && hipEventCreate(&ctx->ev1) == hipSuccess)
+      ctx->events_ok = true;
+    if (hipEventCreate(&ctx->kev0) == hipSuccess && hipEventCreate(&ctx->kev1) == hipSuccess)
+      ctx->kevents_ok = true;
+  } while (0);
+  if (rc) {
+    delete ctx;
+    return rc;
+  }
+  *out = ctx;
+  return ECMC_OK;
+}
+
+int ecmc_set_active(ecmc_ctx *ctx, const int32_t *idx, int32_t k) {
+  if (!ctx || !idx || k < 1 || k > ctx->kmax || k > ctx->D.n) return ECMC_EINVAL;
+  std::vector<char> seen((size_t)ctx->D.n, 0);
+  for (int32_t c = 0; c < k; ++c) {
+    if (idx[c] < 0 || idx[c] >= ctx->D.n || seen[(size_t)idx[c]]) {
+      ctx->err = "active set: index out of range or repeated";
+      return ECMC_EINVAL;
+    }
+    seen[(size_t)idx[c]] = 1;
+  }
+  Dev &D = ctx->D;
+  D.k = k;
+  HIPCHK(hipMemcpyAsync(D.ACTIVE, idx, sizeof(int32_t) * (size_t)k, hipMemcpyHostToDevice, ctx->stream));
+  int rc = fill<long long>(ctx, D.CNT_C, 0, (int64_t)k * NCNT);
+  if (!rc) rc = fill<double>(ctx, D.SUMB_C, 0.0, k);
+  if (!rc) rc = fill<long long>(ctx, D.LOGLEN_C, 0, k);
+  if (!rc) rc = fill<double>(ctx, D.STAMP, 0.0, D.n);
+  if (rc) return rc;
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  ctx->active_set = true;
+  ctx->legs = ctx->legs_violated = ctx->attempts = ctx->reruns = ctx->global_legs = 0;
+  ctx->chain_time = 0.0;
+  ctx->device_ms = 0.0;
+  ctx->event_kernel_ms = 0.0;
+  ctx->event_launches = ctx->timed_events = ctx->timed_slots = 0;
+  return ECMC_OK;
+}
+
+int ecmc_run(ecmc_ctx *ctx, int32_t n_chains, double chain_time, double breakpoint_interval,
+             int32_t direction) {
+  if (!ctx) return ECMC_EINVAL;
+  if (!ctx->active_set) {
+    ctx->err = "ecmc_set_active was not called";
+    return ECMC_ESTATE;
+  }
+  if (n_chains != ctx->D.k) {
+    ctx->err = "n_chains differs from the active set size";
+    return ECMC_EINVAL;
+  }
+  const double T = breakpoint_interval;
+  const Geo &g = ctx->g;
+  if (!(T >= 0.0) || !(T <= g.L - 4.0 * g.c - g.d) || !(chain_time >= 0.0)) {
+    ctx->err = "leg length outside [0, box - 4 cell - 2 sigma]";
+    return ECMC_EINVAL;
+  }
+  if (direction != 0 && direction != 1 && direction != 4) {
+    ctx->err = "direction must be 0 (+x), 1 (+y) or 4 (alternate)";
+    return ECMC_EINVAL;
+  }
+  int64_t n_legs = 0;
+  if (chain_time > 0.0) {
+    if (!(T > 0.0)) return ECMC_EINVAL;
+    const double r = chain_time / T;
+    n_legs = (int64_t)std::llround(r);
+    if (std::fabs(r - (double)n_legs) > 1e-9 * std::max(1.0, r)) {
+      ctx->err = "chain_time is not a whole number of breakpoint intervals";
+      return ECMC_EINVAL;
+    }
+  }
+  if (ctx->events_ok) (void)hipEventRecord(ctx->ev0, ctx->stream);
+  for (int64_t l = 0; l < n_legs; ++l) {
+    const int dir = direction == 4 ? (int)(ctx->leg_counter & 1) : direction;
+    int rc = run_leg(ctx, dir, T);
+    if (rc) return rc;
+    ctx->leg_counter++;
+    ctx->legs++;
+    ctx->chain_time += (double)ctx->D.k * T;
+  }
+  if (ctx->events_ok) {
+    (void)hipEventRecord(ctx->ev1, ctx->stream);
+    HIPCHK(hipEventSynchronize(ctx->ev1));
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1) == hipSuccess) ctx->device_ms += ms;
+  }
+  return ECMC_OK;
+}
+
+int ecmc_stats(ecmc_ctx *ctx, ecmc_stats_t *out) {
+  if (!ctx || !out) return ECMC_EINVAL;
+  std::memset(out, 0, sizeof(*out));
+  const int32_t k = ctx->D.k;
+  std::vector<long long> cnt((size_t)std::max(k, 1) * NCNT, 0);
+  std::vector<double> sb((size_t)std::max(k, 1), 0.0);
+  if (k > 0) {
+    HIPCHK(hipMemcpyAsync(cnt.data(), ctx->D.CNT_C, sizeof(long long) * (size_t)k * NCNT,
+                          hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipMemcpyAsync(sb.data(), ctx->D.SUMB_C, sizeof(double) * (size_t)k, hipMemcpyDeviceToHost,
+                          ctx->stream));
+  }
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  double sum_b = 0.0;
+  for (int32_t c = 0; c < k; ++c) {
+    out->events += cnt[(size_t)c * NCNT + C_EVENTS];
+    out->cas_fail += cnt[(size_t)c * NCNT + C_CASFAIL];
+    out->active_waits += cnt[(size_t)c * NCNT + C_WAITS];
+    out->contact_moves += cnt[(size_t)c * NCNT + C_MOVES];
+    out->fp32_refines += cnt[(size_t)c * NCNT + C_REFINES];
+    out->slots_scanned += cnt[(size_t)c * NCNT + C_SCANNED];
+    sum_b += sb[(size_t)c];
+  }
+  out->legs = ctx->legs;
+  out->legs_violated = ctx->legs_violated;
+  out->attempts = ctx->attempts;
+  out->reruns = ctx->reruns;
+  out->global_legs = ctx->global_legs;
+  out->overlaps = ctx->last_overlaps;
+  out->sum_b = sum_b;
+  out->chain_time = ctx->chain_time;
+  out->pressure = ctx->chain_time > 0.0 ? 1.0 + sum_b / ctx->chain_time : 0.0;
+  out->device_ms = ctx->device_ms;
+  out->event_kernel_ms = ctx->event_kernel_ms;
+  out->event_launches = ctx->event_launches;
+  out->timed_events = ctx->timed_events;
+  out->timed_slots = ctx->timed_slots;
+  return ECMC_OK;
+}
+
+int ecmc_get_positions(ecmc_ctx *ctx, double *out_xy) {
+  if (!ctx || !out_xy) return ECMC_EINVAL;
+  Dev &D = ctx->D;
+  Layout Lo = make_layout(D.n, ctx->g.nc, ctx->kmax, ctx->log_cap, ctx->flags);
+  double *stage = (double *)((char *)D.X - Lo.off[0] + Lo.off[23]);
+  k_join_xy<<<blocks_for(D.n, 256), 256, 0, ctx->stream>>>(D, stage);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipMemcpyAsync(out_xy, stage, sizeof(double) * 2 * (size_t)D.n, hipMemcpyDeviceToHost,
+                        ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  return ECMC_OK;
+}
+
+int ecmc_get_stamps(ecmc_ctx *ctx, double *out) {
+  if (!ctx || !out) return ECMC_EINVAL;
+  HIPCHK(hipMemcpyAsync(out, ctx->D.STAMP, sizeof(double) * (size_t)ctx->D.n, hipMemcpyDeviceToHost,
+                        ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  return ECMC_OK;
+}
+
+int ecmc_get_active(ecmc_ctx *ctx, int32_t *out) {
+  if (!ctx || !out) return ECMC_EINVAL;
+  if (!ctx->active_set) return ECMC_ESTATE;
+  HIPCHK(hipMemcpyAsync(out, ctx->D.ACTIVE, sizeof(int32_t) * (size_t)ctx->D.k, hipMemcpyDeviceToHost,
+                        ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  return ECMC_OK;
+}
+
+int ecmc_get_chain_sums(ecmc_ctx *ctx, double *sum_b, int64_t *events) {
+  if (!ctx) return ECMC_EINVAL;
+  if (!ctx->active_set) return ECMC_ESTATE;
+  const int32_t k = ctx->D.k;
+  if (sum_b)
+    HIPCHK(hipMemcpyAsync(sum_b, ctx->D.SUMB_C, sizeof(double) * (size_t)k, hipMemcpyDeviceToHost,
+                          ctx->stream));
+  if (events) {
+    std::vector<long long> cnt((size_t)k * NCNT);
+    HIPCHK(hipMemcpyAsync(cnt.data(), ctx->D.CNT_C, sizeof(long long) * (size_t)k * NCNT,
+                          hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    for (int32_t c = 0; c < k; ++c) events[c] = cnt[(size_t)c * NCNT + C_EVENTS];
+  }
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  return ECMC_OK;
+}
+
+int ecmc_get_log(ecmc_ctx *ctx, int32_t chain, int32_t *targets, int64_t cap, int64_t *n_out) {
+  if (!ctx || !n_out) return ECMC_EINVAL;
+  if (!ctx->active_set) return ECMC_ESTATE;
+  if (chain < 0 || chain >= ctx->D.k) return ECMC_EINVAL;
+  long long len = 0;
+  HIPCHK(hipMemcpyAsync(&len, ctx->D.LOGLEN_C + chain, sizeof(long long), hipMemcpyDeviceToHost,
+                        ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  *n_out = len;
+  const int64_t keep = std::min<int64_t>(len, ctx->log_cap);
+  if (keep == 0) return ECMC_OK;
+  if (!targets || cap < keep) return ECMC_EINVAL;
+  std::vector<int32_t> ring((size_t)ctx->log_cap);
+  HIPCHK(hipMemcpyAsync(ring.data(), ctx->D.LOG + (int64_t)chain * ctx->log_cap,
+                        sizeof(int32_t) * (size_t)ctx->log_cap, hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  const int64_t first = len - keep;
+  for (int64_t q = 0; q < keep; ++q) targets[q] = ring[(size_t)((first + q) % ctx->log_cap)];
+  return ECMC_OK;
+}
+
+int ecmc_overlaps(ecmc_ctx *ctx, int64_t *count) {
+  if (!ctx || !count) return ECMC_EINVAL;
+  Dev &D = ctx->D;
+  int rc = build_cells(ctx, 0);
+  if (rc) return rc;
+  Ctl h;
+  rc = read_ctl(ctx, &h);
+  if (rc) return rc;
+  if (h.error) {
+    ctx->err = "a cell received more than 4 disks";
+    int e = h.error;
+    h.error = 0;
+    HIPCHK(hipMemcpyAsync(D.ctl, &h, sizeof(Ctl), hipMemcpyHostToDevice, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    return e == ECMC_ECELL ? ECMC_EOVERLAP : e;
+  }
+  h.overlaps = 0;
+  HIPCHK(hipMemcpyAsync(D.ctl, &h, sizeof(Ctl), hipMemcpyHostToDevice, ctx->stream));
+  const double lim = ctx->g.d - 4.0 * (std::nextafter(ctx->g.L, INFINITY) - ctx->g.L);
+  k_overlap<<<blocks_for(D.n, 256), 256, 0, ctx->stream>>>(D, ctx->g, lim * lim);
+  HIPCHK(hipGetLastError());
+  rc = read_ctl(ctx, &h);
+  if (rc) return rc;
+  *count = (int64_t)h.overlaps;
+  ctx->last_overlaps = *count;
+  return ECMC_OK;
+}
+
+int ecmc_set_option(ecmc_ctx *ctx, int32_t key, int64_t value) {
+  if (!ctx) return ECMC_EINVAL;
+  switch (key) {
+    case ECMC_OPT_LANES:
+      if (value != 16 && value != 32 && value != 64) return ECMC_EINVAL;
+      ctx->lanes = (int32_t)value;
+      return ECMC_OK;
+    case ECMC_OPT_WAIT_RETRIES:
+      if (value < 1 || value > (1 << 20)) return ECMC_EINVAL;
+      ctx->wait_retries = (int32_t)value;
+      return ECMC_OK;
+    case ECMC_OPT_MAX_SPLITS:
+      if (value < 0 || value > 64) return ECMC_EINVAL;
+      ctx->max_splits = (int32_t)value;
+      return ECMC_OK;
+    case ECMC_OPT_FORCE_GLOBAL:
+      if (value != 0 && value != 1) return ECMC_EINVAL;
+      ctx->force_global = (int32_t)value;
+      return ECMC_OK;
+    case ECMC_OPT_INJECT_CHAIN:
+      if (value < -1 || value >= (1 << 24)) return ECMC_EINVAL;
+      ctx->inject_chain = (int32_t)value;
+      return set_inject(ctx, ctx->inject_chain, ctx->inject_event);
+    case ECMC_OPT_STRICT_ORDER:
+      if (value != 0 && value != 1) return ECMC_EINVAL;
+      ctx->strict_order = (int32_t)value;
+      return ECMC_OK;
+    case ECMC_OPT_KERNEL_TIMING:
+      if (value != 0 && value != 1) return ECMC_EINVAL;
+      ctx->kernel_timing = (int32_t)value;
+      return ECMC_OK;
+    case ECMC_OPT_INJECT_EVENT:
+      if (value < -1 || value > (1 << 30)) return ECMC_EINVAL;
+      ctx->inject_event = (int32_t)value;
+      return set_inject(ctx, ctx->inject_chain, ctx->inject_event);
+    default:
+      return ECMC_EINVAL;
+  }
+}
+
+const char *ecmc_last_error(const ecmc_ctx *ctx) { return ctx ? ctx->err : "null context"; }
+
+void ecmc_free(ecmc_ctx *ctx) {
+  if (!ctx) return;
+  if (ctx->events_ok) {
+    (void)hipEventDestroy(ctx->ev0);
+    (void)hipEventDestroy(ctx->ev1);
+  }
+  if (ctx->kevents_ok) {
+    (void)hipEventDestroy(ctx->kev0);
+    (void)hipEventDestroy(ctx->kev1);
+  }
+  delete ctx;
+}
+
+}  // extern "C"

@@ -1,0 +1,59 @@
+"""Host-side checks of the C ABI (no GPU needed): the built library loads,
+exports every function include/ecmc.h declares, and sizes workspaces."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_2004_11040_amd as pkg
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_functions():
+    src = open(os.path.join(ROOT, "include", "ecmc.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"\b(ecmc_[a-z_]+)\s*\(", src)
+    return sorted(set(names))
+
+
+def test_header_and_binding_agree():
+    assert _declared_functions() == sorted(pkg.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(pkg.LIB_PATH)
+    for name in _declared_functions():
+        assert hasattr(lib, name), name
+
+
+def test_workspace_bytes_host_only():
+    n = 4096
+    L = 135.58
+    b = pkg.workspace_bytes(n, 1.0, L, 0, 64, 1024)
+    assert b > 0 and b % 256 == 0
+    # grows with chains and log capacity
+    assert pkg.workspace_bytes(n, 1.0, L, 0, 128, 1024) > b
+    assert pkg.workspace_bytes(n, 1.0, L, 0, 64, 4096) > b
+    # FP32 mirror adds 8 bytes per slot
+    assert pkg.workspace_bytes(n, 1.0, L, 0, 64, 1024, pkg.FP32_MIXED) > b
+
+
+@pytest.mark.parametrize("args", [
+    (1, 1.0, 50.0, 0, 1, 1),          # n < 2
+    (100, 0.0, 50.0, 0, 1, 1),        # sigma <= 0
+    (100, 1.0, -1.0, 0, 1, 1),        # box <= 0
+    (100, 1.0, 50.0, 30, 1, 1),       # cell narrower than 2 sigma
+    (100, 1.0, 50.0, 5, 1, 1),        # cell wider than 2 sqrt(2) sigma
+    (100, 1.0, 8.0, 0, 1, 1),         # fewer than 5 cells per side
+    (100, 1.0, 50.0, 0, 0, 1),        # no chains
+    (100, 1.0, 50.0, 0, 1, 0),        # no log
+    (10000, 1.0, 50.0, 0, 1, 1),      # more disks than slots
+])
+def test_workspace_bytes_rejects(args):
+    assert pkg.workspace_bytes(*args) == pkg.EINVAL
+
+
+def test_workspace_flags_rejected():
+    assert pkg.workspace_bytes(100, 1.0, 50.0, 0, 1, 1, flags=8) == pkg.EINVAL

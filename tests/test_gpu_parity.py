@@ -1,0 +1,240 @@
+"""GPU hot path versus the CPU oracle (global-time Alg. 2), through the C ABI.
+
+Contract (Lemma 2 of the paper: without horizon violations the local-time
+method reproduces the global-time liftings exactly):
+  * event counts and every chain's sequence of target disks: bit-exact;
+  * final active set: exact;
+  * positions, local times and per-chain sums of b: bit-exact as well.  Every
+    event is evaluated from the chain's activation state with the same binary64
+    operations the oracle uses; reruns pause chains without moving them and a
+    move up to contact only publishes an intermediate point, so neither path
+    changes any rounding.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_2004_11040_amd as pkg  # noqa: E402
+
+
+def _wrapdiff(a, b, L):
+    return np.abs((a - b + L / 2) % L - L / 2)
+
+
+def gpu_run(x, y, L, act, dirs, T, lanes=64, flags=pkg.FP64, log_cap=1 << 15, opts=(),
+            sigma=1.0, cells=0):
+    e = pkg.Ecmc(np.stack([x, y], 1), sigma, L, cells=cells, flags=flags,
+                 max_chains=len(act), log_cap=log_cap)
+    e.set_option(pkg.OPT_LANES, lanes)
+    for key, val in opts:
+        e.set_option(key, val)
+    e.set_active(act)
+    for d in dirs:
+        e.run(T, T, d)
+    return e
+
+
+def check_parity(e, ref, L, k, tag=""):
+    st = e.stats()
+    assert st["events"] == ref.n_events, (tag, st["events"], ref.n_events)
+    for c in range(k):
+        lg = e.log(c)
+        want = ref.targets(c)
+        assert lg.count == want.shape[0], (tag, c, lg.count, want.shape[0])
+        assert np.array_equal(lg.targets, want), (tag, c)
+    assert np.array_equal(e.active(), ref.active), tag
+    pos = e.positions()
+    dx = _wrapdiff(pos[:, 0], ref.x, L).max()
+    dy = _wrapdiff(pos[:, 1], ref.y, L).max()
+    sb, ev = e.chain_sums()
+    stamps = e.stamps()
+    assert dx == 0.0 and dy == 0.0, (tag, dx, dy, st)
+    assert np.array_equal(sb, ref.sum_b), (tag, st)
+    assert np.array_equal(stamps, ref.stamps), (tag, st)
+    ev_ref = np.array([ref.targets(c).shape[0] for c in range(k)])
+    assert np.array_equal(ev, ev_ref), tag
+    return st
+
+
+def _square(seed, n_side, eta, k, amp=0.05):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    a = W.box_side(n_side * n_side, eta) / n_side
+    amp = min(amp, 0.45 * (a - 2.0))
+    x, y, L = W.square_jittered(n_side, eta, amp, rng)
+    act = W.active_set(rng, n_side * n_side, k)
+    return x, y, L, act
+
+
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("lanes", [64, 32, 16])
+def test_small_parity_lanes(lanes):
+    s = W.config(0)
+    dirs = [0] * 10
+    e = gpu_run(s.x, s.y, s.L, s.active, dirs, s.T, lanes=lanes)
+    ref = oracle.run(s.x, s.y, 1.0, s.L, s.active, dirs, s.T)
+    check_parity(e, ref, s.L, s.k, f"lanes={lanes}")
+
+
+@pytest.mark.parametrize("seed,n_side,eta,k,tfrac", [
+    (101, 8, 0.50, 1, 0.25),
+    (102, 10, 0.60, 3, 0.25),
+    (103, 12, 0.70, 12, 0.20),   # k = sqrt(N)
+    (104, 16, 0.65, 16, 0.25),
+    (105, 9, 0.40, 5, 0.20),     # ragged: 81 disks
+])
+def test_alternating_parity(seed, n_side, eta, k, tfrac):
+    x, y, L, act = _square(seed, n_side, eta, k)
+    T = tfrac * L
+    dirs = [0, 1] * 4
+    e = gpu_run(x, y, L, act, dirs, T)
+    ref = oracle.run(x, y, 1.0, L, act, dirs, T)
+    check_parity(e, ref, L, k, f"seed={seed}")
+
+
+def test_many_chains_with_violations():
+    """k = 4 sqrt(N) and long legs: horizon violations do happen; reruns and
+    the global-order fallback must still reproduce the oracle's liftings."""
+    x, y, L, act = _square(111, 32, 0.70, 128)
+    T = 0.2 * L
+    dirs = [0, 1, 0, 1]
+    e = gpu_run(x, y, L, act, dirs, T)
+    ref = oracle.run(x, y, 1.0, L, act, dirs, T)
+    st = check_parity(e, ref, L, 128, "k=128")
+    print("violated legs", st["legs_violated"], "reruns", st["reruns"], "global", st["global_legs"])
+
+
+def test_contact_moves_keep_exact_arithmetic():
+    """One failed claim on an active target is enough to publish a move up to
+    contact: many moves, still the oracle's liftings and bits."""
+    x, y, L, act = _square(151, 12, 0.60, 36)
+    T = 0.2 * L
+    dirs = [0, 1, 0, 1]
+    e = gpu_run(x, y, L, act, dirs, T, opts=((pkg.OPT_WAIT_RETRIES, 1),))
+    ref = oracle.run(x, y, 1.0, L, act, dirs, T)
+    st = check_parity(e, ref, L, 36, "moves")
+    print("moves", st["contact_moves"], "waits", st["active_waits"], "reruns", st["reruns"])
+
+
+def test_force_global_order_is_exact():
+    s = W.config(0)
+    dirs = [0] * 5
+    e = gpu_run(s.x, s.y, s.L, s.active, dirs, s.T, opts=((pkg.OPT_FORCE_GLOBAL, 1),))
+    ref = oracle.run(s.x, s.y, 1.0, s.L, s.active, dirs, s.T)
+    st = check_parity(e, ref, s.L, s.k, "global")
+    assert st["global_legs"] == 5
+
+
+def test_injected_violation_is_rerun():
+    """A violation forced from the host (chain 1 reports one at its 7th event)
+    must be absorbed by a rerun from the breakpoint, results unchanged."""
+    s = W.config(0)
+    dirs = [0] * 3
+    e = gpu_run(s.x, s.y, s.L, s.active, dirs[:0], s.T)
+    e.set_option(pkg.OPT_INJECT_EVENT, 7)
+    e.set_option(pkg.OPT_INJECT_CHAIN, 1)
+    for d in dirs:
+        e.run(s.T, s.T, d)
+    ref = oracle.run(s.x, s.y, 1.0, s.L, s.active, dirs, s.T)
+    st = check_parity(e, ref, s.L, s.k, "inject")
+    assert st["reruns"] >= 1 and st["legs_violated"] == 1
+
+
+def test_all_disks_active_no_lifting():
+    x, y, L, _ = _square(121, 6, 0.5, 1)
+    act = np.arange(36, dtype=np.int32)
+    T = 0.15 * L
+    e = gpu_run(x, y, L, act, [0, 1], T)
+    st = e.stats()
+    assert st["events"] == 0
+    pos = e.positions()
+    assert _wrapdiff(pos[:, 0], np.mod(x + T, L), L).max() < 1e-9
+    assert _wrapdiff(pos[:, 1], np.mod(y + T, L), L).max() < 1e-9
+
+
+def test_one_row_of_disks():
+    rng = np.random.Generator(np.random.PCG64(131))
+    L = 60.0
+    x, y = W.tonks_row(12, L, rng)
+    act = np.array([5], np.int32)
+    T = 0.3 * L
+    e = gpu_run(x, y, L, act, [0] * 3, T)
+    ref = oracle.run(x, y, 1.0, L, act, [0] * 3, T)
+    check_parity(e, ref, L, 1, "row")
+
+
+@pytest.mark.parametrize("strict", [0, 1])
+def test_mid_size_parity(strict):
+    s = W.config(1)
+    dirs = s.leg_dirs(4)
+    e = gpu_run(s.x, s.y, s.L, s.active, dirs, s.T, log_cap=1 << 14,
+                opts=((pkg.OPT_STRICT_ORDER, strict),))
+    ref = oracle.run(s.x, s.y, 1.0, s.L, s.active, dirs, s.T)
+    st = check_parity(e, ref, s.L, s.k, "cfg1")
+    assert e.overlaps() == 0
+    print("cfg1 4 legs:", st)
+
+
+def test_small_config_full_budget():
+    """The small parity workload over its whole event budget (>= 1e5 liftings)."""
+    s = W.config(0)
+    ref0 = oracle.run(s.x, s.y, 1.0, s.L, s.active, [0], s.T, log=False)
+    n_legs = int(math.ceil(s.target_events / max(ref0.n_events, 1) * 1.1))
+    dirs = [0] * n_legs
+    ref = oracle.run(s.x, s.y, 1.0, s.L, s.active, dirs, s.T, log_cap=1 << 20)
+    assert ref.n_events >= s.target_events
+    e = gpu_run(s.x, s.y, s.L, s.active, [], s.T, log_cap=1 << 16)
+    e.run(n_legs * s.T, s.T, pkg.DIR_X)
+    check_parity(e, ref, s.L, s.k, "cfg0-full")
+    assert e.overlaps() == 0
+
+
+def test_headline_size_first_leg():
+    """N = 2^20, k = 1024, in the launch configuration the benchmark uses:
+    the first leg, complete, against the oracle."""
+    s = W.config(4)
+    e = gpu_run(s.x, s.y, s.L, s.active, [0], s.T, log_cap=1 << 10)
+    ref = oracle.run(s.x, s.y, 1.0, s.L, s.active, [0], s.T, log_cap=1 << 21)
+    check_parity(e, ref, s.L, s.k, "cfg4-leg0")
+
+
+# ---------------------------------------------------------------------------
+def test_init_rejects_overlap():
+    x, y, L, act = _square(141, 8, 0.5, 2)
+    x = x.copy()
+    y = y.copy()
+    x[1] = (x[0] + 1.0) % L
+    y[1] = y[0]
+    with pytest.raises(pkg.EcmcError) as ei:
+        pkg.Ecmc(np.stack([x, y], 1), 1.0, L, max_chains=2)
+    assert ei.value.code == pkg.EOVERLAP
+
+
+def test_invalid_arguments():
+    x, y, L, act = _square(142, 8, 0.5, 2)
+    e = pkg.Ecmc(np.stack([x, y], 1), 1.0, L, max_chains=4)
+    with pytest.raises(pkg.EcmcError):
+        e.run(1.0, 1.0, 0)                      # no active set yet
+    with pytest.raises(pkg.EcmcError):
+        e.set_active(np.array([3, 3], np.int32))
+    with pytest.raises(pkg.EcmcError):
+        e.set_active(np.arange(5, dtype=np.int32))   # more than max_chains
+    e.set_active(act)
+    with pytest.raises(pkg.EcmcError):
+        e.run(1.0, 1.0, 0, n_chains=3)          # k mismatch
+    with pytest.raises(pkg.EcmcError):
+        e.run(1.0, 0.3, 0)                      # not a whole number of legs
+    with pytest.raises(pkg.EcmcError):
+        e.run(L, L, 0)                          # leg longer than the box allows
+    with pytest.raises(pkg.EcmcError):
+        e.run(1.0, 1.0, 2)                      # -x is not offered
+    e.run(0.0, 1.0, 0)                          # zero legs is a no-op
+    assert e.stats()["events"] == 0
