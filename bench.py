@@ -60,6 +60,7 @@ def cpu_baseline(seconds: float):
         t0 = time.perf_counter()
         r = oracle.run(x, y, s.sigma, s.L, act, [legs % 2], s.T, log=False)
         t_used += time.perf_counter() - t0
+        print(f"[bench] cpu baseline: leg {legs} done, {t_used:.1f} s", file=sys.stderr, flush=True)
         events += r.n_events
         x, y, act = r.x, r.y, r.active
         legs += 1
@@ -68,7 +69,7 @@ def cpu_baseline(seconds: float):
                       f"workload, serial C global-time event queue, 1 host thread"}
 
 
-def run_form(form, steps, warmup, lanes):
+def run_form(form, steps, warmup, lanes, window_micro):
     import numpy as np
     import torch
 
@@ -80,13 +81,19 @@ def run_form(form, steps, warmup, lanes):
     e = pkg.Ecmc(np.stack([s.x, s.y], 1), s.sigma, s.L, flags=flags, max_chains=s.k, log_cap=1 << 12)
     e.set_option(pkg.OPT_LANES, lanes)
     e.set_option(pkg.OPT_KERNEL_TIMING, 1)
+    e.set_option(pkg.OPT_WINDOW_MICRO, window_micro)
     e.set_active(s.active)
     if warmup:
         e.run(warmup * s.T, s.T, pkg.DIR_ALTERNATE)
     st0 = e.stats()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    e.run(steps * s.T, s.T, pkg.DIR_ALTERNATE)
+    done = 0
+    while done < steps:  # chunks only to report progress; one timed region
+        n = min(10, steps - done)
+        e.run(n * s.T, s.T, pkg.DIR_ALTERNATE)
+        done += n
+        print(f"[bench] {form}: {done}/{steps} legs", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     st1 = e.stats()
@@ -110,13 +117,42 @@ def run_form(form, steps, warmup, lanes):
     return res
 
 
+def profile_run(legs, lanes, window_micro):
+    """Short run for hardware-counter collection: a few legs of the workload,
+    then a device copy of 256 MiB (read 256 MiB, write 256 MiB) whose counter
+    readings calibrate the bytes the counters report."""
+    import numpy as np
+    import torch
+
+    import paper_2004_11040_amd as pkg
+    import workloads as W
+    s = W.config(4)
+    e = pkg.Ecmc(np.stack([s.x, s.y], 1), s.sigma, s.L, max_chains=s.k, log_cap=1 << 12)
+    e.set_option(pkg.OPT_LANES, lanes)
+    e.set_option(pkg.OPT_WINDOW_MICRO, window_micro)
+    e.set_active(s.active)
+    e.run(legs * s.T, s.T, pkg.DIR_ALTERNATE)
+    st = e.stats()
+    print(json.dumps({"profile_run": True, "events": st["events"], "attempts": st["attempts"],
+                      "slots_scanned": st["slots_scanned"]}), flush=True)
+    a = torch.ones(256 << 20, dtype=torch.uint8, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    b.copy_(a)
+    torch.cuda.synchronize()
+
+
 def main():
     ap = argparse.ArgumentParser()
+    ap.add_argument("--profile-run", type=int, default=0, metavar="LEGS",
+                    help="only run LEGS legs and a 256 MiB copy (for rocprofv3 counters)")
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200, help="timed legs")
+    ap.add_argument("--steps", type=int, default=60, help="timed legs")
     ap.add_argument("--warmup", type=int, default=4, help="untimed legs")
     ap.add_argument("--form", choices=["fp64", "fp32", "both"], default="fp64")
     ap.add_argument("--lanes", type=int, default=64)
+    ap.add_argument("--window-micro", type=int, default=300_000,
+                    help="bounded lag between chains, in 1e-6 sigma (0: free running)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
@@ -127,9 +163,12 @@ def main():
     import torch
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.profile_run:
+        profile_run(args.profile_run, args.lanes, args.window_micro)
+        return
 
     forms = ["fp64", "fp32"] if args.form == "both" else [args.form]
-    results = {f: run_form(f, args.steps, args.warmup, args.lanes) for f in forms}
+    results = {f: run_form(f, args.steps, args.warmup, args.lanes, args.window_micro) for f in forms}
     main_form = "fp32" if "fp32" in results else "fp64"
     r = results[main_form]
     kb = r["kernel_bytes_per_launch"]
@@ -144,7 +183,8 @@ def main():
         "dtype": "f32+f64" if main_form == "fp32" else "f64", "data": "synthetic",
         "config": {"workload": "hard disks N=1048576 eta=0.708, jittered 1024x1024 centred-rectangular "
                                "lattice, k=1024 chains, legs of T=33.896 alternating +x/+y",
-                   "form": main_form, "lanes_per_chain": args.lanes, "parallelism": "1 GPU"},
+                   "form": main_form, "lanes_per_chain": args.lanes,
+                   "window_sigma": args.window_micro * 1e-6, "parallelism": "1 GPU"},
         "roofline": roof,
         "forms": results,
     }

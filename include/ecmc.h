@@ -11,10 +11,14 @@
  * of each of its three lanes (Sec. 3.1, the out-arrows of the constraint graph
  * G(3)), claims the target with a compare-and-swap on its tag (Alg. 5
  * statement 10), re-checks the target's position and local time (statement
- * 13), and lifts (statements 14-19; Eq. 1).  A horizon violation aborts the
- * attempt, which is undone and rerun from its breakpoint with a shorter
- * sub-leg (restart strategy 1, Sec. 3.4); if that keeps failing, a short
- * window runs in global-time order (Alg. 2), which cannot violate.  Without
+ * 13), and lifts (statements 14-19; Eq. 1).  A horizon violation stops
+ * every chain; the liftings at or after the earliest time that is not settled
+ * (min of the violation times and of the chains' pending event times) are
+ * taken back from per-chain undo records and the leg resumes from there
+ * (restart strategy 2, Sec. 3.4).  If the same race keeps recurring, a short
+ * stretch runs with a tiny bounded lag (chains then commit in global-time
+ * order up to near-ties), and as a last resort in global-time order (Alg. 2),
+ * which cannot violate.  Without
  * violations the liftings equal those of Alg. 2 (Lemma 2); every path
  * evaluates each lifting from the chain's activation state with the same
  * binary64 operations, so results are bit-identical to global-time order.
@@ -64,9 +68,10 @@ extern "C" {
 #define ECMC_OPT_LANES 1          /* lanes per chain: 16, 32 or 64 (default 64) */
 #define ECMC_OPT_WAIT_RETRIES 2   /* failed claims on an active target before the
                                      chain moves up to contact (default 64)     */
-#define ECMC_OPT_MAX_SPLITS 3     /* consecutive violating attempts (each rerun
-                                     with a shorter sub-leg) before a short
-                                     window runs in global-time order (default 4) */
+#define ECMC_OPT_MAX_SPLITS 3     /* consecutive rollbacks that do not move
+                                     past the earliest unsettled time before a
+                                     short stretch runs with a tiny bounded lag
+                                     (default 4)                                 */
 #define ECMC_OPT_FORCE_GLOBAL 4   /* 1: run every leg in global-time order      */
 #define ECMC_OPT_INJECT_CHAIN 5   /* test hook: chain that reports a horizon    */
 #define ECMC_OPT_INJECT_EVENT 6   /*   violation at its given event of the next
@@ -78,16 +83,21 @@ extern "C" {
 #define ECMC_OPT_STRICT_ORDER 8   /* 1: add agent-scope acquire/release fences to
                                      the completion waits that order the shared
                                      fields (validation mode; slower)           */
+#define ECMC_OPT_WINDOW_MICRO 9   /* bounded lag, in units of 1e-6 sigma: a chain
+                                     commits an event only if its time is within
+                                     this of the smallest next-event time over
+                                     all chains (0: chains run freely).  Pure
+                                     scheduling: results do not depend on it.   */
 
 typedef struct ecmc_ctx ecmc_ctx;
 
 typedef struct {
   int64_t events;          /* committed liftings (elements of L)              */
   int64_t legs;            /* legs completed                                  */
-  int64_t legs_violated;   /* legs whose first parallel attempt violated      */
-  int64_t attempts;        /* parallel leg or sub-leg attempts launched       */
-  int64_t reruns;          /* attempts discarded because of a violation       */
-  int64_t global_legs;     /* windows run in global-time order                */
+  int64_t legs_violated;   /* legs in which a horizon violation was seen      */
+  int64_t attempts;        /* event-kernel launches                           */
+  int64_t reruns;          /* rollbacks to the earliest unsettled time        */
+  int64_t global_legs;     /* legs or stretches run in global-time order       */
   int64_t cas_fail;        /* lock-less lock re-checks that failed            */
   int64_t active_waits;    /* claims that found the target active             */
   int64_t contact_moves;   /* moves up to contact with an active target       */
@@ -102,6 +112,19 @@ typedef struct {
   int64_t event_launches;  /* number of timed event-kernel launches            */
   int64_t timed_events;    /* liftings committed inside the timed launches     */
   int64_t timed_slots;     /* cell slots scanned inside the timed launches     */
+  int64_t violations_by_kind[4]; /* horizon violations seen: [0] in the scan,
+                                  [1] re-checked after a claim, [2] target at a
+                                  breakpoint (stalled or paused), [3] before a
+                                  move up to contact                           */
+  int32_t last_violation_kind;   /* first violation of the last violating attempt */
+  int32_t last_violation_chain;  /*   chain that saw it                           */
+  int32_t last_violation_disk;   /*   disk whose local time was too late          */
+  int32_t pad_;
+  double last_violation_t;       /*   the chain's local time                     */
+  double last_violation_tj;      /*   that disk's local time                     */
+  double last_violation_tau;     /*   time of flight to that disk                */
+  double last_violation_h;       /*   start of the attempt                       */
+  int64_t lockstep_runs;         /* stall-breaking stretches with a tiny lag      */
 } ecmc_stats_t;
 
 /* Bytes of device workspace for a context.  n disks of radius sigma in a box of
@@ -142,8 +165,8 @@ int ecmc_set_active(ecmc_ctx *ctx, const int32_t *idx, int32_t k);
  * +x, and the alternation continues across calls).
  * n_chains must equal the k given to ecmc_set_active.  T must satisfy
  * 0 <= T <= box - 4 (box/cells) - 2 sigma.  Horizon violations are absorbed by
- * reruns and counted in the statistics.  Synchronises the stream once per
- * attempt (to read the violation flag).  Errors: ECMC_EINVAL, ECMC_ESTATE,
+ * rollbacks and counted in the statistics.  Synchronises the stream once per
+ * event-kernel launch (to read the violation flag).  Errors: ECMC_EINVAL, ECMC_ESTATE,
  * ECMC_ECELL, ECMC_EHANG, ECMC_EDEVICE. */
 int ecmc_run(ecmc_ctx *ctx, int32_t n_chains, double chain_time,
              double breakpoint_interval, int32_t direction);

@@ -21,6 +21,7 @@ EINVAL, EOVERLAP, EDEVICE, ECELL, EHANG, ESTATE = -1, -2, -3, -4, -5, -6
 FP64, FP32_MIXED = 0, 1
 OPT_LANES, OPT_WAIT_RETRIES, OPT_MAX_SPLITS, OPT_FORCE_GLOBAL = 1, 2, 3, 4
 OPT_INJECT_CHAIN, OPT_INJECT_EVENT, OPT_KERNEL_TIMING, OPT_STRICT_ORDER = 5, 6, 7, 8
+OPT_WINDOW_MICRO = 9
 DIR_X, DIR_Y, DIR_ALTERNATE = 0, 1, 4
 
 # every symbol the header declares
@@ -43,10 +44,18 @@ class Stats(ctypes.Structure):
         "active_waits", "contact_moves", "fp32_refines", "slots_scanned", "overlaps")] + [
         (n, ctypes.c_double) for n in ("sum_b", "chain_time", "pressure", "device_ms",
                                        "event_kernel_ms")] + [
-        (n, ctypes.c_int64) for n in ("event_launches", "timed_events", "timed_slots")]
+        (n, ctypes.c_int64) for n in ("event_launches", "timed_events", "timed_slots")] + [
+        ("violations_by_kind", ctypes.c_int64 * 4)] + [
+        (n, ctypes.c_int32) for n in ("last_violation_kind", "last_violation_chain",
+                                      "last_violation_disk", "pad_")] + [
+        (n, ctypes.c_double) for n in ("last_violation_t", "last_violation_tj",
+                                       "last_violation_tau", "last_violation_h")] + [
+        ("lockstep_runs", ctypes.c_int64)]
 
     def as_dict(self):
-        return {n: getattr(self, n) for n, _ in self._fields_}
+        d = {n: getattr(self, n) for n, _ in self._fields_ if n != "pad_"}
+        d["violations_by_kind"] = list(self.violations_by_kind)
+        return d
 
 
 _lib = None

@@ -58,12 +58,14 @@ namespace {
 
 constexpr uint32_t TAG_STATIC = 0xFFFFFFFFu;
 constexpr uint32_t TAG_STALLED = 0xFFFFFFFEu;
-constexpr uint32_t TAG_PAUSED = 0xFFFFFFFDu;  // active, waiting for the next sub-leg
+constexpr uint32_t TAG_PAUSED = 0xFFFFFFFDu;  // active, paused at the end of a stretch
 constexpr int CAP = 4;          // disks per cell (rigorous for cell width < 2 sqrt(2) sigma)
 constexpr int ROWS = 3;         // rows of cells covering the corridor |dp| < 2 sigma
 constexpr int NCNT = 6;         // per-chain counters
 enum { C_EVENTS = 0, C_CASFAIL, C_WAITS, C_MOVES, C_REFINES, C_SCANNED };
 constexpr double STOP_MARGIN = 1e-7;  // slack in the column lower bound (>> rounding)
+constexpr int64_t UNDO_CAP = 4096;     // undo records per chain and leg
+constexpr double LOCKSTEP_LAG = 1e-4;  // bounded lag (units of sigma) of a stall-breaking stretch
 
 struct MutRec {
   double a, t;
@@ -81,8 +83,19 @@ struct Ctl {
   unsigned long long overlaps;
   int32_t inject_chain, inject_event;
   int32_t pad[2];
-  long long delta_events, delta_slots;  // work of the last attempt (all chains)
+  long long tot_events[2], tot_slots[2];  // work counters before / after the last launch
+  double clock;     // H: smallest next-event time published by the chains
+  int32_t done;     // chains that finished the attempt
+  int32_t vkind_first;       // kind of the first violation of the attempt (-1: none)
+  unsigned long long vkind_cnt[4];  // violations by kind (see VK_*)
+  // first violation of the attempt: chain, its local time, the disk's stamp, tau, disk id
+  int32_t v_chain, v_id;
+  double v_t, v_tj, v_tau;
+  int32_t undo_overflow;  // a chain committed more liftings than its undo ring holds
+  int32_t pad3;
 };
+// kinds of horizon violations
+enum { VK_SCAN = 0, VK_CLAIM = 1, VK_BREAKPOINT_TARGET = 2, VK_MOVE = 3 };
 
 struct Geo {
   double L, halfL, d, d2, sigma, c, inv_c;
@@ -106,13 +119,15 @@ struct Dev {
   // global-order candidates
   double *GC_TAU, *GC_B;
   int32_t *GC_SLOT;
-  // first-touch undo of an attempt: original records of the slots it modified
-  MutRec *MUT_SNAP;
-  float2 *M32_SNAP;
-  uint32_t *EPOCH;
-  int32_t *CH_SLOT_SNAP;
-  // chain references (activation position and local time) and their copies
-  double *CH_A, *CH_T, *CH_A_SNAP, *CH_T_SNAP;
+  // chain references (activation position and local time)
+  double *CH_A, *CH_T;
+  // per-chain undo records of the liftings committed in the current leg
+  struct UndoRec *UNDO;
+  long long *UNDO_N, *UNDO_N_OLD;
+  int64_t undo_cap;
+  // rollback keys per slot (earliest undone claim of the slot)
+  unsigned long long *RKEY, *RKEY2;
+  double *NEXT;  // per chain: time of the event it is about to commit (+inf: done)
   Ctl *ctl;
   int64_t n;
   int32_t k;
@@ -124,28 +139,21 @@ struct LegP {
   int32_t final;   // 1: tend is the leg's breakpoint h' (stall); 0: intermediate (pause)
   double h;        // start of this attempt (leg-relative time)
   double tend;     // end of this attempt
-  uint32_t epoch;  // attempt number (first-touch undo marker)
   int32_t strict;  // 1: add the formal agent-scope acquire/release fences
+  double window;   // bounded lag: commit only events with time <= H + window (0: off)
 };
 
-// Save a slot's record before its first modification in this attempt.  Only
-// the chain that owns the slot (holds its tag) modifies it, so one writer at a
-// time; ownership moves between chains on different XCDs, so the marker and
-// the saved copy are agent-scope atomics like every other shared field (they
-// are ordered before the tag release that hands the slot over).
-__device__ __forceinline__ void save_first_touch(const Dev &D, int sl, double a, double t, uint32_t epoch) {
-  if (__hip_atomic_load(&D.EPOCH[sl], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != epoch) {
-    __hip_atomic_store(&D.MUT_SNAP[sl].a, a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __hip_atomic_store(&D.MUT_SNAP[sl].t, t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (D.M32) {
-      const float mx = __hip_atomic_load(&D.M32[sl].x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      const float my = __hip_atomic_load(&D.M32[sl].y, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __hip_atomic_store(&D.M32_SNAP[sl].x, mx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __hip_atomic_store(&D.M32_SNAP[sl].y, my, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-    __hip_atomic_store(&D.EPOCH[sl], epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  }
-}
+// One committed lifting, as needed to take it back (restart from the earliest
+// violation time, Sec. 3.4): when, which slots, the moving disk's reference
+// before the lifting, the target's record before it, and the chain's sum of b.
+struct UndoRec {
+  double e;        // lifting time
+  int32_t si, sj;  // slot of the disk that stopped, slot of the target
+  double ai, ti;   // reference (activation position, time) of the disk that stopped
+  double aj, tj;   // target's position and local time before the lifting
+  double sumb;     // chain's sum of b before the lifting
+  double pad;
+};
 
 // ------------------------------------------------------------------------
 // agent-scope atomic helpers
@@ -305,48 +313,110 @@ __global__ void k_chains_leg(Dev D, int64_t nslots) {
   D.CH_SLOT[c] = s;
   D.CH_A[c] = D.MUT[s].a;
   D.CH_T[c] = D.MUT[s].t;
+  D.UNDO_N[c] = 0;
+  if (c == 0) D.ctl->undo_overflow = 0;
+  for (int q = 0; q < NCNT; ++q) D.CNT_W[c * NCNT + q] = D.CNT_C[c * NCNT + q];
+  D.SUMB_W[c] = D.SUMB_C[c];
+  D.LOGLEN_W[c] = D.LOGLEN_C[c];
 }
 
-// Before every attempt: tag each chain's disk, keep a copy of the chain slots,
-// reset working counters from the committed ones (a discarded attempt leaves
-// no trace).
-__global__ void k_chains_attempt(Dev D) {
+// Before an attempt from h: tag each chain's disk, seed its published
+// next-event time with a lower bound (the state at h is settled, so no chain
+// has a lifting left before h), clear its violation flag.
+__global__ void k_chains_attempt(Dev D, double h) {
   int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= D.k) return;
   if (D.ctl->error) return;
   const int s = D.CH_SLOT[c];
-  D.CH_SLOT_SNAP[c] = s;
-  D.CH_A_SNAP[c] = D.CH_A[c];
-  D.CH_T_SNAP[c] = D.CH_T[c];
   D.TAG[s] = (uint32_t)c;
-  for (int q = 0; q < NCNT; ++q) D.CNT_W[c * NCNT + q] = D.CNT_C[c * NCNT + q];
-  D.SUMB_W[c] = D.SUMB_C[c];
-  D.LOGLEN_W[c] = D.LOGLEN_C[c];
+  const double t = D.CH_T[c];
+  D.NEXT[c] = t > h ? t : h;
   D.FLAG[c] = INFINITY;
 }
 
-// After a violating attempt: put back every slot it modified, free the tags.
-__global__ void k_restore(Dev D, int64_t nslots, uint32_t epoch) {
-  int64_t sl = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (sl < nslots) {
-    if (D.EPOCH[sl] == epoch) {
-      D.MUT[sl] = D.MUT_SNAP[sl];
-      if (D.M32) D.M32[sl] = D.M32_SNAP[sl];
-    }
-    // tags: only chains own disks between attempts; they are set again below
-    if (D.TAG[sl] != TAG_STATIC) D.TAG[sl] = TAG_STATIC;
-  }
-  if (sl < D.k) {
-    D.CH_SLOT[sl] = D.CH_SLOT_SNAP[sl];
-    D.CH_A[sl] = D.CH_A_SNAP[sl];
-    D.CH_T[sl] = D.CH_T_SNAP[sl];
+// ---- rollback to time R: take back every lifting with time >= R ----------
+// A slot that was static at R gets the record saved by its earliest undone
+// claim (smallest lifting time, then smallest old local time: local times of a
+// disk only grow, so that is the first claim); a chain gets the reference it had
+// at R and republishes the point its disk reaches at R (a pause at R).
+__global__ void k_rb_mark(Dev D, double R) {
+  int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= D.k) return;
+  const long long n = D.UNDO_N[c];
+  D.UNDO_N_OLD[c] = n;
+  for (long long m = n - 1; m >= 0; --m) {
+    const UndoRec &u = D.UNDO[(int64_t)c * D.undo_cap + m];
+    if (!(u.e >= R)) break;
+    atomicMin(&D.RKEY[u.sj], (unsigned long long)__double_as_longlong(u.e));
   }
 }
+__global__ void k_rb_mark2(Dev D, double R) {
+  int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= D.k) return;
+  for (long long m = D.UNDO_N_OLD[c] - 1; m >= 0; --m) {
+    const UndoRec &u = D.UNDO[(int64_t)c * D.undo_cap + m];
+    if (!(u.e >= R)) break;
+    if (D.RKEY[u.sj] == (unsigned long long)__double_as_longlong(u.e))
+      atomicMin(&D.RKEY2[u.sj], (unsigned long long)__double_as_longlong(u.tj));
+  }
+}
+__global__ void k_rb_apply(Dev D, Geo g, double R) {
+  int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= D.k) return;
+  const long long n = D.UNDO_N_OLD[c];
+  long long m = n - 1;
+  for (; m >= 0; --m) {
+    const UndoRec &u = D.UNDO[(int64_t)c * D.undo_cap + m];
+    if (!(u.e >= R)) break;
+    D.TAG[u.si] = TAG_STATIC;
+    if (D.RKEY[u.sj] == (unsigned long long)__double_as_longlong(u.e) &&
+        D.RKEY2[u.sj] == (unsigned long long)__double_as_longlong(u.tj)) {
+      MutRec r;
+      r.a = u.aj;
+      r.t = u.tj;
+      D.MUT[u.sj] = r;
+      D.TAG[u.sj] = TAG_STATIC;
+      if (D.M32) D.M32[u.sj].x = (float)(u.aj - ((u.sj >> 2) % g.nc) * g.c);
+    }
+  }
+  const long long nu = n - 1 - m;  // liftings taken back
+  if (nu > 0) {
+    const UndoRec &u0 = D.UNDO[(int64_t)c * D.undo_cap + m + 1];  // the earliest one
+    D.CH_SLOT[c] = u0.si;
+    D.CH_A[c] = u0.ai;
+    D.CH_T[c] = u0.ti;
+    D.SUMB_W[c] = u0.sumb;
+    D.CNT_W[c * NCNT + C_EVENTS] -= nu;
+    D.LOGLEN_W[c] -= nu;
+    D.UNDO_N[c] = n - nu;
+  }
+}
+__global__ void k_rb_reset(Dev D, Geo g, double R) {
+  int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= D.k) return;
+  for (long long m = D.UNDO_N[c]; m < D.UNDO_N_OLD[c]; ++m) {
+    const UndoRec &u = D.UNDO[(int64_t)c * D.undo_cap + m];
+    D.RKEY[u.sj] = 0x7FF0000000000000ull;
+    D.RKEY2[u.sj] = 0x7FF0000000000000ull;
+  }
+  // the chain's disk at R: a pause there
+  const int s = D.CH_SLOT[c];
+  MutRec r;
+  r.a = fwd_move(D.CH_A[c], R - D.CH_T[c], g);
+  r.t = R;
+  D.MUT[s] = r;
+  D.TAG[s] = (uint32_t)c;
+  if (D.M32) D.M32[s].x = (float)(r.a - ((s >> 2) % g.nc) * g.c);
+}
 
-__global__ void k_ctl_reset(Dev D) {
+__global__ void k_ctl_reset(Dev D, double h) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     D.ctl->tstar_bits = 0x7FF0000000000000ull;  // +inf
     D.ctl->abort = 0;
+    D.ctl->clock = h;
+    D.ctl->done = 0;
+    D.ctl->vkind_first = -1;
+    for (int q = 0; q < 4; ++q) D.ctl->vkind_cnt[q] = 0ull;
   }
 }
 
@@ -397,11 +467,62 @@ struct Cand {
 };
 
 template <int G>
-__device__ __forceinline__ void flag_violation(const Dev &D, int c, double t, int lane) {
+__device__ __forceinline__ void flag_violation(const Dev &D, int c, double t, int lane, int kind = VK_SCAN,
+                                               double tj = 0.0, double tau = 0.0, int id = -1) {
   if (lane == 0) {
     D.FLAG[c] = t;
     atomicMin(&D.ctl->tstar_bits, (unsigned long long)__double_as_longlong(t));
+    atomicAdd(&D.ctl->vkind_cnt[kind], 1ull);
+    if (atomicCAS(&D.ctl->vkind_first, -1, kind) == -1) {  // details of the first one
+      D.ctl->v_chain = c;
+      D.ctl->v_id = id;
+      D.ctl->v_t = t;
+      D.ctl->v_tj = tj;
+      D.ctl->v_tau = tau;
+    }
     __hip_atomic_store(&D.ctl->abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+// The clock workgroup: H = min over chains of NEXT, republished until every
+// chain has finished (or the attempt aborts).  H never decreases.
+__device__ void clock_loop(const Dev &D, long long iter_cap) {
+  __shared__ double red[256];
+  __shared__ int s_quit;
+  double hc = ld_a(&D.ctl->clock);
+  for (long long it = 0;; ++it) {
+    double m = INFINITY;
+    for (int c = threadIdx.x; c < D.k; c += blockDim.x) {
+      const double v = ld_a(&D.NEXT[c]);
+      m = v < m ? v : m;
+    }
+    red[threadIdx.x] = m;
+    __syncthreads();
+    for (int off = blockDim.x / 2; off > 0; off >>= 1) {
+      if ((int)threadIdx.x < off) red[threadIdx.x] = fmin(red[threadIdx.x], red[threadIdx.x + off]);
+      __syncthreads();
+    }
+    m = red[0];
+    __syncthreads();
+    if (m > hc) {
+      hc = m;
+      if (threadIdx.x == 0) st_a(&D.ctl->clock, hc);
+    }
+    if (threadIdx.x == 0) {  // one thread decides, the block follows
+      const int done = __hip_atomic_load(&D.ctl->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      const int ab = __hip_atomic_load(&D.ctl->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      const int er = __hip_atomic_load(&D.ctl->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      int quit = (done >= D.k || ab || er) ? 1 : 0;
+      if (!quit && it >= iter_cap) {
+        atomicExch(&D.ctl->error, ECMC_EHANG);
+        __hip_atomic_store(&D.ctl->abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        quit = 1;
+      }
+      s_quit = quit;
+    }
+    __syncthreads();
+    if (s_quit) break;
+    __builtin_amdgcn_s_sleep(1);
   }
 }
 
@@ -418,6 +539,10 @@ __global__ void __launch_bounds__(256) k_event(Dev D, Geo g, LegP lp, int32_t wa
                                                long long iter_cap) {
   const int lane = threadIdx.x & (G - 1);
   const int c = (int)(((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G);
+  if (lp.window > 0.0 && blockIdx.x == gridDim.x - 1) {  // the clock workgroup
+    clock_loop(D, iter_cap);
+    return;
+  }
   if (c >= D.k) return;  // whole groups leave together
   if (D.ctl->error) return;
   using W = Win<G>;
@@ -427,7 +552,8 @@ __global__ void __launch_bounds__(256) k_event(Dev D, Geo g, LegP lp, int32_t wa
   double t = D.CH_T[c];  // reference local time
   double p = D.CST[s].p;
   double t_pub = ld_a(&D.MUT[s].t);  // published point
-  if (lane == 0) save_first_touch(D, s, ld_a(&D.MUT[s].a), t_pub, lp.epoch);
+  double nxt_pub = -1.0;              // last next-event time published
+  long long undo_n = D.UNDO_N[c];
   long long cnt[NCNT];
   for (int q = 0; q < NCNT; ++q) cnt[q] = D.CNT_W[c * NCNT + q];
   double sumb = D.SUMB_W[c];
@@ -436,13 +562,18 @@ __global__ void __launch_bounds__(256) k_event(Dev D, Geo g, LegP lp, int32_t wa
   long long lane_scanned = 0;
   const int inj_ev = (D.ctl->inject_chain == c) ? D.ctl->inject_event : -1;
   int retries = 0;
+  bool finished = false;
   const double tend = lp.tend, h = lp.h;
 
   for (long long it = 0;; ++it) {
     // the abort word (another chain saw a violation) is read with the scan's
     // loads and tested after them
     int ab = 0;
-    if (lane == 0) ab = __hip_atomic_load(&D.ctl->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    double hclk = 0.0;
+    if (lane == 0) {
+      ab = __hip_atomic_load(&D.ctl->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      hclk = ld_a(&D.ctl->clock);
+    }
     if (it >= iter_cap) {
       if (lane == 0) {
         atomicExch(&D.ctl->error, ECMC_EHANG);
@@ -451,7 +582,7 @@ __global__ void __launch_bounds__(256) k_event(Dev D, Geo g, LegP lp, int32_t wa
       break;
     }
     if (inj_ev >= 0 && cnt[C_EVENTS] - ev_start == inj_ev) {  // test hook
-      flag_violation<G>(D, c, t, lane);
+      flag_violation<G>(D, c, t > h ? t : h, lane);
       break;
     }
 
@@ -546,19 +677,83 @@ __global__ void __launch_bounds__(256) k_event(Dev D, Geo g, LegP lp, int32_t wa
       gpj[q] = __shfl(bl.p[q], own, G);
       gsl[q] = __shfl(bl.slot[q], own, G);
     }
-    int tc = 0;
-    if (key_less(gt[1], gi[1], gt[tc], gi[tc])) tc = 1;
-    if (key_less(gt[2], gi[2], gt[tc], gi[tc])) tc = 2;
-    const double tau = gt[tc];
-    const int ts = gsl[tc];
+    // the target: smallest of the three minima (selects, not indexing, keep
+    // everything in registers)
+    double tau = gt[0], t_aj = gaj[0], t_tj = gtj[0], t_b = gbj[0], t_p = gpj[0];
+    int t_id = gi[0], ts = gsl[0];
+#pragma unroll
+    for (int q = 1; q < 3; ++q)
+      if (key_less(gt[q], gi[q], tau, t_id)) {
+        tau = gt[q];
+        t_id = gi[q];
+        ts = gsl[q];
+        t_aj = gaj[q];
+        t_tj = gtj[q];
+        t_b = gbj[q];
+        t_p = gpj[q];
+      }
+
+    // ---- bounded lag: the next event (a lifting, or the breakpoint) may be
+    // committed only if its time is within `window` of the clock H, the
+    // smallest next-event time of all chains.  While blocked, the disk
+    // publishes the point of its free flight at the window's edge. ----
+    const double e_next = tau < trem ? t + tau : tend;
+    if (lane == 0 && e_next != nxt_pub) {
+      st_a(&D.NEXT[c], e_next);
+      nxt_pub = e_next;
+    }
+    if (lp.window > 0.0) {
+      double hc = __shfl(hclk, 0, G);
+      bool stop = false;
+      while (e_next > hc + lp.window) {
+        const double tw = hc + lp.window;
+        if (tw > t_pub) {
+          const double aw = fwd_move(a, tw - t, g);
+          if (lane == 0) {
+            st_a(&D.MUT[s].t, tw);
+            fence_rel();
+            st_a(&D.MUT[s].a, aw);
+          }
+          t_pub = tw;
+        }
+        if (++it >= iter_cap) {
+          if (lane == 0) {
+            atomicExch(&D.ctl->error, ECMC_EHANG);
+            __hip_atomic_store(&D.ctl->abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          }
+          stop = true;
+          break;
+        }
+        __builtin_amdgcn_s_sleep(2);
+        int ab2 = 0;
+        double h2 = 0.0;
+        if (lane == 0) {
+          ab2 = __hip_atomic_load(&D.ctl->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          h2 = ld_a(&D.ctl->clock);
+        }
+        if (__shfl(ab2, 0, G)) {
+          stop = true;
+          break;
+        }
+        hc = __shfl(h2, 0, G);
+      }
+      if (stop) break;
+    }
 
     // ---- statement 5: horizon condition on the lane minima (scanned times) ----
     bool viol = false;
+    double vtj = 0.0, vta = 0.0;
+    int vid = -1;
 #pragma unroll
     for (int q = 0; q < 3; ++q)
-      if (gt[q] < trem && t + gt[q] < gtj[q]) viol = true;
+      if (gt[q] < trem && t + gt[q] < gtj[q]) {
+        viol = true;
+        vtj = gtj[q];
+        vta = gt[q];
+        vid = gi[q];
+      }
     if (viol) {
-      flag_violation<G>(D, c, t, lane);
+      flag_violation<G>(D, c, t > h ? t : h, lane, VK_SCAN, vtj, vta, vid);
       break;
     }
 
@@ -574,11 +769,8 @@ __global__ void __launch_bounds__(256) k_event(Dev D, Geo g, LegP lp, int32_t wa
         strict_rel(lp.strict);
         st_rel(&D.TAG[s], lp.final ? TAG_STALLED : TAG_PAUSED);
       }
-      if (lp.final) {
-        a = an;
-        t = tend;
-      }
-      break;
+      finished = true;
+      break;  // the reference stays: a rollback may resume this chain
     }
 
     // ---- statement 10: claim the target ----
@@ -606,7 +798,7 @@ __global__ void __launch_bounds__(256) k_event(Dev D, Geo g, LegP lp, int32_t wa
       if (old == TAG_STALLED || old == TAG_PAUSED) {
         // it sits where it is at the breakpoint with t = breakpoint, and this
         // chain would reach it earlier: a horizon violation
-        flag_violation<G>(D, c, t, lane);
+        flag_violation<G>(D, c, t > h ? t : h, lane, VK_BREAKPOINT_TARGET, tend, tau, t_id);
         break;
       }
       // the target is active on another chain: retry; after wait_retries
@@ -614,7 +806,7 @@ __global__ void __launch_bounds__(256) k_event(Dev D, Geo g, LegP lp, int32_t wa
       cnt[C_WAITS] += (lane == 0);
       if (++retries >= wait_retries) {
         retries = 0;
-        const double tn = t + tau;
+        const double tn = t + tau;  // within the window: checked above
         if (tn > t_pub) {
           int bad = 0;
           if (lane == 0) {
@@ -626,7 +818,7 @@ __global__ void __launch_bounds__(256) k_event(Dev D, Geo g, LegP lp, int32_t wa
           }
           bad = __shfl(bad, 0, G);
           if (bad) {
-            flag_violation<G>(D, c, t, lane);
+            flag_violation<G>(D, c, t > h ? t : h, lane, VK_MOVE);
             break;
           }
           const double an = fwd_move(a, tau, g);
@@ -648,7 +840,7 @@ __global__ void __launch_bounds__(256) k_event(Dev D, Geo g, LegP lp, int32_t wa
 #pragma unroll
     for (int q = 0; q < 3; ++q) tcls[q] = __shfl(tcls[q], 0, G);
     // statement 13: the target must not have moved (nor been stamped) since the scan
-    if (aj2 != gaj[tc] || tj2 != gtj[tc]) {
+    if (aj2 != t_aj || tj2 != t_tj) {
       if (lane == 0) {
         strict_rel(lp.strict);
         st_rel(&D.TAG[ts], TAG_STATIC);  // statement 20
@@ -659,10 +851,15 @@ __global__ void __launch_bounds__(256) k_event(Dev D, Geo g, LegP lp, int32_t wa
     // statement 5 again with local times read after the claim
 #pragma unroll
     for (int q = 0; q < 3; ++q)
-      if (gt[q] < trem && t + gt[q] < tcls[q]) viol = true;
+      if (gt[q] < trem && t + gt[q] < tcls[q]) {
+        viol = true;
+        vtj = tcls[q];
+        vta = gt[q];
+        vid = gi[q];
+      }
     if (viol) {
       if (lane == 0) st_rel(&D.TAG[ts], TAG_STATIC);
-      flag_violation<G>(D, c, t, lane);
+      flag_violation<G>(D, c, t > h ? t : h, lane, VK_CLAIM, vtj, vta, vid);
       break;
     }
 
@@ -670,7 +867,19 @@ __global__ void __launch_bounds__(256) k_event(Dev D, Geo g, LegP lp, int32_t wa
     const double tn = t + tau;
     const double an = fwd_move(a, tau, g);
     if (lane == 0) {
-      save_first_touch(D, ts, aj2, tj2, lp.epoch);
+      if (undo_n < D.undo_cap) {  // what it takes to take this lifting back
+        UndoRec *u = &D.UNDO[(int64_t)c * D.undo_cap + undo_n];
+        u->e = tn;
+        u->si = s;
+        u->sj = ts;
+        u->ai = a;
+        u->ti = t;
+        u->aj = aj2;
+        u->tj = tj2;
+        u->sumb = sumb;
+      } else {
+        atomicExch(&D.ctl->undo_overflow, 1);
+      }
       st_a(&D.MUT[ts].t, tn);  // 14: t_j
       st_a(&D.MUT[s].t, tn);   // 15: t_i
       fence_rel();
@@ -682,14 +891,15 @@ __global__ void __launch_bounds__(256) k_event(Dev D, Geo g, LegP lp, int32_t wa
       }
       strict_rel(lp.strict);
       st_rel(&D.TAG[s], TAG_STATIC);  // 17: release i
-      D.LOG[(int64_t)c * D.log_cap + (loglen % D.log_cap)] = gi[tc];
+      D.LOG[(int64_t)c * D.log_cap + (loglen % D.log_cap)] = t_id;
     }
     ++loglen;
+    ++undo_n;
     cnt[C_EVENTS] += 1;
-    sumb = sumb + gbj[tc];
+    sumb = sumb + t_b;
     s = ts;  // 19: continue with j
     a = aj2;
-    p = gpj[tc];
+    p = t_p;
     t = tn;
     t_pub = tn;
     retries = 0;
@@ -699,10 +909,15 @@ __global__ void __launch_bounds__(256) k_event(Dev D, Geo g, LegP lp, int32_t wa
 #pragma unroll
   for (int off = G / 2; off > 0; off >>= 1) sc += __shfl_xor(sc, off, G);
   if (lane == 0) {
+    // a chain stopped by an abort keeps its last next-event time: a lower
+    // bound of every lifting it has still to make
+    if (finished) st_a(&D.NEXT[c], INFINITY);
+    atomicAdd(&D.ctl->done, 1);
     cnt[C_SCANNED] += sc;
     for (int q = 0; q < NCNT; ++q) D.CNT_W[c * NCNT + q] = cnt[q];
     D.SUMB_W[c] = sumb;
     D.LOGLEN_W[c] = loglen;
+    D.UNDO_N[c] = undo_n;
     D.CH_SLOT[c] = s;
     D.CH_A[c] = a;
     D.CH_T[c] = t;
@@ -729,13 +944,14 @@ __global__ void k_writeback(Dev D, Geo g, int32_t dir) {
   D.STAMP[id] = m.t;
 }
 
-// Work done by the last attempt, summed over chains (one block).
-__global__ void k_count_delta(Dev D) {
+// Work counters summed over chains (one block), stored in pair `which`
+// (0: before an event launch, 1: after it).
+__global__ void k_count_delta(Dev D, int which) {
   __shared__ long long se[256], ss[256];
   long long e = 0, sl = 0;
   for (int c = threadIdx.x; c < D.k; c += blockDim.x) {
-    e += D.CNT_W[c * NCNT + C_EVENTS] - D.CNT_C[c * NCNT + C_EVENTS];
-    sl += D.CNT_W[c * NCNT + C_SCANNED] - D.CNT_C[c * NCNT + C_SCANNED];
+    e += D.CNT_W[c * NCNT + C_EVENTS];
+    sl += D.CNT_W[c * NCNT + C_SCANNED];
   }
   se[threadIdx.x] = e;
   ss[threadIdx.x] = sl;
@@ -748,13 +964,28 @@ __global__ void k_count_delta(Dev D) {
     __syncthreads();
   }
   if (threadIdx.x == 0) {
-    D.ctl->delta_events = se[0];
-    D.ctl->delta_slots = ss[0];
+    D.ctl->tot_events[which] = se[0];
+    D.ctl->tot_slots[which] = ss[0];
   }
 }
 
+// After an event launch: H = min over chains of NEXT.  Next-event times only
+// grow during a launch, so H bounds from below every lifting not committed yet.
+__global__ void k_next_min(Dev D) {
+  __shared__ double red[256];
+  double m = INFINITY;
+  for (int c = threadIdx.x; c < D.k; c += blockDim.x) m = fmin(m, D.NEXT[c]);
+  red[threadIdx.x] = m;
+  __syncthreads();
+  for (int off = blockDim.x / 2; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) red[threadIdx.x] = fmin(red[threadIdx.x], red[threadIdx.x + off]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) D.ctl->clock = red[0];
+}
+
 __global__ void k_chains_commit(Dev D) {
-  if (D.ctl->abort || D.ctl->error) return;
+  if (D.ctl->error) return;
   int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= D.k) return;
   for (int q = 0; q < NCNT; ++q) D.CNT_C[c * NCNT + q] = D.CNT_W[c * NCNT + q];
@@ -863,6 +1094,23 @@ __global__ void __launch_bounds__(1024) k_global(Dev D, Geo g, LegP lp) {
       const double tau = D.GC_TAU[w];
       const double tn = D.CH_T[w] + tau;
       const double an = fwd_move(D.CH_A[w], tau, g);
+      const long long un = D.UNDO_N[w];
+      if (un < D.undo_cap) {
+        UndoRec u;
+        u.e = tn;
+        u.si = s;
+        u.sj = ts;
+        u.ai = D.CH_A[w];
+        u.ti = D.CH_T[w];
+        u.aj = D.MUT[ts].a;
+        u.tj = D.MUT[ts].t;
+        u.sumb = D.SUMB_W[w];
+        u.pad = 0.0;
+        D.UNDO[(int64_t)w * D.undo_cap + un] = u;
+      } else {
+        D.ctl->undo_overflow = 1;
+      }
+      D.UNDO_N[w] = un + 1;
       MutRec mi;
       mi.a = an;
       mi.t = tn;
@@ -923,10 +1171,6 @@ __global__ void __launch_bounds__(1024) k_global(Dev D, Geo g, LegP lp) {
     m.t = tend;
     D.MUT[s] = m;
     D.TAG[s] = lp.final ? TAG_STALLED : TAG_PAUSED;
-    if (lp.final) {
-      D.CH_A[c] = an;
-      D.CH_T[c] = tend;
-    }
   }
 }
 
@@ -993,21 +1237,24 @@ struct ecmc_ctx {
   int64_t log_cap;
   int32_t lanes = 64;
   int32_t wait_retries = 64;
-  int32_t max_splits = 4;     // consecutive failed attempts before a global-order window
-  double sub_frac = 1.0;      // current sub-leg length as a fraction of the leg (adaptive)
-  uint32_t epoch = 0;
+  int32_t max_splits = 4;     // rollbacks without progress before a lockstep stretch
+  int64_t undo_cap = 4096;     // undo records per chain and leg
   int32_t force_global = 0;
   int32_t inject_chain = -1, inject_event = -1;
   int64_t leg_counter = 0;
   bool active_set = false;
   int32_t kernel_timing = 0;
   int32_t strict_order = 0;
+  int64_t vkind[4] = {0, 0, 0, 0};
+  int32_t last_v_kind = -1, last_v_chain = -1, last_v_id = -1;
+  double last_v_t = 0.0, last_v_tj = 0.0, last_v_tau = 0.0, last_v_h = 0.0;
+  double window = 0.0;  // bounded lag in units of time (0: chains run freely)
   double event_kernel_ms = 0.0;
   int64_t event_launches = 0, timed_events = 0, timed_slots = 0;
   hipEvent_t kev0, kev1;
   bool kevents_ok = false;
   // host-side statistics
-  int64_t legs = 0, legs_violated = 0, attempts = 0, reruns = 0, global_legs = 0;
+  int64_t legs = 0, legs_violated = 0, attempts = 0, reruns = 0, global_legs = 0, lockstep_runs = 0;
   double chain_time = 0.0;
   double device_ms = 0.0;
   int64_t last_overlaps = 0;
@@ -1070,14 +1317,15 @@ Layout make_layout(int64_t n, int32_t nc, int32_t kmax, int64_t log_cap, uint32_
       (int64_t)kmax * 4,      // 21 GC_SLOT
       (int64_t)sizeof(Ctl),   // 22 ctl
       n * 16,                 // 23 staging for interleaved xy readback
-      S * 16,                 // 24 MUT_SNAP
-      (flags & ECMC_FP32_MIXED) ? S * 8 : 0,  // 25 M32_SNAP
-      S * 4,                  // 26 EPOCH
-      (int64_t)kmax * 4,      // 27 CH_SLOT_SNAP
+      S * 8,                  // 24 RKEY
+      S * 8,                  // 25 RKEY2
+      (int64_t)kmax * UNDO_CAP * 64,  // 26 UNDO
+      (int64_t)kmax * 8,      // 27 UNDO_N
       (int64_t)kmax * 8,      // 28 CH_A
       (int64_t)kmax * 8,      // 29 CH_T
-      (int64_t)kmax * 8,      // 30 CH_A_SNAP
-      (int64_t)kmax * 8,      // 31 CH_T_SNAP
+      (int64_t)kmax * 8,      // 30 UNDO_N_OLD
+      0,                      // 31 (unused)
+      (int64_t)kmax * 8,      // 32 NEXT
   };
   int64_t o = 0;
   int nsz = (int)(sizeof(sizes) / sizeof(sizes[0]));
@@ -1148,7 +1396,7 @@ int launch_event(ecmc_ctx *ctx, LegP lp) {
   const long long cap = 1ll << 24;
   const int G = ctx->lanes;
   const int64_t threads = (int64_t)D.k * G;
-  const unsigned nb = blocks_for(threads, 256);
+  const unsigned nb = blocks_for(threads, 256) + (lp.window > 0.0 ? 1u : 0u);  // + clock
   int rc = G == 64 ? check_resident<64>(ctx, nb)
                    : (G == 32 ? check_resident<32>(ctx, nb) : check_resident<16>(ctx, nb));
   if (rc) return rc;
@@ -1162,15 +1410,17 @@ int launch_event(ecmc_ctx *ctx, LegP lp) {
   return ECMC_OK;
 }
 
-// One attempt over [h, tend) of the current leg (home cells already built).
-// On a violation every slot the attempt modified is put back.
-int attempt(ecmc_ctx *ctx, int dir, double h, double tend, bool final, bool global, bool *violated,
-            double *tstar) {
+// One attempt over [h, tend) of the current leg (home cells already built and
+// chains attached).  Reports whether a chain saw a horizon violation, the
+// earliest violation time t*, the clock H (smallest pending event time) and
+// whether an undo ring overflowed; the caller decides how to recover.
+int attempt(ecmc_ctx *ctx, int dir, double h, double tend, bool final, bool global, double window,
+            bool *violated, double *tstar, double *clock, bool *undo_overflow) {
   Dev &D = ctx->D;
   const int64_t S = (int64_t)ctx->g.nc * ctx->g.nc * CAP;
-  k_ctl_reset<<<1, 1, 0, ctx->stream>>>(D);
+  k_ctl_reset<<<1, 1, 0, ctx->stream>>>(D, h);
   HIPCHK(hipGetLastError());
-  k_chains_attempt<<<blocks_for(D.k, 256), 256, 0, ctx->stream>>>(D);
+  k_chains_attempt<<<blocks_for(D.k, 256), 256, 0, ctx->stream>>>(D, h);
   HIPCHK(hipGetLastError());
   LegP lp;
   lp.dir = dir;
@@ -1178,10 +1428,11 @@ int attempt(ecmc_ctx *ctx, int dir, double h, double tend, bool final, bool glob
   lp.h = h;
   lp.tend = tend;
   lp.strict = ctx->strict_order;
-  lp.epoch = ++ctx->epoch;
-  if (lp.epoch == 0) lp.epoch = ++ctx->epoch;  // 0 marks "never touched"
+  lp.window = window;
   const bool timed = !global && ctx->kernel_timing && ctx->kevents_ok;
   int rc;
+  k_count_delta<<<1, 256, 0, ctx->stream>>>(D, 0);
+  HIPCHK(hipGetLastError());
   if (global) {
     k_global<<<1, 1024, 0, ctx->stream>>>(D, ctx->g, lp);
     HIPCHK(hipGetLastError());
@@ -1190,10 +1441,10 @@ int attempt(ecmc_ctx *ctx, int dir, double h, double tend, bool final, bool glob
     rc = launch_event(ctx, lp);
     if (rc) return rc;
     if (timed) HIPCHK(hipEventRecord(ctx->kev1, ctx->stream));
+    k_next_min<<<1, 256, 0, ctx->stream>>>(D);
+    HIPCHK(hipGetLastError());
   }
-  k_count_delta<<<1, 256, 0, ctx->stream>>>(D);
-  HIPCHK(hipGetLastError());
-  k_chains_commit<<<blocks_for(D.k, 256), 256, 0, ctx->stream>>>(D);
+  k_count_delta<<<1, 256, 0, ctx->stream>>>(D, 1);
   HIPCHK(hipGetLastError());
   Ctl hc;
   rc = read_ctl(ctx, &hc);
@@ -1206,13 +1457,23 @@ int attempt(ecmc_ctx *ctx, int dir, double h, double tend, bool final, bool glob
     return hc.error;
   }
   *violated = hc.abort != 0;
+  for (int q = 0; q < 4; ++q) ctx->vkind[q] += (int64_t)hc.vkind_cnt[q];
+  if (hc.vkind_first >= 0) {
+    ctx->last_v_kind = hc.vkind_first;
+    ctx->last_v_chain = hc.v_chain;
+    ctx->last_v_id = hc.v_id;
+    ctx->last_v_t = hc.v_t;
+    ctx->last_v_tj = hc.v_tj;
+    ctx->last_v_tau = hc.v_tau;
+    ctx->last_v_h = h;
+  }
   if (timed) {
     float ms = 0.f;
     HIPCHK(hipEventElapsedTime(&ms, ctx->kev0, ctx->kev1));
     ctx->event_kernel_ms += ms;
     ctx->event_launches += 1;
-    ctx->timed_events += hc.delta_events;  // work done inside the timed launch
-    ctx->timed_slots += hc.delta_slots;
+    ctx->timed_events += hc.tot_events[1] - hc.tot_events[0];  // work done inside the launch
+    ctx->timed_slots += hc.tot_slots[1] - hc.tot_slots[0];
   }
   double ts;
   std::memcpy(&ts, &hc.tstar_bits, 8);
@@ -1221,10 +1482,9 @@ int attempt(ecmc_ctx *ctx, int dir, double h, double tend, bool final, bool glob
     ctx->err = "global-time order reported a violation";
     return ECMC_EDEVICE;
   }
-  if (*violated) {
-    k_restore<<<blocks_for(S, 256), 256, 0, ctx->stream>>>(D, S, lp.epoch);
-    HIPCHK(hipGetLastError());
-  }
+  (void)S;
+  *undo_overflow = hc.undo_overflow != 0;
+  *clock = hc.clock;
   return ECMC_OK;
 }
 
@@ -1239,76 +1499,121 @@ int set_inject(ecmc_ctx *ctx, int32_t chain, int32_t ev) {
   return ECMC_OK;
 }
 
-// One leg [0, T] in direction dir.  The home cells are built once; the leg is
-// then run as a sequence of attempts [h, h + dt) ("sub-legs": extra
-// breakpoints in the same direction, at which chains pause without moving, so
-// results do not depend on where they fall).  A violating attempt is undone
-// and rerun with a shorter sub-leg, taking the earliest violation time t* as
-// its end when it lies inside (restart strategy 1, Sec. 3.4; Remark on partial
-// validation); successful attempts let the sub-leg grow back.  After
-// max_splits consecutive failures a short window runs in global-time order
-// (Alg. 2), which cannot violate.
+int rollback(ecmc_ctx *ctx, double R) {
+  Dev &D = ctx->D;
+  const unsigned nb = blocks_for(D.k, 256);
+  k_rb_mark<<<nb, 256, 0, ctx->stream>>>(D, R);
+  k_rb_mark2<<<nb, 256, 0, ctx->stream>>>(D, R);
+  k_rb_apply<<<nb, 256, 0, ctx->stream>>>(D, ctx->g, R);
+  k_rb_reset<<<nb, 256, 0, ctx->stream>>>(D, ctx->g, R);
+  HIPCHK(hipGetLastError());
+  return ECMC_OK;
+}
+
+int begin_leg(ecmc_ctx *ctx, int dir) {
+  Dev &D = ctx->D;
+  int rc = build_cells(ctx, dir);
+  if (rc) return rc;
+  k_chains_leg<<<blocks_for(D.k, 256), 256, 0, ctx->stream>>>(D, (int64_t)ctx->g.nc * ctx->g.nc * CAP);
+  HIPCHK(hipGetLastError());
+  return ECMC_OK;
+}
+
+// One leg [0, T] in direction dir.  The home cells are built once and all
+// chains run to the breakpoint.  When a chain sees a horizon violation every
+// chain stops; liftings at or after R = min(t*, H) are taken back from the
+// undo records (t*: earliest violation time, before which liftings are valid,
+// Remark on partial validation; H: the clock, below which no chain has a
+// pending event) and the leg resumes from R with every chain paused there
+// (restart strategy 2, Sec. 3.4).  If rollbacks stop making progress, a short
+// window runs in global-time order (Alg. 2), which cannot violate.
 int run_leg(ecmc_ctx *ctx, int dir, double T) {
   Dev &D = ctx->D;
   int rc = fill<double>(ctx, D.STAMP, 0.0, D.n);  // Alg. 1: local times start at h
   if (rc) return rc;
-  rc = build_cells(ctx, dir);
+  rc = begin_leg(ctx, dir);
   if (rc) return rc;
-  k_chains_leg<<<blocks_for(D.k, 256), 256, 0, ctx->stream>>>(D, (int64_t)ctx->g.nc * ctx->g.nc * CAP);
-  HIPCHK(hipGetLastError());
-  bool v;
-  double ts;
-  const double dt_min = T / 4096.0;
-  double h = 0.0;
-  int fails = 0;
+  bool v, ovf;
+  double ts, clk;
+  double h = 0.0, last_R = -1.0;
+  double gwin = std::max(ctx->window > 0.0 ? 4.0 * ctx->window : 0.0, T / 256.0);
+  int stuck = 0;
+  int64_t tries = 0;
   bool first = true;
-  double frac = ctx->sub_frac;
-  while (h < T) {
-    if (ctx->force_global) {
-      rc = attempt(ctx, dir, h, T, true, true, &v, &ts);
-      if (rc) return rc;
-      ctx->global_legs++;
-      break;
-    }
-    double dt = frac * T;
-    if (dt < dt_min) dt = dt_min;
-    double tend = h + dt;
-    if (tend >= T * (1.0 - 1e-12)) tend = T;
-    const bool final = tend >= T;
-    bool violated = false;
-    double tstar = INFINITY;
-    rc = attempt(ctx, dir, h, tend, final, false, &violated, &tstar);
+  if (ctx->force_global) {
+    rc = attempt(ctx, dir, 0.0, T, true, true, 0.0, &v, &ts, &clk, &ovf);
     if (rc) return rc;
-    if (ctx->inject_chain >= 0) {  // the hook fires on one attempt only
-      ctx->inject_chain = -1;
-      rc = set_inject(ctx, -1, -1);
+    ctx->global_legs++;
+  } else {
+    for (;;) {
+      bool violated = false;
+      double tstar = INFINITY, clock = 0.0;
+      rc = attempt(ctx, dir, h, T, true, false, ctx->window, &violated, &tstar, &clock, &ovf);
       if (rc) return rc;
-    }
-    if (!violated) {
-      h = tend;
-      fails = 0;
-      frac = std::min(1.0, frac * 1.5);
-      continue;
-    }
-    if (first) ctx->legs_violated++;
-    first = false;
-    ctx->reruns++;
-    ++fails;
-    double shrink = 0.5 * (tend - h);
-    if (tstar > h && tstar - h < shrink) shrink = tstar - h;
-    frac = std::max(shrink / T, dt_min / T);
-    if (fails > ctx->max_splits) {
-      // a short window in global-time order guarantees progress
-      double gend = h + std::max(shrink, dt_min);
-      if (gend >= T * (1.0 - 1e-12)) gend = T;
-      rc = attempt(ctx, dir, h, gend, gend >= T, true, &v, &ts);
+      if (ctx->inject_chain >= 0) {  // the hook fires on one attempt only
+        ctx->inject_chain = -1;
+        rc = set_inject(ctx, -1, -1);
+        if (rc) return rc;
+      }
+      if (!violated) break;
+      if (++tries > (int64_t)1 << 20) {
+        ctx->err = "rollbacks exhausted";
+        return ECMC_EHANG;
+      }
+      if (first) ctx->legs_violated++;
+      first = false;
+      ctx->reruns++;
+      // every chain's pending lifting is at or after h, and so is t*
+      double R = std::max(std::min(tstar, clock), h);
+      if (ovf) {
+        // the undo records do not reach back far enough: the leg again from
+        // the breakpoint, in global-time order
+        rc = begin_leg(ctx, dir);
+        if (rc) return rc;
+        rc = attempt(ctx, dir, 0.0, T, true, true, 0.0, &v, &ts, &clk, &ovf);
+        if (rc) return rc;
+        ctx->global_legs++;
+        break;
+      }
+      stuck = (R <= last_R) ? stuck + 1 : 0;
+      last_R = std::max(last_R, R);
+      rc = rollback(ctx, R);
       if (rc) return rc;
-      ctx->global_legs++;
-      h = gend;
-      fails = 0;
+      h = R;
+      if (stuck >= ctx->max_splits) {
+        // The same race keeps coming back.  Run a stretch [h, gend] with a
+        // bounded lag far below the mean free time: liftings are then
+        // committed in global-time order up to near-ties, so the stretch
+        // completes unless two liftings fall within that lag of each other;
+        // then the stretch is finished in global-time order (Alg. 2).
+        double gend = h + gwin;
+        gwin *= 2.0;  // repeated stalls: longer stretches
+        if (gend >= T * (1.0 - 1e-12)) gend = T;
+        bool v2 = false, ovf2 = false;
+        double ts2 = INFINITY, clk2 = 0.0;
+        rc = attempt(ctx, dir, h, gend, gend >= T, false, LOCKSTEP_LAG * ctx->g.sigma, &v2, &ts2, &clk2,
+                     &ovf2);
+        if (rc) return rc;
+        ctx->lockstep_runs++;
+        if (v2) {
+          if (ovf2) continue;  // handled at the top of the loop on the next violation
+          const double R2 = std::max(std::min(ts2, clk2), h);
+          rc = rollback(ctx, R2);
+          if (rc) return rc;
+          h = R2;
+          rc = attempt(ctx, dir, h, gend, gend >= T, true, 0.0, &v, &ts, &clk, &ovf);
+          if (rc) return rc;
+          ctx->global_legs++;
+        }
+        if (gend >= T) break;
+        h = gend;
+        stuck = 0;
+        last_R = h;
+      }
     }
   }
-  ctx->sub_frac = frac;
+  k_chains_commit<<<blocks_for(D.k, 256), 256, 0, ctx->stream>>>(D);
+  HIPCHK(hipGetLastError());
   const int64_t S = (int64_t)ctx->g.nc * ctx->g.nc * CAP;
   k_writeback<<<blocks_for(S, 256), 256, 0, ctx->stream>>>(D, ctx->g, dir);
   HIPCHK(hipGetLastError());
@@ -1385,14 +1690,15 @@ int ecmc_init(ecmc_ctx **out, const double *positions_xy, int64_t n, double sigm
   D.GC_B = (double *)(b + Lo.off[20]);
   D.GC_SLOT = (int32_t *)(b + Lo.off[21]);
   D.ctl = (Ctl *)(b + Lo.off[22]);
-  D.MUT_SNAP = (MutRec *)(b + Lo.off[24]);
-  D.M32_SNAP = (flags & ECMC_FP32_MIXED) ? (float2 *)(b + Lo.off[25]) : nullptr;
-  D.EPOCH = (uint32_t *)(b + Lo.off[26]);
-  D.CH_SLOT_SNAP = (int32_t *)(b + Lo.off[27]);
+  D.RKEY = (unsigned long long *)(b + Lo.off[24]);
+  D.RKEY2 = (unsigned long long *)(b + Lo.off[25]);
+  D.UNDO = (UndoRec *)(b + Lo.off[26]);
+  D.UNDO_N = (long long *)(b + Lo.off[27]);
   D.CH_A = (double *)(b + Lo.off[28]);
   D.CH_T = (double *)(b + Lo.off[29]);
-  D.CH_A_SNAP = (double *)(b + Lo.off[30]);
-  D.CH_T_SNAP = (double *)(b + Lo.off[31]);
+  D.UNDO_N_OLD = (long long *)(b + Lo.off[30]);
+  D.undo_cap = UNDO_CAP;
+  D.NEXT = (double *)(b + Lo.off[32]);
   D.n = n;
   D.k = 0;
   D.log_cap = log_cap;
@@ -1406,7 +1712,8 @@ int ecmc_init(ecmc_ctx **out, const double *positions_xy, int64_t n, double sigm
       rc = ECMC_EDEVICE;
       break;
     }
-    if (fill<uint32_t>(ctx, D.EPOCH, 0u, (int64_t)nc * nc * CAP) != ECMC_OK) {
+    if (fill<unsigned long long>(ctx, D.RKEY, 0x7FF0000000000000ull, (int64_t)nc * nc * CAP) != ECMC_OK ||
+        fill<unsigned long long>(ctx, D.RKEY2, 0x7FF0000000000000ull, (int64_t)nc * nc * CAP) != ECMC_OK) {
       rc = ECMC_EDEVICE;
       break;
     }
@@ -1465,6 +1772,7 @@ int ecmc_set_active(ecmc_ctx *ctx, const int32_t *idx, int32_t k) {
   HIPCHK(hipStreamSynchronize(ctx->stream));
   ctx->active_set = true;
   ctx->legs = ctx->legs_violated = ctx->attempts = ctx->reruns = ctx->global_legs = 0;
+  ctx->lockstep_runs = 0;
   ctx->chain_time = 0.0;
   ctx->device_ms = 0.0;
   ctx->event_kernel_ms = 0.0;
@@ -1549,6 +1857,7 @@ int ecmc_stats(ecmc_ctx *ctx, ecmc_stats_t *out) {
   out->attempts = ctx->attempts;
   out->reruns = ctx->reruns;
   out->global_legs = ctx->global_legs;
+  out->lockstep_runs = ctx->lockstep_runs;
   out->overlaps = ctx->last_overlaps;
   out->sum_b = sum_b;
   out->chain_time = ctx->chain_time;
@@ -1558,6 +1867,14 @@ int ecmc_stats(ecmc_ctx *ctx, ecmc_stats_t *out) {
   out->event_launches = ctx->event_launches;
   out->timed_events = ctx->timed_events;
   out->timed_slots = ctx->timed_slots;
+  for (int q = 0; q < 4; ++q) out->violations_by_kind[q] = ctx->vkind[q];
+  out->last_violation_kind = ctx->last_v_kind;
+  out->last_violation_chain = ctx->last_v_chain;
+  out->last_violation_disk = ctx->last_v_id;
+  out->last_violation_t = ctx->last_v_t;
+  out->last_violation_tj = ctx->last_v_tj;
+  out->last_violation_tau = ctx->last_v_tau;
+  out->last_violation_h = ctx->last_v_h;
   return ECMC_OK;
 }
 
@@ -1681,6 +1998,10 @@ int ecmc_set_option(ecmc_ctx *ctx, int32_t key, int64_t value) {
       if (value < -1 || value >= (1 << 24)) return ECMC_EINVAL;
       ctx->inject_chain = (int32_t)value;
       return set_inject(ctx, ctx->inject_chain, ctx->inject_event);
+    case ECMC_OPT_WINDOW_MICRO:
+      if (value < 0 || value > (1ll << 50)) return ECMC_EINVAL;
+      ctx->window = (double)value * 1e-6 * ctx->g.sigma;
+      return ECMC_OK;
     case ECMC_OPT_STRICT_ORDER:
       if (value != 0 && value != 1) return ECMC_EINVAL;
       ctx->strict_order = (int32_t)value;

@@ -112,6 +112,27 @@ def test_many_chains_with_violations():
     print("violated legs", st["legs_violated"], "reruns", st["reruns"], "global", st["global_legs"])
 
 
+@pytest.mark.parametrize("window_micro", [50_000, 300_000])
+def test_bounded_lag_window_is_pure_scheduling(window_micro):
+    """The bounded-lag clock only delays commits: same liftings, same bits."""
+    s = W.config(1)
+    dirs = s.leg_dirs(3)
+    e = gpu_run(s.x, s.y, s.L, s.active, dirs, s.T, log_cap=1 << 14,
+                opts=((pkg.OPT_WINDOW_MICRO, window_micro),))
+    ref = oracle.run(s.x, s.y, 1.0, s.L, s.active, dirs, s.T)
+    st = check_parity(e, ref, s.L, s.k, f"window={window_micro}")
+    print("window", window_micro, "attempts", st["attempts"], "reruns", st["reruns"])
+
+
+def test_window_with_many_chains():
+    x, y, L, act = _square(161, 32, 0.70, 128)
+    T = 0.2 * L
+    dirs = [0, 1, 0, 1]
+    e = gpu_run(x, y, L, act, dirs, T, opts=((pkg.OPT_WINDOW_MICRO, 200_000),))
+    ref = oracle.run(x, y, 1.0, L, act, dirs, T)
+    check_parity(e, ref, L, 128, "window k=128")
+
+
 def test_contact_moves_keep_exact_arithmetic():
     """One failed claim on an active target is enough to publish a move up to
     contact: many moves, still the oracle's liftings and bits."""
