@@ -35,18 +35,22 @@ def _src_hash():
     return h.hexdigest()[:16]
 
 
-def _traffic(kernel_bytes_per_launch):
-    """HBM traffic per event-kernel launch from the committed rocprofv3 counter
-    summary, if it was taken on the current kernel source; else None."""
-    path = os.path.join(ROOT, "profiles", "event_kernel_N1048576_pmc.json")
+PMC_SUMMARY = os.path.join(ROOT, "profiles", "event_kernel_N1048576_pmc.json")
+
+
+def _traffic(events_per_launch):
+    """HBM bytes per event-kernel launch: the bytes per lifting measured by the
+    committed rocprofv3 counter summary (FETCH_SIZE + WRITE_SIZE, calibrated on
+    a copy of known size) times this run's liftings per launch.  None if the
+    summary is missing or was taken on another kernel source."""
     try:
-        with open(path) as f:
+        with open(PMC_SUMMARY) as f:
             d = json.load(f)
     except (OSError, ValueError):
         return None
-    if d.get("source_sha256_16") != _src_hash():
+    if d.get("source_sha256_16") != _src_hash() or not d.get("hbm_bytes_per_event"):
         return None
-    return d.get("hbm_bytes_per_launch")
+    return d["hbm_bytes_per_event"] * events_per_launch
 
 
 def cpu_baseline(seconds: float):
@@ -67,6 +71,12 @@ def cpu_baseline(seconds: float):
     return {"value": events / t_used, "unit": "events/s", "cores": 1, "kind": "oracle",
             "sample": f"first {legs} legs ({events} liftings) of the N=1048576 eta=0.708 k=1024 "
                       f"workload, serial C global-time event queue, 1 host thread"}
+
+
+def _stats_delta(st0, st1):
+    d = {k: st1[k] - st0[k] for k in st1 if isinstance(st1[k], (int, float))}
+    d["violations_by_kind"] = [b - a for a, b in zip(st0["violations_by_kind"], st1["violations_by_kind"])]
+    return d
 
 
 def run_form(form, steps, warmup, lanes, window_micro):
@@ -97,7 +107,7 @@ def run_form(form, steps, warmup, lanes, window_micro):
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     st1 = e.stats()
-    d = {k: st1[k] - st0[k] for k in st1 if isinstance(st1[k], (int, float))}
+    d = _stats_delta(st0, st1)
     wall = t1 - t0
     launches = max(d["event_launches"], 1)
     kbytes = (d["timed_slots"] * BYTES_PER_SLOT + d["timed_events"] * BYTES_PER_EVENT) / launches
@@ -107,11 +117,15 @@ def run_form(form, steps, warmup, lanes, window_micro):
     res = {
         "events": d["events"], "wall_s": wall, "events_per_s": d["events"] / wall,
         "legs": d["legs"], "legs_violated": d["legs_violated"], "reruns": d["reruns"],
-        "global_legs": d["global_legs"], "slots_per_event": d["slots_scanned"] / max(d["events"], 1),
+        "global_legs": d["global_legs"], "lockstep_runs": d["lockstep_runs"],
+        "violations_screened": d["violations_screened"], "claim_yields": d["claim_yields"],
+        "violations_by_kind": d["violations_by_kind"], "attempts": d["attempts"],
+        "slots_per_event": d["slots_scanned"] / max(d["events"], 1),
+        "events_per_launch": d["timed_events"] / launches,
         "kernel_ms_avg": kdur * 1e3, "kernel_bytes_per_launch": kbytes, "achieved_gbs": achieved,
         "kernel_time_frac": d["event_kernel_ms"] / 1e3 / wall, "overlaps": overlaps,
         "pressure_raw": 1.0 + d["sum_b"] / d["chain_time"] if d["chain_time"] else None,
-        "violation_rate_per_leg": d["legs_violated"] / max(d["legs"], 1),
+        "violation_probability_per_breakpoint": d["legs_violated"] / max(d["legs"], 1),
     }
     e.close()
     return res
@@ -130,10 +144,12 @@ def profile_run(legs, lanes, window_micro):
     e = pkg.Ecmc(np.stack([s.x, s.y], 1), s.sigma, s.L, max_chains=s.k, log_cap=1 << 12)
     e.set_option(pkg.OPT_LANES, lanes)
     e.set_option(pkg.OPT_WINDOW_MICRO, window_micro)
+    e.set_option(pkg.OPT_KERNEL_TIMING, 1)
     e.set_active(s.active)
     e.run(legs * s.T, s.T, pkg.DIR_ALTERNATE)
     st = e.stats()
     print(json.dumps({"profile_run": True, "events": st["events"], "attempts": st["attempts"],
+                      "event_launches": st["event_launches"], "timed_events": st["timed_events"],
                       "slots_scanned": st["slots_scanned"]}), flush=True)
     a = torch.ones(256 << 20, dtype=torch.uint8, device="cuda")
     b = torch.empty_like(a)
@@ -142,10 +158,50 @@ def profile_run(legs, lanes, window_micro):
     torch.cuda.synchronize()
 
 
+def _pmc_values(path, counter):
+    """Per-dispatch values of one counter from a rocprofv3 counter_collection
+    CSV: list of (kernel name, value)."""
+    import csv
+    out = []
+    with open(path, newline="") as f:
+        for row in csv.DictReader(f):
+            if row.get("Counter_Name") == counter:
+                out.append((row.get("Kernel_Name", ""), float(row["Counter_Value"])))
+    return out
+
+
+def pmc_summary(fetch_csv, write_csv, profile_log):
+    """Turn two counter runs of --profile-run (FETCH_SIZE, then WRITE_SIZE) into
+    the committed summary: bytes per event-kernel dispatch and per lifting,
+    each counter calibrated by its reading on the 256 MiB device copy."""
+    copy_bytes = 256 << 20
+    fe, wr = _pmc_values(fetch_csv, "FETCH_SIZE"), _pmc_values(write_csv, "WRITE_SIZE")
+    ev_f = [v for n, v in fe if "k_event" in n]
+    ev_w = [v for n, v in wr if "k_event" in n]
+    cp_f = max(v for n, v in fe if "copy" in n.lower() or "elementwise" in n.lower())
+    cp_w = max(v for n, v in wr if "copy" in n.lower() or "elementwise" in n.lower())
+    f_cal = copy_bytes / (cp_f * 1024.0)  # counters are in KiB
+    w_cal = copy_bytes / (cp_w * 1024.0)
+    with open(profile_log) as f:
+        run = next(json.loads(line) for line in f if line.startswith("{") and "profile_run" in line)
+    per_launch = (sum(ev_f) * 1024.0 * f_cal + sum(ev_w) * 1024.0 * w_cal) / max(len(ev_f), 1)
+    events_per_launch = run["timed_events"] / max(run["event_launches"], 1)
+    d = {"source_sha256_16": _src_hash(), "kernel": "k_event<64>", "dispatches": len(ev_f),
+         "fetch_kib_mean": sum(ev_f) / max(len(ev_f), 1), "write_kib_mean": sum(ev_w) / max(len(ev_w), 1),
+         "copy_fetch_kib": cp_f, "copy_write_kib": cp_w, "fetch_calibration": f_cal, "write_calibration": w_cal,
+         "hbm_bytes_per_launch": per_launch, "events_per_launch": events_per_launch,
+         "hbm_bytes_per_event": per_launch / events_per_launch if events_per_launch else None}
+    with open(PMC_SUMMARY, "w") as f:
+        json.dump(d, f, indent=1)
+    print(json.dumps(d))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--profile-run", type=int, default=0, metavar="LEGS",
                     help="only run LEGS legs and a 256 MiB copy (for rocprofv3 counters)")
+    ap.add_argument("--pmc-summary", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "PROFILE_LOG"),
+                    help="write the counter summary from two --profile-run counter runs")
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=60, help="timed legs")
     ap.add_argument("--warmup", type=int, default=4, help="untimed legs")
@@ -156,6 +212,9 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
+    if args.pmc_summary:
+        pmc_summary(*args.pmc_summary)
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(run with --gpus 1)", file=sys.stderr)
@@ -173,7 +232,7 @@ def main():
     r = results[main_form]
     kb = r["kernel_bytes_per_launch"]
     roof = {"bound": "hbm", "achieved": r["achieved_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": r["achieved_gbs"] / HBM_PEAK_GBS, "traffic": _traffic(kb),
+            "frac": r["achieved_gbs"] / HBM_PEAK_GBS, "traffic": _traffic(r["events_per_launch"]),
             "kernel": "k_event<64>", "bytes_per_launch": kb, "avg_launch_ms": r["kernel_ms_avg"]}
     line = {
         "metric": "ECMC events/sec on 1 GPU, N=2^20 disks η=0.708: FP32-mixed vs FP64 form",

@@ -125,6 +125,9 @@ typedef struct {
   double last_violation_tau;     /*   time of flight to that disk                */
   double last_violation_h;       /*   start of the attempt                       */
   int64_t lockstep_runs;         /* stall-breaking stretches with a tiny lag      */
+  int64_t violations_screened;   /* failed Eq. 2 checks on a lane minimum that the
+                                    activation record of its chain showed harmless */
+  int64_t claim_yields;          /* claims given back to an earlier reservation */
 } ecmc_stats_t;
 
 /* Bytes of device workspace for a context.  n disks of radius sigma in a box of

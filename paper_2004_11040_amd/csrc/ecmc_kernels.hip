@@ -61,11 +61,12 @@ constexpr uint32_t TAG_STALLED = 0xFFFFFFFEu;
 constexpr uint32_t TAG_PAUSED = 0xFFFFFFFDu;  // active, paused at the end of a stretch
 constexpr int CAP = 4;          // disks per cell (rigorous for cell width < 2 sqrt(2) sigma)
 constexpr int ROWS = 3;         // rows of cells covering the corridor |dp| < 2 sigma
-constexpr int NCNT = 6;         // per-chain counters
-enum { C_EVENTS = 0, C_CASFAIL, C_WAITS, C_MOVES, C_REFINES, C_SCANNED };
+constexpr int NCNT = 8;         // per-chain counters
+enum { C_EVENTS = 0, C_CASFAIL, C_WAITS, C_MOVES, C_REFINES, C_SCANNED, C_CLEARED, C_YIELDS };
+constexpr unsigned long long RES_EMPTY = ~0ull;  // no reservation on a slot
 constexpr double STOP_MARGIN = 1e-7;  // slack in the column lower bound (>> rounding)
 constexpr int64_t UNDO_CAP = 4096;     // undo records per chain and leg
-constexpr double LOCKSTEP_LAG = 1e-4;  // bounded lag (units of sigma) of a stall-breaking stretch
+constexpr double LOCKSTEP_LAG = 0.03;  // bounded lag (units of sigma) of a stall-breaking stretch
 
 struct MutRec {
   double a, t;
@@ -128,6 +129,8 @@ struct Dev {
   // rollback keys per slot (earliest undone claim of the slot)
   unsigned long long *RKEY, *RKEY2;
   double *NEXT;  // per chain: time of the event it is about to commit (+inf: done)
+  struct RefRec *REF;   // per chain: current activation
+  unsigned long long *RES;  // per slot: earliest (time, chain) that targets the disk
   Ctl *ctl;
   int64_t n;
   int32_t k;
@@ -153,6 +156,17 @@ struct UndoRec {
   double aj, tj;   // target's position and local time before the lifting
   double sumb;     // chain's sum of b before the lifting
   double pad;
+};
+
+// A chain's current activation, readable by the other chains: its disk's slot,
+// the position where the disk was at rest when the chain lifted to it, the
+// lifting time, and the time that rest began.  ver is -1 while the record is
+// being rewritten, else a count that grows with every rewrite (a reader takes
+// the fields only if it reads the same ver before and after them).
+struct RefRec {
+  long long ver;
+  int32_t slot, pad;
+  double a, t_act, t_rest;
 };
 
 // ------------------------------------------------------------------------
@@ -314,6 +328,7 @@ __global__ void k_chains_leg(Dev D, int64_t nslots) {
   D.CH_A[c] = D.MUT[s].a;
   D.CH_T[c] = D.MUT[s].t;
   D.UNDO_N[c] = 0;
+  D.REF[c].ver = -1;
   if (c == 0) D.ctl->undo_overflow = 0;
   for (int q = 0; q < NCNT; ++q) D.CNT_W[c * NCNT + q] = D.CNT_C[c * NCNT + q];
   D.SUMB_W[c] = D.SUMB_C[c];
@@ -399,6 +414,7 @@ __global__ void k_rb_reset(Dev D, Geo g, double R) {
     D.RKEY[u.sj] = 0x7FF0000000000000ull;
     D.RKEY2[u.sj] = 0x7FF0000000000000ull;
   }
+  D.REF[c].ver = -1;  // the activation may have been taken back
   // the chain's disk at R: a pause there
   const int s = D.CH_SLOT[c];
   MutRec r;
@@ -465,6 +481,60 @@ struct Cand {
   double tau[3], t[3], a[3], b[3], p[3];
   int id[3], slot[3];
 };
+
+// Reservation key of a lifting at time e by chain c: the binary32 time rounded
+// down, then the chain (so keys order as (time, chain) up to one binary32 ulp).
+__device__ __forceinline__ unsigned long long res_key(double e, int c) {
+  return ((unsigned long long)__float_as_uint(__double2float_rd(e)) << 32) | (unsigned)c;
+}
+
+// Screening of a lane minimum j whose recorded local time is later than the
+// moving disk's contact with it (Eq. 2 fails).  Along the velocity a disk's
+// position minus time never grows, so the moving disk (reference a, t) meets
+// j before time x exactly if j's record at any time <= x already lies within
+// reach; the recorded point is later than the contact, so that alone cannot
+// tell.  If j is active on another chain whose published activation shows j
+// at rest at a_ref during [t_rest, t_act] with t_rest <= e < t_act, j sat at
+// a_ref at time e (the candidate lifting time), and no contact happens before
+// e iff the contact with a_ref comes after e.  Returns true if that proves j
+// harmless; false (keep the violation) in every other case.  Lane 0 only.
+__device__ bool screen_clear(const Dev &D, const Geo &g, double a, double p, double t, double e, int slot_j,
+                             double p_j) {
+  const uint32_t tg = __hip_atomic_load(&D.TAG[slot_j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (tg >= (uint32_t)D.k) return false;  // at rest or at a breakpoint: history unknown
+  RefRec *r = &D.REF[tg];
+  const long long v1 = __hip_atomic_load(&r->ver, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  wait_mem();
+  const int rs = __hip_atomic_load(&r->slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  const double ra = ld_a(&r->a), rt = ld_a(&r->t_act), rr = ld_a(&r->t_rest);
+  wait_mem();
+  const long long v2 = __hip_atomic_load(&r->ver, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (v1 < 0 || v1 != v2 || rs != slot_j) return false;
+  if (!(rr <= e && e < rt)) return false;
+  double b, dp;
+  const double tau_ref = tof(a, p, ra, p_j, g, b, dp);
+  return t + tau_ref > e;
+}
+
+// Eq. 2 on the three lane minima with recorded times tr[]; non-target minima
+// that fail it are screened.  Returns the lane of a remaining violation, or
+// -1.  Lane 0 only (the others get the answer by broadcast).
+__device__ __forceinline__ int horizon_check(const Dev &D, const Geo &g, double a, double p, double t,
+                                             double trem, double e, const double (&gt)[3], const int (&gi)[3],
+                                             const int (&gsl)[3], const double (&gpj)[3],
+                                             const double (&tr)[3], int t_slot, int &cleared) {
+  int bad = -1;
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    if (gt[q] < trem && t + gt[q] < tr[q] && bad < 0) {
+      if (gsl[q] != t_slot && screen_clear(D, g, a, p, t, e, gsl[q], gpj[q]))
+        ++cleared;
+      else
+        bad = q;
+    }
+  }
+  return bad;
+}
 
 template <int G>
 __device__ __forceinline__ void flag_violation(const Dev &D, int c, double t, int lane, int kind = VK_SCAN,
@@ -554,6 +624,7 @@ __global__ void __launch_bounds__(256) k_event(Dev D, Geo g, LegP lp, int32_t wa
   double t_pub = ld_a(&D.MUT[s].t);  // published point
   double nxt_pub = -1.0;              // last next-event time published
   long long undo_n = D.UNDO_N[c];
+  long long ref_ver = D.REF[c].ver;  // version of this chain's published activation
   long long cnt[NCNT];
   for (int q = 0; q < NCNT; ++q) cnt[q] = D.CNT_W[c * NCNT + q];
   double sumb = D.SUMB_W[c];
@@ -698,9 +769,14 @@ __global__ void __launch_bounds__(256) k_event(Dev D, Geo g, LegP lp, int32_t wa
     // smallest next-event time of all chains.  While blocked, the disk
     // publishes the point of its free flight at the window's edge. ----
     const double e_next = tau < trem ? t + tau : tend;
-    if (lane == 0 && e_next != nxt_pub) {
-      st_a(&D.NEXT[c], e_next);
-      nxt_pub = e_next;
+    const unsigned long long mykey = res_key(e_next, c);
+    if (lane == 0) {
+      if (e_next != nxt_pub) {
+        st_a(&D.NEXT[c], e_next);
+        nxt_pub = e_next;
+      }
+      // reserve the target: a chain with a later lifting on it yields
+      if (tau < trem) atomicMin(&D.RES[ts], mykey);
     }
     if (lp.window > 0.0) {
       double hc = __shfl(hclk, 0, G);
@@ -746,15 +822,24 @@ __global__ void __launch_bounds__(256) k_event(Dev D, Geo g, LegP lp, int32_t wa
     int vid = -1;
 #pragma unroll
     for (int q = 0; q < 3; ++q)
-      if (gt[q] < trem && t + gt[q] < gtj[q]) {
-        viol = true;
-        vtj = gtj[q];
-        vta = gt[q];
-        vid = gi[q];
-      }
+      if (gt[q] < trem && t + gt[q] < gtj[q]) viol = true;
     if (viol) {
-      flag_violation<G>(D, c, t > h ? t : h, lane, VK_SCAN, vtj, vta, vid);
-      break;
+      int bad = -1, clr = 0;
+      if (lane == 0) bad = horizon_check(D, g, a, p, t, trem, e_next, gt, gi, gsl, gpj, gtj, ts, clr);
+      bad = __shfl(bad, 0, G);
+      cnt[C_CLEARED] += clr;
+      if (bad >= 0) {
+#pragma unroll
+        for (int q = 0; q < 3; ++q)
+          if (q == bad) {
+            vtj = gtj[q];
+            vta = gt[q];
+            vid = gi[q];
+          }
+        flag_violation<G>(D, c, t > h ? t : h, lane, VK_SCAN, vtj, vta, vid);
+        break;
+      }
+      viol = false;
     }
 
     // ---- no admissible lifting before the breakpoint: stall (statements
@@ -777,7 +862,11 @@ __global__ void __launch_bounds__(256) k_event(Dev D, Geo g, LegP lp, int32_t wa
     int won = 0;
     uint32_t old = TAG_STATIC;
     double aj2 = 0.0, tj2 = 0.0, tcls[3] = {0.0, 0.0, 0.0};
+    unsigned long long rk = RES_EMPTY;
     if (lane == 0) {
+      // the activation record is rewritten if the claim succeeds: mark it
+      // invalid first (the wait after the claim orders this store)
+      __hip_atomic_store(&D.REF[c].ver, -1ll, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       won = __hip_atomic_compare_exchange_strong(&D.TAG[ts], &old, (uint32_t)c, __ATOMIC_RELAXED,
                                                  __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
                 ? 1
@@ -790,6 +879,9 @@ __global__ void __launch_bounds__(256) k_event(Dev D, Geo g, LegP lp, int32_t wa
         tj2 = ld_a(&D.MUT[ts].t);
 #pragma unroll
         for (int q = 0; q < 3; ++q) tcls[q] = (gt[q] < trem) ? ld_a(&D.MUT[gsl[q]].t) : 0.0;
+        rk = __hip_atomic_load(&D.RES[ts], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      } else {
+        __hip_atomic_store(&D.REF[c].ver, ref_ver, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       }
     }
     won = __shfl(won, 0, G);
@@ -842,25 +934,61 @@ __global__ void __launch_bounds__(256) k_event(Dev D, Geo g, LegP lp, int32_t wa
     // statement 13: the target must not have moved (nor been stamped) since the scan
     if (aj2 != t_aj || tj2 != t_tj) {
       if (lane == 0) {
+        __hip_atomic_store(&D.REF[c].ver, ref_ver, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         strict_rel(lp.strict);
         st_rel(&D.TAG[ts], TAG_STATIC);  // statement 20
       }
       cnt[C_CASFAIL] += (lane == 0);
       continue;
     }
+    // another chain reserved the target for an earlier lifting and still has
+    // that lifting pending: give the target back and let it go first
+    rk = __shfl(rk, 0, G);
+    if (rk != RES_EMPTY && rk < mykey && (int)(rk & 0xffffffffu) != c) {
+      int live = 0;
+      if (lane == 0) {
+        const int o = (int)(rk & 0xffffffffu);
+        if (o < D.k) {
+          const double nx = ld_a(&D.NEXT[o]);
+          live = __float_as_uint(__double2float_rd(nx)) == (uint32_t)(rk >> 32);
+        }
+        if (live) {
+          __hip_atomic_store(&D.REF[c].ver, ref_ver, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          strict_rel(lp.strict);
+          st_rel(&D.TAG[ts], TAG_STATIC);
+        }
+      }
+      live = __shfl(live, 0, G);
+      if (live) {
+        cnt[C_YIELDS] += (lane == 0);
+        __builtin_amdgcn_s_sleep(4);
+        continue;
+      }
+    }
     // statement 5 again with local times read after the claim
 #pragma unroll
     for (int q = 0; q < 3; ++q)
-      if (gt[q] < trem && t + gt[q] < tcls[q]) {
-        viol = true;
-        vtj = tcls[q];
-        vta = gt[q];
-        vid = gi[q];
-      }
+      if (gt[q] < trem && t + gt[q] < tcls[q]) viol = true;
     if (viol) {
-      if (lane == 0) st_rel(&D.TAG[ts], TAG_STATIC);
-      flag_violation<G>(D, c, t > h ? t : h, lane, VK_CLAIM, vtj, vta, vid);
-      break;
+      int bad = -1, clr = 0;
+      if (lane == 0) bad = horizon_check(D, g, a, p, t, trem, t + tau, gt, gi, gsl, gpj, tcls, ts, clr);
+      bad = __shfl(bad, 0, G);
+      cnt[C_CLEARED] += clr;
+      if (bad >= 0) {
+        if (lane == 0) {
+          __hip_atomic_store(&D.REF[c].ver, ref_ver, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          st_rel(&D.TAG[ts], TAG_STATIC);
+        }
+#pragma unroll
+        for (int q = 0; q < 3; ++q)
+          if (q == bad) {
+            vtj = tcls[q];
+            vta = gt[q];
+            vid = gi[q];
+          }
+        flag_violation<G>(D, c, t > h ? t : h, lane, VK_CLAIM, vtj, vta, vid);
+        break;
+      }
     }
 
     // ---- statements 14-19: commit the lifting ----
@@ -882,9 +1010,15 @@ __global__ void __launch_bounds__(256) k_event(Dev D, Geo g, LegP lp, int32_t wa
       }
       st_a(&D.MUT[ts].t, tn);  // 14: t_j
       st_a(&D.MUT[s].t, tn);   // 15: t_i
+      __hip_atomic_store(&D.REF[c].slot, ts, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      st_a(&D.REF[c].a, aj2);
+      st_a(&D.REF[c].t_act, tn);
+      st_a(&D.REF[c].t_rest, tj2);
+      atomicCAS(&D.RES[ts], mykey, RES_EMPTY);  // the reservation is used
       fence_rel();
       strict_rel(lp.strict);
       st_a(&D.MUT[s].a, an);   // 16: x_i
+      __hip_atomic_store(&D.REF[c].ver, cnt[C_EVENTS] + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       if (D.M32) {
         const int cc = (s >> 2) % g.nc;
         __hip_atomic_store(&D.M32[s].x, (float)(an - cc * g.c), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -896,6 +1030,7 @@ __global__ void __launch_bounds__(256) k_event(Dev D, Geo g, LegP lp, int32_t wa
     ++loglen;
     ++undo_n;
     cnt[C_EVENTS] += 1;
+    ref_ver = cnt[C_EVENTS];
     sumb = sumb + t_b;
     s = ts;  // 19: continue with j
     a = aj2;
@@ -1324,8 +1459,9 @@ Layout make_layout(int64_t n, int32_t nc, int32_t kmax, int64_t log_cap, uint32_
       (int64_t)kmax * 8,      // 28 CH_A
       (int64_t)kmax * 8,      // 29 CH_T
       (int64_t)kmax * 8,      // 30 UNDO_N_OLD
-      0,                      // 31 (unused)
+      (int64_t)kmax * (int64_t)sizeof(RefRec),  // 31 REF
       (int64_t)kmax * 8,      // 32 NEXT
+      S * 8,                  // 33 RES
   };
   int64_t o = 0;
   int nsz = (int)(sizeof(sizes) / sizeof(sizes[0]));
@@ -1422,6 +1558,8 @@ int attempt(ecmc_ctx *ctx, int dir, double h, double tend, bool final, bool glob
   HIPCHK(hipGetLastError());
   k_chains_attempt<<<blocks_for(D.k, 256), 256, 0, ctx->stream>>>(D, h);
   HIPCHK(hipGetLastError());
+  int rc = fill<unsigned long long>(ctx, D.RES, RES_EMPTY, S);  // no reservations yet
+  if (rc) return rc;
   LegP lp;
   lp.dir = dir;
   lp.final = final ? 1 : 0;
@@ -1430,7 +1568,6 @@ int attempt(ecmc_ctx *ctx, int dir, double h, double tend, bool final, bool glob
   lp.strict = ctx->strict_order;
   lp.window = window;
   const bool timed = !global && ctx->kernel_timing && ctx->kevents_ok;
-  int rc;
   k_count_delta<<<1, 256, 0, ctx->stream>>>(D, 0);
   HIPCHK(hipGetLastError());
   if (global) {
@@ -1536,7 +1673,6 @@ int run_leg(ecmc_ctx *ctx, int dir, double T) {
   bool v, ovf;
   double ts, clk;
   double h = 0.0, last_R = -1.0;
-  double gwin = std::max(ctx->window > 0.0 ? 4.0 * ctx->window : 0.0, T / 256.0);
   int stuck = 0;
   int64_t tries = 0;
   bool first = true;
@@ -1582,30 +1718,44 @@ int run_leg(ecmc_ctx *ctx, int dir, double T) {
       h = R;
       if (stuck >= ctx->max_splits) {
         // The same race keeps coming back.  Run a stretch [h, gend] with a
-        // bounded lag far below the mean free time: liftings are then
-        // committed in global-time order up to near-ties, so the stretch
-        // completes unless two liftings fall within that lag of each other;
-        // then the stretch is finished in global-time order (Alg. 2).
-        double gend = h + gwin;
-        gwin *= 2.0;  // repeated stalls: longer stretches
-        if (gend >= T * (1.0 - 1e-12)) gend = T;
-        bool v2 = false, ovf2 = false;
-        double ts2 = INFINITY, clk2 = 0.0;
-        rc = attempt(ctx, dir, h, gend, gend >= T, false, LOCKSTEP_LAG * ctx->g.sigma, &v2, &ts2, &clk2,
-                     &ovf2);
-        if (rc) return rc;
-        ctx->lockstep_runs++;
-        if (v2) {
-          if (ovf2) continue;  // handled at the top of the loop on the next violation
+        // bounded lag well below the mean free time, dividing the lag by 8
+        // after each violation; liftings are then committed in global-time
+        // order except for near-ties.  Three failures: the stretch runs in
+        // global-time order (Alg. 2), which cannot violate.
+        const double gend = std::min(T, h + T / 64.0);
+        const bool fin = !(gend < T);
+        double lag = (ctx->window > 0.0 ? ctx->window : LOCKSTEP_LAG * ctx->g.sigma) / 4.0;
+        bool restarted = false;
+        for (int lvl = 0;; ++lvl) {
+          if (lvl == 3) {
+            rc = attempt(ctx, dir, h, fin ? T : gend, fin, true, 0.0, &v, &ts, &clk, &ovf);
+            if (rc) return rc;
+            ctx->global_legs++;
+            break;
+          }
+          bool v2 = false, ovf2 = false;
+          double ts2 = INFINITY, clk2 = 0.0;
+          rc = attempt(ctx, dir, h, fin ? T : gend, fin, false, lag, &v2, &ts2, &clk2, &ovf2);
+          if (rc) return rc;
+          ctx->lockstep_runs++;
+          if (!v2) break;
+          ctx->reruns++;
+          if (ovf2) {
+            rc = begin_leg(ctx, dir);
+            if (rc) return rc;
+            rc = attempt(ctx, dir, 0.0, T, true, true, 0.0, &v, &ts, &clk, &ovf);
+            if (rc) return rc;
+            ctx->global_legs++;
+            restarted = true;
+            break;
+          }
           const double R2 = std::max(std::min(ts2, clk2), h);
           rc = rollback(ctx, R2);
           if (rc) return rc;
           h = R2;
-          rc = attempt(ctx, dir, h, gend, gend >= T, true, 0.0, &v, &ts, &clk, &ovf);
-          if (rc) return rc;
-          ctx->global_legs++;
+          lag /= 8.0;
         }
-        if (gend >= T) break;
+        if (fin || restarted) break;
         h = gend;
         stuck = 0;
         last_R = h;
@@ -1699,6 +1849,8 @@ int ecmc_init(ecmc_ctx **out, const double *positions_xy, int64_t n, double sigm
   D.UNDO_N_OLD = (long long *)(b + Lo.off[30]);
   D.undo_cap = UNDO_CAP;
   D.NEXT = (double *)(b + Lo.off[32]);
+  D.REF = (RefRec *)(b + Lo.off[31]);
+  D.RES = (unsigned long long *)(b + Lo.off[33]);
   D.n = n;
   D.k = 0;
   D.log_cap = log_cap;
@@ -1850,6 +2002,8 @@ int ecmc_stats(ecmc_ctx *ctx, ecmc_stats_t *out) {
     out->contact_moves += cnt[(size_t)c * NCNT + C_MOVES];
     out->fp32_refines += cnt[(size_t)c * NCNT + C_REFINES];
     out->slots_scanned += cnt[(size_t)c * NCNT + C_SCANNED];
+    out->violations_screened += cnt[(size_t)c * NCNT + C_CLEARED];
+    out->claim_yields += cnt[(size_t)c * NCNT + C_YIELDS];
     sum_b += sb[(size_t)c];
   }
   out->legs = ctx->legs;
