@@ -21,11 +21,14 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0        # MI355X HBM3E, published
-# algorithmic bytes: per scanned cell slot 16 B fixed record (p, id) + 16 B
-# mutable record (a, t); per lifting: tag CAS 8 B, target re-read 16 B, lane
-# minima re-read 16 B, commit 24 B (t_j, t_i, a_i), tag release 4 B, log 4 B
+# Algorithmic bytes of the event kernel.  Per scanned cell slot: the fixed
+# record (p, id; 16 B) and the mutable record (a, t; 16 B).  Per lifting:
+# next-event time 8, reservation 8, activation-record invalidation 8, claim 4,
+# target re-read 16, lane-minima re-read 48, reservation read 8, undo record
+# 60, commit (t_j, t_i, a_i) 24, activation record 36, reservation release 8,
+# tag release 4, log 4: 236 B.
 BYTES_PER_SLOT = 32
-BYTES_PER_EVENT = 72
+BYTES_PER_EVENT = 236
 
 
 def _src_hash():

@@ -88,6 +88,24 @@ extern "C" {
                                      this of the smallest next-event time over
                                      all chains (0: chains run freely).  Pure
                                      scheduling: results do not depend on it.   */
+#define ECMC_OPT_FEATURES 10      /* bit set of the ECMC_FEAT_* refinements of the
+                                     horizon protocol that are switched on
+                                     (default ECMC_FEAT_ALL); each only avoids
+                                     needless rollbacks                         */
+
+/* ---- refinements of the horizon protocol (ECMC_OPT_FEATURES) ------------ */
+#define ECMC_FEAT_SCREEN 1u   /* a lane minimum that fails Eq. 2 but is active on
+                                 a chain whose activation record shows it at
+                                 rest until after the lifting is not a violation */
+#define ECMC_FEAT_RESERVE 2u  /* chains reserve their target; a claim for a
+                                 later lifting gives the target back           */
+#define ECMC_FEAT_REREAD 4u   /* a failure of Eq. 2 is confirmed on a record read
+                                 again after a pause (a disk being stopped shows
+                                 its new time with its old position for a moment) */
+#define ECMC_FEAT_FRESH 8u    /* after a claim, lane minima whose records changed
+                                 are checked on the new records (else the new
+                                 local time with the scanned position)         */
+#define ECMC_FEAT_ALL 15u
 
 typedef struct ecmc_ctx ecmc_ctx;
 

@@ -22,6 +22,8 @@ FP64, FP32_MIXED = 0, 1
 OPT_LANES, OPT_WAIT_RETRIES, OPT_MAX_SPLITS, OPT_FORCE_GLOBAL = 1, 2, 3, 4
 OPT_INJECT_CHAIN, OPT_INJECT_EVENT, OPT_KERNEL_TIMING, OPT_STRICT_ORDER = 5, 6, 7, 8
 OPT_WINDOW_MICRO = 9
+OPT_FEATURES = 10
+FEAT_SCREEN, FEAT_RESERVE, FEAT_REREAD, FEAT_FRESH, FEAT_ALL = 1, 2, 4, 8, 15
 DIR_X, DIR_Y, DIR_ALTERNATE = 0, 1, 4
 
 # every symbol the header declares

@@ -11,7 +11,6 @@
 //     CST[S]  {p, id, -}   16 B  perpendicular position and disk id (fixed for
 //                                the leg; id = -1 for an empty slot)
 //     TAG[S]  u32          STATIC, STALLED, or the chain that owns the disk
-//     M32[S]  {a-a0, p-p0} 8 B  binary32 cell-relative mirror (FP32-mixed form)
 //   per chain: slot of its disk, counters, sum of b, log ring, violation flag.
 //
 // During a leg a disk's record never leaves the slot of the cell it occupied at
@@ -102,6 +101,7 @@ struct Geo {
   double L, halfL, d, d2, sigma, c, inv_c;
   int32_t nc;
   int32_t mmax;  // largest column offset a scan may reach
+  float c32, L32, d2_32, sigma32;  // binary32 copies for the FP32-mixed filter
 };
 
 struct Dev {
@@ -110,7 +110,6 @@ struct Dev {
   MutRec *MUT;
   CstRec *CST;
   uint32_t *TAG;
-  float2 *M32;
   int32_t *CH_SLOT;
   long long *CNT_W, *CNT_C;  // working / committed counters [k][NCNT]
   double *SUMB_W, *SUMB_C;
@@ -144,6 +143,7 @@ struct LegP {
   double tend;     // end of this attempt
   int32_t strict;  // 1: add the formal agent-scope acquire/release fences
   double window;   // bounded lag: commit only events with time <= H + window (0: off)
+  int32_t features;  // ECMC_FEAT_* bits
 };
 
 // One committed lifting, as needed to take it back (restart from the earliest
@@ -279,7 +279,6 @@ __global__ void k_cellfill(Dev D, Geo g, int32_t dir) {
       ids[r - 1] = tmp;
     }
   int row = (int)(cell / g.nc), col = (int)(cell % g.nc);
-  double a0 = col * g.c, p0 = row * g.c;
   for (int q = 0; q < CAP; ++q) {
     int64_t s = cell * CAP + q;
     if (q < cnt) {
@@ -297,7 +296,6 @@ __global__ void k_cellfill(Dev D, Geo g, int32_t dir) {
       D.MUT[s] = mr;
       D.TAG[s] = TAG_STATIC;
       D.SLOT_OF[i] = (int32_t)s;
-      if (D.M32) D.M32[s] = make_float2((float)(a - a0), (float)(p - p0));
     } else {
       CstRec cr;
       cr.p = 0.0;
@@ -309,7 +307,6 @@ __global__ void k_cellfill(Dev D, Geo g, int32_t dir) {
       mr.t = 0.0;
       D.MUT[s] = mr;
       D.TAG[s] = TAG_STATIC;
-      if (D.M32) D.M32[s] = make_float2(0.f, 0.f);
     }
   }
 }
@@ -391,7 +388,6 @@ __global__ void k_rb_apply(Dev D, Geo g, double R) {
       r.t = u.tj;
       D.MUT[u.sj] = r;
       D.TAG[u.sj] = TAG_STATIC;
-      if (D.M32) D.M32[u.sj].x = (float)(u.aj - ((u.sj >> 2) % g.nc) * g.c);
     }
   }
   const long long nu = n - 1 - m;  // liftings taken back
@@ -422,7 +418,6 @@ __global__ void k_rb_reset(Dev D, Geo g, double R) {
   r.t = R;
   D.MUT[s] = r;
   D.TAG[s] = (uint32_t)c;
-  if (D.M32) D.M32[s].x = (float)(r.a - ((s >> 2) % g.nc) * g.c);
 }
 
 __global__ void k_ctl_reset(Dev D, double h) {
@@ -474,6 +469,71 @@ __device__ __forceinline__ int grp_owner(bool mine, int lane) {
   }
 }
 
+// FP32-mixed filter (systems pattern, not in the paper): the time of flight
+// from disk i to disk j in binary32 on cell-relative coordinates, as an
+// interval [lo, hi] that contains the binary64 value, and the lanes of the
+// corridor j may belong to.  Inputs: column and row offsets of j's home cell
+// from i's (mc >= 0, dr in {-1, 0, 1}), the offsets of i and j inside their
+// home cells (binary32 roundings of binary64 differences, |error| <= half an
+// ulp each).  Each binary32 operation adds at most half an ulp of its result;
+// the bounds below add those up with a factor-of-two margin.  A slot whose
+// interval cannot undercut a lane's current upper bound is never recomputed
+// in binary64; every other slot is (and decides the lane minima exactly).
+struct F32Cand {
+  float lo, hi;   // bounds on tau (lo = +inf: certainly outside the corridor)
+  int cls_mask;   // lanes j may be in (bit q)
+  int cls;        // the lane if certain, else -1
+};
+__device__ __forceinline__ F32Cand tof_f32(int mc, int dr, float rai, float rpi, float raj, float rpj,
+                                           const Geo &g) {
+  constexpr float U = 5.9604645e-8f;  // 2^-24, half an ulp of 1
+  F32Cand r;
+  r.lo = r.hi = INFINITY;
+  r.cls_mask = 0;
+  r.cls = -1;
+  // forward distance along v, reduced to [0, L) like the binary64 path
+  const float off = (float)mc * g.c32;
+  float da = (off + raj) - rai;
+  float eda = 4.f * U * (fabsf(off) + fabsf(raj) + fabsf(rai) + g.c32 * (float)mc);
+  bool wrap_unsure = false;
+  if (da < 0.f) {
+    wrap_unsure = da > -eda;  // could be a tiny positive distance
+    da = da + g.L32;
+    eda += 4.f * U * g.L32;
+  } else if (da >= g.L32) {
+    da = da - g.L32;
+    eda += 4.f * U * g.L32;
+  }
+  if (da < eda || da > g.L32 - eda) wrap_unsure = true;
+  // perpendicular offset (minimum image through the row offset)
+  const float dp = ((float)dr * g.c32 + rpj) - rpi;
+  const float edp = 4.f * U * (g.c32 + fabsf(rpj) + fabsf(rpi));
+  const float adp = fabsf(dp);
+  const float x = g.d2_32 - dp * dp;
+  const float ex = (2.f * adp + 2.f * edp) * edp + 4.f * U * (g.d2_32 + dp * dp);
+  if (!(x + ex > 0.f)) return r;  // certainly dp^2 >= d^2: outside the corridor
+  const float blo = sqrtf(fmaxf(x - ex, 0.f)) * (1.f - 4.f * U);
+  const float bhi = sqrtf(x + ex) * (1.f + 4.f * U);
+  const float err = eda + 8.f * U * (da + bhi) + 1e-30f;
+  r.lo = wrap_unsure ? 0.f : fmaxf((da - bhi) - err, 0.f);
+  r.hi = (x - ex > 0.f && !wrap_unsure) ? fmaxf((da - blo) + err, 0.f) + 1e-30f : INFINITY;
+  // lanes: |dp| < sigma -> 0, dp >= sigma -> 1, dp <= -sigma -> 2
+  const float es = edp + 4.f * U * g.sigma32;
+  if (adp + es < g.sigma32) {
+    r.cls_mask = 1;
+    r.cls = 0;
+  } else if (dp - es >= g.sigma32) {
+    r.cls_mask = 2;
+    r.cls = 1;
+  } else if (dp + es <= -g.sigma32) {
+    r.cls_mask = 4;
+    r.cls = 2;
+  } else {
+    r.cls_mask = dp > 0.f ? 3 : 5;
+  }
+  return r;
+}
+
 // Per-lane candidates: the nearest disk in each of the three lanes of the
 // corridor (the horizon set) with its record; the target is the smallest of
 // the three.
@@ -516,24 +576,51 @@ __device__ bool screen_clear(const Dev &D, const Geo &g, double a, double p, dou
   return t + tau_ref > e;
 }
 
-// Eq. 2 on the three lane minima with recorded times tr[]; non-target minima
-// that fail it are screened.  Returns the lane of a remaining violation, or
-// -1.  Lane 0 only (the others get the answer by broadcast).
+// Eq. 2 on the three lane minima (records ar[], tr[] as scanned); non-target
+// minima that fail it are screened.  A failure that screening does not explain
+// is read again after a short pause: a chain that moves a disk's record along
+// its trajectory writes the local time before the position, so a record read
+// in between pairs the new time with the old position and can fail Eq. 2
+// although the disk's trajectory does not.  Only that signature (same time,
+// new position) discards the first reading, and only if the completed record
+// passes; then the caller scans again (-2).  Any other failure is a violation
+// (a complete record that fails must be reported when it is seen: later the
+// disk may be out of reach and never checked again).  Returns the lane of the
+// violation, -2, or -1 if there is none.  Lane 0 only.
 __device__ __forceinline__ int horizon_check(const Dev &D, const Geo &g, double a, double p, double t,
-                                             double trem, double e, const double (&gt)[3], const int (&gi)[3],
-                                             const int (&gsl)[3], const double (&gpj)[3],
-                                             const double (&tr)[3], int t_slot, int &cleared) {
+                                             double trem, double e, const double (&gt)[3], const int (&gsl)[3],
+                                             const double (&gpj)[3], const double (&ar)[3],
+                                             const double (&tr)[3], int t_slot, int &cleared, int feat) {
   int bad = -1;
+  bool fail[3] = {false, false, false};
 #pragma unroll
   for (int q = 0; q < 3; ++q) {
-    if (gt[q] < trem && t + gt[q] < tr[q] && bad < 0) {
-      if (gsl[q] != t_slot && screen_clear(D, g, a, p, t, e, gsl[q], gpj[q]))
+    if (gt[q] < trem && t + gt[q] < tr[q]) {
+      if ((feat & ECMC_FEAT_SCREEN) && gsl[q] != t_slot && screen_clear(D, g, a, p, t, e, gsl[q], gpj[q])) {
         ++cleared;
-      else
-        bad = q;
+      } else {
+        fail[q] = true;
+        if (bad < 0) bad = q;
+      }
     }
   }
-  return bad;
+  if (bad < 0 || !(feat & ECMC_FEAT_REREAD)) return bad;
+  __builtin_amdgcn_s_sleep(32);  // ~1 us: longer than a commit's store completion
+  int real = -1;
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    if (fail[q] && real < 0) {
+      const double a2 = ld_a(&D.MUT[gsl[q]].a);
+      const double t2 = ld_a(&D.MUT[gsl[q]].t);
+      bool torn_ok = false;
+      if (t2 == tr[q] && a2 != ar[q]) {
+        double b2, dp2;
+        torn_ok = !(t + tof(a, p, a2, gpj[q], g, b2, dp2) < t2);
+      }
+      if (!torn_ok) real = q;
+    }
+  }
+  return real >= 0 ? real : -2;
 }
 
 template <int G>
@@ -604,7 +691,7 @@ __device__ void clock_loop(const Dev &D, long long iter_cap) {
 // itself, a move up to contact, or, at a breakpoint, the point reached there
 // (stall at h', or pause at an intermediate breakpoint: the disk then looks
 // exactly like a stalled one to the others, t = breakpoint).
-template <int G>
+template <int G, bool F32>
 __global__ void __launch_bounds__(256) k_event(Dev D, Geo g, LegP lp, int32_t wait_retries,
                                                long long iter_cap) {
   const int lane = threadIdx.x & (G - 1);
@@ -630,7 +717,7 @@ __global__ void __launch_bounds__(256) k_event(Dev D, Geo g, LegP lp, int32_t wa
   double sumb = D.SUMB_W[c];
   long long loglen = D.LOGLEN_W[c];
   const long long ev_start = cnt[C_EVENTS];
-  long long lane_scanned = 0;
+  long long lane_scanned = 0, lane_refined = 0;
   const int inj_ev = (D.ctl->inject_chain == c) ? D.ctl->inject_event : -1;
   int retries = 0;
   bool finished = false;
@@ -672,13 +759,24 @@ __global__ void __launch_bounds__(256) k_event(Dev D, Geo g, LegP lp, int32_t wa
       bl.id[q] = 0x7fffffff;
       bl.slot[q] = -1;
     }
-    double gt[3];
-    int gi[3];
+    double gt[3] = {INFINITY, INFINITY, INFINITY};
+    int gi[3] = {0x7fffffff, 0x7fffffff, 0x7fffffff};
     int scanned = 0;
+    // binary32 offsets of the moving disk inside its home cell (FP32-mixed)
+    const float rai = (float)u, rpi = (float)(p - row0 * g.c);
     for (int m0 = 0;; m0 += W::M) {
+      // the slots of this pass, loaded once (records are reread only after a claim)
+      CstRec crs[W::SPL];
+      double ajs[W::SPL], tjs[W::SPL];
+      int sls[W::SPL], mcs[W::SPL], drs[W::SPL];
 #pragma unroll
       for (int r = 0; r < W::SPL; ++r) {
         const int w = lane + r * G;
+        sls[r] = -1;
+        crs[r].id = -1;
+        crs[r].p = 0.0;
+        ajs[r] = tjs[r] = 0.0;
+        mcs[r] = drs[r] = 0;
         if (w < W::NS) {
           const int mc = m0 + w / (ROWS * CAP);
           const int rem = w % (ROWS * CAP);
@@ -688,30 +786,82 @@ __global__ void __launch_bounds__(256) k_event(Dev D, Geo g, LegP lp, int32_t wa
             int row = row0 + rem / CAP - 1;
             row = row < 0 ? row + g.nc : (row >= g.nc ? row - g.nc : row);
             const int sl = ((row * g.nc + col) << 2) + (rem % CAP);
-            const CstRec cr = D.CST[sl];
-            const double aj = ld_a(&D.MUT[sl].a);
-            const double tj = ld_a(&D.MUT[sl].t);
-            if (cr.id >= 0 && sl != s) {
-              ++scanned;
-              double b, dp;
-              const double tau = tof(a, p, aj, cr.p, g, b, dp);
-              // a disk that came to rest behind the moving disk before this
-              // attempt began (its stamp <= h) is not ahead of it
-              const bool behind = (t + tau < tj) && (tj <= h);
-              if (tau < INFINITY && !behind) {
-                const int cls = lane_class(dp, g);
+            sls[r] = sl;
+            mcs[r] = mc;
+            drs[r] = rem / CAP - 1;
+            crs[r] = D.CST[sl];
+            ajs[r] = ld_a(&D.MUT[sl].a);
+            tjs[r] = ld_a(&D.MUT[sl].t);
+          }
+        }
+      }
+      bool refine[W::SPL];
 #pragma unroll
-                for (int q = 0; q < 3; ++q) {  // unrolled: no dynamic indexing
-                  if (q == cls && key_less(tau, cr.id, bl.tau[q], bl.id[q])) {
-                    bl.tau[q] = tau;
-                    bl.id[q] = cr.id;
-                    bl.slot[q] = sl;
-                    bl.t[q] = tj;
-                    bl.a[q] = aj;
-                    bl.b[q] = b;
-                    bl.p[q] = cr.p;
-                  }
-                }
+      for (int r = 0; r < W::SPL; ++r) refine[r] = sls[r] >= 0 && crs[r].id >= 0 && sls[r] != s;
+      if constexpr (F32) {
+        // binary32 intervals; a lane's upper bound is the smallest upper end
+        // over slots certainly in that lane (and certainly not behind)
+        F32Cand fc[W::SPL];
+        float ub[3] = {INFINITY, INFINITY, INFINITY};
+#pragma unroll
+        for (int r = 0; r < W::SPL; ++r) {
+          fc[r].lo = fc[r].hi = INFINITY;
+          fc[r].cls_mask = 0;
+          fc[r].cls = -1;
+          if (refine[r]) {
+            const int col = (sls[r] >> 2) % g.nc;
+            const int row = (sls[r] >> 2) / g.nc;
+            const float raj = (float)(ajs[r] - col * g.c), rpj = (float)(crs[r].p - row * g.c);
+            fc[r] = tof_f32(mcs[r], drs[r], rai, rpi, raj, rpj, g);
+            const bool not_behind = (tjs[r] > h) || (t + (double)fc[r].lo >= tjs[r]);
+#pragma unroll
+            for (int q = 0; q < 3; ++q)
+              if (fc[r].cls == q && not_behind && fc[r].hi < ub[q]) ub[q] = fc[r].hi;
+          }
+        }
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+#pragma unroll
+          for (int off = G / 2; off > 0; off >>= 1) ub[q] = fminf(ub[q], __shfl_xor(ub[q], off, G));
+          const float ex = gt[q] < INFINITY ? (float)gt[q] * (1.f + 1e-6f) + 1e-6f : INFINITY;
+          ub[q] = fminf(ub[q], ex);  // exact minimum of the earlier passes, rounded up
+        }
+#pragma unroll
+        for (int r = 0; r < W::SPL; ++r) {
+          if (refine[r]) {
+            bool need = false;
+#pragma unroll
+            for (int q = 0; q < 3; ++q)
+              if (((fc[r].cls_mask >> q) & 1) && fc[r].lo <= ub[q]) need = true;
+            refine[r] = need;
+          }
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < W::SPL; ++r) {
+        if (sls[r] >= 0 && crs[r].id >= 0 && sls[r] != s) ++scanned;
+        if (refine[r]) {
+          const int sl = sls[r];
+          const CstRec cr = crs[r];
+          const double aj = ajs[r], tj = tjs[r];
+          if (F32) ++lane_refined;
+          double b, dp;
+          const double tau = tof(a, p, aj, cr.p, g, b, dp);
+          // a disk that came to rest behind the moving disk before this
+          // attempt began (its stamp <= h) is not ahead of it
+          const bool behind = (t + tau < tj) && (tj <= h);
+          if (tau < INFINITY && !behind) {
+            const int cls = lane_class(dp, g);
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {  // unrolled: no dynamic indexing
+              if (q == cls && key_less(tau, cr.id, bl.tau[q], bl.id[q])) {
+                bl.tau[q] = tau;
+                bl.id[q] = cr.id;
+                bl.slot[q] = sl;
+                bl.t[q] = tj;
+                bl.a[q] = aj;
+                bl.b[q] = b;
+                bl.p[q] = cr.p;
               }
             }
           }
@@ -776,7 +926,7 @@ __global__ void __launch_bounds__(256) k_event(Dev D, Geo g, LegP lp, int32_t wa
         nxt_pub = e_next;
       }
       // reserve the target: a chain with a later lifting on it yields
-      if (tau < trem) atomicMin(&D.RES[ts], mykey);
+      if (tau < trem && (lp.features & ECMC_FEAT_RESERVE)) atomicMin(&D.RES[ts], mykey);
     }
     if (lp.window > 0.0) {
       double hc = __shfl(hclk, 0, G);
@@ -825,9 +975,13 @@ __global__ void __launch_bounds__(256) k_event(Dev D, Geo g, LegP lp, int32_t wa
       if (gt[q] < trem && t + gt[q] < gtj[q]) viol = true;
     if (viol) {
       int bad = -1, clr = 0;
-      if (lane == 0) bad = horizon_check(D, g, a, p, t, trem, e_next, gt, gi, gsl, gpj, gtj, ts, clr);
+      if (lane == 0) bad = horizon_check(D, g, a, p, t, trem, e_next, gt, gsl, gpj, gaj, gtj, ts, clr, lp.features);
       bad = __shfl(bad, 0, G);
       cnt[C_CLEARED] += clr;
+      if (bad == -2) {  // a record was being rewritten: scan again
+        cnt[C_CASFAIL] += (lane == 0);
+        continue;
+      }
       if (bad >= 0) {
 #pragma unroll
         for (int q = 0; q < 3; ++q)
@@ -861,7 +1015,8 @@ __global__ void __launch_bounds__(256) k_event(Dev D, Geo g, LegP lp, int32_t wa
     // ---- statement 10: claim the target ----
     int won = 0;
     uint32_t old = TAG_STATIC;
-    double aj2 = 0.0, tj2 = 0.0, tcls[3] = {0.0, 0.0, 0.0};
+    double aj2 = 0.0, tj2 = 0.0;
+    int stale = 0;
     unsigned long long rk = RES_EMPTY;
     if (lane == 0) {
       // the activation record is rewritten if the claim succeeds: mark it
@@ -877,9 +1032,31 @@ __global__ void __launch_bounds__(256) k_event(Dev D, Geo g, LegP lp, int32_t wa
         // statement 13 (extended to the local time): reads issued after the claim completed
         aj2 = ld_a(&D.MUT[ts].a);
         tj2 = ld_a(&D.MUT[ts].t);
+        double acl[3], tcl[3];
 #pragma unroll
-        for (int q = 0; q < 3; ++q) tcls[q] = (gt[q] < trem) ? ld_a(&D.MUT[gsl[q]].t) : 0.0;
+        for (int q = 0; q < 3; ++q) {
+          acl[q] = (gt[q] < trem) ? ld_a(&D.MUT[gsl[q]].a) : 0.0;
+          tcl[q] = (gt[q] < trem) ? ld_a(&D.MUT[gsl[q]].t) : 0.0;
+        }
         rk = __hip_atomic_load(&D.RES[ts], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        // statement 5 again on records read after the claim: a lane minimum
+        // whose record changed must still pass Eq. 2 and stay behind the
+        // target, else the chain scans again
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+          if (gt[q] < trem && gsl[q] != ts && (acl[q] != gaj[q] || tcl[q] != gtj[q])) {
+            if (lp.features & ECMC_FEAT_FRESH) {
+              double b2, dp2;
+              const double tq = tof(a, p, acl[q], gpj[q], g, b2, dp2);
+              if (t + tq < tcl[q])
+                stale = 2;  // a record that fails Eq. 2: a violation
+              else if (key_less(tq, gi[q], tau, t_id) && stale == 0)
+                stale = 1;  // no longer behind the target: scan again
+            } else if (t + gt[q] < tcl[q]) {
+              stale = 2;  // the time read after the claim fails Eq. 2: a violation
+            }
+          }
+        }
       } else {
         __hip_atomic_store(&D.REF[c].ver, ref_ver, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       }
@@ -900,18 +1077,26 @@ __global__ void __launch_bounds__(256) k_event(Dev D, Geo g, LegP lp, int32_t wa
         retries = 0;
         const double tn = t + tau;  // within the window: checked above
         if (tn > t_pub) {
+          // publish only if every lane minimum still passes Eq. 2 on a
+          // fresh record (the point published is on this disk's trajectory
+          // either way; a failure is left to the next scan)
           int bad = 0;
           if (lane == 0) {
             fence_acq();
             strict_acq(lp.strict);
 #pragma unroll
-            for (int q = 0; q < 3; ++q)
-              if (gt[q] < trem && t + gt[q] < ld_a(&D.MUT[gsl[q]].t)) bad = 1;
+            for (int q = 0; q < 3; ++q) {
+              if (gt[q] < trem) {
+                const double aq = ld_a(&D.MUT[gsl[q]].a), tq = ld_a(&D.MUT[gsl[q]].t);
+                double b2, dp2;
+                if (t + tof(a, p, aq, gpj[q], g, b2, dp2) < tq) bad = 1;
+              }
+            }
           }
           bad = __shfl(bad, 0, G);
           if (bad) {
-            flag_violation<G>(D, c, t > h ? t : h, lane, VK_MOVE);
-            break;
+            __builtin_amdgcn_s_sleep(4);
+            continue;
           }
           const double an = fwd_move(a, tau, g);
           if (lane == 0) {
@@ -929,10 +1114,18 @@ __global__ void __launch_bounds__(256) k_event(Dev D, Geo g, LegP lp, int32_t wa
     }
     aj2 = __shfl(aj2, 0, G);
     tj2 = __shfl(tj2, 0, G);
-#pragma unroll
-    for (int q = 0; q < 3; ++q) tcls[q] = __shfl(tcls[q], 0, G);
-    // statement 13: the target must not have moved (nor been stamped) since the scan
-    if (aj2 != t_aj || tj2 != t_tj) {
+    stale = __shfl(stale, 0, G);
+    if (stale == 2) {
+      if (lane == 0) {
+        __hip_atomic_store(&D.REF[c].ver, ref_ver, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        st_rel(&D.TAG[ts], TAG_STATIC);
+      }
+      flag_violation<G>(D, c, t > h ? t : h, lane, VK_CLAIM, 0.0, tau, t_id);
+      break;
+    }
+    // statement 13: the target must not have moved (nor been stamped) since
+    // the scan, and no lane minimum may have moved into question
+    if (aj2 != t_aj || tj2 != t_tj || stale) {
       if (lane == 0) {
         __hip_atomic_store(&D.REF[c].ver, ref_ver, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         strict_rel(lp.strict);
@@ -944,7 +1137,7 @@ __global__ void __launch_bounds__(256) k_event(Dev D, Geo g, LegP lp, int32_t wa
     // another chain reserved the target for an earlier lifting and still has
     // that lifting pending: give the target back and let it go first
     rk = __shfl(rk, 0, G);
-    if (rk != RES_EMPTY && rk < mykey && (int)(rk & 0xffffffffu) != c) {
+    if ((lp.features & ECMC_FEAT_RESERVE) && rk != RES_EMPTY && rk < mykey && (int)(rk & 0xffffffffu) != c) {
       int live = 0;
       if (lane == 0) {
         const int o = (int)(rk & 0xffffffffu);
@@ -965,32 +1158,6 @@ __global__ void __launch_bounds__(256) k_event(Dev D, Geo g, LegP lp, int32_t wa
         continue;
       }
     }
-    // statement 5 again with local times read after the claim
-#pragma unroll
-    for (int q = 0; q < 3; ++q)
-      if (gt[q] < trem && t + gt[q] < tcls[q]) viol = true;
-    if (viol) {
-      int bad = -1, clr = 0;
-      if (lane == 0) bad = horizon_check(D, g, a, p, t, trem, t + tau, gt, gi, gsl, gpj, tcls, ts, clr);
-      bad = __shfl(bad, 0, G);
-      cnt[C_CLEARED] += clr;
-      if (bad >= 0) {
-        if (lane == 0) {
-          __hip_atomic_store(&D.REF[c].ver, ref_ver, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          st_rel(&D.TAG[ts], TAG_STATIC);
-        }
-#pragma unroll
-        for (int q = 0; q < 3; ++q)
-          if (q == bad) {
-            vtj = tcls[q];
-            vta = gt[q];
-            vid = gi[q];
-          }
-        flag_violation<G>(D, c, t > h ? t : h, lane, VK_CLAIM, vtj, vta, vid);
-        break;
-      }
-    }
-
     // ---- statements 14-19: commit the lifting ----
     const double tn = t + tau;
     const double an = fwd_move(a, tau, g);
@@ -1019,10 +1186,6 @@ __global__ void __launch_bounds__(256) k_event(Dev D, Geo g, LegP lp, int32_t wa
       strict_rel(lp.strict);
       st_a(&D.MUT[s].a, an);   // 16: x_i
       __hip_atomic_store(&D.REF[c].ver, cnt[C_EVENTS] + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      if (D.M32) {
-        const int cc = (s >> 2) % g.nc;
-        __hip_atomic_store(&D.M32[s].x, (float)(an - cc * g.c), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      }
       strict_rel(lp.strict);
       st_rel(&D.TAG[s], TAG_STATIC);  // 17: release i
       D.LOG[(int64_t)c * D.log_cap + (loglen % D.log_cap)] = t_id;
@@ -1040,15 +1203,19 @@ __global__ void __launch_bounds__(256) k_event(Dev D, Geo g, LegP lp, int32_t wa
     retries = 0;
   }
   // group-wide sum of per-lane scan counts
-  long long sc = lane_scanned;
+  long long sc = lane_scanned, rf = lane_refined;
 #pragma unroll
-  for (int off = G / 2; off > 0; off >>= 1) sc += __shfl_xor(sc, off, G);
+  for (int off = G / 2; off > 0; off >>= 1) {
+    sc += __shfl_xor(sc, off, G);
+    rf += __shfl_xor(rf, off, G);
+  }
   if (lane == 0) {
     // a chain stopped by an abort keeps its last next-event time: a lower
     // bound of every lifting it has still to make
     if (finished) st_a(&D.NEXT[c], INFINITY);
     atomicAdd(&D.ctl->done, 1);
     cnt[C_SCANNED] += sc;
+    cnt[C_REFINES] += rf;
     for (int q = 0; q < NCNT; ++q) D.CNT_W[c * NCNT + q] = cnt[q];
     D.SUMB_W[c] = sumb;
     D.LOGLEN_W[c] = loglen;
@@ -1251,7 +1418,6 @@ __global__ void __launch_bounds__(1024) k_global(Dev D, Geo g, LegP lp) {
       mi.t = tn;
       D.MUT[s] = mi;
       D.MUT[ts].t = tn;
-      if (D.M32) D.M32[s].x = (float)(an - ((s >> 2) % g.nc) * g.c);
       D.TAG[s] = TAG_STATIC;
       D.TAG[ts] = (uint32_t)w;
       const long long len = D.LOGLEN_W[w];
@@ -1380,6 +1546,7 @@ struct ecmc_ctx {
   bool active_set = false;
   int32_t kernel_timing = 0;
   int32_t strict_order = 0;
+  int32_t features = ECMC_FEAT_ALL;
   int64_t vkind[4] = {0, 0, 0, 0};
   int32_t last_v_kind = -1, last_v_chain = -1, last_v_id = -1;
   double last_v_t = 0.0, last_v_tj = 0.0, last_v_tau = 0.0, last_v_h = 0.0;
@@ -1437,7 +1604,7 @@ Layout make_layout(int64_t n, int32_t nc, int32_t kmax, int64_t log_cap, uint32_
       S * 16,                 // 6 MUT
       S * 16,                 // 7 CST
       S * 4,                  // 8 TAG
-      (flags & ECMC_FP32_MIXED) ? S * 8 : 0,  // 9 M32
+      0,                      // 9 (unused)
       (int64_t)kmax * 4,      // 10 CH_SLOT
       (int64_t)kmax * NCNT * 8,  // 11 CNT_W
       (int64_t)kmax * NCNT * 8,  // 12 CNT_C
@@ -1513,12 +1680,12 @@ int build_cells(ecmc_ctx *ctx, int dir) {
 
 // Every chain's group must be resident at once: a chain that never started
 // would keep its disk tagged active and others would wait on it.
-template <int G>
+template <int G, bool F32>
 int check_resident(ecmc_ctx *ctx, unsigned nb) {
   int dev = 0, ncu = 0, per_cu = 0;
   HIPCHK(hipGetDevice(&dev));
   HIPCHK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
-  HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_event<G>, 256, 0));
+  HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_event<G, F32>, 256, 0));
   if ((int64_t)per_cu * ncu < (int64_t)nb) {
     ctx->err = "too many chains for one resident launch at this lane count";
     return ECMC_EINVAL;
@@ -1533,15 +1700,30 @@ int launch_event(ecmc_ctx *ctx, LegP lp) {
   const int G = ctx->lanes;
   const int64_t threads = (int64_t)D.k * G;
   const unsigned nb = blocks_for(threads, 256) + (lp.window > 0.0 ? 1u : 0u);  // + clock
-  int rc = G == 64 ? check_resident<64>(ctx, nb)
-                   : (G == 32 ? check_resident<32>(ctx, nb) : check_resident<16>(ctx, nb));
-  if (rc) return rc;
-  if (G == 64)
-    k_event<64><<<nb, 256, 0, ctx->stream>>>(D, ctx->g, lp, ctx->wait_retries, cap);
-  else if (G == 32)
-    k_event<32><<<nb, 256, 0, ctx->stream>>>(D, ctx->g, lp, ctx->wait_retries, cap);
+  const bool f32 = (ctx->flags & ECMC_FP32_MIXED) != 0;
+  int rc;
+  if (f32)
+    rc = G == 64 ? check_resident<64, true>(ctx, nb)
+                 : (G == 32 ? check_resident<32, true>(ctx, nb) : check_resident<16, true>(ctx, nb));
   else
-    k_event<16><<<nb, 256, 0, ctx->stream>>>(D, ctx->g, lp, ctx->wait_retries, cap);
+    rc = G == 64 ? check_resident<64, false>(ctx, nb)
+                 : (G == 32 ? check_resident<32, false>(ctx, nb) : check_resident<16, false>(ctx, nb));
+  if (rc) return rc;
+  if (f32) {
+    if (G == 64)
+      k_event<64, true><<<nb, 256, 0, ctx->stream>>>(D, ctx->g, lp, ctx->wait_retries, cap);
+    else if (G == 32)
+      k_event<32, true><<<nb, 256, 0, ctx->stream>>>(D, ctx->g, lp, ctx->wait_retries, cap);
+    else
+      k_event<16, true><<<nb, 256, 0, ctx->stream>>>(D, ctx->g, lp, ctx->wait_retries, cap);
+  } else {
+    if (G == 64)
+      k_event<64, false><<<nb, 256, 0, ctx->stream>>>(D, ctx->g, lp, ctx->wait_retries, cap);
+    else if (G == 32)
+      k_event<32, false><<<nb, 256, 0, ctx->stream>>>(D, ctx->g, lp, ctx->wait_retries, cap);
+    else
+      k_event<16, false><<<nb, 256, 0, ctx->stream>>>(D, ctx->g, lp, ctx->wait_retries, cap);
+  }
   HIPCHK(hipGetLastError());
   return ECMC_OK;
 }
@@ -1566,6 +1748,7 @@ int attempt(ecmc_ctx *ctx, int dir, double h, double tend, bool final, bool glob
   lp.h = h;
   lp.tend = tend;
   lp.strict = ctx->strict_order;
+  lp.features = ctx->features;
   lp.window = window;
   const bool timed = !global && ctx->kernel_timing && ctx->kevents_ok;
   k_count_delta<<<1, 256, 0, ctx->stream>>>(D, 0);
@@ -1814,6 +1997,10 @@ int ecmc_init(ecmc_ctx **out, const double *positions_xy, int64_t n, double sigm
   g.c = box / (double)nc;
   g.inv_c = 1.0 / g.c;
   g.mmax = nc - 3;
+  g.c32 = (float)g.c;
+  g.L32 = (float)box;
+  g.d2_32 = (float)g.d2;
+  g.sigma32 = (float)sigma;
   Layout Lo = make_layout(n, nc, max_chains, log_cap, flags);
   char *b = (char *)workspace;
   Dev &D = ctx->D;
@@ -1826,7 +2013,6 @@ int ecmc_init(ecmc_ctx **out, const double *positions_xy, int64_t n, double sigm
   D.MUT = (MutRec *)(b + Lo.off[6]);
   D.CST = (CstRec *)(b + Lo.off[7]);
   D.TAG = (uint32_t *)(b + Lo.off[8]);
-  D.M32 = (flags & ECMC_FP32_MIXED) ? (float2 *)(b + Lo.off[9]) : nullptr;
   D.CH_SLOT = (int32_t *)(b + Lo.off[10]);
   D.CNT_W = (long long *)(b + Lo.off[11]);
   D.CNT_C = (long long *)(b + Lo.off[12]);
@@ -2155,6 +2341,10 @@ int ecmc_set_option(ecmc_ctx *ctx, int32_t key, int64_t value) {
     case ECMC_OPT_WINDOW_MICRO:
       if (value < 0 || value > (1ll << 50)) return ECMC_EINVAL;
       ctx->window = (double)value * 1e-6 * ctx->g.sigma;
+      return ECMC_OK;
+    case ECMC_OPT_FEATURES:
+      if (value < 0 || value > ECMC_FEAT_ALL) return ECMC_EINVAL;
+      ctx->features = (int32_t)value;
       return ECMC_OK;
     case ECMC_OPT_STRICT_ORDER:
       if (value != 0 && value != 1) return ECMC_EINVAL;

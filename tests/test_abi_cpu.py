@@ -36,8 +36,8 @@ def test_workspace_bytes_host_only():
     # grows with chains and log capacity
     assert pkg.workspace_bytes(n, 1.0, L, 0, 128, 1024) > b
     assert pkg.workspace_bytes(n, 1.0, L, 0, 64, 4096) > b
-    # FP32 mirror adds 8 bytes per slot
-    assert pkg.workspace_bytes(n, 1.0, L, 0, 64, 1024, pkg.FP32_MIXED) > b
+    # the FP32-mixed form filters in registers: same workspace
+    assert pkg.workspace_bytes(n, 1.0, L, 0, 64, 1024, pkg.FP32_MIXED) == b
 
 
 @pytest.mark.parametrize("args", [

@@ -259,3 +259,70 @@ def test_invalid_arguments():
         e.run(1.0, 1.0, 2)                      # -x is not offered
     e.run(0.0, 1.0, 0)                          # zero legs is a no-op
     assert e.stats()["events"] == 0
+
+
+# ---------------------------------------------------------------------------
+# FP32-mixed form: binary32 filter, binary64 decisions -> identical results
+@pytest.mark.parametrize("lanes", [64, 32, 16])
+def test_fp32_mixed_small_parity(lanes):
+    s = W.config(0)
+    dirs = [0] * 10
+    e = gpu_run(s.x, s.y, s.L, s.active, dirs, s.T, lanes=lanes, flags=pkg.FP32_MIXED)
+    ref = oracle.run(s.x, s.y, 1.0, s.L, s.active, dirs, s.T)
+    st = check_parity(e, ref, s.L, s.k, f"fp32 lanes={lanes}")
+    assert 0 < st["fp32_refines"] < st["slots_scanned"]
+
+
+@pytest.mark.parametrize("seed,n_side,eta,k,tfrac", [
+    (201, 8, 0.50, 1, 0.25),
+    (203, 12, 0.70, 12, 0.20),
+    (205, 9, 0.40, 5, 0.20),
+])
+def test_fp32_mixed_alternating_parity(seed, n_side, eta, k, tfrac):
+    x, y, L, act = _square(seed, n_side, eta, k)
+    T = tfrac * L
+    dirs = [0, 1] * 4
+    e = gpu_run(x, y, L, act, dirs, T, flags=pkg.FP32_MIXED)
+    ref = oracle.run(x, y, 1.0, L, act, dirs, T)
+    check_parity(e, ref, L, k, f"fp32 seed={seed}")
+
+
+def test_fp32_mixed_many_chains_with_violations():
+    x, y, L, act = _square(111, 32, 0.70, 128)
+    T = 0.2 * L
+    dirs = [0, 1, 0, 1]
+    e = gpu_run(x, y, L, act, dirs, T, flags=pkg.FP32_MIXED,
+                opts=((pkg.OPT_WINDOW_MICRO, 200_000),))
+    ref = oracle.run(x, y, 1.0, L, act, dirs, T)
+    check_parity(e, ref, L, 128, "fp32 k=128")
+
+
+def test_fp32_mixed_mid_size_parity():
+    s = W.config(1)
+    dirs = s.leg_dirs(4)
+    e = gpu_run(s.x, s.y, s.L, s.active, dirs, s.T, log_cap=1 << 14, flags=pkg.FP32_MIXED,
+                opts=((pkg.OPT_WINDOW_MICRO, 300_000),))
+    ref = oracle.run(s.x, s.y, 1.0, s.L, s.active, dirs, s.T)
+    check_parity(e, ref, s.L, s.k, "fp32 cfg1")
+    assert e.overlaps() == 0
+
+
+def test_fp32_mixed_headline_size_first_leg():
+    s = W.config(4)
+    e = gpu_run(s.x, s.y, s.L, s.active, [0], s.T, log_cap=1 << 10, flags=pkg.FP32_MIXED,
+                opts=((pkg.OPT_WINDOW_MICRO, 300_000),))
+    ref = oracle.run(s.x, s.y, 1.0, s.L, s.active, [0], s.T, log_cap=1 << 21)
+    check_parity(e, ref, s.L, s.k, "fp32 cfg4-leg0")
+
+
+@pytest.mark.parametrize("features", [0, 1, 2, 4, 8])
+def test_protocol_refinements_are_scheduling_only(features):
+    """Each refinement of the horizon protocol switched on alone (and none):
+    violations, rollbacks and liftings must still match the oracle."""
+    x, y, L, act = _square(161, 32, 0.70, 128)
+    T = 0.2 * L
+    dirs = [0, 1, 0, 1]
+    e = gpu_run(x, y, L, act, dirs, T, opts=((pkg.OPT_FEATURES, features),
+                                             (pkg.OPT_WINDOW_MICRO, 200_000)))
+    ref = oracle.run(x, y, 1.0, L, act, dirs, T)
+    check_parity(e, ref, L, 128, f"features={features}")
