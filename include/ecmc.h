@@ -106,6 +106,9 @@ extern "C" {
                                  are checked on the new records (else the new
                                  local time with the scanned position)         */
 #define ECMC_FEAT_ALL 15u
+#define ECMC_OPT_GRAPH 11         /* batches: 1 captures the persistent launch
+                                     in a hipGraph once per lane count and
+                                     replays it (default 0)                     */
 
 typedef struct ecmc_ctx ecmc_ctx;
 
@@ -230,6 +233,69 @@ const char *ecmc_last_error(const ecmc_ctx *ctx);
 /* Release the context (host memory only; the workspace stays the caller's).
  * Accepts NULL. */
 void ecmc_free(ecmc_ctx *ctx);
+
+/* ---- batched replicas -----------------------------------------------------
+ * Many independent systems ("replicas"), each a context set up as usual
+ * (ecmc_init, ecmc_set_active), run together in ONE persistent launch: a
+ * workgroup takes a replica from a device queue and runs its legs, with the
+ * breakpoint synchronisation, rollbacks (Sec. 3.4, strategy 2) and the
+ * global-order fallback (Alg. 2) done on the device; its chains share the
+ * workgroup's compute unit, so their shared fields need workgroup-scope
+ * atomics only.  Results are read per replica with the per-context calls
+ * (ecmc_stats, ecmc_get_positions, ecmc_get_log, ...), and are identical to
+ * running each context with ecmc_run and no bounded lag.
+ * Requirements: all contexts on one stream, all FP64 or all FP32-mixed,
+ * k * lanes <= 512 for the lane count used. */
+typedef struct ecmc_batch ecmc_batch;
+
+typedef struct {
+  int32_t lanes;        /* lanes per chain of the last run                  */
+  int32_t graph;        /* 1 if the last run replayed a captured hipGraph   */
+  int32_t workgroups;   /* persistent grid of the last launch             */
+  int32_t pad_;
+  double device_ms;     /* duration of the last run's main launch (HIP events) */
+  int64_t events;       /* liftings committed by the main launch, all replicas */
+  int64_t legs;         /* legs run by the last call, all replicas         */
+  int64_t rollbacks;    /* rollbacks in the last call, all replicas        */
+  int64_t global_runs;  /* global-order stretches in the last call         */
+  double tune_events_per_ms[4]; /* autotuner: liftings per ms with 4, 8, 16,
+                                   32 lanes per chain (0: not tried)      */
+} ecmc_batch_info_t;
+
+/* Bytes of device scratch for a batch of n_ctx contexts (descriptors and the
+ * work queue).  Negative ECMC_EINVAL for n_ctx outside [1, 2^20]. */
+int64_t ecmc_batch_scratch_bytes(int32_t n_ctx);
+
+/* Group n_ctx distinct contexts (HOST array of handles; the contexts must
+ * outlive the batch) with a DEVICE scratch buffer of at least
+ * ecmc_batch_scratch_bytes(n_ctx) bytes, 256-byte aligned, owned by the
+ * caller.  Errors: ECMC_EINVAL (sizes, duplicates, mixed streams or forms),
+ * ECMC_ESTATE (a context without an active set). */
+int ecmc_batch_create(ecmc_batch **out, ecmc_ctx *const *ctxs, int32_t n_ctx,
+                      void *scratch, int64_t scratch_bytes);
+
+/* ECMC_OPT_LANES (0: autotune at the first run; 4, 8, 16, 32),
+ * ECMC_OPT_GRAPH, ECMC_OPT_FEATURES, ECMC_OPT_WAIT_RETRIES. */
+int ecmc_batch_set_option(ecmc_batch *b, int32_t key, int64_t value);
+
+/* Run every replica r with legs of length leg_T[r] (HOST arrays of n_ctx)
+ * until its committed liftings reach target_events[r], or for at most
+ * max_legs legs in this call (0: no limit).  direction as for ecmc_run,
+ * continuing each context's alternation.  With lanes 0 the autotuner first
+ * runs one leg per replica with each admissible lane count (those legs count)
+ * and keeps the fastest.  Synchronises the stream.  Errors: ECMC_EINVAL,
+ * ECMC_ECELL, ECMC_EHANG, ECMC_EDEVICE. */
+int ecmc_batch_run(ecmc_batch *b, const int64_t *target_events,
+                   const double *leg_T, int32_t direction, int32_t max_legs);
+
+/* Details of the last ecmc_batch_run. */
+int ecmc_batch_info(const ecmc_batch *b, ecmc_batch_info_t *out);
+
+/* Static description of the last error of the batch (never NULL). */
+const char *ecmc_batch_last_error(const ecmc_batch *b);
+
+/* Release the batch (host memory and the captured graph).  Accepts NULL. */
+void ecmc_batch_free(ecmc_batch *b);
 
 #ifdef __cplusplus
 }

@@ -23,6 +23,7 @@ OPT_LANES, OPT_WAIT_RETRIES, OPT_MAX_SPLITS, OPT_FORCE_GLOBAL = 1, 2, 3, 4
 OPT_INJECT_CHAIN, OPT_INJECT_EVENT, OPT_KERNEL_TIMING, OPT_STRICT_ORDER = 5, 6, 7, 8
 OPT_WINDOW_MICRO = 9
 OPT_FEATURES = 10
+OPT_GRAPH = 11
 FEAT_SCREEN, FEAT_RESERVE, FEAT_REREAD, FEAT_FRESH, FEAT_ALL = 1, 2, 4, 8, 15
 DIR_X, DIR_Y, DIR_ALTERNATE = 0, 1, 4
 
@@ -31,6 +32,8 @@ EXPORTS = (
     "ecmc_workspace_bytes", "ecmc_init", "ecmc_set_active", "ecmc_run", "ecmc_stats",
     "ecmc_get_positions", "ecmc_get_stamps", "ecmc_get_active", "ecmc_get_chain_sums",
     "ecmc_get_log", "ecmc_overlaps", "ecmc_set_option", "ecmc_last_error", "ecmc_free",
+    "ecmc_batch_scratch_bytes", "ecmc_batch_create", "ecmc_batch_set_option", "ecmc_batch_run",
+    "ecmc_batch_info", "ecmc_batch_last_error", "ecmc_batch_free",
 )
 
 
@@ -57,6 +60,18 @@ class Stats(ctypes.Structure):
     def as_dict(self):
         d = {n: getattr(self, n) for n, _ in self._fields_ if n != "pad_"}
         d["violations_by_kind"] = list(self.violations_by_kind)
+        return d
+
+
+class BatchInfo(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int32) for n in ("lanes", "graph", "workgroups", "pad_")] + [
+        ("device_ms", ctypes.c_double)] + [
+        (n, ctypes.c_int64) for n in ("events", "legs", "rollbacks", "global_runs")] + [
+        ("tune_events_per_ms", ctypes.c_double * 4)]
+
+    def as_dict(self):
+        d = {n: getattr(self, n) for n, _ in self._fields_ if n != "pad_"}
+        d["tune_events_per_ms"] = list(self.tune_events_per_ms)
         return d
 
 
@@ -97,6 +112,20 @@ def load_library(path: str = LIB_PATH):
     lib.ecmc_last_error.argtypes = [P]
     lib.ecmc_free.restype = None
     lib.ecmc_free.argtypes = [P]
+    lib.ecmc_batch_scratch_bytes.restype = I64
+    lib.ecmc_batch_scratch_bytes.argtypes = [I32]
+    lib.ecmc_batch_create.restype = ctypes.c_int
+    lib.ecmc_batch_create.argtypes = [ctypes.POINTER(P), P, I32, P, I64]
+    lib.ecmc_batch_set_option.restype = ctypes.c_int
+    lib.ecmc_batch_set_option.argtypes = [P, I32, I64]
+    lib.ecmc_batch_run.restype = ctypes.c_int
+    lib.ecmc_batch_run.argtypes = [P, P, P, I32, I32]
+    lib.ecmc_batch_info.restype = ctypes.c_int
+    lib.ecmc_batch_info.argtypes = [P, ctypes.POINTER(BatchInfo)]
+    lib.ecmc_batch_last_error.restype = ctypes.c_char_p
+    lib.ecmc_batch_last_error.argtypes = [P]
+    lib.ecmc_batch_free.restype = None
+    lib.ecmc_batch_free.argtypes = [P]
     _lib = lib
     return lib
 
@@ -228,3 +257,56 @@ class Ecmc:
         c = ctypes.c_int64(0)
         self._check(self.lib.ecmc_overlaps(self._ctx, ctypes.byref(c)))
         return int(c.value)
+
+
+class Batch:
+    """Independent replicas (each an Ecmc with its active set) run together
+    in one persistent launch; results are read from the Ecmc objects."""
+
+    def __init__(self, systems, device="cuda"):
+        import torch
+        self.lib = load_library()
+        self.systems = list(systems)
+        n = len(self.systems)
+        nbytes = int(self.lib.ecmc_batch_scratch_bytes(n))
+        if nbytes < 0:
+            raise EcmcError(nbytes, "invalid batch size")
+        self.scratch = torch.empty(nbytes, dtype=torch.uint8, device=device)
+        handles = (ctypes.c_void_p * n)(*[e._ctx.value for e in self.systems])
+        self._b = ctypes.c_void_p()
+        rc = self.lib.ecmc_batch_create(ctypes.byref(self._b), handles, n,
+                                        ctypes.c_void_p(self.scratch.data_ptr()), nbytes)
+        if rc != OK:
+            raise EcmcError(rc, "ecmc_batch_create failed")
+
+    def _check(self, rc):
+        if rc != OK:
+            msg = self.lib.ecmc_batch_last_error(self._b)
+            raise EcmcError(rc, msg.decode() if msg else "")
+
+    def set_option(self, key, value):
+        self._check(self.lib.ecmc_batch_set_option(self._b, int(key), int(value)))
+
+    def run(self, target_events, leg_T, direction=DIR_ALTERNATE, max_legs=0):
+        tg = np.ascontiguousarray(target_events, dtype=np.int64)
+        lt = np.ascontiguousarray(leg_T, dtype=np.float64)
+        if tg.shape[0] != len(self.systems) or lt.shape[0] != len(self.systems):
+            raise ValueError("one target and one leg length per replica")
+        self._check(self.lib.ecmc_batch_run(self._b, _np_ptr(tg), _np_ptr(lt), int(direction),
+                                            int(max_legs)))
+
+    def info(self) -> dict:
+        s = BatchInfo()
+        self._check(self.lib.ecmc_batch_info(self._b, ctypes.byref(s)))
+        return s.as_dict()
+
+    def close(self):
+        if getattr(self, "_b", None) and self._b.value:
+            self.lib.ecmc_batch_free(self._b)
+            self._b = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

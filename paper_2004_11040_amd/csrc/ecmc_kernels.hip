@@ -170,30 +170,49 @@ struct RefRec {
 };
 
 // ------------------------------------------------------------------------
-// agent-scope atomic helpers
+// Atomic helpers.  SC is the memory scope of the fields that chains share:
+// the whole device (one box spread over the chip) or one workgroup (a replica
+// whose chains all run in one workgroup, on one CU).
 // ------------------------------------------------------------------------
+constexpr int SCA = __HIP_MEMORY_SCOPE_AGENT;
+constexpr int SCW = __HIP_MEMORY_SCOPE_WORKGROUP;
+template <int SC = SCA>
 __device__ __forceinline__ double ld_a(const double *p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, SC);
 }
+template <int SC = SCA>
 __device__ __forceinline__ void st_a(double *p, double v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, SC);
 }
 // wait until every memory operation this wave issued has completed
 // (s_waitcnt vmcnt(0); expcnt and lgkmcnt left at their maximum)
 __device__ __forceinline__ void wait_mem() { __builtin_amdgcn_s_waitcnt(0x0F70); }
 // publish: earlier stores complete before the tag store is issued
+template <int SC = SCA>
 __device__ __forceinline__ void st_rel(uint32_t *p, uint32_t v) {
   wait_mem();
-  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, SC);
 }
 __device__ __forceinline__ void fence_rel() { wait_mem(); }
 __device__ __forceinline__ void fence_acq() { wait_mem(); }
-// validation mode: the formal agent-scope fences on top of the waits
+// validation mode: the formal release/acquire fences on top of the waits
+template <int SC = SCA>
 __device__ __forceinline__ void strict_rel(int on) {
-  if (on) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  if (on) {
+    if constexpr (SC == SCW)
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    else
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  }
 }
+template <int SC = SCA>
 __device__ __forceinline__ void strict_acq(int on) {
-  if (on) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  if (on) {
+    if constexpr (SC == SCW)
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    else
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  }
 }
 
 // ------------------------------------------------------------------------
@@ -245,9 +264,7 @@ __global__ void k_fill(T *p, T v, int64_t n) {
 // ------------------------------------------------------------------------
 // a1: home-cell build.  Bin every disk by its (a, p) at the breakpoint.
 // ------------------------------------------------------------------------
-__global__ void k_bin(Dev D, Geo g, int32_t dir) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= D.n) return;
+__device__ void bin_one(const Dev &D, const Geo &g, int32_t dir, int64_t i) {
   double a = dir ? D.Y[i] : D.X[i];
   double p = dir ? D.X[i] : D.Y[i];
   int col = (int)(a * g.inv_c), row = (int)(p * g.inv_c);
@@ -261,13 +278,14 @@ __global__ void k_bin(Dev D, Geo g, int32_t dir) {
     atomicExch(&D.ctl->error, ECMC_ECELL);
   }
 }
+__global__ void k_bin(Dev D, Geo g, int32_t dir) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < D.n) bin_one(D, g, dir, i);
+}
 
 // One thread per cell: order the cell's disks by id (deterministic layout) and
 // write their slot records.
-__global__ void k_cellfill(Dev D, Geo g, int32_t dir) {
-  int64_t cell = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  int64_t ncell = (int64_t)g.nc * g.nc;
-  if (cell >= ncell) return;
+__device__ void cellfill_one(const Dev &D, const Geo &g, int32_t dir, int64_t cell) {
   int cnt = D.CELL_CNT[cell];
   cnt = cnt > CAP ? CAP : cnt;
   int ids[CAP];
@@ -310,11 +328,13 @@ __global__ void k_cellfill(Dev D, Geo g, int32_t dir) {
     }
   }
 }
+__global__ void k_cellfill(Dev D, Geo g, int32_t dir) {
+  int64_t cell = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (cell < (int64_t)g.nc * g.nc) cellfill_one(D, g, dir, cell);
+}
 
 // Once per leg, after the home-cell build: attach each chain to its disk's slot.
-__global__ void k_chains_leg(Dev D, int64_t nslots) {
-  int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= D.k) return;
+__device__ void chains_leg_one(const Dev &D, int64_t nslots, int c) {
   if (D.ctl->error) return;  // a failed build leaves SLOT_OF unusable
   int s = D.SLOT_OF[D.ACTIVE[c]];
   if (s < 0 || s >= nslots || D.CST[s].id != D.ACTIVE[c]) {
@@ -331,13 +351,15 @@ __global__ void k_chains_leg(Dev D, int64_t nslots) {
   D.SUMB_W[c] = D.SUMB_C[c];
   D.LOGLEN_W[c] = D.LOGLEN_C[c];
 }
+__global__ void k_chains_leg(Dev D, int64_t nslots) {
+  int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c < D.k) chains_leg_one(D, nslots, c);
+}
 
 // Before an attempt from h: tag each chain's disk, seed its published
 // next-event time with a lower bound (the state at h is settled, so no chain
 // has a lifting left before h), clear its violation flag.
-__global__ void k_chains_attempt(Dev D, double h) {
-  int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= D.k) return;
+__device__ void chains_attempt_one(const Dev &D, double h, int c) {
   if (D.ctl->error) return;
   const int s = D.CH_SLOT[c];
   D.TAG[s] = (uint32_t)c;
@@ -345,15 +367,17 @@ __global__ void k_chains_attempt(Dev D, double h) {
   D.NEXT[c] = t > h ? t : h;
   D.FLAG[c] = INFINITY;
 }
+__global__ void k_chains_attempt(Dev D, double h) {
+  int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c < D.k) chains_attempt_one(D, h, c);
+}
 
 // ---- rollback to time R: take back every lifting with time >= R ----------
 // A slot that was static at R gets the record saved by its earliest undone
 // claim (smallest lifting time, then smallest old local time: local times of a
 // disk only grow, so that is the first claim); a chain gets the reference it had
 // at R and republishes the point its disk reaches at R (a pause at R).
-__global__ void k_rb_mark(Dev D, double R) {
-  int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= D.k) return;
+__device__ void rb_mark_one(const Dev &D, double R, int c) {
   const long long n = D.UNDO_N[c];
   D.UNDO_N_OLD[c] = n;
   for (long long m = n - 1; m >= 0; --m) {
@@ -362,9 +386,11 @@ __global__ void k_rb_mark(Dev D, double R) {
     atomicMin(&D.RKEY[u.sj], (unsigned long long)__double_as_longlong(u.e));
   }
 }
-__global__ void k_rb_mark2(Dev D, double R) {
+__global__ void k_rb_mark(Dev D, double R) {
   int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= D.k) return;
+  if (c < D.k) rb_mark_one(D, R, c);
+}
+__device__ void rb_mark2_one(const Dev &D, double R, int c) {
   for (long long m = D.UNDO_N_OLD[c] - 1; m >= 0; --m) {
     const UndoRec &u = D.UNDO[(int64_t)c * D.undo_cap + m];
     if (!(u.e >= R)) break;
@@ -372,9 +398,11 @@ __global__ void k_rb_mark2(Dev D, double R) {
       atomicMin(&D.RKEY2[u.sj], (unsigned long long)__double_as_longlong(u.tj));
   }
 }
-__global__ void k_rb_apply(Dev D, Geo g, double R) {
+__global__ void k_rb_mark2(Dev D, double R) {
   int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= D.k) return;
+  if (c < D.k) rb_mark2_one(D, R, c);
+}
+__device__ void rb_apply_one(const Dev &D, const Geo &g, double R, int c) {
   const long long n = D.UNDO_N_OLD[c];
   long long m = n - 1;
   for (; m >= 0; --m) {
@@ -402,9 +430,11 @@ __global__ void k_rb_apply(Dev D, Geo g, double R) {
     D.UNDO_N[c] = n - nu;
   }
 }
-__global__ void k_rb_reset(Dev D, Geo g, double R) {
+__global__ void k_rb_apply(Dev D, Geo g, double R) {
   int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= D.k) return;
+  if (c < D.k) rb_apply_one(D, g, R, c);
+}
+__device__ void rb_reset_one(const Dev &D, const Geo &g, double R, int c) {
   for (long long m = D.UNDO_N[c]; m < D.UNDO_N_OLD[c]; ++m) {
     const UndoRec &u = D.UNDO[(int64_t)c * D.undo_cap + m];
     D.RKEY[u.sj] = 0x7FF0000000000000ull;
@@ -418,6 +448,10 @@ __global__ void k_rb_reset(Dev D, Geo g, double R) {
   r.t = R;
   D.MUT[s] = r;
   D.TAG[s] = (uint32_t)c;
+}
+__global__ void k_rb_reset(Dev D, Geo g, double R) {
+  int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c < D.k) rb_reset_one(D, g, R, c);
 }
 
 __global__ void k_ctl_reset(Dev D, double h) {
@@ -439,7 +473,8 @@ __global__ void k_ctl_reset(Dev D, double h) {
 // ------------------------------------------------------------------------
 template <int G>
 struct Win {
-  static constexpr int M = (G == 16) ? 4 : 5;  // columns per pass
+  // columns per pass: as many as keep a few slots per lane
+  static constexpr int M = G >= 32 ? 5 : (G >= 8 ? 4 : 2);
   static constexpr int NS = ROWS * CAP * M;   // slots per pass
   static constexpr int SPL = (NS + G - 1) / G;
 };
@@ -558,17 +593,18 @@ __device__ __forceinline__ unsigned long long res_key(double e, int c) {
 // a_ref at time e (the candidate lifting time), and no contact happens before
 // e iff the contact with a_ref comes after e.  Returns true if that proves j
 // harmless; false (keep the violation) in every other case.  Lane 0 only.
+template <int SC>
 __device__ bool screen_clear(const Dev &D, const Geo &g, double a, double p, double t, double e, int slot_j,
                              double p_j) {
-  const uint32_t tg = __hip_atomic_load(&D.TAG[slot_j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  const uint32_t tg = __hip_atomic_load(&D.TAG[slot_j], __ATOMIC_RELAXED, SC);
   if (tg >= (uint32_t)D.k) return false;  // at rest or at a breakpoint: history unknown
   RefRec *r = &D.REF[tg];
-  const long long v1 = __hip_atomic_load(&r->ver, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  const long long v1 = __hip_atomic_load(&r->ver, __ATOMIC_RELAXED, SC);
   wait_mem();
-  const int rs = __hip_atomic_load(&r->slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  const double ra = ld_a(&r->a), rt = ld_a(&r->t_act), rr = ld_a(&r->t_rest);
+  const int rs = __hip_atomic_load(&r->slot, __ATOMIC_RELAXED, SC);
+  const double ra = ld_a<SC>(&r->a), rt = ld_a<SC>(&r->t_act), rr = ld_a<SC>(&r->t_rest);
   wait_mem();
-  const long long v2 = __hip_atomic_load(&r->ver, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  const long long v2 = __hip_atomic_load(&r->ver, __ATOMIC_RELAXED, SC);
   if (v1 < 0 || v1 != v2 || rs != slot_j) return false;
   if (!(rr <= e && e < rt)) return false;
   double b, dp;
@@ -587,6 +623,7 @@ __device__ bool screen_clear(const Dev &D, const Geo &g, double a, double p, dou
 // (a complete record that fails must be reported when it is seen: later the
 // disk may be out of reach and never checked again).  Returns the lane of the
 // violation, -2, or -1 if there is none.  Lane 0 only.
+template <int SC>
 __device__ __forceinline__ int horizon_check(const Dev &D, const Geo &g, double a, double p, double t,
                                              double trem, double e, const double (&gt)[3], const int (&gsl)[3],
                                              const double (&gpj)[3], const double (&ar)[3],
@@ -596,7 +633,7 @@ __device__ __forceinline__ int horizon_check(const Dev &D, const Geo &g, double 
 #pragma unroll
   for (int q = 0; q < 3; ++q) {
     if (gt[q] < trem && t + gt[q] < tr[q]) {
-      if ((feat & ECMC_FEAT_SCREEN) && gsl[q] != t_slot && screen_clear(D, g, a, p, t, e, gsl[q], gpj[q])) {
+      if ((feat & ECMC_FEAT_SCREEN) && gsl[q] != t_slot && screen_clear<SC>(D, g, a, p, t, e, gsl[q], gpj[q])) {
         ++cleared;
       } else {
         fail[q] = true;
@@ -610,8 +647,8 @@ __device__ __forceinline__ int horizon_check(const Dev &D, const Geo &g, double 
 #pragma unroll
   for (int q = 0; q < 3; ++q) {
     if (fail[q] && real < 0) {
-      const double a2 = ld_a(&D.MUT[gsl[q]].a);
-      const double t2 = ld_a(&D.MUT[gsl[q]].t);
+      const double a2 = ld_a<SC>(&D.MUT[gsl[q]].a);
+      const double t2 = ld_a<SC>(&D.MUT[gsl[q]].t);
       bool torn_ok = false;
       if (t2 == tr[q] && a2 != ar[q]) {
         double b2, dp2;
@@ -623,21 +660,23 @@ __device__ __forceinline__ int horizon_check(const Dev &D, const Geo &g, double 
   return real >= 0 ? real : -2;
 }
 
-template <int G>
+template <int G, int SC>
 __device__ __forceinline__ void flag_violation(const Dev &D, int c, double t, int lane, int kind = VK_SCAN,
                                                double tj = 0.0, double tau = 0.0, int id = -1) {
   if (lane == 0) {
     D.FLAG[c] = t;
-    atomicMin(&D.ctl->tstar_bits, (unsigned long long)__double_as_longlong(t));
-    atomicAdd(&D.ctl->vkind_cnt[kind], 1ull);
-    if (atomicCAS(&D.ctl->vkind_first, -1, kind) == -1) {  // details of the first one
+    __hip_atomic_fetch_min(&D.ctl->tstar_bits, (unsigned long long)__double_as_longlong(t), __ATOMIC_RELAXED, SC);
+    __hip_atomic_fetch_add(&D.ctl->vkind_cnt[kind], 1ull, __ATOMIC_RELAXED, SC);
+    int first = -1;
+    if (__hip_atomic_compare_exchange_strong(&D.ctl->vkind_first, &first, kind, __ATOMIC_RELAXED,
+                                             __ATOMIC_RELAXED, SC)) {  // details of the first one
       D.ctl->v_chain = c;
       D.ctl->v_id = id;
       D.ctl->v_t = t;
       D.ctl->v_tj = tj;
       D.ctl->v_tau = tau;
     }
-    __hip_atomic_store(&D.ctl->abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(&D.ctl->abort, 1, __ATOMIC_RELAXED, SC);
   }
 }
 
@@ -691,24 +730,18 @@ __device__ void clock_loop(const Dev &D, long long iter_cap) {
 // itself, a move up to contact, or, at a breakpoint, the point reached there
 // (stall at h', or pause at an intermediate breakpoint: the disk then looks
 // exactly like a stalled one to the others, t = breakpoint).
-template <int G, bool F32>
-__global__ void __launch_bounds__(256) k_event(Dev D, Geo g, LegP lp, int32_t wait_retries,
-                                               long long iter_cap) {
-  const int lane = threadIdx.x & (G - 1);
-  const int c = (int)(((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G);
-  if (lp.window > 0.0 && blockIdx.x == gridDim.x - 1) {  // the clock workgroup
-    clock_loop(D, iter_cap);
-    return;
-  }
-  if (c >= D.k) return;  // whole groups leave together
-  if (D.ctl->error) return;
+// One chain's events for one launch: from its reference to the breakpoint, an
+// abort, or an error.  Lanes `lane` of a group of G run it together.
+template <int G, bool F32, int SC>
+__device__ void chain_events(const Dev &D, const Geo &g, const LegP &lp, int32_t wait_retries,
+                             long long iter_cap, int c, int lane) {
   using W = Win<G>;
 
   int s = D.CH_SLOT[c];
   double a = D.CH_A[c];  // reference position of the chain's disk
   double t = D.CH_T[c];  // reference local time
   double p = D.CST[s].p;
-  double t_pub = ld_a(&D.MUT[s].t);  // published point
+  double t_pub = ld_a<SC>(&D.MUT[s].t);  // published point
   double nxt_pub = -1.0;              // last next-event time published
   long long undo_n = D.UNDO_N[c];
   long long ref_ver = D.REF[c].ver;  // version of this chain's published activation
@@ -721,6 +754,12 @@ __global__ void __launch_bounds__(256) k_event(Dev D, Geo g, LegP lp, int32_t wa
   const int inj_ev = (D.ctl->inject_chain == c) ? D.ctl->inject_event : -1;
   int retries = 0;
   bool finished = false;
+  // after giving a target back to an earlier reservation, the chain does not
+  // claim that target again while the reservation is pending (two chains of
+  // one wavefront issue their claims in the same instruction, and the same
+  // lane would always win)
+  int yield_slot = -1;
+  unsigned long long yield_key = RES_EMPTY;
   const double tend = lp.tend, h = lp.h;
 
   for (long long it = 0;; ++it) {
@@ -729,18 +768,18 @@ __global__ void __launch_bounds__(256) k_event(Dev D, Geo g, LegP lp, int32_t wa
     int ab = 0;
     double hclk = 0.0;
     if (lane == 0) {
-      ab = __hip_atomic_load(&D.ctl->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      hclk = ld_a(&D.ctl->clock);
+      ab = __hip_atomic_load(&D.ctl->abort, __ATOMIC_RELAXED, SC);
+      hclk = ld_a<SC>(&D.ctl->clock);
     }
     if (it >= iter_cap) {
       if (lane == 0) {
-        atomicExch(&D.ctl->error, ECMC_EHANG);
-        __hip_atomic_store(&D.ctl->abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_exchange(&D.ctl->error, (int32_t)ECMC_EHANG, __ATOMIC_RELAXED, SC);
+        __hip_atomic_store(&D.ctl->abort, 1, __ATOMIC_RELAXED, SC);
       }
       break;
     }
     if (inj_ev >= 0 && cnt[C_EVENTS] - ev_start == inj_ev) {  // test hook
-      flag_violation<G>(D, c, t > h ? t : h, lane);
+      flag_violation<G, SC>(D, c, t > h ? t : h, lane);
       break;
     }
 
@@ -768,7 +807,7 @@ __global__ void __launch_bounds__(256) k_event(Dev D, Geo g, LegP lp, int32_t wa
       // the slots of this pass, loaded once (records are reread only after a claim)
       CstRec crs[W::SPL];
       double ajs[W::SPL], tjs[W::SPL];
-      int sls[W::SPL], mcs[W::SPL], drs[W::SPL];
+      int sls[W::SPL];
 #pragma unroll
       for (int r = 0; r < W::SPL; ++r) {
         const int w = lane + r * G;
@@ -776,7 +815,6 @@ __global__ void __launch_bounds__(256) k_event(Dev D, Geo g, LegP lp, int32_t wa
         crs[r].id = -1;
         crs[r].p = 0.0;
         ajs[r] = tjs[r] = 0.0;
-        mcs[r] = drs[r] = 0;
         if (w < W::NS) {
           const int mc = m0 + w / (ROWS * CAP);
           const int rem = w % (ROWS * CAP);
@@ -787,11 +825,9 @@ __global__ void __launch_bounds__(256) k_event(Dev D, Geo g, LegP lp, int32_t wa
             row = row < 0 ? row + g.nc : (row >= g.nc ? row - g.nc : row);
             const int sl = ((row * g.nc + col) << 2) + (rem % CAP);
             sls[r] = sl;
-            mcs[r] = mc;
-            drs[r] = rem / CAP - 1;
             crs[r] = D.CST[sl];
-            ajs[r] = ld_a(&D.MUT[sl].a);
-            tjs[r] = ld_a(&D.MUT[sl].t);
+            ajs[r] = ld_a<SC>(&D.MUT[sl].a);
+            tjs[r] = ld_a<SC>(&D.MUT[sl].t);
           }
         }
       }
@@ -812,7 +848,8 @@ __global__ void __launch_bounds__(256) k_event(Dev D, Geo g, LegP lp, int32_t wa
             const int col = (sls[r] >> 2) % g.nc;
             const int row = (sls[r] >> 2) / g.nc;
             const float raj = (float)(ajs[r] - col * g.c), rpj = (float)(crs[r].p - row * g.c);
-            fc[r] = tof_f32(mcs[r], drs[r], rai, rpi, raj, rpj, g);
+            const int w = lane + r * G;
+            fc[r] = tof_f32(m0 + w / (ROWS * CAP), (w % (ROWS * CAP)) / CAP - 1, rai, rpi, raj, rpj, g);
             const bool not_behind = (tjs[r] > h) || (t + (double)fc[r].lo >= tjs[r]);
 #pragma unroll
             for (int q = 0; q < 3; ++q)
@@ -922,11 +959,12 @@ __global__ void __launch_bounds__(256) k_event(Dev D, Geo g, LegP lp, int32_t wa
     const unsigned long long mykey = res_key(e_next, c);
     if (lane == 0) {
       if (e_next != nxt_pub) {
-        st_a(&D.NEXT[c], e_next);
+        st_a<SC>(&D.NEXT[c], e_next);
         nxt_pub = e_next;
       }
       // reserve the target: a chain with a later lifting on it yields
-      if (tau < trem && (lp.features & ECMC_FEAT_RESERVE)) atomicMin(&D.RES[ts], mykey);
+      if (tau < trem && (lp.features & ECMC_FEAT_RESERVE))
+        __hip_atomic_fetch_min(&D.RES[ts], mykey, __ATOMIC_RELAXED, SC);
     }
     if (lp.window > 0.0) {
       double hc = __shfl(hclk, 0, G);
@@ -936,16 +974,16 @@ __global__ void __launch_bounds__(256) k_event(Dev D, Geo g, LegP lp, int32_t wa
         if (tw > t_pub) {
           const double aw = fwd_move(a, tw - t, g);
           if (lane == 0) {
-            st_a(&D.MUT[s].t, tw);
+            st_a<SC>(&D.MUT[s].t, tw);
             fence_rel();
-            st_a(&D.MUT[s].a, aw);
+            st_a<SC>(&D.MUT[s].a, aw);
           }
           t_pub = tw;
         }
         if (++it >= iter_cap) {
           if (lane == 0) {
-            atomicExch(&D.ctl->error, ECMC_EHANG);
-            __hip_atomic_store(&D.ctl->abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_exchange(&D.ctl->error, (int32_t)ECMC_EHANG, __ATOMIC_RELAXED, SC);
+            __hip_atomic_store(&D.ctl->abort, 1, __ATOMIC_RELAXED, SC);
           }
           stop = true;
           break;
@@ -954,8 +992,8 @@ __global__ void __launch_bounds__(256) k_event(Dev D, Geo g, LegP lp, int32_t wa
         int ab2 = 0;
         double h2 = 0.0;
         if (lane == 0) {
-          ab2 = __hip_atomic_load(&D.ctl->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          h2 = ld_a(&D.ctl->clock);
+          ab2 = __hip_atomic_load(&D.ctl->abort, __ATOMIC_RELAXED, SC);
+          h2 = ld_a<SC>(&D.ctl->clock);
         }
         if (__shfl(ab2, 0, G)) {
           stop = true;
@@ -975,7 +1013,7 @@ __global__ void __launch_bounds__(256) k_event(Dev D, Geo g, LegP lp, int32_t wa
       if (gt[q] < trem && t + gt[q] < gtj[q]) viol = true;
     if (viol) {
       int bad = -1, clr = 0;
-      if (lane == 0) bad = horizon_check(D, g, a, p, t, trem, e_next, gt, gsl, gpj, gaj, gtj, ts, clr, lp.features);
+      if (lane == 0) bad = horizon_check<SC>(D, g, a, p, t, trem, e_next, gt, gsl, gpj, gaj, gtj, ts, clr, lp.features);
       bad = __shfl(bad, 0, G);
       cnt[C_CLEARED] += clr;
       if (bad == -2) {  // a record was being rewritten: scan again
@@ -990,7 +1028,7 @@ __global__ void __launch_bounds__(256) k_event(Dev D, Geo g, LegP lp, int32_t wa
             vta = gt[q];
             vid = gi[q];
           }
-        flag_violation<G>(D, c, t > h ? t : h, lane, VK_SCAN, vtj, vta, vid);
+        flag_violation<G, SC>(D, c, t > h ? t : h, lane, VK_SCAN, vtj, vta, vid);
         break;
       }
       viol = false;
@@ -1001,18 +1039,34 @@ __global__ void __launch_bounds__(256) k_event(Dev D, Geo g, LegP lp, int32_t wa
     if (!(tau < trem)) {
       const double an = fwd_move(a, trem, g);
       if (lane == 0) {
-        st_a(&D.MUT[s].t, tend);
+        st_a<SC>(&D.MUT[s].t, tend);
         fence_rel();
-        strict_rel(lp.strict);
-        st_a(&D.MUT[s].a, an);
-        strict_rel(lp.strict);
-        st_rel(&D.TAG[s], lp.final ? TAG_STALLED : TAG_PAUSED);
+        strict_rel<SC>(lp.strict);
+        st_a<SC>(&D.MUT[s].a, an);
+        strict_rel<SC>(lp.strict);
+        st_rel<SC>(&D.TAG[s], lp.final ? TAG_STALLED : TAG_PAUSED);
       }
       finished = true;
       break;  // the reference stays: a rollback may resume this chain
     }
 
     // ---- statement 10: claim the target ----
+    if (yield_slot >= 0) {
+      int live = 0;
+      if (yield_slot == ts && lane == 0) {
+        const unsigned long long rk0 = __hip_atomic_load(&D.RES[ts], __ATOMIC_RELAXED, SC);
+        const int o = (int)(yield_key & 0xffffffffu);
+        if (rk0 == yield_key && o < D.k)
+          live = __float_as_uint(__double2float_rd(ld_a<SC>(&D.NEXT[o]))) == (uint32_t)(yield_key >> 32);
+      }
+      live = __shfl(live, 0, G);
+      if (live) {
+        cnt[C_WAITS] += (lane == 0);
+        __builtin_amdgcn_s_sleep(4);
+        continue;
+      }
+      yield_slot = -1;
+    }
     int won = 0;
     uint32_t old = TAG_STATIC;
     double aj2 = 0.0, tj2 = 0.0;
@@ -1021,24 +1075,24 @@ __global__ void __launch_bounds__(256) k_event(Dev D, Geo g, LegP lp, int32_t wa
     if (lane == 0) {
       // the activation record is rewritten if the claim succeeds: mark it
       // invalid first (the wait after the claim orders this store)
-      __hip_atomic_store(&D.REF[c].ver, -1ll, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(&D.REF[c].ver, -1ll, __ATOMIC_RELAXED, SC);
       won = __hip_atomic_compare_exchange_strong(&D.TAG[ts], &old, (uint32_t)c, __ATOMIC_RELAXED,
-                                                 __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                                                 __ATOMIC_RELAXED, SC)
                 ? 1
                 : 0;
       fence_acq();
-      strict_acq(lp.strict);
+      strict_acq<SC>(lp.strict);
       if (won) {
         // statement 13 (extended to the local time): reads issued after the claim completed
-        aj2 = ld_a(&D.MUT[ts].a);
-        tj2 = ld_a(&D.MUT[ts].t);
+        aj2 = ld_a<SC>(&D.MUT[ts].a);
+        tj2 = ld_a<SC>(&D.MUT[ts].t);
         double acl[3], tcl[3];
 #pragma unroll
         for (int q = 0; q < 3; ++q) {
-          acl[q] = (gt[q] < trem) ? ld_a(&D.MUT[gsl[q]].a) : 0.0;
-          tcl[q] = (gt[q] < trem) ? ld_a(&D.MUT[gsl[q]].t) : 0.0;
+          acl[q] = (gt[q] < trem) ? ld_a<SC>(&D.MUT[gsl[q]].a) : 0.0;
+          tcl[q] = (gt[q] < trem) ? ld_a<SC>(&D.MUT[gsl[q]].t) : 0.0;
         }
-        rk = __hip_atomic_load(&D.RES[ts], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        rk = __hip_atomic_load(&D.RES[ts], __ATOMIC_RELAXED, SC);
         // statement 5 again on records read after the claim: a lane minimum
         // whose record changed must still pass Eq. 2 and stay behind the
         // target, else the chain scans again
@@ -1058,7 +1112,7 @@ __global__ void __launch_bounds__(256) k_event(Dev D, Geo g, LegP lp, int32_t wa
           }
         }
       } else {
-        __hip_atomic_store(&D.REF[c].ver, ref_ver, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&D.REF[c].ver, ref_ver, __ATOMIC_RELAXED, SC);
       }
     }
     won = __shfl(won, 0, G);
@@ -1067,7 +1121,7 @@ __global__ void __launch_bounds__(256) k_event(Dev D, Geo g, LegP lp, int32_t wa
       if (old == TAG_STALLED || old == TAG_PAUSED) {
         // it sits where it is at the breakpoint with t = breakpoint, and this
         // chain would reach it earlier: a horizon violation
-        flag_violation<G>(D, c, t > h ? t : h, lane, VK_BREAKPOINT_TARGET, tend, tau, t_id);
+        flag_violation<G, SC>(D, c, t > h ? t : h, lane, VK_BREAKPOINT_TARGET, tend, tau, t_id);
         break;
       }
       // the target is active on another chain: retry; after wait_retries
@@ -1083,11 +1137,11 @@ __global__ void __launch_bounds__(256) k_event(Dev D, Geo g, LegP lp, int32_t wa
           int bad = 0;
           if (lane == 0) {
             fence_acq();
-            strict_acq(lp.strict);
+            strict_acq<SC>(lp.strict);
 #pragma unroll
             for (int q = 0; q < 3; ++q) {
               if (gt[q] < trem) {
-                const double aq = ld_a(&D.MUT[gsl[q]].a), tq = ld_a(&D.MUT[gsl[q]].t);
+                const double aq = ld_a<SC>(&D.MUT[gsl[q]].a), tq = ld_a<SC>(&D.MUT[gsl[q]].t);
                 double b2, dp2;
                 if (t + tof(a, p, aq, gpj[q], g, b2, dp2) < tq) bad = 1;
               }
@@ -1100,10 +1154,10 @@ __global__ void __launch_bounds__(256) k_event(Dev D, Geo g, LegP lp, int32_t wa
           }
           const double an = fwd_move(a, tau, g);
           if (lane == 0) {
-            st_a(&D.MUT[s].t, tn);
+            st_a<SC>(&D.MUT[s].t, tn);
             fence_rel();
-            strict_rel(lp.strict);
-            st_a(&D.MUT[s].a, an);
+            strict_rel<SC>(lp.strict);
+            st_a<SC>(&D.MUT[s].a, an);
           }
           t_pub = tn;
           cnt[C_MOVES] += (lane == 0);
@@ -1117,19 +1171,19 @@ __global__ void __launch_bounds__(256) k_event(Dev D, Geo g, LegP lp, int32_t wa
     stale = __shfl(stale, 0, G);
     if (stale == 2) {
       if (lane == 0) {
-        __hip_atomic_store(&D.REF[c].ver, ref_ver, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        st_rel(&D.TAG[ts], TAG_STATIC);
+        __hip_atomic_store(&D.REF[c].ver, ref_ver, __ATOMIC_RELAXED, SC);
+        st_rel<SC>(&D.TAG[ts], TAG_STATIC);
       }
-      flag_violation<G>(D, c, t > h ? t : h, lane, VK_CLAIM, 0.0, tau, t_id);
+      flag_violation<G, SC>(D, c, t > h ? t : h, lane, VK_CLAIM, 0.0, tau, t_id);
       break;
     }
     // statement 13: the target must not have moved (nor been stamped) since
     // the scan, and no lane minimum may have moved into question
     if (aj2 != t_aj || tj2 != t_tj || stale) {
       if (lane == 0) {
-        __hip_atomic_store(&D.REF[c].ver, ref_ver, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        strict_rel(lp.strict);
-        st_rel(&D.TAG[ts], TAG_STATIC);  // statement 20
+        __hip_atomic_store(&D.REF[c].ver, ref_ver, __ATOMIC_RELAXED, SC);
+        strict_rel<SC>(lp.strict);
+        st_rel<SC>(&D.TAG[ts], TAG_STATIC);  // statement 20
       }
       cnt[C_CASFAIL] += (lane == 0);
       continue;
@@ -1142,18 +1196,20 @@ __global__ void __launch_bounds__(256) k_event(Dev D, Geo g, LegP lp, int32_t wa
       if (lane == 0) {
         const int o = (int)(rk & 0xffffffffu);
         if (o < D.k) {
-          const double nx = ld_a(&D.NEXT[o]);
+          const double nx = ld_a<SC>(&D.NEXT[o]);
           live = __float_as_uint(__double2float_rd(nx)) == (uint32_t)(rk >> 32);
         }
         if (live) {
-          __hip_atomic_store(&D.REF[c].ver, ref_ver, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          strict_rel(lp.strict);
-          st_rel(&D.TAG[ts], TAG_STATIC);
+          __hip_atomic_store(&D.REF[c].ver, ref_ver, __ATOMIC_RELAXED, SC);
+          strict_rel<SC>(lp.strict);
+          st_rel<SC>(&D.TAG[ts], TAG_STATIC);
         }
       }
       live = __shfl(live, 0, G);
       if (live) {
         cnt[C_YIELDS] += (lane == 0);
+        yield_slot = ts;
+        yield_key = rk;
         __builtin_amdgcn_s_sleep(4);
         continue;
       }
@@ -1173,21 +1229,22 @@ __global__ void __launch_bounds__(256) k_event(Dev D, Geo g, LegP lp, int32_t wa
         u->tj = tj2;
         u->sumb = sumb;
       } else {
-        atomicExch(&D.ctl->undo_overflow, 1);
+        __hip_atomic_store(&D.ctl->undo_overflow, 1, __ATOMIC_RELAXED, SC);
       }
-      st_a(&D.MUT[ts].t, tn);  // 14: t_j
-      st_a(&D.MUT[s].t, tn);   // 15: t_i
-      __hip_atomic_store(&D.REF[c].slot, ts, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      st_a(&D.REF[c].a, aj2);
-      st_a(&D.REF[c].t_act, tn);
-      st_a(&D.REF[c].t_rest, tj2);
-      atomicCAS(&D.RES[ts], mykey, RES_EMPTY);  // the reservation is used
+      st_a<SC>(&D.MUT[ts].t, tn);  // 14: t_j
+      st_a<SC>(&D.MUT[s].t, tn);   // 15: t_i
+      __hip_atomic_store(&D.REF[c].slot, ts, __ATOMIC_RELAXED, SC);
+      st_a<SC>(&D.REF[c].a, aj2);
+      st_a<SC>(&D.REF[c].t_act, tn);
+      st_a<SC>(&D.REF[c].t_rest, tj2);
+      unsigned long long used = mykey;  // the reservation is used
+      __hip_atomic_compare_exchange_strong(&D.RES[ts], &used, RES_EMPTY, __ATOMIC_RELAXED, __ATOMIC_RELAXED, SC);
       fence_rel();
-      strict_rel(lp.strict);
-      st_a(&D.MUT[s].a, an);   // 16: x_i
-      __hip_atomic_store(&D.REF[c].ver, cnt[C_EVENTS] + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      strict_rel(lp.strict);
-      st_rel(&D.TAG[s], TAG_STATIC);  // 17: release i
+      strict_rel<SC>(lp.strict);
+      st_a<SC>(&D.MUT[s].a, an);   // 16: x_i
+      __hip_atomic_store(&D.REF[c].ver, cnt[C_EVENTS] + 1, __ATOMIC_RELAXED, SC);
+      strict_rel<SC>(lp.strict);
+      st_rel<SC>(&D.TAG[s], TAG_STATIC);  // 17: release i
       D.LOG[(int64_t)c * D.log_cap + (loglen % D.log_cap)] = t_id;
     }
     ++loglen;
@@ -1212,8 +1269,8 @@ __global__ void __launch_bounds__(256) k_event(Dev D, Geo g, LegP lp, int32_t wa
   if (lane == 0) {
     // a chain stopped by an abort keeps its last next-event time: a lower
     // bound of every lifting it has still to make
-    if (finished) st_a(&D.NEXT[c], INFINITY);
-    atomicAdd(&D.ctl->done, 1);
+    if (finished) st_a<SC>(&D.NEXT[c], INFINITY);
+    __hip_atomic_fetch_add(&D.ctl->done, 1, __ATOMIC_RELAXED, SC);
     cnt[C_SCANNED] += sc;
     cnt[C_REFINES] += rf;
     for (int q = 0; q < NCNT; ++q) D.CNT_W[c * NCNT + q] = cnt[q];
@@ -1224,6 +1281,20 @@ __global__ void __launch_bounds__(256) k_event(Dev D, Geo g, LegP lp, int32_t wa
     D.CH_A[c] = a;
     D.CH_T[c] = t;
   }
+}
+
+template <int G, bool F32>
+__global__ void __launch_bounds__(256) k_event(Dev D, Geo g, LegP lp, int32_t wait_retries,
+                                               long long iter_cap) {
+  const int lane = threadIdx.x & (G - 1);
+  const int c = (int)(((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G);
+  if (lp.window > 0.0 && blockIdx.x == gridDim.x - 1) {  // the clock workgroup
+    clock_loop(D, iter_cap);
+    return;
+  }
+  if (c >= D.k) return;  // whole groups leave together
+  if (D.ctl->error) return;
+  chain_events<G, F32, SCA>(D, g, lp, wait_retries, iter_cap, c, lane);
 }
 
 // ------------------------------------------------------------------------
@@ -1340,7 +1411,7 @@ __device__ void g_scan(const Dev &D, const Geo &g, int s, double a, double p, do
   }
 }
 
-__global__ void __launch_bounds__(1024) k_global(Dev D, Geo g, LegP lp) {
+__device__ void global_order(const Dev &D, const Geo &g, const LegP &lp) {
   if (D.ctl->error) return;
   __shared__ double red_e[1024];
   __shared__ int red_c[1024];
@@ -1474,6 +1545,7 @@ __global__ void __launch_bounds__(1024) k_global(Dev D, Geo g, LegP lp) {
     D.TAG[s] = lp.final ? TAG_STALLED : TAG_PAUSED;
   }
 }
+__global__ void __launch_bounds__(1024) k_global(Dev D, Geo g, LegP lp) { global_order(D, g, lp); }
 
 // ------------------------------------------------------------------------
 // a9: overlap check on the canonical positions, using a +x home-cell build.
@@ -1522,6 +1594,234 @@ __global__ void k_join_xy(Dev D, double *xy) {
   if (i >= D.n) return;
   xy[2 * i] = D.X[i];
   xy[2 * i + 1] = D.Y[i];
+}
+
+
+// ------------------------------------------------------------------------
+// a10: batched replicas.  Every replica is a complete system with its own
+// context (workspace, cells, chains).  One workgroup runs one replica at a
+// time: its chains share the workgroup's CU, so the fields they share need
+// only workgroup-scope atomics (coherent in the CU's L1), and the breakpoint
+// synchronisation, the rollbacks and the global-order fallback are workgroup
+// barriers instead of host round trips.  A persistent grid takes replicas
+// from a queue until every replica has reached its lifting target.
+// ------------------------------------------------------------------------
+struct RepIn {
+  Dev D;
+  Geo g;
+  double T;              // leg length
+  int64_t target;        // run legs until the committed liftings reach this
+  int64_t legs_done;     // legs completed before this run (direction parity)
+  int32_t dir_mode;      // 0 +x, 1 +y, 4 alternate
+  int32_t max_splits;
+  int32_t max_legs;      // at most this many legs in this run (0: no limit)
+  int32_t pad;
+};
+struct RepOut {          // results of the run
+  int32_t status;        // ECMC_OK or the first error
+  int32_t pad;
+  int64_t legs_run, legs_violated, rollbacks, global_runs;
+  int64_t events_run;
+  int64_t vkind[4];
+};
+
+__device__ double block_min_d(double v) {
+  __shared__ double red[16];
+  for (int off = 32; off > 0; off >>= 1) v = fmin(v, __shfl_xor(v, off, 64));
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double r = INFINITY;
+  for (int q = 0; q < (int)((blockDim.x + 63) >> 6); ++q) r = fmin(r, red[q]);
+  return r;
+}
+__device__ long long block_sum_ll(long long v) {
+  __shared__ long long red[16];
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  long long r = 0;
+  for (int q = 0; q < (int)((blockDim.x + 63) >> 6); ++q) r += red[q];
+  return r;
+}
+
+// a1 for one replica: local times to zero, home cells, chains attached.
+__device__ __noinline__ void replica_build(const Dev &D, const Geo &g, int dir) {
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int64_t ncell = (int64_t)g.nc * g.nc;
+  for (int64_t i = tid; i < D.n; i += nt) D.STAMP[i] = 0.0;
+  for (int64_t i = tid; i < ncell; i += nt) D.CELL_CNT[i] = 0;
+  __syncthreads();
+  for (int64_t i = tid; i < D.n; i += nt) bin_one(D, g, dir, i);
+  __syncthreads();
+  for (int64_t i = tid; i < ncell; i += nt) cellfill_one(D, g, dir, i);
+  __syncthreads();
+  for (int c = tid; c < D.k; c += nt) chains_leg_one(D, ncell * CAP, c);
+  __syncthreads();
+}
+
+// One leg [0, T] of one replica, all of a8 on the device.  Returns ECMC_OK or
+// an error code (the same value in every thread).
+template <int G, bool F32>
+__device__ int replica_leg(const RepIn &ri, RepOut *rp, int dir, int32_t wait_retries, int32_t features) {
+  const Dev &D = ri.D;
+  const Geo &g = ri.g;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int64_t S = (int64_t)g.nc * g.nc * CAP;
+  const double T = ri.T;
+  __shared__ int s_i[3];
+  __shared__ double s_d[2];
+  replica_build(D, g, dir);
+  if (D.ctl->error) return D.ctl->error;
+  double h = 0.0, last_R = -1.0;
+  int stuck = 0;
+  bool first = true;
+  for (long long tries = 0;; ++tries) {
+    if (tid == 0) {
+      D.ctl->tstar_bits = 0x7FF0000000000000ull;
+      D.ctl->abort = 0;
+      D.ctl->clock = h;
+      D.ctl->done = 0;
+      D.ctl->vkind_first = -1;
+      for (int q = 0; q < 4; ++q) D.ctl->vkind_cnt[q] = 0ull;
+    }
+    for (int c = tid; c < D.k; c += nt) chains_attempt_one(D, h, c);
+    for (int64_t i = tid; i < S; i += nt) D.RES[i] = RES_EMPTY;
+    __syncthreads();
+    LegP lp;
+    lp.dir = dir;
+    lp.final = 1;
+    lp.h = h;
+    lp.tend = T;
+    lp.strict = 0;
+    lp.window = 0.0;
+    lp.features = features;
+    {
+      const int c = tid / G, lane = tid & (G - 1);
+      if (c < D.k) chain_events<G, F32, SCA>(D, g, lp, wait_retries, 1ll << 24, c, lane);
+    }
+    __syncthreads();
+    double m = INFINITY;
+    for (int c = tid; c < D.k; c += nt) m = fmin(m, D.NEXT[c]);
+    m = block_min_d(m);
+    if (tid == 0) {
+      s_i[0] = D.ctl->abort;
+      s_i[1] = D.ctl->error;
+      s_i[2] = D.ctl->undo_overflow;
+      s_d[0] = __longlong_as_double((long long)D.ctl->tstar_bits);
+      s_d[1] = m;
+      for (int q = 0; q < 4; ++q) rp->vkind[q] += (long long)D.ctl->vkind_cnt[q];
+    }
+    __syncthreads();
+    const int abort = s_i[0], err = s_i[1], ovf = s_i[2];
+    const double tstar = s_d[0], clock = s_d[1];
+    __syncthreads();
+    if (err) return err;
+    if (!abort) break;
+    if (tid == 0) {
+      if (first) rp->legs_violated++;
+      rp->rollbacks++;
+    }
+    first = false;
+    if (tries > (1ll << 20)) return ECMC_EHANG;
+    if (ovf) {  // the undo records do not reach back: the leg in global-time order
+      replica_build(D, g, dir);
+      if (D.ctl->error) return D.ctl->error;
+      lp.h = 0.0;
+      global_order(D, g, lp);
+      __syncthreads();
+      if (tid == 0) rp->global_runs++;
+      break;
+    }
+    const double R = fmax(fmin(tstar, clock), h);
+    stuck = (R <= last_R) ? stuck + 1 : 0;
+    last_R = fmax(last_R, R);
+    for (int c = tid; c < D.k; c += nt) rb_mark_one(D, R, c);
+    __syncthreads();
+    for (int c = tid; c < D.k; c += nt) rb_mark2_one(D, R, c);
+    __syncthreads();
+    for (int c = tid; c < D.k; c += nt) rb_apply_one(D, g, R, c);
+    __syncthreads();
+    for (int c = tid; c < D.k; c += nt) rb_reset_one(D, g, R, c);
+    __syncthreads();
+    h = R;
+    if (stuck >= ri.max_splits) {
+      // a stretch in global-time order (Alg. 2) guarantees progress
+      const double gend = fmin(T, h + T / 64.0);
+      const bool fin = !(gend < T);
+      lp.final = fin ? 1 : 0;
+      lp.h = h;
+      lp.tend = fin ? T : gend;
+      global_order(D, g, lp);
+      __syncthreads();
+      if (tid == 0) rp->global_runs++;
+      if (D.ctl->error) return D.ctl->error;
+      if (fin) break;
+      h = gend;
+      stuck = 0;
+      last_R = h;
+    }
+  }
+  for (int c = tid; c < D.k; c += nt) {
+    for (int q = 0; q < NCNT; ++q) D.CNT_C[c * NCNT + q] = D.CNT_W[c * NCNT + q];
+    D.SUMB_C[c] = D.SUMB_W[c];
+    D.LOGLEN_C[c] = D.LOGLEN_W[c];
+    D.ACTIVE[c] = D.CST[D.CH_SLOT[c]].id;
+  }
+  for (int64_t sl = tid; sl < S; sl += nt) {
+    const int id = D.CST[sl].id;
+    if (id >= 0) {
+      const MutRec mr = D.MUT[sl];
+      if (dir)
+        D.Y[id] = mr.a;
+      else
+        D.X[id] = mr.a;
+      D.STAMP[id] = mr.t;
+    }
+  }
+  __syncthreads();
+  return ECMC_OK;
+}
+
+template <int G, bool F32>
+__global__ void __launch_bounds__(512) k_batch(const RepIn *__restrict__ reps, RepOut *outs, int32_t n_rep,
+                                               int32_t *queue, int32_t wait_retries, int32_t features) {
+  __shared__ int s_rep;
+  for (;;) {
+    __syncthreads();
+    if (threadIdx.x == 0) s_rep = atomicAdd(queue, 1);
+    __syncthreads();
+    // the same value in every thread (the block leaves together); made a
+    // scalar so that the replica's descriptor is read with scalar loads
+    const int r = __builtin_amdgcn_readfirstlane(s_rep);
+    if (r >= n_rep) return;
+    const RepIn &ri = reps[r];
+    RepOut *rp = &outs[r];
+    const Dev &D = ri.D;
+    long long ev0 = 0;
+    for (int c = threadIdx.x; c < D.k; c += blockDim.x) ev0 += D.CNT_C[c * NCNT + C_EVENTS];
+    ev0 = block_sum_ll(ev0);
+    long long ev = ev0;
+    int64_t legs = 0;
+    while (ev < ri.target && (ri.max_legs == 0 || legs < ri.max_legs)) {
+      const int64_t ln = ri.legs_done + legs;
+      const int dir = ri.dir_mode == 4 ? (int)(ln & 1) : ri.dir_mode;
+      const int rc = replica_leg<G, F32>(ri, rp, dir, wait_retries, features);
+      if (rc) {
+        if (threadIdx.x == 0) rp->status = rc;
+        break;
+      }
+      ++legs;
+      long long e = 0;
+      for (int c = threadIdx.x; c < D.k; c += blockDim.x) e += D.CNT_C[c * NCNT + C_EVENTS];
+      ev = block_sum_ll(e);
+    }
+    if (threadIdx.x == 0) {
+      rp->legs_run = legs;
+      rp->events_run = ev - ev0;
+    }
+  }
 }
 
 }  // namespace
@@ -2376,6 +2676,336 @@ void ecmc_free(ecmc_ctx *ctx) {
     (void)hipEventDestroy(ctx->kev1);
   }
   delete ctx;
+}
+
+}  // extern "C"
+
+// ==========================================================================
+// Batched replicas (host side)
+// ==========================================================================
+struct ecmc_batch {
+  std::vector<ecmc_ctx *> ctxs;
+  hipStream_t stream = nullptr;
+  bool f32 = false;
+  RepIn *d_in = nullptr;
+  RepOut *d_out = nullptr;
+  int32_t *d_queue = nullptr;
+  int32_t lanes = 0;        // 0: autotune at the first run
+  int32_t tuned = 0;        // lanes chosen by the autotuner
+  int32_t use_graph = 0;
+  int32_t features = ECMC_FEAT_ALL;
+  int32_t wait_retries = 64;
+  int32_t max_splits = 4;
+  hipGraphExec_t exec = nullptr;
+  int32_t exec_lanes = 0, exec_grid = 0, last_grid = 0;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  // graphs are captured and replayed on a private stream (a caller's legacy
+  // default stream cannot be captured), ordered after and before the
+  // caller's stream with events
+  hipStream_t gstream = nullptr;
+  hipEvent_t g0 = nullptr, g1 = nullptr;
+  ecmc_batch_info_t info;
+  const char *err = "no error";
+};
+
+namespace {
+
+#define BCHK(expr)                              \
+  do {                                          \
+    if ((expr) != hipSuccess) {                 \
+      b->err = "HIP runtime call failed: " #expr; \
+      return ECMC_EDEVICE;                      \
+    }                                           \
+  } while (0)
+
+template <int G, bool F32>
+int batch_grid(ecmc_batch *b, int *grid) {
+  int dev = 0, ncu = 0, per_cu = 0;
+  BCHK(hipGetDevice(&dev));
+  BCHK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+  BCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch<G, F32>, 512, 0));
+  if (per_cu < 1) {
+    b->err = "batch kernel does not fit on a compute unit";
+    return ECMC_EDEVICE;
+  }
+  *grid = std::max(1, std::min((int)b->ctxs.size(), ncu * per_cu));
+  return ECMC_OK;
+}
+
+template <int G, bool F32>
+int batch_enqueue(ecmc_batch *b, int grid, hipStream_t st) {
+  k_fill<int32_t><<<1, 64, 0, st>>>(b->d_queue, 0, 1);
+  k_batch<G, F32><<<grid, 512, 0, st>>>(b->d_in, b->d_out, (int32_t)b->ctxs.size(), b->d_queue, b->wait_retries,
+                                        b->features);
+  BCHK(hipGetLastError());
+  return ECMC_OK;
+}
+
+template <bool F32>
+int batch_launch_f(ecmc_batch *b, int lanes, int *grid, hipStream_t st) {
+  switch (lanes) {
+    case 4: {
+      int rc = batch_grid<4, F32>(b, grid);
+      return rc ? rc : batch_enqueue<4, F32>(b, *grid, st);
+    }
+    case 8: {
+      int rc = batch_grid<8, F32>(b, grid);
+      return rc ? rc : batch_enqueue<8, F32>(b, *grid, st);
+    }
+    case 16: {
+      int rc = batch_grid<16, F32>(b, grid);
+      return rc ? rc : batch_enqueue<16, F32>(b, *grid, st);
+    }
+    case 32: {
+      int rc = batch_grid<32, F32>(b, grid);
+      return rc ? rc : batch_enqueue<32, F32>(b, *grid, st);
+    }
+    default:
+      b->err = "lanes per chain must be 4, 8, 16 or 32 for batches";
+      return ECMC_EINVAL;
+  }
+}
+
+// Enqueue one persistent launch (directly, or as a captured hipGraph that is
+// instantiated once per lane count and replayed).
+int batch_launch(ecmc_batch *b, int lanes) {
+  int grid = 0;
+  if (!b->use_graph) {
+    const int rc =
+        b->f32 ? batch_launch_f<true>(b, lanes, &grid, b->stream) : batch_launch_f<false>(b, lanes, &grid, b->stream);
+    b->last_grid = grid;
+    return rc;
+  }
+  if (!b->gstream) {
+    BCHK(hipStreamCreateWithFlags(&b->gstream, hipStreamNonBlocking));
+    BCHK(hipEventCreateWithFlags(&b->g0, hipEventDisableTiming));
+    BCHK(hipEventCreateWithFlags(&b->g1, hipEventDisableTiming));
+  }
+  if (!b->exec || b->exec_lanes != lanes) {
+    if (b->exec) {
+      (void)hipGraphExecDestroy(b->exec);
+      b->exec = nullptr;
+    }
+    hipGraph_t graph = nullptr;
+    BCHK(hipStreamBeginCapture(b->gstream, hipStreamCaptureModeThreadLocal));
+    int rc = b->f32 ? batch_launch_f<true>(b, lanes, &grid, b->gstream)
+                    : batch_launch_f<false>(b, lanes, &grid, b->gstream);
+    hipError_t ec = hipStreamEndCapture(b->gstream, &graph);
+    if (rc) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return rc;
+    }
+    BCHK(ec);
+    hipError_t ei = hipGraphInstantiate(&b->exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    BCHK(ei);
+    b->exec_lanes = lanes;
+    b->exec_grid = grid;
+  }
+  BCHK(hipEventRecord(b->g0, b->stream));
+  BCHK(hipStreamWaitEvent(b->gstream, b->g0, 0));
+  BCHK(hipGraphLaunch(b->exec, b->gstream));
+  BCHK(hipEventRecord(b->g1, b->gstream));
+  BCHK(hipStreamWaitEvent(b->stream, b->g1, 0));
+  b->last_grid = b->exec_grid;
+  return ECMC_OK;
+}
+
+// Fill the replica descriptors, run one launch, fold the results back into
+// the contexts.  events: liftings committed by the launch (all replicas).
+int batch_once(ecmc_batch *b, const int64_t *target, const double *leg_T, int32_t direction, int32_t max_legs,
+               int lanes, int64_t *events, float *ms) {
+  const int n = (int)b->ctxs.size();
+  std::vector<RepIn> h((size_t)n);
+  std::vector<RepOut> ho((size_t)n);
+  std::memset(ho.data(), 0, sizeof(RepOut) * (size_t)n);
+  for (int r = 0; r < n; ++r) {
+    ecmc_ctx *ctx = b->ctxs[(size_t)r];
+    RepIn &R = h[(size_t)r];
+    std::memset(&R, 0, sizeof(RepIn));
+    R.D = ctx->D;
+    R.g = ctx->g;
+    R.T = leg_T[r];
+    R.target = target[r];
+    R.legs_done = ctx->leg_counter;
+    R.dir_mode = direction;
+    R.max_splits = ctx->max_splits;
+    R.max_legs = max_legs;
+  }
+  BCHK(hipMemcpyAsync(b->d_in, h.data(), sizeof(RepIn) * (size_t)n, hipMemcpyHostToDevice, b->stream));
+  BCHK(hipMemcpyAsync(b->d_out, ho.data(), sizeof(RepOut) * (size_t)n, hipMemcpyHostToDevice, b->stream));
+  BCHK(hipEventRecord(b->e0, b->stream));
+  int rc = batch_launch(b, lanes);
+  if (rc) return rc;
+  BCHK(hipEventRecord(b->e1, b->stream));
+  BCHK(hipMemcpyAsync(ho.data(), b->d_out, sizeof(RepOut) * (size_t)n, hipMemcpyDeviceToHost, b->stream));
+  BCHK(hipStreamSynchronize(b->stream));
+  BCHK(hipEventElapsedTime(ms, b->e0, b->e1));
+  int status = ECMC_OK;
+  int64_t ev = 0;
+  for (int r = 0; r < n; ++r) {
+    ecmc_ctx *ctx = b->ctxs[(size_t)r];
+    const RepOut &R = ho[(size_t)r];
+    ctx->legs += R.legs_run;
+    ctx->leg_counter += R.legs_run;
+    ctx->chain_time += (double)R.legs_run * (double)ctx->D.k * h[(size_t)r].T;
+    ctx->legs_violated += R.legs_violated;
+    ctx->reruns += R.rollbacks;
+    ctx->global_legs += R.global_runs;
+    for (int q = 0; q < 4; ++q) ctx->vkind[q] += R.vkind[q];
+    ev += R.events_run;
+    b->info.legs += R.legs_run;
+    b->info.rollbacks += R.rollbacks;
+    b->info.global_runs += R.global_runs;
+    if (R.status && status == ECMC_OK) {
+      status = R.status;
+      ctx->err = "a replica failed in the batch launch";
+    }
+  }
+  *events = ev;
+  if (status) b->err = status == ECMC_ECELL ? "a cell received more than 4 disks"
+                                           : (status == ECMC_EHANG ? "event chain iteration limit reached"
+                                                                   : "device error in a replica");
+  return status;
+}
+
+}  // namespace
+
+extern "C" {
+
+int64_t ecmc_batch_scratch_bytes(int32_t n_ctx) {
+  if (n_ctx < 1 || n_ctx > (1 << 20)) return ECMC_EINVAL;
+  return align_up((int64_t)n_ctx * (int64_t)sizeof(RepIn)) + align_up((int64_t)n_ctx * (int64_t)sizeof(RepOut)) +
+         ALIGN;
+}
+
+int ecmc_batch_create(ecmc_batch **out, ecmc_ctx *const *ctxs, int32_t n_ctx, void *scratch,
+                      int64_t scratch_bytes) {
+  if (!out || !ctxs || n_ctx < 1 || !scratch) return ECMC_EINVAL;
+  *out = nullptr;
+  if (scratch_bytes < ecmc_batch_scratch_bytes(n_ctx)) return ECMC_EINVAL;
+  if (((uintptr_t)scratch) % ALIGN) return ECMC_EINVAL;
+  for (int32_t r = 0; r < n_ctx; ++r) {
+    if (!ctxs[r] || !ctxs[r]->active_set) return ECMC_ESTATE;
+    if (ctxs[r]->stream != ctxs[0]->stream) return ECMC_EINVAL;
+    if ((ctxs[r]->flags & ECMC_FP32_MIXED) != (ctxs[0]->flags & ECMC_FP32_MIXED)) return ECMC_EINVAL;
+    for (int32_t q = 0; q < r; ++q)
+      if (ctxs[q] == ctxs[r]) return ECMC_EINVAL;
+  }
+  ecmc_batch *b = new (std::nothrow) ecmc_batch();
+  if (!b) return ECMC_EDEVICE;
+  b->ctxs.assign(ctxs, ctxs + n_ctx);
+  b->stream = ctxs[0]->stream;
+  b->f32 = (ctxs[0]->flags & ECMC_FP32_MIXED) != 0;
+  b->d_in = (RepIn *)scratch;
+  b->d_out = (RepOut *)((char *)scratch + align_up((int64_t)n_ctx * (int64_t)sizeof(RepIn)));
+  b->d_queue = (int32_t *)((char *)b->d_out + align_up((int64_t)n_ctx * (int64_t)sizeof(RepOut)));
+  std::memset(&b->info, 0, sizeof(b->info));
+  if (hipEventCreate(&b->e0) != hipSuccess || hipEventCreate(&b->e1) != hipSuccess) {
+    delete b;
+    return ECMC_EDEVICE;
+  }
+  *out = b;
+  return ECMC_OK;
+}
+
+int ecmc_batch_set_option(ecmc_batch *b, int32_t key, int64_t value) {
+  if (!b) return ECMC_EINVAL;
+  switch (key) {
+    case ECMC_OPT_LANES:
+      if (value != 0 && value != 4 && value != 8 && value != 16 && value != 32) return ECMC_EINVAL;
+      b->lanes = (int32_t)value;
+      return ECMC_OK;
+    case ECMC_OPT_GRAPH:
+      if (value != 0 && value != 1) return ECMC_EINVAL;
+      b->use_graph = (int32_t)value;
+      return ECMC_OK;
+    case ECMC_OPT_FEATURES:
+      if (value < 0 || value > ECMC_FEAT_ALL) return ECMC_EINVAL;
+      b->features = (int32_t)value;
+      return ECMC_OK;
+    case ECMC_OPT_WAIT_RETRIES:
+      if (value < 1 || value > (1 << 20)) return ECMC_EINVAL;
+      b->wait_retries = (int32_t)value;
+      return ECMC_OK;
+    default:
+      return ECMC_EINVAL;
+  }
+}
+
+int ecmc_batch_run(ecmc_batch *b, const int64_t *target_events, const double *leg_T, int32_t direction,
+                   int32_t max_legs) {
+  if (!b || !target_events || !leg_T || max_legs < 0) return ECMC_EINVAL;
+  if (direction != 0 && direction != 1 && direction != 4) {
+    b->err = "direction must be 0 (+x), 1 (+y) or 4 (alternate)";
+    return ECMC_EINVAL;
+  }
+  int kmax = 1;
+  for (size_t r = 0; r < b->ctxs.size(); ++r) {
+    const ecmc_ctx *ctx = b->ctxs[r];
+    const Geo &g = ctx->g;
+    const double T = leg_T[r];
+    if (!(T > 0.0) || !(T <= g.L - 4.0 * g.c - g.d) || (ctx->D.k > 1 && !(T < g.L - 2.0 * g.sigma))) {
+      b->err = "leg length outside (0, box - 4 cell - 2 sigma]";
+      return ECMC_EINVAL;
+    }
+    if (target_events[r] < 0) return ECMC_EINVAL;
+    kmax = std::max(kmax, (int)ctx->D.k);
+  }
+  std::memset(&b->info, 0, sizeof(b->info));
+  int lanes = b->lanes ? b->lanes : b->tuned;
+  if (lanes && kmax * lanes > 512) {
+    b->err = "chains times lanes per chain exceeds the 512 threads of a workgroup";
+    return ECMC_EINVAL;
+  }
+  if (!lanes) {
+    // autotune: one leg per replica with each admissible lane count; the legs
+    // are real legs of the run (results do not depend on the lane count)
+    const int cand[4] = {4, 8, 16, 32};
+    double best = -1.0;
+    for (int q = 0; q < 4; ++q) {
+      if (kmax * cand[q] > 512) continue;
+      int64_t ev = 0;
+      float ms = 0.f;
+      int rc = batch_once(b, target_events, leg_T, direction, 1, cand[q], &ev, &ms);
+      if (rc) return rc;
+      const double rate = ms > 0.f ? (double)ev / ms : 0.0;
+      b->info.tune_events_per_ms[q] = rate;
+      if (rate > best) {
+        best = rate;
+        lanes = cand[q];
+      }
+    }
+    b->tuned = lanes;
+  }
+  int64_t ev = 0;
+  float ms = 0.f;
+  int rc = batch_once(b, target_events, leg_T, direction, max_legs, lanes, &ev, &ms);
+  b->info.lanes = lanes;
+  b->info.graph = b->use_graph;
+  b->info.device_ms = ms;
+  b->info.events = ev;
+  b->info.workgroups = b->last_grid;
+  return rc;
+}
+
+int ecmc_batch_info(const ecmc_batch *b, ecmc_batch_info_t *out) {
+  if (!b || !out) return ECMC_EINVAL;
+  *out = b->info;
+  return ECMC_OK;
+}
+
+const char *ecmc_batch_last_error(const ecmc_batch *b) { return b ? b->err : "null batch"; }
+
+void ecmc_batch_free(ecmc_batch *b) {
+  if (!b) return;
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->e0) (void)hipEventDestroy(b->e0);
+  if (b->e1) (void)hipEventDestroy(b->e1);
+  if (b->g0) (void)hipEventDestroy(b->g0);
+  if (b->g1) (void)hipEventDestroy(b->g1);
+  if (b->gstream) (void)hipStreamDestroy(b->gstream);
+  delete b;
 }
 
 }  // extern "C"

@@ -1,0 +1,140 @@
+"""Batched replicas in one persistent launch versus the oracle, per replica.
+
+Every replica is an independent system; the batch runs its legs, rollbacks
+and global-order fallback on the device.  Results must equal the oracle's
+(Alg. 2) bit for bit, whatever the lane count, with or without the hipGraph.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_2004_11040_amd as pkg  # noqa: E402
+
+
+def _small_replicas(n_rep, seed):
+    """Replicas of uneven size and density (N = 64 m, eta in [0.60, 0.72])."""
+    out = []
+    for ss in np.random.SeedSequence(seed).spawn(n_rep):
+        rng = np.random.Generator(np.random.PCG64(ss))
+        n = 64 * int(rng.integers(4, 17))
+        eta = float(rng.uniform(0.60, 0.72))
+        nx, ny, a, L = W.choose_grid(n, eta)
+        amp = min(0.05, 0.45 * (a - 2.0))
+        x, y, L = W.centred_rect_jittered(nx, ny, eta, amp, rng, n_sites=n)
+        k = int(round(math.sqrt(n)))
+        act = W.active_set(rng, n, k)
+        out.append((x, y, L, act, 0.25 * L))
+    return out
+
+
+def _make(reps, flags=pkg.FP64):
+    systems = []
+    for x, y, L, act, T in reps:
+        e = pkg.Ecmc(np.stack([x, y], 1), 1.0, L, flags=flags, max_chains=len(act), log_cap=1 << 14)
+        e.set_active(act)
+        systems.append(e)
+    return systems
+
+
+def _check(e, ref, k, tag):
+    st = e.stats()
+    assert st["events"] == ref.n_events, (tag, st["events"], ref.n_events)
+    for c in range(k):
+        assert np.array_equal(e.log(c).targets, ref.targets(c)), (tag, c)
+    assert np.array_equal(e.active(), ref.active), tag
+    pos = e.positions()
+    assert np.array_equal(pos[:, 0], ref.x) and np.array_equal(pos[:, 1], ref.y), tag
+    assert np.array_equal(e.stamps(), ref.stamps), tag
+    sb, _ = e.chain_sums()
+    assert np.array_equal(sb, ref.sum_b), tag
+    return st
+
+
+@pytest.mark.parametrize("lanes,graph", [(4, 0), (8, 1), (16, 0), (16, 1)])
+def test_batch_parity(lanes, graph):
+    reps = _small_replicas(6, 7)
+    systems = _make(reps)
+    b = pkg.Batch(systems)
+    b.set_option(pkg.OPT_LANES, lanes)
+    b.set_option(pkg.OPT_GRAPH, graph)
+    legs = 3
+    big = np.full(len(reps), 1 << 60, np.int64)
+    b.run(big, [r[4] for r in reps], pkg.DIR_ALTERNATE, max_legs=legs)
+    info = b.info()
+    assert info["lanes"] == lanes and info["legs"] == legs * len(reps), info
+    for i, ((x, y, L, act, T), e) in enumerate(zip(reps, systems)):
+        ref = oracle.run(x, y, 1.0, L, act, [0, 1, 0], T)
+        _check(e, ref, len(act), f"rep{i} lanes={lanes}")
+    # a second call continues the alternation (+y next)
+    b.run(big, [r[4] for r in reps], pkg.DIR_ALTERNATE, max_legs=1)
+    for i, ((x, y, L, act, T), e) in enumerate(zip(reps, systems)):
+        ref = oracle.run(x, y, 1.0, L, act, [0, 1, 0, 1], T)
+        _check(e, ref, len(act), f"rep{i} continued")
+
+
+def test_batch_fp32_mixed_and_autotune():
+    reps = _small_replicas(5, 11)
+    systems = _make(reps, flags=pkg.FP32_MIXED)
+    b = pkg.Batch(systems)
+    big = np.full(len(reps), 1 << 60, np.int64)
+    b.run(big, [r[4] for r in reps], pkg.DIR_ALTERNATE, max_legs=2)
+    info = b.info()
+    tried = [v for v in info["tune_events_per_ms"] if v > 0]
+    assert len(tried) >= 2, info
+    assert info["lanes"] in (4, 8, 16, 32)
+    # the tuning legs count: one per tried lane count, then two more
+    n_legs = len(tried) + 2
+    for i, ((x, y, L, act, T), e) in enumerate(zip(reps, systems)):
+        dirs = [l % 2 for l in range(n_legs)]
+        ref = oracle.run(x, y, 1.0, L, act, dirs, T)
+        st = _check(e, ref, len(act), f"fp32 rep{i}")
+        assert st["legs"] == n_legs
+
+
+def test_batch_event_targets():
+    """Replicas stop at the end of the leg in which they reach their target."""
+    reps = _small_replicas(4, 13)
+    systems = _make(reps)
+    b = pkg.Batch(systems)
+    b.set_option(pkg.OPT_LANES, 8)
+    targets = np.array([1, 2000, 5000, 0], np.int64)
+    b.run(targets, [r[4] for r in reps], pkg.DIR_X)
+    for i, ((x, y, L, act, T), e) in enumerate(zip(reps, systems)):
+        st = e.stats()
+        if targets[i] == 0:
+            assert st["legs"] == 0 and st["events"] == 0
+            continue
+        ref = oracle.run(x, y, 1.0, L, act, [0] * st["legs"], T)
+        _check(e, ref, len(act), f"target rep{i}")
+        assert st["events"] >= targets[i]
+        if st["legs"] > 1:
+            prev = oracle.run(x, y, 1.0, L, act, [0] * (st["legs"] - 1), T, log=False)
+            assert prev.n_events < targets[i]
+
+
+def test_batch_replica_workload_sample():
+    """The first replicas of the 512-replica workload (N up to 16384, k up to
+    128), one leg each, against the oracle."""
+    reps = W.replica_batch(3)
+    systems = []
+    for s in reps:
+        e = pkg.Ecmc(np.stack([s.x, s.y], 1), 1.0, s.L, flags=pkg.FP32_MIXED, max_chains=s.k,
+                     log_cap=1 << 12)
+        e.set_active(s.active)
+        systems.append(e)
+    b = pkg.Batch(systems)
+    b.set_option(pkg.OPT_LANES, 4)
+    big = np.full(len(reps), 1 << 60, np.int64)
+    b.run(big, [s.T for s in reps], pkg.DIR_ALTERNATE, max_legs=1)
+    for s, e in zip(reps, systems):
+        ref = oracle.run(s.x, s.y, 1.0, s.L, s.active, [0], s.T, log_cap=1 << 20)
+        _check(e, ref, s.k, s.name)
