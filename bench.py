@@ -134,6 +134,63 @@ def run_form(form, steps, warmup, lanes, window_micro):
     return res
 
 
+def birthday_estimate(k, L, T, sigma=1.0):
+    """Generalized birthday estimate of the violation probability per
+    breakpoint (Sec. 3.4): k chains, each confined during a leg to a region of
+    area about T x 4 sigma (its path along v and the corridor around it), in a
+    box of area L^2 cut into L^2 / (4 sigma T) such regions; p = 1 - exp(-k^2 / 2 n)."""
+    import math
+    n_regions = L * L / (4.0 * sigma * T)
+    return 1.0 - math.exp(-k * k / (2.0 * n_regions))
+
+
+def run_batch(n_rep, target, t_frac, graph=1):
+    """The replica workload: n_rep seeded replicas of N in {1024..16384}, eta in
+    [0.60, 0.72], k = round(sqrt N), FP32-mixed, run in one persistent launch
+    (captured in a hipGraph) until every replica has `target` liftings; the
+    autotuner's legs come first and are not timed."""
+    import numpy as np
+    import torch
+
+    import paper_2004_11040_amd as pkg
+    import workloads as W
+    reps = W.replica_batch(n_rep)
+    systems = []
+    for s in reps:
+        e = pkg.Ecmc(np.stack([s.x, s.y], 1), s.sigma, s.L, flags=pkg.FP32_MIXED, max_chains=s.k,
+                     log_cap=1 << 8)
+        e.set_active(s.active)
+        systems.append(e)
+    b = pkg.Batch(systems)
+    b.set_option(pkg.OPT_GRAPH, graph)
+    T = [t_frac * s.L for s in reps]
+    big = np.full(n_rep, 1 << 60, np.int64)
+    b.run(big, T, pkg.DIR_ALTERNATE, max_legs=1)  # autotune (one leg per lane count)
+    tune = b.info()
+    ev0 = sum(e.stats()["events"] for e in systems)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.run(np.full(n_rep, target, np.int64), T, pkg.DIR_ALTERNATE, max_legs=0)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    info = b.info()
+    ev1 = sum(e.stats()["events"] for e in systems)
+    print(f"[bench] batch: {ev1 - ev0} liftings in {wall:.2f} s", file=sys.stderr, flush=True)
+    overlaps = sum(e.overlaps() for e in systems)
+    out = {"workload": f"{n_rep} replicas, N in 64*[16,256], eta in [0.60,0.72], k=round(sqrt N), "
+                       f"legs of {t_frac} L alternating +x/+y, FP32-mixed, {target} liftings per replica",
+           "events": ev1 - ev0, "wall_s": wall, "events_per_s": (ev1 - ev0) / wall,
+           "device_ms": info["device_ms"], "lanes": info["lanes"], "graph": info["graph"],
+           "workgroups": info["workgroups"], "legs": info["legs"], "rollbacks": info["rollbacks"],
+           "global_runs": info["global_runs"], "autotune_events_per_ms": tune["tune_events_per_ms"],
+           "overlaps": overlaps, "total_disks": int(sum(s.n for s in reps)),
+           "total_chains": int(sum(s.k for s in reps))}
+    b.close()
+    for e in systems:
+        e.close()
+    return out
+
+
 def profile_run(legs, lanes, window_micro):
     """Short run for hardware-counter collection: a few legs of the workload,
     then a device copy of 256 MiB (read 256 MiB, write 256 MiB) whose counter
@@ -208,12 +265,16 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=60, help="timed legs")
     ap.add_argument("--warmup", type=int, default=4, help="untimed legs")
-    ap.add_argument("--form", choices=["fp64", "fp32", "both"], default="fp64")
+    ap.add_argument("--form", choices=["fp64", "fp32", "both"], default="both")
     ap.add_argument("--lanes", type=int, default=64)
     ap.add_argument("--window-micro", type=int, default=300_000,
                     help="bounded lag between chains, in 1e-6 sigma (0: free running)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--batch-replicas", type=int, default=512)
+    ap.add_argument("--batch-events", type=int, default=1_000_000)
+    ap.add_argument("--batch-leg-frac", type=float, default=0.25)
+    ap.add_argument("--no-batch", action="store_true")
     args = ap.parse_args()
     if args.pmc_summary:
         pmc_summary(*args.pmc_summary)
@@ -235,8 +296,14 @@ def main():
     r = results[main_form]
     kb = r["kernel_bytes_per_launch"]
     roof = {"bound": "hbm", "achieved": r["achieved_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": r["achieved_gbs"] / HBM_PEAK_GBS, "traffic": _traffic(r["events_per_launch"]),
-            "kernel": "k_event<64>", "bytes_per_launch": kb, "avg_launch_ms": r["kernel_ms_avg"]}
+            "frac": r["achieved_gbs"] / HBM_PEAK_GBS,
+            "traffic": _traffic(r["events_per_launch"]) if main_form == "fp64" else None,
+            "kernel": f"k_event<{args.lanes}, {main_form}>", "bytes_per_launch": kb,
+            "avg_launch_ms": r["kernel_ms_avg"]}
+    import workloads as W
+    s4 = W.config(4)
+    for f in results.values():
+        f["birthday_estimate_per_breakpoint"] = birthday_estimate(s4.k, s4.L, s4.T)
     line = {
         "metric": "ECMC events/sec on 1 GPU, N=2^20 disks η=0.708: FP32-mixed vs FP64 form",
         "value": r["events_per_s"], "unit": "events/s", "n_gpus": 1, "steps": args.steps,
@@ -250,6 +317,10 @@ def main():
         "roofline": roof,
         "forms": results,
     }
+    if "fp32" in results and "fp64" in results:
+        line["fp32_over_fp64"] = results["fp32"]["events_per_s"] / results["fp64"]["events_per_s"]
+    if not args.no_batch:
+        line["batch"] = run_batch(args.batch_replicas, args.batch_events, args.batch_leg_frac)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
     print(json.dumps(line), flush=True)

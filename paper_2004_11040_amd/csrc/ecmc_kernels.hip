@@ -1698,8 +1698,15 @@ __device__ int replica_leg(const RepIn &ri, RepOut *rp, int dir, int32_t wait_re
     lp.window = 0.0;
     lp.features = features;
     {
-      const int c = tid / G, lane = tid & (G - 1);
-      if (c < D.k) chain_events<G, F32, SCA>(D, g, lp, wait_retries, 1ll << 24, c, lane);
+      // chains rotate over the lane groups from one attempt to the next: the
+      // lanes of a wavefront issue their claims in one instruction with a fixed
+      // priority, and a rerun should not replay the same race the same way
+      const int tg = tid / G, lane = tid & (G - 1);
+      const int rot = (int)((tries * 37) % D.k);
+      if (tg < D.k) {
+        const int c = tg + rot < D.k ? tg + rot : tg + rot - D.k;
+        chain_events<G, F32, SCA>(D, g, lp, wait_retries, 1ll << 24, c, lane);
+      }
     }
     __syncthreads();
     double m = INFINITY;
