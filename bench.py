@@ -267,7 +267,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=4, help="untimed legs")
     ap.add_argument("--form", choices=["fp64", "fp32", "both"], default="both")
     ap.add_argument("--lanes", type=int, default=64)
-    ap.add_argument("--window-micro", type=int, default=300_000,
+    ap.add_argument("--window-micro", type=int, default=200_000,
                     help="bounded lag between chains, in 1e-6 sigma (0: free running)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")

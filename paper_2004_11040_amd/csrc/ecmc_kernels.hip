@@ -76,6 +76,22 @@ struct CstRec {
   int32_t pad;
 };
 
+// Control of one leg, decided on the device after every attempt so that the
+// host can enqueue several rounds (prepare, attempt, decide, roll back)
+// without waiting for each outcome.  A round whose leg has already finished
+// does nothing.
+enum { PH_RUN = 0, PH_DONE = 1, PH_FAILED = 2, PH_OVERFLOW = 3 };
+enum { MD_NORMAL = 0, MD_LOCKSTEP = 1, MD_GLOBAL = 2 };
+struct LegCtl {
+  int32_t phase, mode;
+  int32_t do_rb;         // a rollback to R is pending for this round
+  int32_t stuck, lvl, violated, final_cur, max_splits;
+  double T, h, last_R, R, gend, tend_cur, lag_cur, window, base_lag;
+  long long attempts, reruns, lockstep_runs, global_runs, legs_violated;
+  long long timed_events, timed_slots, event_launches, event_ticks, rounds;
+  unsigned long long vkind[4];
+};
+
 struct Ctl {
   unsigned long long tstar_bits;  // min over violating chains of their local time
   int32_t abort;                  // a chain flagged a violation in this attempt
@@ -93,6 +109,9 @@ struct Ctl {
   double v_t, v_tj, v_tau;
   int32_t undo_overflow;  // a chain committed more liftings than its undo ring holds
   int32_t pad3;
+  // device timing of the last event launch (s_memrealtime ticks)
+  unsigned long long t_start, t_end;
+  LegCtl lc;
 };
 // kinds of horizon violations
 enum { VK_SCAN = 0, VK_CLAIM = 1, VK_BREAKPOINT_TARGET = 2, VK_MOVE = 3 };
@@ -386,10 +405,6 @@ __device__ void rb_mark_one(const Dev &D, double R, int c) {
     atomicMin(&D.RKEY[u.sj], (unsigned long long)__double_as_longlong(u.e));
   }
 }
-__global__ void k_rb_mark(Dev D, double R) {
-  int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c < D.k) rb_mark_one(D, R, c);
-}
 __device__ void rb_mark2_one(const Dev &D, double R, int c) {
   for (long long m = D.UNDO_N_OLD[c] - 1; m >= 0; --m) {
     const UndoRec &u = D.UNDO[(int64_t)c * D.undo_cap + m];
@@ -397,10 +412,6 @@ __device__ void rb_mark2_one(const Dev &D, double R, int c) {
     if (D.RKEY[u.sj] == (unsigned long long)__double_as_longlong(u.e))
       atomicMin(&D.RKEY2[u.sj], (unsigned long long)__double_as_longlong(u.tj));
   }
-}
-__global__ void k_rb_mark2(Dev D, double R) {
-  int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c < D.k) rb_mark2_one(D, R, c);
 }
 __device__ void rb_apply_one(const Dev &D, const Geo &g, double R, int c) {
   const long long n = D.UNDO_N_OLD[c];
@@ -430,10 +441,6 @@ __device__ void rb_apply_one(const Dev &D, const Geo &g, double R, int c) {
     D.UNDO_N[c] = n - nu;
   }
 }
-__global__ void k_rb_apply(Dev D, Geo g, double R) {
-  int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c < D.k) rb_apply_one(D, g, R, c);
-}
 __device__ void rb_reset_one(const Dev &D, const Geo &g, double R, int c) {
   for (long long m = D.UNDO_N[c]; m < D.UNDO_N_OLD[c]; ++m) {
     const UndoRec &u = D.UNDO[(int64_t)c * D.undo_cap + m];
@@ -448,10 +455,6 @@ __device__ void rb_reset_one(const Dev &D, const Geo &g, double R, int c) {
   r.t = R;
   D.MUT[s] = r;
   D.TAG[s] = (uint32_t)c;
-}
-__global__ void k_rb_reset(Dev D, Geo g, double R) {
-  int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c < D.k) rb_reset_one(D, g, R, c);
 }
 
 __global__ void k_ctl_reset(Dev D, double h) {
@@ -760,6 +763,11 @@ __device__ void chain_events(const Dev &D, const Geo &g, const LegP &lp, int32_t
   // lane would always win)
   int yield_slot = -1;
   unsigned long long yield_key = RES_EMPTY;
+  // statement 17 of the last lifting (release of the disk that stopped) and
+  // the new version of the activation record wait for the next completion
+  // wait, instead of a round trip of their own
+  int rel_slot = -1;
+  long long rel_ver = 0;
   const double tend = lp.tend, h = lp.h;
 
   for (long long it = 0;; ++it) {
@@ -830,6 +838,15 @@ __device__ void chain_events(const Dev &D, const Geo &g, const LegP &lp, int32_t
             tjs[r] = ld_a<SC>(&D.MUT[sl].t);
           }
         }
+      }
+      if (rel_slot >= 0) {  // the last commit's stores have completed with these loads
+        wait_mem();
+        if (lane == 0) {
+          strict_rel<SC>(lp.strict);
+          __hip_atomic_store(&D.REF[c].ver, rel_ver, __ATOMIC_RELAXED, SC);
+          __hip_atomic_store(&D.TAG[rel_slot], TAG_STATIC, __ATOMIC_RELAXED, SC);  // 17
+        }
+        rel_slot = -1;
       }
       bool refine[W::SPL];
 #pragma unroll
@@ -1072,10 +1089,15 @@ __device__ void chain_events(const Dev &D, const Geo &g, const LegP &lp, int32_t
     double aj2 = 0.0, tj2 = 0.0;
     int stale = 0;
     unsigned long long rk = RES_EMPTY;
+    const double t_prev = t_pub;
     if (lane == 0) {
       // the activation record is rewritten if the claim succeeds: mark it
-      // invalid first (the wait after the claim orders this store)
+      // invalid first; statement 15 (the local time of the disk that will
+      // stop) is written ahead of the claim.  The wait after the claim
+      // completes both, so the position (statement 16) needs no wait of its
+      // own.  If the lifting does not happen the local time is put back.
       __hip_atomic_store(&D.REF[c].ver, -1ll, __ATOMIC_RELAXED, SC);
+      st_a<SC>(&D.MUT[s].t, t + tau);
       won = __hip_atomic_compare_exchange_strong(&D.TAG[ts], &old, (uint32_t)c, __ATOMIC_RELAXED,
                                                  __ATOMIC_RELAXED, SC)
                 ? 1
@@ -1113,6 +1135,7 @@ __device__ void chain_events(const Dev &D, const Geo &g, const LegP &lp, int32_t
         }
       } else {
         __hip_atomic_store(&D.REF[c].ver, ref_ver, __ATOMIC_RELAXED, SC);
+        st_a<SC>(&D.MUT[s].t, t_prev);
       }
     }
     won = __shfl(won, 0, G);
@@ -1172,6 +1195,7 @@ __device__ void chain_events(const Dev &D, const Geo &g, const LegP &lp, int32_t
     if (stale == 2) {
       if (lane == 0) {
         __hip_atomic_store(&D.REF[c].ver, ref_ver, __ATOMIC_RELAXED, SC);
+        st_a<SC>(&D.MUT[s].t, t_prev);
         st_rel<SC>(&D.TAG[ts], TAG_STATIC);
       }
       flag_violation<G, SC>(D, c, t > h ? t : h, lane, VK_CLAIM, 0.0, tau, t_id);
@@ -1182,6 +1206,7 @@ __device__ void chain_events(const Dev &D, const Geo &g, const LegP &lp, int32_t
     if (aj2 != t_aj || tj2 != t_tj || stale) {
       if (lane == 0) {
         __hip_atomic_store(&D.REF[c].ver, ref_ver, __ATOMIC_RELAXED, SC);
+        st_a<SC>(&D.MUT[s].t, t_prev);
         strict_rel<SC>(lp.strict);
         st_rel<SC>(&D.TAG[ts], TAG_STATIC);  // statement 20
       }
@@ -1201,6 +1226,7 @@ __device__ void chain_events(const Dev &D, const Geo &g, const LegP &lp, int32_t
         }
         if (live) {
           __hip_atomic_store(&D.REF[c].ver, ref_ver, __ATOMIC_RELAXED, SC);
+          st_a<SC>(&D.MUT[s].t, t_prev);
           strict_rel<SC>(lp.strict);
           st_rel<SC>(&D.TAG[ts], TAG_STATIC);
         }
@@ -1232,21 +1258,21 @@ __device__ void chain_events(const Dev &D, const Geo &g, const LegP &lp, int32_t
         __hip_atomic_store(&D.ctl->undo_overflow, 1, __ATOMIC_RELAXED, SC);
       }
       st_a<SC>(&D.MUT[ts].t, tn);  // 14: t_j
-      st_a<SC>(&D.MUT[s].t, tn);   // 15: t_i
+      // 15 (t_i = tn) was written before the claim and has completed
       __hip_atomic_store(&D.REF[c].slot, ts, __ATOMIC_RELAXED, SC);
       st_a<SC>(&D.REF[c].a, aj2);
       st_a<SC>(&D.REF[c].t_act, tn);
       st_a<SC>(&D.REF[c].t_rest, tj2);
       unsigned long long used = mykey;  // the reservation is used
       __hip_atomic_compare_exchange_strong(&D.RES[ts], &used, RES_EMPTY, __ATOMIC_RELAXED, __ATOMIC_RELAXED, SC);
-      fence_rel();
       strict_rel<SC>(lp.strict);
       st_a<SC>(&D.MUT[s].a, an);   // 16: x_i
-      __hip_atomic_store(&D.REF[c].ver, cnt[C_EVENTS] + 1, __ATOMIC_RELAXED, SC);
-      strict_rel<SC>(lp.strict);
-      st_rel<SC>(&D.TAG[s], TAG_STATIC);  // 17: release i
       D.LOG[(int64_t)c * D.log_cap + (loglen % D.log_cap)] = t_id;
     }
+    // 17 (release of i) and the activation record's new version follow the
+    // next completion wait (the next scan's loads, or the exit)
+    rel_slot = s;
+    rel_ver = cnt[C_EVENTS] + 1;
     ++loglen;
     ++undo_n;
     cnt[C_EVENTS] += 1;
@@ -1265,6 +1291,14 @@ __device__ void chain_events(const Dev &D, const Geo &g, const LegP &lp, int32_t
   for (int off = G / 2; off > 0; off >>= 1) {
     sc += __shfl_xor(sc, off, G);
     rf += __shfl_xor(rf, off, G);
+  }
+  if (rel_slot >= 0) {
+    wait_mem();
+    if (lane == 0) {
+      strict_rel<SC>(lp.strict);
+      __hip_atomic_store(&D.REF[c].ver, rel_ver, __ATOMIC_RELAXED, SC);
+      __hip_atomic_store(&D.TAG[rel_slot], TAG_STATIC, __ATOMIC_RELAXED, SC);  // 17
+    }
   }
   if (lane == 0) {
     // a chain stopped by an abort keeps its last next-event time: a lower
@@ -1288,13 +1322,28 @@ __global__ void __launch_bounds__(256) k_event(Dev D, Geo g, LegP lp, int32_t wa
                                                long long iter_cap) {
   const int lane = threadIdx.x & (G - 1);
   const int c = (int)(((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G);
-  if (lp.window > 0.0 && blockIdx.x == gridDim.x - 1) {  // the clock workgroup
-    clock_loop(D, iter_cap);
-    return;
+  if (lp.final < 0) {  // parameters of this attempt come from the leg control block
+    const LegCtl &lc = D.ctl->lc;
+    if (lc.phase != PH_RUN || lc.mode == MD_GLOBAL) return;
+    lp.final = lc.final_cur;
+    lp.h = lc.h;
+    lp.tend = lc.tend_cur;
+    lp.window = lc.lag_cur;
   }
-  if (c >= D.k) return;  // whole groups leave together
-  if (D.ctl->error) return;
-  chain_events<G, F32, SCA>(D, g, lp, wait_retries, iter_cap, c, lane);
+  if (threadIdx.x == 0) {
+    const unsigned long long now = __builtin_amdgcn_s_memrealtime();
+    __hip_atomic_fetch_min(&D.ctl->t_start, now, __ATOMIC_RELAXED, SCA);
+  }
+  if (blockIdx.x == gridDim.x - 1) {  // the clock workgroup (idle without a bounded lag)
+    if (lp.window > 0.0) clock_loop(D, iter_cap);
+  } else if (c < D.k && !D.ctl->error) {
+    chain_events<G, F32, SCA>(D, g, lp, wait_retries, iter_cap, c, lane);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const unsigned long long now = __builtin_amdgcn_s_memrealtime();
+    __hip_atomic_fetch_max(&D.ctl->t_end, now, __ATOMIC_RELAXED, SCA);
+  }
 }
 
 // ------------------------------------------------------------------------
@@ -1356,6 +1405,7 @@ __global__ void k_next_min(Dev D) {
   }
   if (threadIdx.x == 0) D.ctl->clock = red[0];
 }
+
 
 __global__ void k_chains_commit(Dev D) {
   if (D.ctl->error) return;
@@ -1546,6 +1596,238 @@ __device__ void global_order(const Dev &D, const Geo &g, const LegP &lp) {
   }
 }
 __global__ void __launch_bounds__(1024) k_global(Dev D, Geo g, LegP lp) { global_order(D, g, lp); }
+// ---- device-decided rounds --------------------------------------------------
+// A round is two launches: the event kernel, then k_round_end on one block of
+// 1024 threads, which runs a global-order stretch if one is due, decides the
+// next step from the attempt's outcome, performs the rollback, and prepares
+// the next attempt.  Every launch of a round returns at once when the leg is
+// over, so the host can enqueue rounds ahead of the outcome.
+
+// Block-wide (1024 threads max) sums of the chains' lifting and scan counters
+// and minimum of their next-event times.
+__device__ void round_reduce(const Dev &D, double *m_out, long long *e_out, long long *sl_out) {
+  __shared__ double rm[32];
+  __shared__ long long re[32], rs[32];
+  double m = INFINITY;
+  long long e = 0, sl = 0;
+  for (int c = threadIdx.x; c < D.k; c += blockDim.x) {
+    m = fmin(m, D.NEXT[c]);
+    e += D.CNT_W[c * NCNT + C_EVENTS];
+    sl += D.CNT_W[c * NCNT + C_SCANNED];
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    m = fmin(m, __shfl_xor(m, off, 64));
+    e += __shfl_xor(e, off, 64);
+    sl += __shfl_xor(sl, off, 64);
+  }
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) {
+    rm[threadIdx.x >> 6] = m;
+    re[threadIdx.x >> 6] = e;
+    rs[threadIdx.x >> 6] = sl;
+  }
+  __syncthreads();
+  m = INFINITY;
+  e = sl = 0;
+  for (int q = 0; q < (int)((blockDim.x + 63) >> 6); ++q) {
+    m = fmin(m, rm[q]);
+    e += re[q];
+    sl += rs[q];
+  }
+  *m_out = m;
+  *e_out = e;
+  *sl_out = sl;
+}
+
+// Prepare an attempt from lc.h: reset the attempt's flags, tag every chain's
+// disk, seed next-event times, record the work counters before the launch.
+__device__ void round_prep(const Dev &D) {
+  const double h = D.ctl->lc.h;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    Ctl &C = *D.ctl;
+    C.lc.do_rb = 0;
+    C.tstar_bits = 0x7FF0000000000000ull;
+    C.abort = 0;
+    C.clock = h;
+    C.done = 0;
+    C.vkind_first = -1;
+    for (int q = 0; q < 4; ++q) C.vkind_cnt[q] = 0ull;
+    C.t_start = ~0ull;
+    C.t_end = 0ull;
+  }
+  for (int c = threadIdx.x; c < D.k; c += blockDim.x) chains_attempt_one(D, h, c);
+  double m;
+  long long e, sl;
+  round_reduce(D, &m, &e, &sl);
+  if (threadIdx.x == 0) {
+    D.ctl->tot_events[0] = e;
+    D.ctl->tot_slots[0] = sl;
+  }
+  __syncthreads();
+}
+
+__global__ void __launch_bounds__(1024) k_leg_init(Dev D, double T, double window, double base_lag,
+                                                   int32_t max_splits) {
+  if (threadIdx.x == 0) {
+    LegCtl &lc = D.ctl->lc;
+    lc.phase = PH_RUN;
+    lc.mode = MD_NORMAL;
+    lc.do_rb = 0;
+    lc.stuck = 0;
+    lc.lvl = 0;
+    lc.violated = 0;
+    lc.final_cur = 1;
+    lc.max_splits = max_splits;
+    lc.T = T;
+    lc.h = 0.0;
+    lc.last_R = -1.0;
+    lc.R = 0.0;
+    lc.gend = T;
+    lc.tend_cur = T;
+    lc.lag_cur = window;
+    lc.window = window;
+    lc.base_lag = base_lag;
+    lc.attempts = lc.reruns = lc.lockstep_runs = lc.global_runs = lc.legs_violated = 0;
+    lc.timed_events = lc.timed_slots = lc.event_launches = lc.event_ticks = lc.rounds = 0;
+    for (int q = 0; q < 4; ++q) lc.vkind[q] = 0ull;
+  }
+  __syncthreads();
+  round_prep(D);
+}
+
+// The decision after an attempt (thread 0): returns nothing; writes lc.
+__device__ void round_decide(const Dev &D, double H, long long ev_after, long long sl_after) {
+  Ctl &C = *D.ctl;
+  LegCtl &lc = C.lc;
+  lc.rounds++;
+  if (C.error) {
+    lc.phase = PH_FAILED;
+    return;
+  }
+  C.inject_chain = -1;  // the test hook fires in one attempt only
+  if (lc.mode == MD_GLOBAL) {
+    lc.global_runs++;
+    if (lc.final_cur) {
+      lc.phase = PH_DONE;
+    } else {
+      lc.h = lc.gend;
+      lc.mode = MD_NORMAL;
+      lc.stuck = 0;
+      lc.last_R = lc.h;
+      lc.final_cur = 1;
+      lc.tend_cur = lc.T;
+      lc.lag_cur = lc.window;
+    }
+    return;
+  }
+  lc.attempts++;
+  lc.timed_events += ev_after - C.tot_events[0];
+  lc.timed_slots += sl_after - C.tot_slots[0];
+  if (C.t_end > C.t_start) {
+    lc.event_ticks += (long long)(C.t_end - C.t_start);
+    lc.event_launches++;
+  }
+  for (int q = 0; q < 4; ++q) lc.vkind[q] += C.vkind_cnt[q];
+  if (lc.mode == MD_LOCKSTEP) lc.lockstep_runs++;
+  if (!C.abort) {
+    if (lc.mode == MD_LOCKSTEP && !lc.final_cur) {
+      lc.h = lc.gend;
+      lc.mode = MD_NORMAL;
+      lc.stuck = 0;
+      lc.last_R = lc.h;
+      lc.final_cur = 1;
+      lc.tend_cur = lc.T;
+      lc.lag_cur = lc.window;
+    } else {
+      lc.phase = PH_DONE;
+    }
+    return;
+  }
+  lc.reruns++;
+  if (!lc.violated) {
+    lc.violated = 1;
+    lc.legs_violated++;
+  }
+  if (C.undo_overflow) {
+    lc.phase = PH_OVERFLOW;
+    return;
+  }
+  const double tstar = __longlong_as_double((long long)C.tstar_bits);
+  const double R = fmax(fmin(tstar, H), lc.h);  // every pending lifting is at or after h
+  lc.R = R;
+  lc.do_rb = 1;
+  if (lc.rounds > (1ll << 20)) {
+    C.error = ECMC_EHANG;
+    lc.phase = PH_FAILED;
+    return;
+  }
+  if (lc.mode == MD_NORMAL) {
+    lc.stuck = (R <= lc.last_R) ? lc.stuck + 1 : 0;
+    lc.last_R = fmax(lc.last_R, R);
+    lc.h = R;
+    if (lc.stuck >= lc.max_splits) {
+      // the same race keeps coming back: a stretch with a bounded lag well
+      // below the mean free time (divided by 8 after each violation), then
+      // in global-time order (Alg. 2)
+      lc.mode = MD_LOCKSTEP;
+      lc.lvl = 0;
+      lc.gend = fmin(lc.T, R + lc.T / 64.0);
+      lc.final_cur = lc.gend < lc.T ? 0 : 1;
+      lc.tend_cur = lc.final_cur ? lc.T : lc.gend;
+      lc.lag_cur = lc.base_lag / 4.0;
+    }
+  } else {
+    lc.h = R;
+    lc.lvl++;
+    lc.lag_cur /= 8.0;
+    if (lc.lvl == 3) lc.mode = MD_GLOBAL;
+  }
+}
+
+__global__ void __launch_bounds__(1024) k_round_end(Dev D, Geo g, LegP lp0) {
+  __shared__ int s_run, s_global, s_rb;
+  __shared__ double s_R;
+  if (threadIdx.x == 0) {
+    s_run = D.ctl->lc.phase == PH_RUN;
+    s_global = D.ctl->lc.mode == MD_GLOBAL;
+  }
+  __syncthreads();
+  if (!s_run) return;
+  if (s_global) {
+    LegP lp = lp0;
+    lp.final = D.ctl->lc.final_cur;
+    lp.h = D.ctl->lc.h;
+    lp.tend = D.ctl->lc.tend_cur;
+    lp.window = 0.0;
+    global_order(D, g, lp);
+    __syncthreads();
+  }
+  double H;
+  long long e, sl;
+  round_reduce(D, &H, &e, &sl);
+  if (threadIdx.x == 0) {
+    round_decide(D, H, e, sl);
+    s_rb = D.ctl->lc.do_rb;
+    s_R = D.ctl->lc.R;
+    s_run = D.ctl->lc.phase == PH_RUN;
+  }
+  __syncthreads();
+  if (s_rb) {
+    const double R = s_R;
+    for (int c = threadIdx.x; c < D.k; c += blockDim.x) rb_mark_one(D, R, c);
+    __syncthreads();
+    for (int c = threadIdx.x; c < D.k; c += blockDim.x) rb_mark2_one(D, R, c);
+    __syncthreads();
+    for (int c = threadIdx.x; c < D.k; c += blockDim.x) rb_apply_one(D, g, R, c);
+    __syncthreads();
+    for (int c = threadIdx.x; c < D.k; c += blockDim.x) rb_reset_one(D, g, R, c);
+    __syncthreads();
+  }
+  if (!s_run) return;
+  round_prep(D);
+}
+
 
 // ------------------------------------------------------------------------
 // a9: overlap check on the canonical positions, using a +x home-cell build.
@@ -1854,6 +2136,8 @@ struct ecmc_ctx {
   int32_t kernel_timing = 0;
   int32_t strict_order = 0;
   int32_t features = ECMC_FEAT_ALL;
+  unsigned resident_nb = 0;   // grid size whose residency was last verified
+  int32_t resident_key = 0;   // lanes * 2 + FP32 flag of that check
   int64_t vkind[4] = {0, 0, 0, 0};
   int32_t last_v_kind = -1, last_v_chain = -1, last_v_id = -1;
   double last_v_t = 0.0, last_v_tj = 0.0, last_v_tau = 0.0, last_v_h = 0.0;
@@ -2006,16 +2290,21 @@ int launch_event(ecmc_ctx *ctx, LegP lp) {
   const long long cap = 1ll << 24;
   const int G = ctx->lanes;
   const int64_t threads = (int64_t)D.k * G;
-  const unsigned nb = blocks_for(threads, 256) + (lp.window > 0.0 ? 1u : 0u);  // + clock
+  const unsigned nb = blocks_for(threads, 256) + 1u;  // + the clock workgroup
   const bool f32 = (ctx->flags & ECMC_FP32_MIXED) != 0;
-  int rc;
-  if (f32)
-    rc = G == 64 ? check_resident<64, true>(ctx, nb)
-                 : (G == 32 ? check_resident<32, true>(ctx, nb) : check_resident<16, true>(ctx, nb));
-  else
-    rc = G == 64 ? check_resident<64, false>(ctx, nb)
-                 : (G == 32 ? check_resident<32, false>(ctx, nb) : check_resident<16, false>(ctx, nb));
-  if (rc) return rc;
+  int rc = ECMC_OK;
+  const int32_t key = G * 2 + (f32 ? 1 : 0);
+  if (ctx->resident_nb != nb || ctx->resident_key != key) {
+    if (f32)
+      rc = G == 64 ? check_resident<64, true>(ctx, nb)
+                   : (G == 32 ? check_resident<32, true>(ctx, nb) : check_resident<16, true>(ctx, nb));
+    else
+      rc = G == 64 ? check_resident<64, false>(ctx, nb)
+                   : (G == 32 ? check_resident<32, false>(ctx, nb) : check_resident<16, false>(ctx, nb));
+    if (rc) return rc;
+    ctx->resident_nb = nb;
+    ctx->resident_key = key;
+  }
   if (f32) {
     if (G == 64)
       k_event<64, true><<<nb, 256, 0, ctx->stream>>>(D, ctx->g, lp, ctx->wait_retries, cap);
@@ -2126,17 +2415,6 @@ int set_inject(ecmc_ctx *ctx, int32_t chain, int32_t ev) {
   return ECMC_OK;
 }
 
-int rollback(ecmc_ctx *ctx, double R) {
-  Dev &D = ctx->D;
-  const unsigned nb = blocks_for(D.k, 256);
-  k_rb_mark<<<nb, 256, 0, ctx->stream>>>(D, R);
-  k_rb_mark2<<<nb, 256, 0, ctx->stream>>>(D, R);
-  k_rb_apply<<<nb, 256, 0, ctx->stream>>>(D, ctx->g, R);
-  k_rb_reset<<<nb, 256, 0, ctx->stream>>>(D, ctx->g, R);
-  HIPCHK(hipGetLastError());
-  return ECMC_OK;
-}
-
 int begin_leg(ecmc_ctx *ctx, int dir) {
   Dev &D = ctx->D;
   int rc = build_cells(ctx, dir);
@@ -2146,115 +2424,113 @@ int begin_leg(ecmc_ctx *ctx, int dir) {
   return ECMC_OK;
 }
 
+// One round of a leg, decided on the device: prepare an attempt, run the
+// event kernel (or a global-order stretch), decide the next step, roll back
+// if needed.  Every kernel of a round returns at once when the leg is over.
+int enqueue_round(ecmc_ctx *ctx, const LegP &lp0) {
+  int rc = launch_event(ctx, lp0);
+  if (rc) return rc;
+  k_round_end<<<1, 1024, 0, ctx->stream>>>(ctx->D, ctx->g, lp0);
+  HIPCHK(hipGetLastError());
+  return ECMC_OK;
+}
+
 // One leg [0, T] in direction dir.  The home cells are built once and all
 // chains run to the breakpoint.  When a chain sees a horizon violation every
 // chain stops; liftings at or after R = min(t*, H) are taken back from the
 // undo records (t*: earliest violation time, before which liftings are valid,
-// Remark on partial validation; H: the clock, below which no chain has a
-// pending event) and the leg resumes from R with every chain paused there
-// (restart strategy 2, Sec. 3.4).  If rollbacks stop making progress, a short
-// window runs in global-time order (Alg. 2), which cannot violate.
+// Remark on partial validation; H: smallest pending lifting time) and the leg
+// resumes from R with every chain paused there (restart strategy 2, Sec. 3.4).
+// If rollbacks stop making progress, a short stretch runs with a small
+// bounded lag, then in global-time order (Alg. 2), which cannot violate.  The
+// decisions are taken on the device (k_round_post); the host enqueues rounds
+// ahead and reads the outcome once per batch of rounds.
 int run_leg(ecmc_ctx *ctx, int dir, double T) {
   Dev &D = ctx->D;
+  const int64_t S = (int64_t)ctx->g.nc * ctx->g.nc * CAP;
   int rc = fill<double>(ctx, D.STAMP, 0.0, D.n);  // Alg. 1: local times start at h
   if (rc) return rc;
   rc = begin_leg(ctx, dir);
   if (rc) return rc;
+  rc = fill<unsigned long long>(ctx, D.RES, RES_EMPTY, S);  // no reservations yet
+  if (rc) return rc;
   bool v, ovf;
   double ts, clk;
-  double h = 0.0, last_R = -1.0;
-  int stuck = 0;
-  int64_t tries = 0;
-  bool first = true;
   if (ctx->force_global) {
     rc = attempt(ctx, dir, 0.0, T, true, true, 0.0, &v, &ts, &clk, &ovf);
     if (rc) return rc;
     ctx->global_legs++;
   } else {
-    for (;;) {
-      bool violated = false;
-      double tstar = INFINITY, clock = 0.0;
-      rc = attempt(ctx, dir, h, T, true, false, ctx->window, &violated, &tstar, &clock, &ovf);
-      if (rc) return rc;
-      if (ctx->inject_chain >= 0) {  // the hook fires on one attempt only
-        ctx->inject_chain = -1;
-        rc = set_inject(ctx, -1, -1);
+    const double base = ctx->window > 0.0 ? ctx->window : LOCKSTEP_LAG * ctx->g.sigma;
+    k_leg_init<<<1, 1024, 0, ctx->stream>>>(D, T, ctx->window, base, ctx->max_splits);
+    HIPCHK(hipGetLastError());
+    LegP lp0;
+    lp0.dir = dir;
+    lp0.final = -1;  // the device control block supplies h, tend, final and the lag
+    lp0.h = 0.0;
+    lp0.tend = T;
+    lp0.strict = ctx->strict_order;
+    lp0.window = 0.0;
+    lp0.features = ctx->features;
+    Ctl hc;
+    int nspec = 2;
+    for (int64_t batch = 0;; ++batch) {
+      for (int r = 0; r < nspec; ++r) {
+        rc = enqueue_round(ctx, lp0);
         if (rc) return rc;
       }
-      if (!violated) break;
-      if (++tries > (int64_t)1 << 20) {
+      rc = read_ctl(ctx, &hc);
+      if (rc) return rc;
+      if (hc.lc.phase != PH_RUN) break;
+      nspec = std::min(nspec * 2, 16);
+      if (batch > (int64_t)1 << 22) {
         ctx->err = "rollbacks exhausted";
         return ECMC_EHANG;
       }
-      if (first) ctx->legs_violated++;
-      first = false;
-      ctx->reruns++;
-      // every chain's pending lifting is at or after h, and so is t*
-      double R = std::max(std::min(tstar, clock), h);
-      if (ovf) {
-        // the undo records do not reach back far enough: the leg again from
-        // the breakpoint, in global-time order
-        rc = begin_leg(ctx, dir);
-        if (rc) return rc;
-        rc = attempt(ctx, dir, 0.0, T, true, true, 0.0, &v, &ts, &clk, &ovf);
-        if (rc) return rc;
-        ctx->global_legs++;
-        break;
-      }
-      stuck = (R <= last_R) ? stuck + 1 : 0;
-      last_R = std::max(last_R, R);
-      rc = rollback(ctx, R);
+    }
+    const LegCtl &lc = hc.lc;
+    ctx->attempts += lc.attempts;
+    ctx->reruns += lc.reruns;
+    ctx->lockstep_runs += lc.lockstep_runs;
+    ctx->global_legs += lc.global_runs;
+    ctx->legs_violated += lc.legs_violated;
+    for (int q = 0; q < 4; ++q) ctx->vkind[q] += (int64_t)lc.vkind[q];
+    if (hc.vkind_first >= 0) {
+      ctx->last_v_kind = hc.vkind_first;
+      ctx->last_v_chain = hc.v_chain;
+      ctx->last_v_id = hc.v_id;
+      ctx->last_v_t = hc.v_t;
+      ctx->last_v_tj = hc.v_tj;
+      ctx->last_v_tau = hc.v_tau;
+      ctx->last_v_h = lc.h;
+    }
+    if (ctx->kernel_timing) {  // s_memrealtime runs at 100 MHz
+      ctx->event_kernel_ms += (double)lc.event_ticks * 1e-5;
+      ctx->event_launches += lc.event_launches;
+      ctx->timed_events += lc.timed_events;
+      ctx->timed_slots += lc.timed_slots;
+    }
+    ctx->inject_chain = -1;  // the hook has fired (the device cleared it)
+    if (lc.phase == PH_FAILED) {
+      const int e = hc.error ? hc.error : ECMC_EDEVICE;
+      ctx->err = e == ECMC_ECELL ? "a cell received more than 4 disks"
+                                 : (e == ECMC_EHANG ? "event chain iteration limit reached" : "device error");
+      return e;
+    }
+    if (lc.phase == PH_OVERFLOW) {
+      // the undo records do not reach back far enough: the leg again from
+      // the breakpoint, in global-time order
+      rc = fill<double>(ctx, D.STAMP, 0.0, D.n);
       if (rc) return rc;
-      h = R;
-      if (stuck >= ctx->max_splits) {
-        // The same race keeps coming back.  Run a stretch [h, gend] with a
-        // bounded lag well below the mean free time, dividing the lag by 8
-        // after each violation; liftings are then committed in global-time
-        // order except for near-ties.  Three failures: the stretch runs in
-        // global-time order (Alg. 2), which cannot violate.
-        const double gend = std::min(T, h + T / 64.0);
-        const bool fin = !(gend < T);
-        double lag = (ctx->window > 0.0 ? ctx->window : LOCKSTEP_LAG * ctx->g.sigma) / 4.0;
-        bool restarted = false;
-        for (int lvl = 0;; ++lvl) {
-          if (lvl == 3) {
-            rc = attempt(ctx, dir, h, fin ? T : gend, fin, true, 0.0, &v, &ts, &clk, &ovf);
-            if (rc) return rc;
-            ctx->global_legs++;
-            break;
-          }
-          bool v2 = false, ovf2 = false;
-          double ts2 = INFINITY, clk2 = 0.0;
-          rc = attempt(ctx, dir, h, fin ? T : gend, fin, false, lag, &v2, &ts2, &clk2, &ovf2);
-          if (rc) return rc;
-          ctx->lockstep_runs++;
-          if (!v2) break;
-          ctx->reruns++;
-          if (ovf2) {
-            rc = begin_leg(ctx, dir);
-            if (rc) return rc;
-            rc = attempt(ctx, dir, 0.0, T, true, true, 0.0, &v, &ts, &clk, &ovf);
-            if (rc) return rc;
-            ctx->global_legs++;
-            restarted = true;
-            break;
-          }
-          const double R2 = std::max(std::min(ts2, clk2), h);
-          rc = rollback(ctx, R2);
-          if (rc) return rc;
-          h = R2;
-          lag /= 8.0;
-        }
-        if (fin || restarted) break;
-        h = gend;
-        stuck = 0;
-        last_R = h;
-      }
+      rc = begin_leg(ctx, dir);
+      if (rc) return rc;
+      rc = attempt(ctx, dir, 0.0, T, true, true, 0.0, &v, &ts, &clk, &ovf);
+      if (rc) return rc;
+      ctx->global_legs++;
     }
   }
   k_chains_commit<<<blocks_for(D.k, 256), 256, 0, ctx->stream>>>(D);
   HIPCHK(hipGetLastError());
-  const int64_t S = (int64_t)ctx->g.nc * ctx->g.nc * CAP;
   k_writeback<<<blocks_for(S, 256), 256, 0, ctx->stream>>>(D, ctx->g, dir);
   HIPCHK(hipGetLastError());
   return ECMC_OK;
