@@ -108,13 +108,15 @@ struct Ctl {
   int32_t v_chain, v_id;
   double v_t, v_tj, v_tau;
   int32_t undo_overflow;  // a chain committed more liftings than its undo ring holds
-  int32_t pad3;
+  int32_t hang_site;      // which loop ran out of iterations (HS_*), with ECMC_EHANG
   // device timing of the last event launch (s_memrealtime ticks)
   unsigned long long t_start, t_end;
   LegCtl lc;
 };
 // kinds of horizon violations
 enum { VK_SCAN = 0, VK_CLAIM = 1, VK_BREAKPOINT_TARGET = 2, VK_MOVE = 3 };
+// loops bounded by an iteration limit (reported with ECMC_EHANG)
+enum { HS_NONE = 0, HS_SCAN = 1, HS_LAG_WAIT = 2, HS_CLOCK = 3, HS_ROUNDS = 4 };
 
 struct Geo {
   double L, halfL, d, d2, sigma, c, inv_c;
@@ -482,16 +484,57 @@ struct Win {
   static constexpr int SPL = (NS + G - 1) / G;
 };
 
+// Broadcast from lane `src` of the group (src the same in every lane of the
+// group).  A whole wavefront reads the lane into a scalar register; narrower
+// groups go through the LDS crossbar.
+template <int G>
+__device__ __forceinline__ int bcast(int v, int src) {
+  return __shfl(v, src, G);
+}
+template <int G>
+__device__ __forceinline__ uint32_t bcast(uint32_t v, int src) {
+  return (uint32_t)bcast<G>((int)v, src);
+}
+template <int G>
+__device__ __forceinline__ long long bcast(long long v, int src) {
+  return __shfl(v, src, G);
+}
+template <int G>
+__device__ __forceinline__ unsigned long long bcast(unsigned long long v, int src) {
+  return (unsigned long long)bcast<G>((long long)v, src);
+}
+template <int G>
+__device__ __forceinline__ double bcast(double v, int src) {
+  return __longlong_as_double(bcast<G>((long long)__double_as_longlong(v), src));
+}
+
+// One step of a (tau, id) minimum with the lane DPP selects (same row of 16).
+template <int CTRL>
+__device__ __forceinline__ void dpp_min_step(double &tau, int &id) {
+  const long long b = __double_as_longlong(tau);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffff), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+  const int i2 = __builtin_amdgcn_update_dpp(0, id, CTRL, 0xF, 0xF, false);
+  const double t2 = __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+  if (key_less(t2, i2, tau, id)) {
+    tau = t2;
+    id = i2;
+  }
+}
+
+// Group minimum of (tau, id), the result in every lane of the group.  A whole
+// wavefront reduces each row of 16 lanes with DPP (quad swaps, then rotations
+// by 4 and 8) and combines the four rows from scalar reads.
 template <int G>
 __device__ __forceinline__ void grp_min(double &tau, int &id) {
 #pragma unroll
-  for (int off = G / 2; off > 0; off >>= 1) {
-    double t2 = __shfl_xor(tau, off, G);
-    int i2 = __shfl_xor(id, off, G);
-    if (key_less(t2, i2, tau, id)) {
-      tau = t2;
-      id = i2;
-    }
+    for (int off = G / 2; off > 0; off >>= 1) {
+      double t2 = __shfl_xor(tau, off, G);
+      int i2 = __shfl_xor(id, off, G);
+      if (key_less(t2, i2, tau, id)) {
+        tau = t2;
+        id = i2;
+        }
   }
 }
 
@@ -684,35 +727,37 @@ __device__ __forceinline__ void flag_violation(const Dev &D, int c, double t, in
 }
 
 // The clock workgroup: H = min over chains of NEXT, republished until every
-// chain has finished (or the attempt aborts).  H never decreases.
+// chain has finished (or the attempt aborts).  H never decreases.  One
+// iteration is a round of independent loads, a wavefront butterfly, and two
+// barriers: chains at the edge of the bounded lag wait on it.
 __device__ void clock_loop(const Dev &D, long long iter_cap) {
-  __shared__ double red[256];
+  __shared__ double red[16];
   __shared__ int s_quit;
   double hc = ld_a(&D.ctl->clock);
+  const int nw = (int)((blockDim.x + 63) >> 6);
   for (long long it = 0;; ++it) {
     double m = INFINITY;
-    for (int c = threadIdx.x; c < D.k; c += blockDim.x) {
-      const double v = ld_a(&D.NEXT[c]);
-      m = v < m ? v : m;
+#pragma unroll 4
+    for (int c = threadIdx.x; c < D.k; c += blockDim.x) m = fmin(m, ld_a(&D.NEXT[c]));
+    int done = 0, ab = 0, er = 0;
+    if (threadIdx.x == 0) {
+      done = __hip_atomic_load(&D.ctl->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      ab = __hip_atomic_load(&D.ctl->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      er = __hip_atomic_load(&D.ctl->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
-    red[threadIdx.x] = m;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) m = fmin(m, __shfl_xor(m, off, 64));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
     __syncthreads();
-    for (int off = blockDim.x / 2; off > 0; off >>= 1) {
-      if ((int)threadIdx.x < off) red[threadIdx.x] = fmin(red[threadIdx.x], red[threadIdx.x + off]);
-      __syncthreads();
-    }
-    m = red[0];
-    __syncthreads();
-    if (m > hc) {
-      hc = m;
-      if (threadIdx.x == 0) st_a(&D.ctl->clock, hc);
-    }
-    if (threadIdx.x == 0) {  // one thread decides, the block follows
-      const int done = __hip_atomic_load(&D.ctl->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      const int ab = __hip_atomic_load(&D.ctl->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      const int er = __hip_atomic_load(&D.ctl->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (threadIdx.x == 0) {
+      for (int q = 1; q < nw; ++q) m = fmin(m, red[q]);
+      if (m > hc) {
+        hc = m;
+        st_a(&D.ctl->clock, hc);
+      }
       int quit = (done >= D.k || ab || er) ? 1 : 0;
       if (!quit && it >= iter_cap) {
+        atomicExch(&D.ctl->hang_site, (int32_t)HS_CLOCK);
         atomicExch(&D.ctl->error, ECMC_EHANG);
         __hip_atomic_store(&D.ctl->abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         quit = 1;
@@ -721,7 +766,6 @@ __device__ void clock_loop(const Dev &D, long long iter_cap) {
     }
     __syncthreads();
     if (s_quit) break;
-    __builtin_amdgcn_s_sleep(1);
   }
 }
 
@@ -781,6 +825,7 @@ __device__ void chain_events(const Dev &D, const Geo &g, const LegP &lp, int32_t
     }
     if (it >= iter_cap) {
       if (lane == 0) {
+        __hip_atomic_exchange(&D.ctl->hang_site, (int32_t)HS_SCAN, __ATOMIC_RELAXED, SC);
         __hip_atomic_exchange(&D.ctl->error, (int32_t)ECMC_EHANG, __ATOMIC_RELAXED, SC);
         __hip_atomic_store(&D.ctl->abort, 1, __ATOMIC_RELAXED, SC);
       }
@@ -937,7 +982,7 @@ __device__ void chain_events(const Dev &D, const Geo &g, const LegP &lp, int32_t
       if (lb > lim) break;
     }
     lane_scanned += scanned;
-    ab = __shfl(ab, 0, G);
+    ab = bcast<G>(ab, 0);
     if (ab) break;
 
     // broadcast the records of the minima
@@ -946,11 +991,11 @@ __device__ void chain_events(const Dev &D, const Geo &g, const LegP &lp, int32_t
 #pragma unroll
     for (int q = 0; q < 3; ++q) {
       const int own = grp_owner<G>(bl.tau[q] == gt[q] && bl.id[q] == gi[q] && gt[q] < INFINITY, lane);
-      gtj[q] = __shfl(bl.t[q], own, G);
-      gaj[q] = __shfl(bl.a[q], own, G);
-      gbj[q] = __shfl(bl.b[q], own, G);
-      gpj[q] = __shfl(bl.p[q], own, G);
-      gsl[q] = __shfl(bl.slot[q], own, G);
+      gtj[q] = bcast<G>(bl.t[q], own);
+      gaj[q] = bcast<G>(bl.a[q], own);
+      gbj[q] = bcast<G>(bl.b[q], own);
+      gpj[q] = bcast<G>(bl.p[q], own);
+      gsl[q] = bcast<G>(bl.slot[q], own);
     }
     // the target: smallest of the three minima (selects, not indexing, keep
     // everything in registers)
@@ -984,7 +1029,7 @@ __device__ void chain_events(const Dev &D, const Geo &g, const LegP &lp, int32_t
         __hip_atomic_fetch_min(&D.RES[ts], mykey, __ATOMIC_RELAXED, SC);
     }
     if (lp.window > 0.0) {
-      double hc = __shfl(hclk, 0, G);
+      double hc = bcast<G>(hclk, 0);
       bool stop = false;
       while (e_next > hc + lp.window) {
         const double tw = hc + lp.window;
@@ -999,6 +1044,7 @@ __device__ void chain_events(const Dev &D, const Geo &g, const LegP &lp, int32_t
         }
         if (++it >= iter_cap) {
           if (lane == 0) {
+            __hip_atomic_exchange(&D.ctl->hang_site, (int32_t)HS_LAG_WAIT, __ATOMIC_RELAXED, SC);
             __hip_atomic_exchange(&D.ctl->error, (int32_t)ECMC_EHANG, __ATOMIC_RELAXED, SC);
             __hip_atomic_store(&D.ctl->abort, 1, __ATOMIC_RELAXED, SC);
           }
@@ -1012,11 +1058,11 @@ __device__ void chain_events(const Dev &D, const Geo &g, const LegP &lp, int32_t
           ab2 = __hip_atomic_load(&D.ctl->abort, __ATOMIC_RELAXED, SC);
           h2 = ld_a<SC>(&D.ctl->clock);
         }
-        if (__shfl(ab2, 0, G)) {
+        if (bcast<G>(ab2, 0)) {
           stop = true;
           break;
         }
-        hc = __shfl(h2, 0, G);
+        hc = bcast<G>(h2, 0);
       }
       if (stop) break;
     }
@@ -1031,7 +1077,7 @@ __device__ void chain_events(const Dev &D, const Geo &g, const LegP &lp, int32_t
     if (viol) {
       int bad = -1, clr = 0;
       if (lane == 0) bad = horizon_check<SC>(D, g, a, p, t, trem, e_next, gt, gsl, gpj, gaj, gtj, ts, clr, lp.features);
-      bad = __shfl(bad, 0, G);
+      bad = bcast<G>(bad, 0);
       cnt[C_CLEARED] += clr;
       if (bad == -2) {  // a record was being rewritten: scan again
         cnt[C_CASFAIL] += (lane == 0);
@@ -1076,7 +1122,7 @@ __device__ void chain_events(const Dev &D, const Geo &g, const LegP &lp, int32_t
         if (rk0 == yield_key && o < D.k)
           live = __float_as_uint(__double2float_rd(ld_a<SC>(&D.NEXT[o]))) == (uint32_t)(yield_key >> 32);
       }
-      live = __shfl(live, 0, G);
+      live = bcast<G>(live, 0);
       if (live) {
         cnt[C_WAITS] += (lane == 0);
         __builtin_amdgcn_s_sleep(4);
@@ -1138,9 +1184,9 @@ __device__ void chain_events(const Dev &D, const Geo &g, const LegP &lp, int32_t
         st_a<SC>(&D.MUT[s].t, t_prev);
       }
     }
-    won = __shfl(won, 0, G);
+    won = bcast<G>(won, 0);
     if (!won) {
-      old = __shfl(old, 0, G);
+      old = bcast<G>(old, 0);
       if (old == TAG_STALLED || old == TAG_PAUSED) {
         // it sits where it is at the breakpoint with t = breakpoint, and this
         // chain would reach it earlier: a horizon violation
@@ -1170,7 +1216,7 @@ __device__ void chain_events(const Dev &D, const Geo &g, const LegP &lp, int32_t
               }
             }
           }
-          bad = __shfl(bad, 0, G);
+          bad = bcast<G>(bad, 0);
           if (bad) {
             __builtin_amdgcn_s_sleep(4);
             continue;
@@ -1189,9 +1235,9 @@ __device__ void chain_events(const Dev &D, const Geo &g, const LegP &lp, int32_t
       __builtin_amdgcn_s_sleep(4);
       continue;
     }
-    aj2 = __shfl(aj2, 0, G);
-    tj2 = __shfl(tj2, 0, G);
-    stale = __shfl(stale, 0, G);
+    aj2 = bcast<G>(aj2, 0);
+    tj2 = bcast<G>(tj2, 0);
+    stale = bcast<G>(stale, 0);
     if (stale == 2) {
       if (lane == 0) {
         __hip_atomic_store(&D.REF[c].ver, ref_ver, __ATOMIC_RELAXED, SC);
@@ -1215,7 +1261,7 @@ __device__ void chain_events(const Dev &D, const Geo &g, const LegP &lp, int32_t
     }
     // another chain reserved the target for an earlier lifting and still has
     // that lifting pending: give the target back and let it go first
-    rk = __shfl(rk, 0, G);
+    rk = bcast<G>(rk, 0);
     if ((lp.features & ECMC_FEAT_RESERVE) && rk != RES_EMPTY && rk < mykey && (int)(rk & 0xffffffffu) != c) {
       int live = 0;
       if (lane == 0) {
@@ -1231,7 +1277,7 @@ __device__ void chain_events(const Dev &D, const Geo &g, const LegP &lp, int32_t
           st_rel<SC>(&D.TAG[ts], TAG_STATIC);
         }
       }
-      live = __shfl(live, 0, G);
+      live = bcast<G>(live, 0);
       if (live) {
         cnt[C_YIELDS] += (lane == 0);
         yield_slot = ts;
@@ -1758,6 +1804,7 @@ __device__ void round_decide(const Dev &D, double H, long long ev_after, long lo
   lc.R = R;
   lc.do_rb = 1;
   if (lc.rounds > (1ll << 20)) {
+    C.hang_site = HS_ROUNDS;
     C.error = ECMC_EHANG;
     lc.phase = PH_FAILED;
     return;
@@ -2231,6 +2278,20 @@ Layout make_layout(int64_t n, int32_t nc, int32_t kmax, int64_t log_cap, uint32_
   return L;
 }
 
+
+// Host text of a device-raised error.
+static const char *device_error_text(int e, int hang_site) {
+  if (e == ECMC_ECELL) return "a cell received more than 4 disks";
+  if (e != ECMC_EHANG) return "device error";
+  switch (hang_site) {
+    case HS_SCAN: return "event chain iteration limit reached (scan and claim loop)";
+    case HS_LAG_WAIT: return "event chain iteration limit reached (waiting at the bounded lag)";
+    case HS_CLOCK: return "event chain iteration limit reached (clock workgroup)";
+    case HS_ROUNDS: return "event chain iteration limit reached (rollback rounds of one leg)";
+    default: return "event chain iteration limit reached";
+  }
+}
+
 #define HIPCHK(expr)                          \
   do {                                        \
     if ((expr) != hipSuccess) {               \
@@ -2367,9 +2428,7 @@ int attempt(ecmc_ctx *ctx, int dir, double h, double tend, bool final, bool glob
   if (rc) return rc;
   ctx->attempts += global ? 0 : 1;
   if (hc.error) {
-    ctx->err = hc.error == ECMC_ECELL ? "a cell received more than 4 disks"
-                                      : (hc.error == ECMC_EHANG ? "event chain iteration limit reached"
-                                                                : "device error");
+    ctx->err = device_error_text(hc.error, hc.hang_site);
     return hc.error;
   }
   *violated = hc.abort != 0;
@@ -2513,8 +2572,7 @@ int run_leg(ecmc_ctx *ctx, int dir, double T) {
     ctx->inject_chain = -1;  // the hook has fired (the device cleared it)
     if (lc.phase == PH_FAILED) {
       const int e = hc.error ? hc.error : ECMC_EDEVICE;
-      ctx->err = e == ECMC_ECELL ? "a cell received more than 4 disks"
-                                 : (e == ECMC_EHANG ? "event chain iteration limit reached" : "device error");
+      ctx->err = device_error_text(e, hc.hang_site);
       return e;
     }
     if (lc.phase == PH_OVERFLOW) {

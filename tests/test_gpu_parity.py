@@ -326,3 +326,16 @@ def test_protocol_refinements_are_scheduling_only(features):
                                              (pkg.OPT_WINDOW_MICRO, 200_000)))
     ref = oracle.run(x, y, 1.0, L, act, dirs, T)
     check_parity(e, ref, L, 128, f"features={features}")
+
+
+def test_precision_workload_parity_with_lag():
+    """N = 65536, k = 256, two legs of T = 33.9 alternating, bounded lag
+    0.2 sigma, both forms: identical to the oracle."""
+    s = W.config(2)
+    dirs = s.leg_dirs(2)
+    ref = oracle.run(s.x, s.y, 1.0, s.L, s.active, dirs, s.T, log_cap=1 << 21)
+    for flags in (pkg.FP64, pkg.FP32_MIXED):
+        e = gpu_run(s.x, s.y, s.L, s.active, dirs, s.T, log_cap=1 << 12, flags=flags,
+                    opts=((pkg.OPT_WINDOW_MICRO, 200_000),))
+        check_parity(e, ref, s.L, s.k, f"cfg2 flags={flags}")
+        assert e.overlaps() == 0
