@@ -38,16 +38,17 @@ def _src_hash():
     return h.hexdigest()[:16]
 
 
-PMC_SUMMARY = os.path.join(ROOT, "profiles", "event_kernel_N1048576_pmc.json")
+def pmc_summary_path(form):
+    return os.path.join(ROOT, "profiles", f"event_kernel_N1048576_{form}_pmc.json")
 
 
-def _traffic(events_per_launch):
+def _traffic(form, events_per_launch):
     """HBM bytes per event-kernel launch: the bytes per lifting measured by the
     committed rocprofv3 counter summary (FETCH_SIZE + WRITE_SIZE, calibrated on
     a copy of known size) times this run's liftings per launch.  None if the
     summary is missing or was taken on another kernel source."""
     try:
-        with open(PMC_SUMMARY) as f:
+        with open(pmc_summary_path(form)) as f:
             d = json.load(f)
     except (OSError, ValueError):
         return None
@@ -82,7 +83,7 @@ def _stats_delta(st0, st1):
     return d
 
 
-def run_form(form, steps, warmup, lanes, window_micro):
+def run_form(form, steps, warmup, lanes, window_micro, max_splits=0):
     import numpy as np
     import torch
 
@@ -95,6 +96,8 @@ def run_form(form, steps, warmup, lanes, window_micro):
     e.set_option(pkg.OPT_LANES, lanes)
     e.set_option(pkg.OPT_KERNEL_TIMING, 1)
     e.set_option(pkg.OPT_WINDOW_MICRO, window_micro)
+    if max_splits:
+        e.set_option(pkg.OPT_MAX_SPLITS, max_splits)
     e.set_active(s.active)
     if warmup:
         e.run(warmup * s.T, s.T, pkg.DIR_ALTERNATE)
@@ -122,6 +125,7 @@ def run_form(form, steps, warmup, lanes, window_micro):
         "legs": d["legs"], "legs_violated": d["legs_violated"], "reruns": d["reruns"],
         "global_legs": d["global_legs"], "lockstep_runs": d["lockstep_runs"],
         "violations_screened": d["violations_screened"], "claim_yields": d["claim_yields"],
+        "spin_aborts": d["spin_aborts"],
         "violations_by_kind": d["violations_by_kind"], "attempts": d["attempts"],
         "slots_per_event": d["slots_scanned"] / max(d["events"], 1),
         "events_per_launch": d["timed_events"] / launches,
@@ -191,7 +195,7 @@ def run_batch(n_rep, target, t_frac, graph=1):
     return out
 
 
-def profile_run(legs, lanes, window_micro):
+def profile_run(legs, lanes, window_micro, form):
     """Short run for hardware-counter collection: a few legs of the workload,
     then a device copy of 256 MiB (read 256 MiB, write 256 MiB) whose counter
     readings calibrate the bytes the counters report."""
@@ -201,14 +205,16 @@ def profile_run(legs, lanes, window_micro):
     import paper_2004_11040_amd as pkg
     import workloads as W
     s = W.config(4)
-    e = pkg.Ecmc(np.stack([s.x, s.y], 1), s.sigma, s.L, max_chains=s.k, log_cap=1 << 12)
+    flags = pkg.FP32_MIXED if form == "fp32" else pkg.FP64
+    e = pkg.Ecmc(np.stack([s.x, s.y], 1), s.sigma, s.L, max_chains=s.k, log_cap=1 << 12, flags=flags)
     e.set_option(pkg.OPT_LANES, lanes)
     e.set_option(pkg.OPT_WINDOW_MICRO, window_micro)
     e.set_option(pkg.OPT_KERNEL_TIMING, 1)
     e.set_active(s.active)
     e.run(legs * s.T, s.T, pkg.DIR_ALTERNATE)
     st = e.stats()
-    print(json.dumps({"profile_run": True, "events": st["events"], "attempts": st["attempts"],
+    print(json.dumps({"profile_run": True, "form": form, "lanes": lanes,
+                      "events": st["events"], "attempts": st["attempts"],
                       "event_launches": st["event_launches"], "timed_events": st["timed_events"],
                       "slots_scanned": st["slots_scanned"]}), flush=True)
     a = torch.ones(256 << 20, dtype=torch.uint8, device="cuda")
@@ -246,12 +252,15 @@ def pmc_summary(fetch_csv, write_csv, profile_log):
         run = next(json.loads(line) for line in f if line.startswith("{") and "profile_run" in line)
     per_launch = (sum(ev_f) * 1024.0 * f_cal + sum(ev_w) * 1024.0 * w_cal) / max(len(ev_f), 1)
     events_per_launch = run["timed_events"] / max(run["event_launches"], 1)
-    d = {"source_sha256_16": _src_hash(), "kernel": "k_event<64>", "dispatches": len(ev_f),
+    form = run.get("form", "fp64")
+    d = {"source_sha256_16": _src_hash(), "form": form,
+         "kernel": f"k_event<{run.get('lanes', 64)}, {'true' if form == 'fp32' else 'false'}>",
+         "dispatches": len(ev_f),
          "fetch_kib_mean": sum(ev_f) / max(len(ev_f), 1), "write_kib_mean": sum(ev_w) / max(len(ev_w), 1),
          "copy_fetch_kib": cp_f, "copy_write_kib": cp_w, "fetch_calibration": f_cal, "write_calibration": w_cal,
          "hbm_bytes_per_launch": per_launch, "events_per_launch": events_per_launch,
          "hbm_bytes_per_event": per_launch / events_per_launch if events_per_launch else None}
-    with open(PMC_SUMMARY, "w") as f:
+    with open(pmc_summary_path(form), "w") as f:
         json.dump(d, f, indent=1)
     print(json.dumps(d))
 
@@ -263,11 +272,13 @@ def main():
     ap.add_argument("--pmc-summary", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "PROFILE_LOG"),
                     help="write the counter summary from two --profile-run counter runs")
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=60, help="timed legs")
+    ap.add_argument("--steps", type=int, default=200, help="timed legs")
     ap.add_argument("--warmup", type=int, default=4, help="untimed legs")
     ap.add_argument("--form", choices=["fp64", "fp32", "both"], default="both")
     ap.add_argument("--lanes", type=int, default=64)
-    ap.add_argument("--window-micro", type=int, default=200_000,
+    ap.add_argument("--max-splits", type=int, default=0,
+                    help="rollbacks without progress before a lockstep stretch (0: library default)")
+    ap.add_argument("--window-micro", type=int, default=100_000,
                     help="bounded lag between chains, in 1e-6 sigma (0: free running)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -287,17 +298,19 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
     if args.profile_run:
-        profile_run(args.profile_run, args.lanes, args.window_micro)
+        profile_run(args.profile_run, args.lanes, args.window_micro,
+                    "fp64" if args.form == "fp64" else "fp32")
         return
 
     forms = ["fp64", "fp32"] if args.form == "both" else [args.form]
-    results = {f: run_form(f, args.steps, args.warmup, args.lanes, args.window_micro) for f in forms}
+    results = {f: run_form(f, args.steps, args.warmup, args.lanes, args.window_micro, args.max_splits)
+               for f in forms}
     main_form = "fp32" if "fp32" in results else "fp64"
     r = results[main_form]
     kb = r["kernel_bytes_per_launch"]
     roof = {"bound": "hbm", "achieved": r["achieved_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": r["achieved_gbs"] / HBM_PEAK_GBS,
-            "traffic": _traffic(r["events_per_launch"]) if main_form == "fp64" else None,
+            "traffic": _traffic(main_form, r["events_per_launch"]),
             "kernel": f"k_event<{args.lanes}, {main_form}>", "bytes_per_launch": kb,
             "avg_launch_ms": r["kernel_ms_avg"]}
     import workloads as W

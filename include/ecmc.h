@@ -149,6 +149,12 @@ typedef struct {
   int64_t violations_screened;   /* failed Eq. 2 checks on a lane minimum that the
                                     activation record of its chain showed harmless */
   int64_t claim_yields;          /* claims given back to an earlier reservation */
+  int64_t spin_aborts;           /* attempts a chain aborted after 32768 rounds of
+                                    scan and claim without a lifting (the race goes
+                                    to the rollback; last_violation_kind 4, and
+                                    last_violation_disk then names the retry path:
+                                    1 rescan, 2 yield wait, 3 contact check,
+                                    4 active target, 5 changed records, 6 yield) */
 } ecmc_stats_t;
 
 /* Bytes of device workspace for a context.  n disks of radius sigma in a box of

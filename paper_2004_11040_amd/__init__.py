@@ -55,7 +55,8 @@ class Stats(ctypes.Structure):
                                       "last_violation_disk", "pad_")] + [
         (n, ctypes.c_double) for n in ("last_violation_t", "last_violation_tj",
                                        "last_violation_tau", "last_violation_h")] + [
-        (n, ctypes.c_int64) for n in ("lockstep_runs", "violations_screened", "claim_yields")]
+        (n, ctypes.c_int64) for n in ("lockstep_runs", "violations_screened", "claim_yields",
+                                      "spin_aborts")]
 
     def as_dict(self):
         d = {n: getattr(self, n) for n, _ in self._fields_ if n != "pad_"}

@@ -66,6 +66,7 @@ constexpr unsigned long long RES_EMPTY = ~0ull;  // no reservation on a slot
 constexpr double STOP_MARGIN = 1e-7;  // slack in the column lower bound (>> rounding)
 constexpr int64_t UNDO_CAP = 4096;     // undo records per chain and leg
 constexpr double LOCKSTEP_LAG = 0.03;  // bounded lag (units of sigma) of a stall-breaking stretch
+constexpr int SPIN_LIMIT = 1 << 15;      // scan and claim rounds without a lifting before a rollback
 
 struct MutRec {
   double a, t;
@@ -81,6 +82,12 @@ struct CstRec {
 // without waiting for each outcome.  A round whose leg has already finished
 // does nothing.
 enum { PH_RUN = 0, PH_DONE = 1, PH_FAILED = 2, PH_OVERFLOW = 3 };
+// kinds of horizon violations; VK_SPIN: a chain went SPIN_LIMIT rounds of
+// scan and claim without a lifting and handed its race to the rollback
+enum { VK_SCAN = 0, VK_CLAIM = 1, VK_BREAKPOINT_TARGET = 2, VK_MOVE = 3, VK_SPIN = 4, NVK = 5 };
+// retry paths of the scan and claim loop (recorded with VK_SPIN)
+enum { SP_RESCAN = 1, SP_YIELD_WAIT = 2, SP_CONTACT_CHECK = 3, SP_ACTIVE_TARGET = 4, SP_CHANGED = 5,
+       SP_YIELD = 6 };
 enum { MD_NORMAL = 0, MD_LOCKSTEP = 1, MD_GLOBAL = 2 };
 struct LegCtl {
   int32_t phase, mode;
@@ -89,7 +96,7 @@ struct LegCtl {
   double T, h, last_R, R, gend, tend_cur, lag_cur, window, base_lag;
   long long attempts, reruns, lockstep_runs, global_runs, legs_violated;
   long long timed_events, timed_slots, event_launches, event_ticks, rounds;
-  unsigned long long vkind[4];
+  unsigned long long vkind[NVK];
 };
 
 struct Ctl {
@@ -103,7 +110,7 @@ struct Ctl {
   double clock;     // H: smallest next-event time published by the chains
   int32_t done;     // chains that finished the attempt
   int32_t vkind_first;       // kind of the first violation of the attempt (-1: none)
-  unsigned long long vkind_cnt[4];  // violations by kind (see VK_*)
+  unsigned long long vkind_cnt[NVK];  // violations by kind (see VK_*)
   // first violation of the attempt: chain, its local time, the disk's stamp, tau, disk id
   int32_t v_chain, v_id;
   double v_t, v_tj, v_tau;
@@ -113,8 +120,6 @@ struct Ctl {
   unsigned long long t_start, t_end;
   LegCtl lc;
 };
-// kinds of horizon violations
-enum { VK_SCAN = 0, VK_CLAIM = 1, VK_BREAKPOINT_TARGET = 2, VK_MOVE = 3 };
 // loops bounded by an iteration limit (reported with ECMC_EHANG)
 enum { HS_NONE = 0, HS_SCAN = 1, HS_LAG_WAIT = 2, HS_CLOCK = 3, HS_ROUNDS = 4 };
 
@@ -466,7 +471,7 @@ __global__ void k_ctl_reset(Dev D, double h) {
     D.ctl->clock = h;
     D.ctl->done = 0;
     D.ctl->vkind_first = -1;
-    for (int q = 0; q < 4; ++q) D.ctl->vkind_cnt[q] = 0ull;
+    for (int q = 0; q < NVK; ++q) D.ctl->vkind_cnt[q] = 0ull;
   }
 }
 
@@ -812,6 +817,8 @@ __device__ void chain_events(const Dev &D, const Geo &g, const LegP &lp, int32_t
   // wait, instead of a round trip of their own
   int rel_slot = -1;
   long long rel_ver = 0;
+  // rounds of scan and claim since the last lifting, and the retry path taken last
+  int spins = 0, spin_site = 0;
   const double tend = lp.tend, h = lp.h;
 
   for (long long it = 0;; ++it) {
@@ -833,6 +840,12 @@ __device__ void chain_events(const Dev &D, const Geo &g, const LegP &lp, int32_t
     }
     if (inj_ev >= 0 && cnt[C_EVENTS] - ev_start == inj_ev) {  // test hook
       flag_violation<G, SC>(D, c, t > h ? t : h, lane);
+      break;
+    }
+    // a race that does not resolve itself goes to the rollback (whose ladder
+    // ends in global-time order) instead of spinning
+    if (++spins > SPIN_LIMIT) {
+      flag_violation<G, SC>(D, c, t > h ? t : h, lane, VK_SPIN, 0.0, 0.0, spin_site);
       break;
     }
 
@@ -1030,7 +1043,7 @@ __device__ void chain_events(const Dev &D, const Geo &g, const LegP &lp, int32_t
     }
     if (lp.window > 0.0) {
       double hc = bcast<G>(hclk, 0);
-      bool stop = false;
+      bool stop = false, requeue = false;
       while (e_next > hc + lp.window) {
         const double tw = hc + lp.window;
         if (tw > t_pub) {
@@ -1063,8 +1076,22 @@ __device__ void chain_events(const Dev &D, const Geo &g, const LegP &lp, int32_t
           break;
         }
         hc = bcast<G>(h2, 0);
+        if constexpr (G < 64) {
+          // the groups of a wavefront share one instruction stream: a group
+          // spinning here would keep the others, perhaps the chain that holds
+          // H back, from running.  After one poll it goes round the outer
+          // loop instead (and scans again).
+          if (e_next > hc + lp.window) {
+            requeue = true;
+            break;
+          }
+        }
       }
       if (stop) break;
+      if (requeue) {
+        --spins;  // waiting at the lag is not a stuck race
+        continue;
+      }
     }
 
     // ---- statement 5: horizon condition on the lane minima (scanned times) ----
@@ -1081,6 +1108,7 @@ __device__ void chain_events(const Dev &D, const Geo &g, const LegP &lp, int32_t
       cnt[C_CLEARED] += clr;
       if (bad == -2) {  // a record was being rewritten: scan again
         cnt[C_CASFAIL] += (lane == 0);
+        spin_site = SP_RESCAN;
         continue;
       }
       if (bad >= 0) {
@@ -1126,6 +1154,7 @@ __device__ void chain_events(const Dev &D, const Geo &g, const LegP &lp, int32_t
       if (live) {
         cnt[C_WAITS] += (lane == 0);
         __builtin_amdgcn_s_sleep(4);
+        spin_site = SP_YIELD_WAIT;
         continue;
       }
       yield_slot = -1;
@@ -1219,6 +1248,7 @@ __device__ void chain_events(const Dev &D, const Geo &g, const LegP &lp, int32_t
           bad = bcast<G>(bad, 0);
           if (bad) {
             __builtin_amdgcn_s_sleep(4);
+            spin_site = SP_CONTACT_CHECK;
             continue;
           }
           const double an = fwd_move(a, tau, g);
@@ -1233,6 +1263,7 @@ __device__ void chain_events(const Dev &D, const Geo &g, const LegP &lp, int32_t
         }
       }
       __builtin_amdgcn_s_sleep(4);
+      spin_site = SP_ACTIVE_TARGET;
       continue;
     }
     aj2 = bcast<G>(aj2, 0);
@@ -1257,6 +1288,7 @@ __device__ void chain_events(const Dev &D, const Geo &g, const LegP &lp, int32_t
         st_rel<SC>(&D.TAG[ts], TAG_STATIC);  // statement 20
       }
       cnt[C_CASFAIL] += (lane == 0);
+      spin_site = SP_CHANGED;
       continue;
     }
     // another chain reserved the target for an earlier lifting and still has
@@ -1283,6 +1315,7 @@ __device__ void chain_events(const Dev &D, const Geo &g, const LegP &lp, int32_t
         yield_slot = ts;
         yield_key = rk;
         __builtin_amdgcn_s_sleep(4);
+        spin_site = SP_YIELD;
         continue;
       }
     }
@@ -1330,6 +1363,7 @@ __device__ void chain_events(const Dev &D, const Geo &g, const LegP &lp, int32_t
     t = tn;
     t_pub = tn;
     retries = 0;
+    spins = 0;
   }
   // group-wide sum of per-lane scan counts
   long long sc = lane_scanned, rf = lane_refined;
@@ -1507,13 +1541,26 @@ __device__ void g_scan(const Dev &D, const Geo &g, int s, double a, double p, do
   }
 }
 
+// Minimum of (e, c) over a wavefront (time first, then chain), in every lane.
+__device__ __forceinline__ void wave_min_key(double &e, int &c) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    const double e2 = __shfl_xor(e, off, 64);
+    const int c2 = __shfl_xor(c, off, 64);
+    if (e2 < e || (e2 == e && c2 < c)) {
+      e = e2;
+      c = c2;
+    }
+  }
+}
+
 __device__ void global_order(const Dev &D, const Geo &g, const LegP &lp) {
   if (D.ctl->error) return;
-  __shared__ double red_e[1024];
-  __shared__ int red_c[1024];
-  __shared__ int s_w, s_old, s_new;
+  __shared__ double red_e[16];
+  __shared__ int red_c[16];
+  __shared__ int s_w, s_old, s_new, s_stop;
   __shared__ double s_e;
-  const int tid = threadIdx.x, nt = blockDim.x;
+  const int tid = threadIdx.x, nt = blockDim.x, nwv = (nt + 63) >> 6;
   const double tend = lp.tend;
   // initial minima at global time h (disks that came to rest behind a moving
   // disk before h are not ahead of it).  Chains act from their references.
@@ -1541,23 +1588,22 @@ __device__ void global_order(const Dev &D, const Geo &g, const LegP &lp) {
         bc = c;
       }
     }
-    red_e[tid] = be;
-    red_c[tid] = bc;
-    __syncthreads();
-    for (int off = nt / 2; off > 0; off >>= 1) {
-      if (tid < off) {
-        const double e2 = red_e[tid + off];
-        const int c2 = red_c[tid + off];
-        if (e2 < red_e[tid] || (e2 == red_e[tid] && c2 < red_c[tid])) {
-          red_e[tid] = e2;
-          red_c[tid] = c2;
-        }
-      }
-      __syncthreads();
+    // earliest (time, chain): wavefront butterflies, then wavefront 0 over
+    // the per-wavefront results; thread 0 commits the lifting
+    wave_min_key(be, bc);
+    if ((tid & 63) == 0) {
+      red_e[tid >> 6] = be;
+      red_c[tid >> 6] = bc;
     }
-    if (red_c[0] == 0x7fffffff) break;  // no lifting before tend
-    if (tid == 0) {
-      const int w = red_c[0];
+    __syncthreads();
+    if (tid < 64) {
+      be = tid < nwv ? red_e[tid] : INFINITY;
+      bc = tid < nwv ? red_c[tid] : 0x7fffffff;
+      wave_min_key(be, bc);
+    }
+    if (tid == 0) s_stop = bc == 0x7fffffff;  // no lifting before tend
+    if (tid == 0 && bc != 0x7fffffff) {
+      const int w = bc;
       const int s = D.CH_SLOT[w];
       const int ts = D.GC_SLOT[w];
       const double tau = D.GC_TAU[w];
@@ -1602,6 +1648,7 @@ __device__ void global_order(const Dev &D, const Geo &g, const LegP &lp) {
     }
     __threadfence_block();
     __syncthreads();
+    if (s_stop) break;
     const int w = s_w, si = s_old, sj = s_new;
     const double e = s_e;
     for (int c = tid; c < D.k; c += nt) {
@@ -1698,7 +1745,7 @@ __device__ void round_prep(const Dev &D) {
     C.clock = h;
     C.done = 0;
     C.vkind_first = -1;
-    for (int q = 0; q < 4; ++q) C.vkind_cnt[q] = 0ull;
+    for (int q = 0; q < NVK; ++q) C.vkind_cnt[q] = 0ull;
     C.t_start = ~0ull;
     C.t_end = 0ull;
   }
@@ -1736,7 +1783,7 @@ __global__ void __launch_bounds__(1024) k_leg_init(Dev D, double T, double windo
     lc.base_lag = base_lag;
     lc.attempts = lc.reruns = lc.lockstep_runs = lc.global_runs = lc.legs_violated = 0;
     lc.timed_events = lc.timed_slots = lc.event_launches = lc.event_ticks = lc.rounds = 0;
-    for (int q = 0; q < 4; ++q) lc.vkind[q] = 0ull;
+    for (int q = 0; q < NVK; ++q) lc.vkind[q] = 0ull;
   }
   __syncthreads();
   round_prep(D);
@@ -1774,7 +1821,7 @@ __device__ void round_decide(const Dev &D, double H, long long ev_after, long lo
     lc.event_ticks += (long long)(C.t_end - C.t_start);
     lc.event_launches++;
   }
-  for (int q = 0; q < 4; ++q) lc.vkind[q] += C.vkind_cnt[q];
+  for (int q = 0; q < NVK; ++q) lc.vkind[q] += C.vkind_cnt[q];
   if (lc.mode == MD_LOCKSTEP) lc.lockstep_runs++;
   if (!C.abort) {
     if (lc.mode == MD_LOCKSTEP && !lc.final_cur) {
@@ -1951,7 +1998,7 @@ struct RepOut {          // results of the run
   int32_t pad;
   int64_t legs_run, legs_violated, rollbacks, global_runs;
   int64_t events_run;
-  int64_t vkind[4];
+  int64_t vkind[NVK];
 };
 
 __device__ double block_min_d(double v) {
@@ -2013,7 +2060,7 @@ __device__ int replica_leg(const RepIn &ri, RepOut *rp, int dir, int32_t wait_re
       D.ctl->clock = h;
       D.ctl->done = 0;
       D.ctl->vkind_first = -1;
-      for (int q = 0; q < 4; ++q) D.ctl->vkind_cnt[q] = 0ull;
+      for (int q = 0; q < NVK; ++q) D.ctl->vkind_cnt[q] = 0ull;
     }
     for (int c = tid; c < D.k; c += nt) chains_attempt_one(D, h, c);
     for (int64_t i = tid; i < S; i += nt) D.RES[i] = RES_EMPTY;
@@ -2047,7 +2094,7 @@ __device__ int replica_leg(const RepIn &ri, RepOut *rp, int dir, int32_t wait_re
       s_i[2] = D.ctl->undo_overflow;
       s_d[0] = __longlong_as_double((long long)D.ctl->tstar_bits);
       s_d[1] = m;
-      for (int q = 0; q < 4; ++q) rp->vkind[q] += (long long)D.ctl->vkind_cnt[q];
+      for (int q = 0; q < NVK; ++q) rp->vkind[q] += (long long)D.ctl->vkind_cnt[q];
     }
     __syncthreads();
     const int abort = s_i[0], err = s_i[1], ovf = s_i[2];
@@ -2185,7 +2232,7 @@ struct ecmc_ctx {
   int32_t features = ECMC_FEAT_ALL;
   unsigned resident_nb = 0;   // grid size whose residency was last verified
   int32_t resident_key = 0;   // lanes * 2 + FP32 flag of that check
-  int64_t vkind[4] = {0, 0, 0, 0};
+  int64_t vkind[NVK] = {0, 0, 0, 0, 0};
   int32_t last_v_kind = -1, last_v_chain = -1, last_v_id = -1;
   double last_v_t = 0.0, last_v_tj = 0.0, last_v_tau = 0.0, last_v_h = 0.0;
   double window = 0.0;  // bounded lag in units of time (0: chains run freely)
@@ -2432,7 +2479,7 @@ int attempt(ecmc_ctx *ctx, int dir, double h, double tend, bool final, bool glob
     return hc.error;
   }
   *violated = hc.abort != 0;
-  for (int q = 0; q < 4; ++q) ctx->vkind[q] += (int64_t)hc.vkind_cnt[q];
+  for (int q = 0; q < NVK; ++q) ctx->vkind[q] += (int64_t)hc.vkind_cnt[q];
   if (hc.vkind_first >= 0) {
     ctx->last_v_kind = hc.vkind_first;
     ctx->last_v_chain = hc.v_chain;
@@ -2553,7 +2600,7 @@ int run_leg(ecmc_ctx *ctx, int dir, double T) {
     ctx->lockstep_runs += lc.lockstep_runs;
     ctx->global_legs += lc.global_runs;
     ctx->legs_violated += lc.legs_violated;
-    for (int q = 0; q < 4; ++q) ctx->vkind[q] += (int64_t)lc.vkind[q];
+    for (int q = 0; q < NVK; ++q) ctx->vkind[q] += (int64_t)lc.vkind[q];
     if (hc.vkind_first >= 0) {
       ctx->last_v_kind = hc.vkind_first;
       ctx->last_v_chain = hc.v_chain;
@@ -2849,6 +2896,7 @@ int ecmc_stats(ecmc_ctx *ctx, ecmc_stats_t *out) {
   out->timed_events = ctx->timed_events;
   out->timed_slots = ctx->timed_slots;
   for (int q = 0; q < 4; ++q) out->violations_by_kind[q] = ctx->vkind[q];
+  out->spin_aborts = ctx->vkind[VK_SPIN];
   out->last_violation_kind = ctx->last_v_kind;
   out->last_violation_chain = ctx->last_v_chain;
   out->last_violation_disk = ctx->last_v_id;
@@ -3193,7 +3241,7 @@ int batch_once(ecmc_batch *b, const int64_t *target, const double *leg_T, int32_
     ctx->legs_violated += R.legs_violated;
     ctx->reruns += R.rollbacks;
     ctx->global_legs += R.global_runs;
-    for (int q = 0; q < 4; ++q) ctx->vkind[q] += R.vkind[q];
+    for (int q = 0; q < NVK; ++q) ctx->vkind[q] += R.vkind[q];
     ev += R.events_run;
     b->info.legs += R.legs_run;
     b->info.rollbacks += R.rollbacks;

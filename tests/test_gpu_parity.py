@@ -124,13 +124,16 @@ def test_bounded_lag_window_is_pure_scheduling(window_micro):
     print("window", window_micro, "attempts", st["attempts"], "reruns", st["reruns"])
 
 
-def test_window_with_many_chains():
+@pytest.mark.parametrize("lanes", [64, 32, 16])
+def test_window_with_many_chains(lanes):
+    """With fewer lanes a wavefront runs several chains; a chain waiting at
+    the lag must not keep the others of its wavefront from running."""
     x, y, L, act = _square(161, 32, 0.70, 128)
     T = 0.2 * L
     dirs = [0, 1, 0, 1]
-    e = gpu_run(x, y, L, act, dirs, T, opts=((pkg.OPT_WINDOW_MICRO, 200_000),))
+    e = gpu_run(x, y, L, act, dirs, T, lanes=lanes, opts=((pkg.OPT_WINDOW_MICRO, 200_000),))
     ref = oracle.run(x, y, 1.0, L, act, dirs, T)
-    check_parity(e, ref, L, 128, "window k=128")
+    check_parity(e, ref, L, 128, f"window k=128 lanes={lanes}")
 
 
 def test_contact_moves_keep_exact_arithmetic():
