@@ -250,7 +250,10 @@ def pmc_summary(fetch_csv, write_csv, profile_log):
     w_cal = copy_bytes / (cp_w * 1024.0)
     with open(profile_log) as f:
         run = next(json.loads(line) for line in f if line.startswith("{") and "profile_run" in line)
-    per_launch = (sum(ev_f) * 1024.0 * f_cal + sum(ev_w) * 1024.0 * w_cal) / max(len(ev_f), 1)
+    # rounds enqueued past the end of a leg are dispatched but return at once:
+    # totals over every dispatch, per launch that ran an attempt
+    total = sum(ev_f) * 1024.0 * f_cal + sum(ev_w) * 1024.0 * w_cal
+    per_launch = total / max(run["event_launches"], 1)
     events_per_launch = run["timed_events"] / max(run["event_launches"], 1)
     form = run.get("form", "fp64")
     d = {"source_sha256_16": _src_hash(), "form": form,
@@ -258,6 +261,7 @@ def pmc_summary(fetch_csv, write_csv, profile_log):
          "dispatches": len(ev_f),
          "fetch_kib_mean": sum(ev_f) / max(len(ev_f), 1), "write_kib_mean": sum(ev_w) / max(len(ev_w), 1),
          "copy_fetch_kib": cp_f, "copy_write_kib": cp_w, "fetch_calibration": f_cal, "write_calibration": w_cal,
+         "launches_that_ran": run["event_launches"], "liftings": run["timed_events"],
          "hbm_bytes_per_launch": per_launch, "events_per_launch": events_per_launch,
          "hbm_bytes_per_event": per_launch / events_per_launch if events_per_launch else None}
     with open(pmc_summary_path(form), "w") as f:
