@@ -246,8 +246,9 @@ void ecmc_free(ecmc_ctx *ctx);
  * workgroup takes a replica from a device queue and runs its legs, with the
  * breakpoint synchronisation, rollbacks (Sec. 3.4, strategy 2) and the
  * global-order fallback (Alg. 2) done on the device; its chains share the
- * workgroup's compute unit, so their shared fields need workgroup-scope
- * atomics only.  Results are read per replica with the per-context calls
+ * workgroup's compute unit and use the same agent-scope atomics and
+ * completion waits as ecmc_run.  Results are read per replica with the
+ * per-context calls
  * (ecmc_stats, ecmc_get_positions, ecmc_get_log, ...), and are identical to
  * running each context with ecmc_run and no bounded lag.
  * Requirements: all contexts on one stream, all FP64 or all FP32-mixed,
