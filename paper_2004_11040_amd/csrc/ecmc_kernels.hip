@@ -490,8 +490,7 @@ struct Win {
 };
 
 // Broadcast from lane `src` of the group (src the same in every lane of the
-// group).  A whole wavefront reads the lane into a scalar register; narrower
-// groups go through the LDS crossbar.
+// group), through the LDS crossbar.
 template <int G>
 __device__ __forceinline__ int bcast(int v, int src) {
   return __shfl(v, src, G);
@@ -513,33 +512,85 @@ __device__ __forceinline__ double bcast(double v, int src) {
   return __longlong_as_double(bcast<G>((long long)__double_as_longlong(v), src));
 }
 
-// One step of a (tau, id) minimum with the lane DPP selects (same row of 16).
+// Wavefront-wide minima, the result in every lane, with VALU cross-lane moves
+// only (a few cycles each, against a round trip through the LDS crossbar for
+// a shuffle): DPP inside each row of 16 lanes (swap neighbours, swap pairs,
+// rotate by 4, rotate by 8), then the gfx950 row swaps (rows 0/1 and 2/3,
+// then the two halves).  All 64 lanes must be active.  Non-negative binary32
+// and binary64 values order like their bit patterns as unsigned integers.
 template <int CTRL>
-__device__ __forceinline__ void dpp_min_step(double &tau, int &id) {
-  const long long b = __double_as_longlong(tau);
-  const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffff), CTRL, 0xF, 0xF, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
-  const int i2 = __builtin_amdgcn_update_dpp(0, id, CTRL, 0xF, 0xF, false);
-  const double t2 = __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
-  if (key_less(t2, i2, tau, id)) {
-    tau = t2;
-    id = i2;
+__device__ __forceinline__ uint32_t dpp_u32(uint32_t x) {
+  return (uint32_t)__builtin_amdgcn_update_dpp((int)x, (int)x, CTRL, 0xF, 0xF, false);
+}
+__device__ __forceinline__ uint32_t umin32(uint32_t a, uint32_t b) { return a < b ? a : b; }
+__device__ __forceinline__ unsigned long long umin64(unsigned long long a, unsigned long long b) {
+  return a < b ? a : b;
+}
+__device__ __forceinline__ uint32_t wave_umin32(uint32_t x) {
+  x = umin32(x, dpp_u32<0xB1>(x));   // quad_perm [1,0,3,2]
+  x = umin32(x, dpp_u32<0x4E>(x));   // quad_perm [2,3,0,1]
+  x = umin32(x, dpp_u32<0x124>(x));  // row_ror:4
+  x = umin32(x, dpp_u32<0x128>(x));  // row_ror:8
+  const auto r16 = __builtin_amdgcn_permlane16_swap(x, x, false, false);
+  x = umin32(r16[0], r16[1]);
+  const auto r32 = __builtin_amdgcn_permlane32_swap(x, x, false, false);
+  return umin32(r32[0], r32[1]);
+}
+template <int CTRL>
+__device__ __forceinline__ unsigned long long dpp_u64(unsigned long long x) {
+  const uint32_t lo = dpp_u32<CTRL>((uint32_t)x), hi = dpp_u32<CTRL>((uint32_t)(x >> 32));
+  return ((unsigned long long)hi << 32) | lo;
+}
+__device__ __forceinline__ unsigned long long wave_umin64(unsigned long long x) {
+  x = umin64(x, dpp_u64<0xB1>(x));
+  x = umin64(x, dpp_u64<0x4E>(x));
+  x = umin64(x, dpp_u64<0x124>(x));
+  x = umin64(x, dpp_u64<0x128>(x));
+  {
+    const auto lo = __builtin_amdgcn_permlane16_swap((uint32_t)x, (uint32_t)x, false, false);
+    const auto hi = __builtin_amdgcn_permlane16_swap((uint32_t)(x >> 32), (uint32_t)(x >> 32), false, false);
+    x = umin64(((unsigned long long)hi[0] << 32) | lo[0], ((unsigned long long)hi[1] << 32) | lo[1]);
   }
+  {
+    const auto lo = __builtin_amdgcn_permlane32_swap((uint32_t)x, (uint32_t)x, false, false);
+    const auto hi = __builtin_amdgcn_permlane32_swap((uint32_t)(x >> 32), (uint32_t)(x >> 32), false, false);
+    x = umin64(((unsigned long long)hi[0] << 32) | lo[0], ((unsigned long long)hi[1] << 32) | lo[1]);
+  }
+  return x;
 }
 
-// Group minimum of (tau, id), the result in every lane of the group.  A whole
-// wavefront reduces each row of 16 lanes with DPP (quad swaps, then rotations
-// by 4 and 8) and combines the four rows from scalar reads.
+// Group minimum of (tau, id) in the order of key_less, the result in every
+// lane of the group (tau >= 0 or +inf).  A whole wavefront takes the minimum
+// time, then the smallest id among the lanes that hold it.
 template <int G>
 __device__ __forceinline__ void grp_min(double &tau, int &id) {
+  if constexpr (G == 64) {
+    const unsigned long long k = (unsigned long long)__double_as_longlong(tau + 0.0);  // -0 -> +0
+    const unsigned long long m = wave_umin64(k);
+    id = (int)wave_umin32(k == m ? (uint32_t)id : 0x7fffffffu);
+    tau = __longlong_as_double((long long)m);
+  } else {
 #pragma unroll
     for (int off = G / 2; off > 0; off >>= 1) {
-      double t2 = __shfl_xor(tau, off, G);
-      int i2 = __shfl_xor(id, off, G);
+      const double t2 = __shfl_xor(tau, off, G);
+      const int i2 = __shfl_xor(id, off, G);
       if (key_less(t2, i2, tau, id)) {
         tau = t2;
         id = i2;
-        }
+      }
+    }
+  }
+}
+
+// Group minimum of a non-negative binary32 value (or +inf).
+template <int G>
+__device__ __forceinline__ float grp_min_f32(float v) {
+  if constexpr (G == 64) {
+    return __uint_as_float(wave_umin32(__float_as_uint(v + 0.f)));
+  } else {
+#pragma unroll
+    for (int off = G / 2; off > 0; off >>= 1) v = fminf(v, __shfl_xor(v, off, G));
+    return v;
   }
 }
 
@@ -933,8 +984,7 @@ __device__ void chain_events(const Dev &D, const Geo &g, const LegP &lp, int32_t
         }
 #pragma unroll
         for (int q = 0; q < 3; ++q) {
-#pragma unroll
-          for (int off = G / 2; off > 0; off >>= 1) ub[q] = fminf(ub[q], __shfl_xor(ub[q], off, G));
+          ub[q] = grp_min_f32<G>(ub[q]);
           const float ex = gt[q] < INFINITY ? (float)gt[q] * (1.f + 1e-6f) + 1e-6f : INFINITY;
           ub[q] = fminf(ub[q], ex);  // exact minimum of the earlier passes, rounded up
         }
