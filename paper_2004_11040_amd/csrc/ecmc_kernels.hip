@@ -403,7 +403,7 @@ __global__ void k_chains_attempt(Dev D, double h) {
 // claim (smallest lifting time, then smallest old local time: local times of a
 // disk only grow, so that is the first claim); a chain gets the reference it had
 // at R and republishes the point its disk reaches at R (a pause at R).
-__device__ void rb_mark_one(const Dev &D, double R, int c) {
+__device__ __forceinline__ void rb_mark_one(const Dev &D, double R, int c) {
   const long long n = D.UNDO_N[c];
   D.UNDO_N_OLD[c] = n;
   for (long long m = n - 1; m >= 0; --m) {
@@ -412,7 +412,7 @@ __device__ void rb_mark_one(const Dev &D, double R, int c) {
     atomicMin(&D.RKEY[u.sj], (unsigned long long)__double_as_longlong(u.e));
   }
 }
-__device__ void rb_mark2_one(const Dev &D, double R, int c) {
+__device__ __forceinline__ void rb_mark2_one(const Dev &D, double R, int c) {
   for (long long m = D.UNDO_N_OLD[c] - 1; m >= 0; --m) {
     const UndoRec &u = D.UNDO[(int64_t)c * D.undo_cap + m];
     if (!(u.e >= R)) break;
@@ -420,7 +420,7 @@ __device__ void rb_mark2_one(const Dev &D, double R, int c) {
       atomicMin(&D.RKEY2[u.sj], (unsigned long long)__double_as_longlong(u.tj));
   }
 }
-__device__ void rb_apply_one(const Dev &D, const Geo &g, double R, int c) {
+__device__ __forceinline__ void rb_apply_one(const Dev &D, const Geo &g, double R, int c) {
   const long long n = D.UNDO_N_OLD[c];
   long long m = n - 1;
   for (; m >= 0; --m) {
@@ -448,7 +448,7 @@ __device__ void rb_apply_one(const Dev &D, const Geo &g, double R, int c) {
     D.UNDO_N[c] = n - nu;
   }
 }
-__device__ void rb_reset_one(const Dev &D, const Geo &g, double R, int c) {
+__device__ __forceinline__ void rb_reset_one(const Dev &D, const Geo &g, double R, int c) {
   for (long long m = D.UNDO_N[c]; m < D.UNDO_N_OLD[c]; ++m) {
     const UndoRec &u = D.UNDO[(int64_t)c * D.undo_cap + m];
     D.RKEY[u.sj] = 0x7FF0000000000000ull;
@@ -1553,7 +1553,7 @@ __global__ void k_chains_commit(Dev D) {
 // lifting can change.  Cannot violate a horizon; slow, used only when reruns
 // with shorter breakpoints keep failing.
 // ------------------------------------------------------------------------
-__device__ void g_scan(const Dev &D, const Geo &g, int s, double a, double p, double tc,
+__device__ __forceinline__ void g_scan(const Dev &D, const Geo &g, int s, double a, double p, double tc,
                        double tnow, double bound, double &btau, int &bslot, double &bb) {
   btau = INFINITY;
   bslot = -1;
@@ -1604,7 +1604,7 @@ __device__ __forceinline__ void wave_min_key(double &e, int &c) {
   }
 }
 
-__device__ void global_order(const Dev &D, const Geo &g, const LegP &lp) {
+__device__ __forceinline__ void global_order_gm(const Dev &D, const Geo &g, const LegP &lp) {
   if (D.ctl->error) return;
   __shared__ double red_e[16];
   __shared__ int red_c[16];
@@ -1738,6 +1738,256 @@ __device__ void global_order(const Dev &D, const Geo &g, const LegP &lp) {
     D.TAG[s] = lp.final ? TAG_STALLED : TAG_PAUSED;
   }
 }
+// g_scan by a whole wavefront (all 64 lanes active): 5 home columns x 3 rows
+// x 4 slots per pass, one slot per lane, the minimum (tau, id) with the
+// VALU reductions.  Same candidates and stop rule as g_scan, applied per pass
+// (columns past the stop point hold no disk nearer than the minimum found),
+// so the same result.
+__device__ __forceinline__ void g_scan_wave(const Dev &D, const Geo &g, int s, double a, double p, double tc,
+                            double tnow, double bound, double &btau, int &bslot, double &bb) {
+  const int lane = threadIdx.x & 63;
+  btau = INFINITY;
+  bslot = -1;
+  bb = 0.0;
+  int bid = 0x7fffffff;
+  const int cell0 = s >> 2;
+  const int row0 = cell0 / g.nc, col0 = cell0 - row0 * g.nc;
+  double u = a - col0 * g.c;
+  if (u < 0.0) u = u + g.L;
+  for (int m0 = 0; m0 <= g.mmax; m0 += 5) {
+    double tau = INFINITY, b = 0.0;
+    int id = 0x7fffffff, sl = -1;
+    const int mc = m0 + lane / (ROWS * CAP);
+    if (lane < 5 * ROWS * CAP && mc <= g.mmax) {
+      int col = col0 + mc;
+      if (col >= g.nc) col -= g.nc;
+      int row = row0 + (lane % (ROWS * CAP)) / CAP - 1;
+      row = row < 0 ? row + g.nc : (row >= g.nc ? row - g.nc : row);
+      sl = ((row * g.nc + col) << 2) + (lane % CAP);
+      const int jd = D.CST[sl].id;
+      if (jd >= 0 && sl != s && D.TAG[sl] == TAG_STATIC) {
+        double bj, dp;
+        const double tj = tof(a, p, D.MUT[sl].a, D.CST[sl].p, g, bj, dp);
+        if (tj < bound && !(tc + tj < tnow)) {
+          tau = tj;
+          id = jd;
+          b = bj;
+        }
+      }
+    }
+    double mt = tau;
+    int mi = id;
+    grp_min<64>(mt, mi);
+    if (key_less(mt, mi, btau, bid)) {
+      const int own = grp_owner<64>(tau == mt && id == mi, lane);
+      btau = mt;
+      bid = mi;
+      bslot = __shfl(sl, own, 64);
+      bb = __shfl(b, own, 64);
+    }
+    const double lim = btau < bound ? btau : bound;
+    if ((m0 + 5) * g.c - u - g.d - STOP_MARGIN > lim) break;
+  }
+}
+
+// Chains whose state a global-order stretch keeps in LDS (more: global_order_gm).
+constexpr int GO_KLDS = 1024;
+
+// Global-time order (Alg. 2) over the stretch [h, tend] on one workgroup.
+// Chain state (reference, pending minimum) lives in LDS; per lifting the
+// workgroup takes the earliest (time, chain), thread 0 commits it, every
+// chain compares its minimum with the disk that stopped, and wavefront 0
+// rescans the chain that moved on (and, one by one, any chain whose target
+// just became active).
+__device__ __forceinline__ void global_order(const Dev &D, const Geo &g, const LegP &lp) {
+  if (D.ctl->error) return;
+  if (D.k > GO_KLDS) {
+    global_order_gm(D, g, lp);
+    return;
+  }
+  __shared__ double l_t[GO_KLDS], l_a[GO_KLDS], l_p[GO_KLDS], l_tau[GO_KLDS], l_b[GO_KLDS];
+  __shared__ int l_s[GO_KLDS], l_ts[GO_KLDS], l_tid[GO_KLDS];
+  __shared__ double red_e[16];
+  __shared__ int red_c[16];
+  __shared__ int s_w, s_old, s_new, s_stop, s_idold, s_nrs;
+  __shared__ double s_e, s_an, s_pold;
+  __shared__ int s_rs[64];
+  const int tid = threadIdx.x, nt = blockDim.x, nwv = (nt + 63) >> 6;
+  const double tend = lp.tend;
+  // initial minima at global time h (disks that came to rest behind a moving
+  // disk before h are not ahead of it).  Chains act from their references.
+  for (int c = tid; c < D.k; c += nt) {
+    const int s = D.CH_SLOT[c];
+    const double tc0 = D.CH_T[c], a0 = D.CH_A[c], p0 = D.CST[s].p;
+    double bt, bb;
+    int bs;
+    g_scan(D, g, s, a0, p0, tc0, tc0 > lp.h ? tc0 : lp.h, tend - tc0, bt, bs, bb);
+    l_s[c] = s;
+    l_t[c] = tc0;
+    l_a[c] = a0;
+    l_p[c] = p0;
+    l_tau[c] = bt;
+    l_ts[c] = bs;
+    l_tid[c] = bs >= 0 ? D.CST[bs].id : 0x7fffffff;
+    l_b[c] = bb;
+  }
+  __syncthreads();
+  for (;;) {
+    double be = INFINITY;
+    int bc = 0x7fffffff;
+    for (int c = tid; c < D.k; c += nt) {
+      const double tcc = l_t[c];
+      const double tau = l_tau[c];
+      if (!(tau < tend - tcc)) continue;
+      const double e = tcc + tau;
+      if (e < be || (e == be && c < bc)) {
+        be = e;
+        bc = c;
+      }
+    }
+    // earliest (time, chain): wavefront butterflies, then wavefront 0 over
+    // the per-wavefront results; thread 0 commits the lifting
+    wave_min_key(be, bc);
+    if ((tid & 63) == 0) {
+      red_e[tid >> 6] = be;
+      red_c[tid >> 6] = bc;
+    }
+    __syncthreads();
+    if (tid < 64) {
+      be = tid < nwv ? red_e[tid] : INFINITY;
+      bc = tid < nwv ? red_c[tid] : 0x7fffffff;
+      wave_min_key(be, bc);
+    }
+    if (tid == 0) {
+      s_stop = bc == 0x7fffffff;  // no lifting before tend
+      s_nrs = 0;
+    }
+    if (tid == 0 && bc != 0x7fffffff) {
+      const int w = bc;
+      const int s = l_s[w];
+      const int ts = l_ts[w];
+      const double tau = l_tau[w];
+      const double tn = l_t[w] + tau;
+      const double an = fwd_move(l_a[w], tau, g);
+      const long long un = D.UNDO_N[w];
+      const MutRec mj = D.MUT[ts];
+      const CstRec cj = D.CST[ts];
+      if (un < D.undo_cap) {
+        UndoRec u;
+        u.e = tn;
+        u.si = s;
+        u.sj = ts;
+        u.ai = l_a[w];
+        u.ti = l_t[w];
+        u.aj = mj.a;
+        u.tj = mj.t;
+        u.sumb = D.SUMB_W[w];
+        u.pad = 0.0;
+        D.UNDO[(int64_t)w * D.undo_cap + un] = u;
+      } else {
+        D.ctl->undo_overflow = 1;
+      }
+      D.UNDO_N[w] = un + 1;
+      MutRec mi;
+      mi.a = an;
+      mi.t = tn;
+      D.MUT[s] = mi;
+      D.MUT[ts].t = tn;
+      D.TAG[s] = TAG_STATIC;
+      D.TAG[ts] = (uint32_t)w;
+      const long long len = D.LOGLEN_W[w];
+      D.LOG[(int64_t)w * D.log_cap + (len % D.log_cap)] = cj.id;
+      D.LOGLEN_W[w] = len + 1;
+      D.CNT_W[w * NCNT + C_EVENTS] += 1;
+      D.SUMB_W[w] = D.SUMB_W[w] + l_b[w];
+      D.CH_SLOT[w] = ts;
+      D.CH_A[w] = mj.a;
+      D.CH_T[w] = tn;
+      s_w = w;
+      s_old = s;
+      s_new = ts;
+      s_e = tn;
+      s_an = an;
+      s_pold = l_p[w];
+      s_idold = D.CST[s].id;
+      l_s[w] = ts;
+      l_a[w] = mj.a;
+      l_t[w] = tn;
+      l_p[w] = cj.p;
+    }
+    __threadfence_block();
+    __syncthreads();
+    if (s_stop) break;
+    const int w = s_w, si = s_old, sj = s_new, idold = s_idold;
+    const double e = s_e, an = s_an, pold = s_pold;
+    // every other chain: the disk that stopped may now be its nearest
+    for (int c = tid; c < D.k; c += nt) {
+      if (c == w) continue;
+      if (l_ts[c] == sj) {  // its target became active: full rescan below
+        const int q = atomicAdd(&s_nrs, 1);
+        if (q < 64) s_rs[q] = c;
+        continue;
+      }
+      const double tcc = l_t[c];
+      const double bound = tend - tcc;
+      double b, dp;
+      const double tau = tof(l_a[c], l_p[c], an, pold, g, b, dp);
+      if (tau < bound && !(tcc + tau < e) && key_less(tau, idold, l_tau[c], l_tid[c])) {
+        l_tau[c] = tau;
+        l_ts[c] = si;
+        l_tid[c] = idold;
+        l_b[c] = b;
+      }
+    }
+    __syncthreads();
+    if (tid < 64) {  // wavefront 0: the chain that moved on, then the chains that lost their target
+      const int nrs = s_nrs;
+      for (int q = -1; q < nrs; ++q) {
+        const int c = q < 0 ? w : (q < 64 ? s_rs[q] : -1);
+        if (c < 0) continue;  // more than 64: left to the serial pass below
+        double bt, bb;
+        int bs;
+        g_scan_wave(D, g, l_s[c], l_a[c], l_p[c], l_t[c], e, tend - l_t[c], bt, bs, bb);
+        if (tid == 0) {
+          l_tau[c] = bt;
+          l_ts[c] = bs;
+          l_tid[c] = bs >= 0 ? D.CST[bs].id : 0x7fffffff;
+          l_b[c] = bb;
+        }
+      }
+    }
+    if (s_nrs > 64) {  // rare overflow: the remaining chains rescan serially
+      for (int c = tid; c < D.k; c += nt) {
+        bool listed = (c == w);
+        for (int q = 0; q < 64 && !listed; ++q) listed = s_rs[q] == c;
+        if (!listed && l_ts[c] == sj) {
+          double bt, bb;
+          int bs;
+          g_scan(D, g, l_s[c], l_a[c], l_p[c], l_t[c], e, tend - l_t[c], bt, bs, bb);
+          l_tau[c] = bt;
+          l_ts[c] = bs;
+          l_tid[c] = bs >= 0 ? D.CST[bs].id : 0x7fffffff;
+          l_b[c] = bb;
+        }
+      }
+    }
+    __threadfence_block();
+    __syncthreads();
+  }
+  // breakpoint: every chain publishes the point reached there; at h' it stalls
+  for (int c = tid; c < D.k; c += nt) {
+    const int s = l_s[c];
+    const double tcc = l_t[c];
+    const double an = fwd_move(l_a[c], tend - tcc, g);
+    MutRec m;
+    m.a = an;
+    m.t = tend;
+    D.MUT[s] = m;
+    D.TAG[s] = lp.final ? TAG_STALLED : TAG_PAUSED;
+  }
+}
+// Out-of-line copy for the replica workgroups, whose kernel is large already.
+__device__ __noinline__ void global_order_call(const Dev &D, const Geo &g, const LegP &lp) { global_order(D, g, lp); }
 __global__ void __launch_bounds__(1024) k_global(Dev D, Geo g, LegP lp) { global_order(D, g, lp); }
 // ---- device-decided rounds --------------------------------------------------
 // A round is two launches: the event kernel, then k_round_end on one block of
@@ -1748,7 +1998,7 @@ __global__ void __launch_bounds__(1024) k_global(Dev D, Geo g, LegP lp) { global
 
 // Block-wide (1024 threads max) sums of the chains' lifting and scan counters
 // and minimum of their next-event times.
-__device__ void round_reduce(const Dev &D, double *m_out, long long *e_out, long long *sl_out) {
+__device__ __forceinline__ void round_reduce(const Dev &D, double *m_out, long long *e_out, long long *sl_out) {
   __shared__ double rm[32];
   __shared__ long long re[32], rs[32];
   double m = INFINITY;
@@ -1784,7 +2034,7 @@ __device__ void round_reduce(const Dev &D, double *m_out, long long *e_out, long
 
 // Prepare an attempt from lc.h: reset the attempt's flags, tag every chain's
 // disk, seed next-event times, record the work counters before the launch.
-__device__ void round_prep(const Dev &D) {
+__device__ __forceinline__ void round_prep(const Dev &D) {
   const double h = D.ctl->lc.h;
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -1840,7 +2090,7 @@ __global__ void __launch_bounds__(1024) k_leg_init(Dev D, double T, double windo
 }
 
 // The decision after an attempt (thread 0): returns nothing; writes lc.
-__device__ void round_decide(const Dev &D, double H, long long ev_after, long long sl_after) {
+__device__ __forceinline__ void round_decide(const Dev &D, double H, long long ev_after, long long sl_after) {
   Ctl &C = *D.ctl;
   LegCtl &lc = C.lc;
   lc.rounds++;
@@ -2089,6 +2339,15 @@ __device__ __noinline__ void replica_build(const Dev &D, const Geo &g, int dir) 
 
 // One leg [0, T] of one replica, all of a8 on the device.  Returns ECMC_OK or
 // an error code (the same value in every thread).
+// Out-of-line copy of a chain's events for the replica workgroups: called,
+// it keeps its own register budget apart from the leg and rollback code
+// around it (inlined there, the kernel runs out of registers).
+template <int G, bool F32, int SC>
+__device__ __noinline__ void chain_events_call(const Dev &D, const Geo &g, const LegP &lp, int32_t wait_retries,
+                                               long long iter_cap, int c, int lane) {
+  chain_events<G, F32, SC>(D, g, lp, wait_retries, iter_cap, c, lane);
+}
+
 template <int G, bool F32>
 __device__ int replica_leg(const RepIn &ri, RepOut *rp, int dir, int32_t wait_retries, int32_t features) {
   const Dev &D = ri.D;
@@ -2131,7 +2390,7 @@ __device__ int replica_leg(const RepIn &ri, RepOut *rp, int dir, int32_t wait_re
       const int rot = (int)((tries * 37) % D.k);
       if (tg < D.k) {
         const int c = tg + rot < D.k ? tg + rot : tg + rot - D.k;
-        chain_events<G, F32, SCA>(D, g, lp, wait_retries, 1ll << 24, c, lane);
+        chain_events_call<G, F32, SCA>(D, g, lp, wait_retries, 1ll << 24, c, lane);
       }
     }
     __syncthreads();
@@ -2162,7 +2421,7 @@ __device__ int replica_leg(const RepIn &ri, RepOut *rp, int dir, int32_t wait_re
       replica_build(D, g, dir);
       if (D.ctl->error) return D.ctl->error;
       lp.h = 0.0;
-      global_order(D, g, lp);
+      global_order_call(D, g, lp);
       __syncthreads();
       if (tid == 0) rp->global_runs++;
       break;
@@ -2186,7 +2445,7 @@ __device__ int replica_leg(const RepIn &ri, RepOut *rp, int dir, int32_t wait_re
       lp.final = fin ? 1 : 0;
       lp.h = h;
       lp.tend = fin ? T : gend;
-      global_order(D, g, lp);
+      global_order_call(D, g, lp);
       __syncthreads();
       if (tid == 0) rp->global_runs++;
       if (D.ctl->error) return D.ctl->error;
