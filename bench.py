@@ -187,6 +187,8 @@ def run_batch(n_rep, target, t_frac, graph=1):
            "device_ms": info["device_ms"], "lanes": info["lanes"], "graph": info["graph"],
            "workgroups": info["workgroups"], "legs": info["legs"], "rollbacks": info["rollbacks"],
            "global_runs": info["global_runs"], "autotune_events_per_ms": tune["tune_events_per_ms"],
+           "replica_ms_max": info["replica_ms_max"],
+           "load_balance": info["replica_ms_sum"] / max(info["workgroups"] * info["device_ms"], 1e-9),
            "overlaps": overlaps, "total_disks": int(sum(s.n for s in reps)),
            "total_chains": int(sum(s.k for s in reps))}
     b.close()

@@ -267,10 +267,13 @@ typedef struct {
   int64_t global_runs;  /* global-order stretches in the last call         */
   double tune_events_per_ms[4]; /* autotuner: liftings per ms with 4, 8, 16,
                                    32 lanes per chain (0: not tried)      */
+  double replica_ms_max;  /* longest device time of one replica in the main launch */
+  double replica_ms_sum;  /* summed over replicas: with device_ms and workgroups
+                             this gives the launch's load balance        */
 } ecmc_batch_info_t;
 
-/* Bytes of device scratch for a batch of n_ctx contexts (descriptors and the
- * work queue).  Negative ECMC_EINVAL for n_ctx outside [1, 2^20]. */
+/* Bytes of device scratch for a batch of n_ctx contexts (descriptors, the
+ * work queue and its order, longest expected replica first).  Negative ECMC_EINVAL for n_ctx outside [1, 2^20]. */
 int64_t ecmc_batch_scratch_bytes(int32_t n_ctx);
 
 /* Group n_ctx distinct contexts (HOST array of handles; the contexts must

@@ -68,7 +68,8 @@ class BatchInfo(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int32) for n in ("lanes", "graph", "workgroups", "pad_")] + [
         ("device_ms", ctypes.c_double)] + [
         (n, ctypes.c_int64) for n in ("events", "legs", "rollbacks", "global_runs")] + [
-        ("tune_events_per_ms", ctypes.c_double * 4)]
+        ("tune_events_per_ms", ctypes.c_double * 4)] + [
+        (n, ctypes.c_double) for n in ("replica_ms_max", "replica_ms_sum")]
 
     def as_dict(self):
         d = {n: getattr(self, n) for n, _ in self._fields_ if n != "pad_"}

@@ -2299,6 +2299,7 @@ struct RepOut {          // results of the run
   int64_t legs_run, legs_violated, rollbacks, global_runs;
   int64_t events_run;
   int64_t vkind[NVK];
+  unsigned long long ticks;  // device time the replica's legs took (100 MHz)
 };
 
 __device__ double block_min_d(double v) {
@@ -2478,11 +2479,15 @@ __device__ int replica_leg(const RepIn &ri, RepOut *rp, int dir, int32_t wait_re
 
 template <int G, bool F32>
 __global__ void __launch_bounds__(512) k_batch(const RepIn *__restrict__ reps, RepOut *outs, int32_t n_rep,
-                                               int32_t *queue, int32_t wait_retries, int32_t features) {
+                                               int32_t *queue, const int32_t *__restrict__ order,
+                                               int32_t wait_retries, int32_t features) {
   __shared__ int s_rep;
   for (;;) {
     __syncthreads();
-    if (threadIdx.x == 0) s_rep = atomicAdd(queue, 1);
+    if (threadIdx.x == 0) {  // replicas in the order the host chose (longest expected first)
+      const int q = atomicAdd(queue, 1);
+      s_rep = q < n_rep ? order[q] : n_rep;
+    }
     __syncthreads();
     // the same value in every thread (the block leaves together); made a
     // scalar so that the replica's descriptor is read with scalar loads
@@ -2491,6 +2496,7 @@ __global__ void __launch_bounds__(512) k_batch(const RepIn *__restrict__ reps, R
     const RepIn &ri = reps[r];
     RepOut *rp = &outs[r];
     const Dev &D = ri.D;
+    const unsigned long long tk0 = __builtin_amdgcn_s_memrealtime();
     long long ev0 = 0;
     for (int c = threadIdx.x; c < D.k; c += blockDim.x) ev0 += D.CNT_C[c * NCNT + C_EVENTS];
     ev0 = block_sum_ll(ev0);
@@ -2512,6 +2518,7 @@ __global__ void __launch_bounds__(512) k_batch(const RepIn *__restrict__ reps, R
     if (threadIdx.x == 0) {
       rp->legs_run = legs;
       rp->events_run = ev - ev0;
+      rp->ticks = __builtin_amdgcn_s_memrealtime() - tk0;
     }
   }
 }
@@ -3388,6 +3395,11 @@ struct ecmc_batch {
   RepIn *d_in = nullptr;
   RepOut *d_out = nullptr;
   int32_t *d_queue = nullptr;
+  int32_t *d_order = nullptr;  // queue position -> replica
+  // per replica: liftings committed through this batch, device ticks per lifting (0: not measured)
+  std::vector<int64_t> ev_seen;
+  std::vector<double> ticks_per_event;
+  double rep_ms_max = 0.0, rep_ms_sum = 0.0;  // replicas' device times in the last launch
   int32_t lanes = 0;        // 0: autotune at the first run
   int32_t tuned = 0;        // lanes chosen by the autotuner
   int32_t use_graph = 0;
@@ -3433,8 +3445,8 @@ int batch_grid(ecmc_batch *b, int *grid) {
 template <int G, bool F32>
 int batch_enqueue(ecmc_batch *b, int grid, hipStream_t st) {
   k_fill<int32_t><<<1, 64, 0, st>>>(b->d_queue, 0, 1);
-  k_batch<G, F32><<<grid, 512, 0, st>>>(b->d_in, b->d_out, (int32_t)b->ctxs.size(), b->d_queue, b->wait_retries,
-                                        b->features);
+  k_batch<G, F32><<<grid, 512, 0, st>>>(b->d_in, b->d_out, (int32_t)b->ctxs.size(), b->d_queue, b->d_order,
+                                        b->wait_retries, b->features);
   BCHK(hipGetLastError());
   return ECMC_OK;
 }
@@ -3530,8 +3542,25 @@ int batch_once(ecmc_batch *b, const int64_t *target, const double *leg_T, int32_
     R.max_splits = ctx->max_splits;
     R.max_legs = max_legs;
   }
+  // longest expected run first, so that no long replica starts last: the
+  // remaining liftings times the measured device time per lifting, or per
+  // chain while a replica has not been measured
+  std::vector<int32_t> order((size_t)n);
+  {
+    bool all = true;
+    for (int r = 0; r < n; ++r) all = all && b->ticks_per_event[(size_t)r] > 0.0;
+    std::vector<double> cost((size_t)n);
+    for (int r = 0; r < n; ++r) {
+      const double rem = (double)std::max<int64_t>(target[r] - b->ev_seen[(size_t)r], 1);
+      cost[(size_t)r] = all ? rem * b->ticks_per_event[(size_t)r] : rem / (double)b->ctxs[(size_t)r]->D.k;
+      order[(size_t)r] = r;
+    }
+    std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) { return cost[(size_t)x] > cost[(size_t)y]; });
+  }
   BCHK(hipMemcpyAsync(b->d_in, h.data(), sizeof(RepIn) * (size_t)n, hipMemcpyHostToDevice, b->stream));
   BCHK(hipMemcpyAsync(b->d_out, ho.data(), sizeof(RepOut) * (size_t)n, hipMemcpyHostToDevice, b->stream));
+  BCHK(hipMemcpyAsync(b->d_order, order.data(), sizeof(int32_t) * (size_t)n, hipMemcpyHostToDevice, b->stream));
+  b->rep_ms_max = b->rep_ms_sum = 0.0;
   BCHK(hipEventRecord(b->e0, b->stream));
   int rc = batch_launch(b, lanes);
   if (rc) return rc;
@@ -3552,6 +3581,10 @@ int batch_once(ecmc_batch *b, const int64_t *target, const double *leg_T, int32_
     ctx->global_legs += R.global_runs;
     for (int q = 0; q < NVK; ++q) ctx->vkind[q] += R.vkind[q];
     ev += R.events_run;
+    b->rep_ms_max = std::max(b->rep_ms_max, (double)R.ticks * 1e-5);  // s_memrealtime: 100 MHz
+    b->rep_ms_sum += (double)R.ticks * 1e-5;
+    b->ev_seen[(size_t)r] += R.events_run;
+    if (R.events_run > 0) b->ticks_per_event[(size_t)r] = (double)R.ticks / (double)R.events_run;
     b->info.legs += R.legs_run;
     b->info.rollbacks += R.rollbacks;
     b->info.global_runs += R.global_runs;
@@ -3574,7 +3607,7 @@ extern "C" {
 int64_t ecmc_batch_scratch_bytes(int32_t n_ctx) {
   if (n_ctx < 1 || n_ctx > (1 << 20)) return ECMC_EINVAL;
   return align_up((int64_t)n_ctx * (int64_t)sizeof(RepIn)) + align_up((int64_t)n_ctx * (int64_t)sizeof(RepOut)) +
-         ALIGN;
+         ALIGN + align_up((int64_t)n_ctx * (int64_t)sizeof(int32_t));
 }
 
 int ecmc_batch_create(ecmc_batch **out, ecmc_ctx *const *ctxs, int32_t n_ctx, void *scratch,
@@ -3598,6 +3631,9 @@ int ecmc_batch_create(ecmc_batch **out, ecmc_ctx *const *ctxs, int32_t n_ctx, vo
   b->d_in = (RepIn *)scratch;
   b->d_out = (RepOut *)((char *)scratch + align_up((int64_t)n_ctx * (int64_t)sizeof(RepIn)));
   b->d_queue = (int32_t *)((char *)b->d_out + align_up((int64_t)n_ctx * (int64_t)sizeof(RepOut)));
+  b->d_order = (int32_t *)((char *)b->d_queue + ALIGN);
+  b->ev_seen.assign((size_t)n_ctx, 0);
+  b->ticks_per_event.assign((size_t)n_ctx, 0.0);
   std::memset(&b->info, 0, sizeof(b->info));
   if (hipEventCreate(&b->e0) != hipSuccess || hipEventCreate(&b->e1) != hipSuccess) {
     delete b;
@@ -3684,6 +3720,8 @@ int ecmc_batch_run(ecmc_batch *b, const int64_t *target_events, const double *le
   b->info.device_ms = ms;
   b->info.events = ev;
   b->info.workgroups = b->last_grid;
+  b->info.replica_ms_max = b->rep_ms_max;
+  b->info.replica_ms_sum = b->rep_ms_sum;
   return rc;
 }
 
