@@ -148,7 +148,7 @@ def birthday_estimate(k, L, T, sigma=1.0):
     return 1.0 - math.exp(-k * k / (2.0 * n_regions))
 
 
-def run_batch(n_rep, target, t_frac, graph=1):
+def run_batch(n_rep, target, t_frac, graph=1, window_micro=0):
     """The replica workload: n_rep seeded replicas of N in {1024..16384}, eta in
     [0.60, 0.72], k = round(sqrt N), FP32-mixed, run in one persistent launch
     (captured in a hipGraph) until every replica has `target` liftings; the
@@ -167,6 +167,7 @@ def run_batch(n_rep, target, t_frac, graph=1):
         systems.append(e)
     b = pkg.Batch(systems)
     b.set_option(pkg.OPT_GRAPH, graph)
+    b.set_option(pkg.OPT_WINDOW_MICRO, window_micro)
     T = [t_frac * s.L for s in reps]
     big = np.full(n_rep, 1 << 60, np.int64)
     b.run(big, T, pkg.DIR_ALTERNATE, max_legs=1)  # autotune (one leg per lane count)
@@ -182,7 +183,8 @@ def run_batch(n_rep, target, t_frac, graph=1):
     print(f"[bench] batch: {ev1 - ev0} liftings in {wall:.2f} s", file=sys.stderr, flush=True)
     overlaps = sum(e.overlaps() for e in systems)
     out = {"workload": f"{n_rep} replicas, N in 64*[16,256], eta in [0.60,0.72], k=round(sqrt N), "
-                       f"legs of {t_frac} L alternating +x/+y, FP32-mixed, {target} liftings per replica",
+                       f"legs of {t_frac} L alternating +x/+y, FP32-mixed, {target} liftings per replica, "
+                       f"bounded lag {window_micro * 1e-6:g} sigma",
            "events": ev1 - ev0, "wall_s": wall, "events_per_s": (ev1 - ev0) / wall,
            "device_ms": info["device_ms"], "lanes": info["lanes"], "graph": info["graph"],
            "workgroups": info["workgroups"], "legs": info["legs"], "rollbacks": info["rollbacks"],
@@ -291,6 +293,8 @@ def main():
     ap.add_argument("--batch-replicas", type=int, default=512)
     ap.add_argument("--batch-events", type=int, default=1_000_000)
     ap.add_argument("--batch-leg-frac", type=float, default=0.25)
+    ap.add_argument("--batch-window-micro", type=int, default=250_000,
+                    help="bounded lag between a replica's chains, in 1e-6 sigma (0: free running)")
     ap.add_argument("--no-batch", action="store_true")
     args = ap.parse_args()
     if args.pmc_summary:
@@ -339,7 +343,8 @@ def main():
     if "fp32" in results and "fp64" in results:
         line["fp32_over_fp64"] = results["fp32"]["events_per_s"] / results["fp64"]["events_per_s"]
     if not args.no_batch:
-        line["batch"] = run_batch(args.batch_replicas, args.batch_events, args.batch_leg_frac)
+        line["batch"] = run_batch(args.batch_replicas, args.batch_events, args.batch_leg_frac,
+                                  window_micro=args.batch_window_micro)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
     print(json.dumps(line), flush=True)

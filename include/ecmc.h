@@ -285,7 +285,10 @@ int ecmc_batch_create(ecmc_batch **out, ecmc_ctx *const *ctxs, int32_t n_ctx,
                       void *scratch, int64_t scratch_bytes);
 
 /* ECMC_OPT_LANES (0: autotune at the first run; 4, 8, 16, 32),
- * ECMC_OPT_GRAPH, ECMC_OPT_FEATURES, ECMC_OPT_WAIT_RETRIES. */
+ * ECMC_OPT_GRAPH, ECMC_OPT_FEATURES, ECMC_OPT_WAIT_RETRIES, and
+ * ECMC_OPT_WINDOW_MICRO (bounded lag between a replica's chains in units of
+ * 1e-6 sigma, 0 = free; a chain waiting at the lag takes the replica's H from
+ * its chains' next-event times itself). */
 int ecmc_batch_set_option(ecmc_batch *b, int32_t key, int64_t value);
 
 /* Run every replica r with legs of length leg_T[r] (HOST arrays of n_ctx)

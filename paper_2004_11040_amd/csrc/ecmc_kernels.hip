@@ -170,6 +170,8 @@ struct LegP {
   int32_t strict;  // 1: add the formal agent-scope acquire/release fences
   double window;   // bounded lag: commit only events with time <= H + window (0: off)
   int32_t features;  // ECMC_FEAT_* bits
+  int32_t self_clock;  // 1: a chain waiting at the lag takes H from the chains' next-event
+                       // times itself (no clock workgroup: the replica workgroups)
 };
 
 // One committed lifting, as needed to take it back (restart from the earliest
@@ -1126,6 +1128,19 @@ __device__ void chain_events(const Dev &D, const Geo &g, const LegP &lp, int32_t
           break;
         }
         hc = bcast<G>(h2, 0);
+        if (lp.self_clock) {
+          // H from the next-event times of all chains, strided over the group
+          double m = INFINITY;
+          for (int o = lane; o < D.k; o += G) m = fmin(m, ld_a<SC>(&D.NEXT[o]));
+#pragma unroll
+          for (int off = G / 2; off > 0; off >>= 1) m = fmin(m, __shfl_xor(m, off, G));
+          if (m > hc) {
+            hc = m;
+            if (lane == 0)
+              __hip_atomic_fetch_max((unsigned long long *)&D.ctl->clock,
+                                     (unsigned long long)__double_as_longlong(m), __ATOMIC_RELAXED, SC);
+          }
+        }
         if constexpr (G < 64) {
           // the groups of a wavefront share one instruction stream: a group
           // spinning here would keep the others, perhaps the chain that holds
@@ -2292,6 +2307,7 @@ struct RepIn {
   int32_t max_splits;
   int32_t max_legs;      // at most this many legs in this run (0: no limit)
   int32_t pad;
+  double window;         // bounded lag between the replica's chains (0: free)
 };
 struct RepOut {          // results of the run
   int32_t status;        // ECMC_OK or the first error
@@ -2381,8 +2397,9 @@ __device__ int replica_leg(const RepIn &ri, RepOut *rp, int dir, int32_t wait_re
     lp.h = h;
     lp.tend = T;
     lp.strict = 0;
-    lp.window = 0.0;
+    lp.window = ri.window;
     lp.features = features;
+    lp.self_clock = 1;
     {
       // chains rotate over the lane groups from one attempt to the next: the
       // lanes of a wavefront issue their claims in one instruction with a fixed
@@ -2770,6 +2787,7 @@ int attempt(ecmc_ctx *ctx, int dir, double h, double tend, bool final, bool glob
   lp.strict = ctx->strict_order;
   lp.features = ctx->features;
   lp.window = window;
+  lp.self_clock = 0;
   const bool timed = !global && ctx->kernel_timing && ctx->kevents_ok;
   k_count_delta<<<1, 256, 0, ctx->stream>>>(D, 0);
   HIPCHK(hipGetLastError());
@@ -2894,6 +2912,7 @@ int run_leg(ecmc_ctx *ctx, int dir, double T) {
     lp0.strict = ctx->strict_order;
     lp0.window = 0.0;
     lp0.features = ctx->features;
+    lp0.self_clock = 0;
     Ctl hc;
     int nspec = 2;
     for (int64_t batch = 0;; ++batch) {
@@ -3400,6 +3419,7 @@ struct ecmc_batch {
   std::vector<int64_t> ev_seen;
   std::vector<double> ticks_per_event;
   double rep_ms_max = 0.0, rep_ms_sum = 0.0;  // replicas' device times in the last launch
+  double window_micro = 0.0;                  // bounded lag (1e-6 sigma); 0: chains run freely
   int32_t lanes = 0;        // 0: autotune at the first run
   int32_t tuned = 0;        // lanes chosen by the autotuner
   int32_t use_graph = 0;
@@ -3541,6 +3561,7 @@ int batch_once(ecmc_batch *b, const int64_t *target, const double *leg_T, int32_
     R.dir_mode = direction;
     R.max_splits = ctx->max_splits;
     R.max_legs = max_legs;
+    R.window = b->window_micro * 1e-6 * ctx->g.sigma;
   }
   // longest expected run first, so that no long replica starts last: the
   // remaining liftings times the measured device time per lifting, or per
@@ -3661,6 +3682,10 @@ int ecmc_batch_set_option(ecmc_batch *b, int32_t key, int64_t value) {
     case ECMC_OPT_WAIT_RETRIES:
       if (value < 1 || value > (1 << 20)) return ECMC_EINVAL;
       b->wait_retries = (int32_t)value;
+      return ECMC_OK;
+    case ECMC_OPT_WINDOW_MICRO:
+      if (value < 0 || value > (1ll << 50)) return ECMC_EINVAL;
+      b->window_micro = (double)value;
       return ECMC_OK;
     default:
       return ECMC_EINVAL;

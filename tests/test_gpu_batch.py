@@ -81,6 +81,24 @@ def test_batch_parity(lanes, graph):
         _check(e, ref, len(act), f"rep{i} continued")
 
 
+@pytest.mark.parametrize("window_micro,lanes,flags", [
+    (50_000, 4, pkg.FP64), (200_000, 8, pkg.FP32_MIXED), (1_000_000, 16, pkg.FP64)])
+def test_batch_bounded_lag_parity(window_micro, lanes, flags):
+    """A replica's chains wait at a bounded lag, each taking H from the
+    others' next-event times itself: scheduling only, same liftings and bits."""
+    reps = _small_replicas(6, 17)
+    systems = _make(reps, flags=flags)
+    b = pkg.Batch(systems)
+    b.set_option(pkg.OPT_LANES, lanes)
+    b.set_option(pkg.OPT_GRAPH, 1)
+    b.set_option(pkg.OPT_WINDOW_MICRO, window_micro)
+    big = np.full(len(reps), 1 << 60, np.int64)
+    b.run(big, [r[4] for r in reps], pkg.DIR_ALTERNATE, max_legs=3)
+    for i, ((x, y, L, act, T), e) in enumerate(zip(reps, systems)):
+        ref = oracle.run(x, y, 1.0, L, act, [0, 1, 0], T)
+        _check(e, ref, len(act), f"lag rep{i} w={window_micro} lanes={lanes}")
+
+
 def test_batch_fp32_mixed_and_autotune():
     reps = _small_replicas(5, 11)
     systems = _make(reps, flags=pkg.FP32_MIXED)
@@ -133,6 +151,7 @@ def test_batch_replica_workload_sample():
         systems.append(e)
     b = pkg.Batch(systems)
     b.set_option(pkg.OPT_LANES, 4)
+    b.set_option(pkg.OPT_WINDOW_MICRO, 300_000)
     big = np.full(len(reps), 1 << 60, np.int64)
     b.run(big, [s.T for s in reps], pkg.DIR_ALTERNATE, max_legs=1)
     for s, e in zip(reps, systems):
