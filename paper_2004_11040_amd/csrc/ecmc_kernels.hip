@@ -1758,8 +1758,13 @@ __device__ __forceinline__ void global_order_gm(const Dev &D, const Geo &g, cons
 // VALU reductions.  Same candidates and stop rule as g_scan, applied per pass
 // (columns past the stop point hold no disk nearer than the minimum found),
 // so the same result.
-__device__ __forceinline__ void g_scan_wave(const Dev &D, const Geo &g, int s, double a, double p, double tc,
-                            double tnow, double bound, double &btau, int &bslot, double &bb) {
+// Slot xs (>= 0) is skipped: the disk that just stopped behind the moving one,
+// whose record may be half rewritten by a commit running beside the scan.  It
+// cannot be hit within a leg (it is L - 2b >= L - 2d ahead, and legs are
+// shorter than L - 5d), so skipping it changes no result.
+__device__ __forceinline__ void g_scan_wave(const Dev &D, const Geo &g, int s, int xs, double a, double p,
+                                            double tc, double tnow, double bound, double &btau, int &bslot,
+                                            double &bb) {
   const int lane = threadIdx.x & 63;
   btau = INFINITY;
   bslot = -1;
@@ -1780,7 +1785,7 @@ __device__ __forceinline__ void g_scan_wave(const Dev &D, const Geo &g, int s, d
       row = row < 0 ? row + g.nc : (row >= g.nc ? row - g.nc : row);
       sl = ((row * g.nc + col) << 2) + (lane % CAP);
       const int jd = D.CST[sl].id;
-      if (jd >= 0 && sl != s && D.TAG[sl] == TAG_STATIC) {
+      if (jd >= 0 && sl != s && sl != xs && D.TAG[sl] == TAG_STATIC) {
         double bj, dp;
         const double tj = tof(a, p, D.MUT[sl].a, D.CST[sl].p, g, bj, dp);
         if (tj < bound && !(tc + tj < tnow)) {
@@ -1809,23 +1814,25 @@ __device__ __forceinline__ void g_scan_wave(const Dev &D, const Geo &g, int s, d
 constexpr int GO_KLDS = 1024;
 
 // Global-time order (Alg. 2) over the stretch [h, tend] on one workgroup.
-// Chain state (reference, pending minimum) lives in LDS; per lifting the
-// workgroup takes the earliest (time, chain), thread 0 commits it, every
-// chain compares its minimum with the disk that stopped, and wavefront 0
-// rescans the chain that moved on (and, one by one, any chain whose target
-// just became active).
+// Chain state (reference, pending minimum) lives in LDS.  Per lifting the
+// workgroup takes the earliest (time, chain); then, at once, one thread of
+// wavefront 1 commits it, wavefront 0 rescans the chain that moved on, and
+// the other threads compare their chains' minima with the disk that stopped
+// (everything they need is known before the commit); chains whose target
+// just became active rescan afterwards.  Needs at least two wavefronts.
 __device__ __forceinline__ void global_order(const Dev &D, const Geo &g, const LegP &lp) {
   if (D.ctl->error) return;
-  if (D.k > GO_KLDS) {
+  if (D.k > GO_KLDS || blockDim.x < 128) {
     global_order_gm(D, g, lp);
     return;
   }
   __shared__ double l_t[GO_KLDS], l_a[GO_KLDS], l_p[GO_KLDS], l_tau[GO_KLDS], l_b[GO_KLDS];
-  __shared__ int l_s[GO_KLDS], l_ts[GO_KLDS], l_tid[GO_KLDS];
+  __shared__ int l_s[GO_KLDS], l_ts[GO_KLDS], l_tid[GO_KLDS], l_id[GO_KLDS];
   __shared__ double red_e[16];
   __shared__ int red_c[16];
-  __shared__ int s_w, s_old, s_new, s_stop, s_idold, s_nrs;
-  __shared__ double s_e, s_an, s_pold;
+  // the lifting being committed
+  __shared__ int s_w, s_si, s_sj, s_idold, s_stop, s_nrs;
+  __shared__ double s_e, s_an, s_pold, s_ai, s_ti, s_b;
   __shared__ int s_rs[64];
   const int tid = threadIdx.x, nt = blockDim.x, nwv = (nt + 63) >> 6;
   const double tend = lp.tend;
@@ -1833,14 +1840,16 @@ __device__ __forceinline__ void global_order(const Dev &D, const Geo &g, const L
   // disk before h are not ahead of it).  Chains act from their references.
   for (int c = tid; c < D.k; c += nt) {
     const int s = D.CH_SLOT[c];
-    const double tc0 = D.CH_T[c], a0 = D.CH_A[c], p0 = D.CST[s].p;
+    const double tc0 = D.CH_T[c], a0 = D.CH_A[c];
+    const CstRec ci = D.CST[s];
     double bt, bb;
     int bs;
-    g_scan(D, g, s, a0, p0, tc0, tc0 > lp.h ? tc0 : lp.h, tend - tc0, bt, bs, bb);
+    g_scan(D, g, s, a0, ci.p, tc0, tc0 > lp.h ? tc0 : lp.h, tend - tc0, bt, bs, bb);
     l_s[c] = s;
     l_t[c] = tc0;
     l_a[c] = a0;
-    l_p[c] = p0;
+    l_p[c] = ci.p;
+    l_id[c] = ci.id;
     l_tau[c] = bt;
     l_ts[c] = bs;
     l_tid[c] = bs >= 0 ? D.CST[bs].id : 0x7fffffff;
@@ -1861,84 +1870,109 @@ __device__ __forceinline__ void global_order(const Dev &D, const Geo &g, const L
       }
     }
     // earliest (time, chain): wavefront butterflies, then wavefront 0 over
-    // the per-wavefront results; thread 0 commits the lifting
+    // the per-wavefront results
     wave_min_key(be, bc);
     if ((tid & 63) == 0) {
       red_e[tid >> 6] = be;
       red_c[tid >> 6] = bc;
     }
     __syncthreads();
+    int w = 0x7fffffff;        // wavefront 0: the chain that lifts
+    double wa = 0.0, wp = 0.0, wt = 0.0;  // wavefront 0: its new reference
+    int wsj = -1;
     if (tid < 64) {
       be = tid < nwv ? red_e[tid] : INFINITY;
       bc = tid < nwv ? red_c[tid] : 0x7fffffff;
       wave_min_key(be, bc);
+      w = bc;
+      if (w != 0x7fffffff) {
+        wsj = l_ts[w];
+        wt = l_t[w] + l_tau[w];
+        wa = D.MUT[wsj].a;  // the target's position: its new reference
+        wp = D.CST[wsj].p;
+      }
+      if (tid == 0) {
+        s_stop = w == 0x7fffffff;  // no lifting before tend
+        s_nrs = 0;
+        if (w != 0x7fffffff) {
+          s_w = w;
+          s_si = l_s[w];
+          s_sj = wsj;
+          s_e = wt;
+          s_ai = l_a[w];
+          s_ti = l_t[w];
+          s_b = l_b[w];
+          s_an = fwd_move(l_a[w], l_tau[w], g);
+          s_pold = l_p[w];
+          s_idold = l_id[w];
+        }
+      }
     }
-    if (tid == 0) {
-      s_stop = bc == 0x7fffffff;  // no lifting before tend
-      s_nrs = 0;
-    }
-    if (tid == 0 && bc != 0x7fffffff) {
-      const int w = bc;
-      const int s = l_s[w];
-      const int ts = l_ts[w];
-      const double tau = l_tau[w];
-      const double tn = l_t[w] + tau;
-      const double an = fwd_move(l_a[w], tau, g);
-      const long long un = D.UNDO_N[w];
-      const MutRec mj = D.MUT[ts];
-      const CstRec cj = D.CST[ts];
+    __syncthreads();
+    if (s_stop) break;
+    const int si = s_si, sj = s_sj, idold = s_idold;
+    const double e = s_e, an = s_an, pold = s_pold;
+    if (tid < 64) {
+      // wavefront 0: the chain that moved on scans from the target (its own
+      // old disk, now behind it, and the target's own record are not
+      // candidates, so the commit running beside it changes nothing here)
+      double bt, bb;
+      int bs;
+      g_scan_wave(D, g, sj, si, wa, wp, wt, e, tend - wt, bt, bs, bb);
+      if (tid == 0) {
+        l_tau[w] = bt;
+        l_ts[w] = bs;
+        l_tid[w] = bs >= 0 ? D.CST[bs].id : 0x7fffffff;
+        l_b[w] = bb;
+      }
+    } else if (tid == 64) {
+      // the commit (statements 14-19 of Alg. 2 for chain w)
+      const int cw = s_w;
+      const long long un = D.UNDO_N[cw];
+      const MutRec mj = D.MUT[sj];
+      const CstRec cj = D.CST[sj];
       if (un < D.undo_cap) {
         UndoRec u;
-        u.e = tn;
-        u.si = s;
-        u.sj = ts;
-        u.ai = l_a[w];
-        u.ti = l_t[w];
+        u.e = e;
+        u.si = si;
+        u.sj = sj;
+        u.ai = s_ai;
+        u.ti = s_ti;
         u.aj = mj.a;
         u.tj = mj.t;
-        u.sumb = D.SUMB_W[w];
+        u.sumb = D.SUMB_W[cw];
         u.pad = 0.0;
-        D.UNDO[(int64_t)w * D.undo_cap + un] = u;
+        D.UNDO[(int64_t)cw * D.undo_cap + un] = u;
       } else {
         D.ctl->undo_overflow = 1;
       }
-      D.UNDO_N[w] = un + 1;
+      D.UNDO_N[cw] = un + 1;
       MutRec mi;
       mi.a = an;
-      mi.t = tn;
-      D.MUT[s] = mi;
-      D.MUT[ts].t = tn;
-      D.TAG[s] = TAG_STATIC;
-      D.TAG[ts] = (uint32_t)w;
-      const long long len = D.LOGLEN_W[w];
-      D.LOG[(int64_t)w * D.log_cap + (len % D.log_cap)] = cj.id;
-      D.LOGLEN_W[w] = len + 1;
-      D.CNT_W[w * NCNT + C_EVENTS] += 1;
-      D.SUMB_W[w] = D.SUMB_W[w] + l_b[w];
-      D.CH_SLOT[w] = ts;
-      D.CH_A[w] = mj.a;
-      D.CH_T[w] = tn;
-      s_w = w;
-      s_old = s;
-      s_new = ts;
-      s_e = tn;
-      s_an = an;
-      s_pold = l_p[w];
-      s_idold = D.CST[s].id;
-      l_s[w] = ts;
-      l_a[w] = mj.a;
-      l_t[w] = tn;
-      l_p[w] = cj.p;
+      mi.t = e;
+      D.MUT[si] = mi;
+      D.MUT[sj].t = e;
+      D.TAG[si] = TAG_STATIC;
+      D.TAG[sj] = (uint32_t)cw;
+      const long long len = D.LOGLEN_W[cw];
+      D.LOG[(int64_t)cw * D.log_cap + (len % D.log_cap)] = cj.id;
+      D.LOGLEN_W[cw] = len + 1;
+      D.CNT_W[cw * NCNT + C_EVENTS] += 1;
+      D.SUMB_W[cw] = D.SUMB_W[cw] + s_b;
+      D.CH_SLOT[cw] = sj;
+      D.CH_A[cw] = mj.a;
+      D.CH_T[cw] = e;
+      l_s[cw] = sj;
+      l_a[cw] = mj.a;
+      l_t[cw] = e;
+      l_p[cw] = cj.p;
+      l_id[cw] = cj.id;
     }
-    __threadfence_block();
-    __syncthreads();
-    if (s_stop) break;
-    const int w = s_w, si = s_old, sj = s_new, idold = s_idold;
-    const double e = s_e, an = s_an, pold = s_pold;
     // every other chain: the disk that stopped may now be its nearest
+    const int cw = s_w;
     for (int c = tid; c < D.k; c += nt) {
-      if (c == w) continue;
-      if (l_ts[c] == sj) {  // its target became active: full rescan below
+      if (c == cw) continue;
+      if (l_ts[c] == sj) {  // its target became active: it rescans below
         const int q = atomicAdd(&s_nrs, 1);
         if (q < 64) s_rs[q] = c;
         continue;
@@ -1954,40 +1988,42 @@ __device__ __forceinline__ void global_order(const Dev &D, const Geo &g, const L
         l_b[c] = b;
       }
     }
-    __syncthreads();
-    if (tid < 64) {  // wavefront 0: the chain that moved on, then the chains that lost their target
-      const int nrs = s_nrs;
-      for (int q = -1; q < nrs; ++q) {
-        const int c = q < 0 ? w : (q < 64 ? s_rs[q] : -1);
-        if (c < 0) continue;  // more than 64: left to the serial pass below
-        double bt, bb;
-        int bs;
-        g_scan_wave(D, g, l_s[c], l_a[c], l_p[c], l_t[c], e, tend - l_t[c], bt, bs, bb);
-        if (tid == 0) {
-          l_tau[c] = bt;
-          l_ts[c] = bs;
-          l_tid[c] = bs >= 0 ? D.CST[bs].id : 0x7fffffff;
-          l_b[c] = bb;
-        }
-      }
-    }
-    if (s_nrs > 64) {  // rare overflow: the remaining chains rescan serially
-      for (int c = tid; c < D.k; c += nt) {
-        bool listed = (c == w);
-        for (int q = 0; q < 64 && !listed; ++q) listed = s_rs[q] == c;
-        if (!listed && l_ts[c] == sj) {
-          double bt, bb;
-          int bs;
-          g_scan(D, g, l_s[c], l_a[c], l_p[c], l_t[c], e, tend - l_t[c], bt, bs, bb);
-          l_tau[c] = bt;
-          l_ts[c] = bs;
-          l_tid[c] = bs >= 0 ? D.CST[bs].id : 0x7fffffff;
-          l_b[c] = bb;
-        }
-      }
-    }
     __threadfence_block();
     __syncthreads();
+    const int nrs = s_nrs;
+    if (nrs > 0) {  // rare: chains that lost their target, wavefront 0 one by one
+      if (tid < 64) {
+        for (int q = 0; q < nrs && q < 64; ++q) {
+          const int c = s_rs[q];
+          double bt, bb;
+          int bs;
+          g_scan_wave(D, g, l_s[c], -1, l_a[c], l_p[c], l_t[c], e, tend - l_t[c], bt, bs, bb);
+          if (tid == 0) {
+            l_tau[c] = bt;
+            l_ts[c] = bs;
+            l_tid[c] = bs >= 0 ? D.CST[bs].id : 0x7fffffff;
+            l_b[c] = bb;
+          }
+        }
+      }
+      if (nrs > 64) {  // more than 64: the remaining chains rescan serially
+        for (int c = tid; c < D.k; c += nt) {
+          bool listed = (c == cw);
+          for (int q = 0; q < 64 && !listed; ++q) listed = s_rs[q] == c;
+          if (!listed && l_ts[c] == sj) {
+            double bt, bb;
+            int bs;
+            g_scan(D, g, l_s[c], l_a[c], l_p[c], l_t[c], e, tend - l_t[c], bt, bs, bb);
+            l_tau[c] = bt;
+            l_ts[c] = bs;
+            l_tid[c] = bs >= 0 ? D.CST[bs].id : 0x7fffffff;
+            l_b[c] = bb;
+          }
+        }
+      }
+      __threadfence_block();
+      __syncthreads();
+    }
   }
   // breakpoint: every chain publishes the point reached there; at h' it stalls
   for (int c = tid; c < D.k; c += nt) {
@@ -2001,6 +2037,7 @@ __device__ __forceinline__ void global_order(const Dev &D, const Geo &g, const L
     D.TAG[s] = lp.final ? TAG_STALLED : TAG_PAUSED;
   }
 }
+
 // Out-of-line copy for the replica workgroups, whose kernel is large already.
 __device__ __noinline__ void global_order_call(const Dev &D, const Geo &g, const LegP &lp) { global_order(D, g, lp); }
 __global__ void __launch_bounds__(1024) k_global(Dev D, Geo g, LegP lp) { global_order(D, g, lp); }
