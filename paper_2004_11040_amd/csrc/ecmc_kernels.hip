@@ -627,49 +627,34 @@ __device__ __forceinline__ F32Cand tof_f32(int mc, int dr, float rai, float rpi,
                                            const Geo &g) {
   constexpr float U = 5.9604645e-8f;  // 2^-24, half an ulp of 1
   F32Cand r;
-  r.lo = r.hi = INFINITY;
-  r.cls_mask = 0;
-  r.cls = -1;
   // forward distance along v, reduced to [0, L) like the binary64 path
   const float off = (float)mc * g.c32;
-  float da = (off + raj) - rai;
-  float eda = 4.f * U * (fabsf(off) + fabsf(raj) + fabsf(rai) + g.c32 * (float)mc);
-  bool wrap_unsure = false;
-  if (da < 0.f) {
-    wrap_unsure = da > -eda;  // could be a tiny positive distance
-    da = da + g.L32;
-    eda += 4.f * U * g.L32;
-  } else if (da >= g.L32) {
-    da = da - g.L32;
-    eda += 4.f * U * g.L32;
-  }
-  if (da < eda || da > g.L32 - eda) wrap_unsure = true;
+  const float da0 = (off + raj) - rai;
+  const float eda0 = 4.f * U * (fabsf(off) + fabsf(raj) + fabsf(rai) + g.c32 * (float)mc);
+  const bool neg = da0 < 0.f, over = da0 >= g.L32;
+  const float da = neg ? da0 + g.L32 : (over ? da0 - g.L32 : da0);
+  const float eda = (neg || over) ? eda0 + 4.f * U * g.L32 : eda0;
+  // a wrapped distance that could be a tiny positive one, or one near 0 or L
+  const bool wrap_unsure = (neg && da0 > -eda0) || da < eda || da > g.L32 - eda;
   // perpendicular offset (minimum image through the row offset)
   const float dp = ((float)dr * g.c32 + rpj) - rpi;
   const float edp = 4.f * U * (g.c32 + fabsf(rpj) + fabsf(rpi));
   const float adp = fabsf(dp);
   const float x = g.d2_32 - dp * dp;
   const float ex = (2.f * adp + 2.f * edp) * edp + 4.f * U * (g.d2_32 + dp * dp);
-  if (!(x + ex > 0.f)) return r;  // certainly dp^2 >= d^2: outside the corridor
-  const float blo = sqrtf(fmaxf(x - ex, 0.f)) * (1.f - 4.f * U);
-  const float bhi = sqrtf(x + ex) * (1.f + 4.f * U);
+  const bool in = x + ex > 0.f;  // else certainly dp^2 >= d^2: outside the corridor
+  // v_sqrt_f32 is within one ulp (2U relative); with the subtraction's
+  // rounding and the product's, the factors 1 -+ 8U keep both ends outside
+  const float blo = __builtin_amdgcn_sqrtf(fmaxf(x - ex, 0.f)) * (1.f - 8.f * U);
+  const float bhi = __builtin_amdgcn_sqrtf(fmaxf(x + ex, 0.f)) * (1.f + 8.f * U);
   const float err = eda + 8.f * U * (da + bhi) + 1e-30f;
-  r.lo = wrap_unsure ? 0.f : fmaxf((da - bhi) - err, 0.f);
-  r.hi = (x - ex > 0.f && !wrap_unsure) ? fmaxf((da - blo) + err, 0.f) + 1e-30f : INFINITY;
+  r.lo = !in ? INFINITY : (wrap_unsure ? 0.f : fmaxf((da - bhi) - err, 0.f));
+  r.hi = (in && x - ex > 0.f && !wrap_unsure) ? fmaxf((da - blo) + err, 0.f) + 1e-30f : INFINITY;
   // lanes: |dp| < sigma -> 0, dp >= sigma -> 1, dp <= -sigma -> 2
   const float es = edp + 4.f * U * g.sigma32;
-  if (adp + es < g.sigma32) {
-    r.cls_mask = 1;
-    r.cls = 0;
-  } else if (dp - es >= g.sigma32) {
-    r.cls_mask = 2;
-    r.cls = 1;
-  } else if (dp + es <= -g.sigma32) {
-    r.cls_mask = 4;
-    r.cls = 2;
-  } else {
-    r.cls_mask = dp > 0.f ? 3 : 5;
-  }
+  const bool c0 = adp + es < g.sigma32, c1 = dp - es >= g.sigma32, c2 = dp + es <= -g.sigma32;
+  r.cls = !in ? -1 : (c0 ? 0 : (c1 ? 1 : (c2 ? 2 : -1)));
+  r.cls_mask = !in ? 0 : (c0 ? 1 : (c1 ? 2 : (c2 ? 4 : (dp > 0.f ? 3 : 5))));
   return r;
 }
 
@@ -926,11 +911,12 @@ __device__ void chain_events(const Dev &D, const Geo &g, const LegP &lp, int32_t
       // the slots of this pass, loaded once (records are reread only after a claim)
       CstRec crs[W::SPL];
       double ajs[W::SPL], tjs[W::SPL];
-      int sls[W::SPL];
+      int sls[W::SPL], scol[W::SPL], srow[W::SPL];
 #pragma unroll
       for (int r = 0; r < W::SPL; ++r) {
         const int w = lane + r * G;
         sls[r] = -1;
+        scol[r] = srow[r] = 0;
         crs[r].id = -1;
         crs[r].p = 0.0;
         ajs[r] = tjs[r] = 0.0;
@@ -944,6 +930,8 @@ __device__ void chain_events(const Dev &D, const Geo &g, const LegP &lp, int32_t
             row = row < 0 ? row + g.nc : (row >= g.nc ? row - g.nc : row);
             const int sl = ((row * g.nc + col) << 2) + (rem % CAP);
             sls[r] = sl;
+            scol[r] = col;
+            srow[r] = row;
             crs[r] = D.CST[sl];
             ajs[r] = ld_a<SC>(&D.MUT[sl].a);
             tjs[r] = ld_a<SC>(&D.MUT[sl].t);
@@ -973,9 +961,7 @@ __device__ void chain_events(const Dev &D, const Geo &g, const LegP &lp, int32_t
           fc[r].cls_mask = 0;
           fc[r].cls = -1;
           if (refine[r]) {
-            const int col = (sls[r] >> 2) % g.nc;
-            const int row = (sls[r] >> 2) / g.nc;
-            const float raj = (float)(ajs[r] - col * g.c), rpj = (float)(crs[r].p - row * g.c);
+            const float raj = (float)(ajs[r] - scol[r] * g.c), rpj = (float)(crs[r].p - srow[r] * g.c);
             const int w = lane + r * G;
             fc[r] = tof_f32(m0 + w / (ROWS * CAP), (w % (ROWS * CAP)) / CAP - 1, rai, rpi, raj, rpj, g);
             const bool not_behind = (tjs[r] > h) || (t + (double)fc[r].lo >= tjs[r]);
