@@ -858,6 +858,52 @@ __device__ void chain_events(const Dev &D, const Geo &g, const LegP &lp, int32_t
   // rounds of scan and claim since the last lifting, and the retry path taken last
   int spins = 0, spin_site = 0;
   const double tend = lp.tend, h = lp.h;
+  // The first pass of the next scan, loaded while the post-claim records are
+  // read (one round trip for both): the slots around the target's home cell,
+  // and the abort word and the clock.  Used only if the lifting is committed.
+  // Such a scan sees the records as they were just before this chain's own
+  // commit; the commit changes only the two disks of the lifting: the new
+  // moving disk (its own slot, never a candidate) and the disk that stopped,
+  // which sits at contact behind it, L - 2b >= L - 2d ahead along v, out of
+  // reach of any leg (legs are shorter than L - 5d), so scans skip its slot.
+  constexpr bool PREFETCH = G == 64;
+  bool pf = false;
+  CstRec pf_crs[W::SPL];
+  double pf_a[W::SPL], pf_t[W::SPL];
+  int pf_sl[W::SPL], pf_col[W::SPL], pf_row[W::SPL];
+  int pf_ab = 0;
+  double pf_hclk = 0.0;
+  int xs = -1;  // the slot of the disk that stopped at the last lifting
+  // the records of one pass of home columns m0 .. m0 + M - 1 (row offsets -1..1)
+  auto load_pass = [&](int m0, int col0, int row0, CstRec(&cr)[W::SPL], double(&aa)[W::SPL],
+                       double(&tt)[W::SPL], int(&sl_)[W::SPL], int(&co)[W::SPL], int(&ro)[W::SPL]) {
+#pragma unroll
+    for (int r = 0; r < W::SPL; ++r) {
+      const int w = lane + r * G;
+      sl_[r] = -1;
+      co[r] = ro[r] = 0;
+      cr[r].id = -1;
+      cr[r].p = 0.0;
+      aa[r] = tt[r] = 0.0;
+      if (w < W::NS) {
+        const int mc = m0 + w / (ROWS * CAP);
+        const int rem = w % (ROWS * CAP);
+        if (mc <= g.mmax) {
+          int col = col0 + mc;
+          if (col >= g.nc) col -= g.nc;
+          int row = row0 + rem / CAP - 1;
+          row = row < 0 ? row + g.nc : (row >= g.nc ? row - g.nc : row);
+          const int sl = ((row * g.nc + col) << 2) + (rem % CAP);
+          sl_[r] = sl;
+          co[r] = col;
+          ro[r] = row;
+          cr[r] = D.CST[sl];
+          aa[r] = ld_a<SC>(&D.MUT[sl].a);
+          tt[r] = ld_a<SC>(&D.MUT[sl].t);
+        }
+      }
+    }
+  };
 
   for (long long it = 0;; ++it) {
     // the abort word (another chain saw a violation) is read with the scan's
@@ -865,8 +911,13 @@ __device__ void chain_events(const Dev &D, const Geo &g, const LegP &lp, int32_t
     int ab = 0;
     double hclk = 0.0;
     if (lane == 0) {
-      ab = __hip_atomic_load(&D.ctl->abort, __ATOMIC_RELAXED, SC);
-      hclk = ld_a<SC>(&D.ctl->clock);
+      if (pf) {
+        ab = pf_ab;
+        hclk = pf_hclk;
+      } else {
+        ab = __hip_atomic_load(&D.ctl->abort, __ATOMIC_RELAXED, SC);
+        hclk = ld_a<SC>(&D.ctl->clock);
+      }
     }
     if (it >= iter_cap) {
       if (lane == 0) {
@@ -912,33 +963,22 @@ __device__ void chain_events(const Dev &D, const Geo &g, const LegP &lp, int32_t
       CstRec crs[W::SPL];
       double ajs[W::SPL], tjs[W::SPL];
       int sls[W::SPL], scol[W::SPL], srow[W::SPL];
+      const bool from_pf = pf && m0 == 0;
+      if (from_pf) {
 #pragma unroll
-      for (int r = 0; r < W::SPL; ++r) {
-        const int w = lane + r * G;
-        sls[r] = -1;
-        scol[r] = srow[r] = 0;
-        crs[r].id = -1;
-        crs[r].p = 0.0;
-        ajs[r] = tjs[r] = 0.0;
-        if (w < W::NS) {
-          const int mc = m0 + w / (ROWS * CAP);
-          const int rem = w % (ROWS * CAP);
-          if (mc <= g.mmax) {
-            int col = col0 + mc;
-            if (col >= g.nc) col -= g.nc;
-            int row = row0 + rem / CAP - 1;
-            row = row < 0 ? row + g.nc : (row >= g.nc ? row - g.nc : row);
-            const int sl = ((row * g.nc + col) << 2) + (rem % CAP);
-            sls[r] = sl;
-            scol[r] = col;
-            srow[r] = row;
-            crs[r] = D.CST[sl];
-            ajs[r] = ld_a<SC>(&D.MUT[sl].a);
-            tjs[r] = ld_a<SC>(&D.MUT[sl].t);
-          }
+        for (int r = 0; r < W::SPL; ++r) {
+          crs[r] = pf_crs[r];
+          ajs[r] = pf_a[r];
+          tjs[r] = pf_t[r];
+          sls[r] = pf_sl[r];
+          scol[r] = pf_col[r];
+          srow[r] = pf_row[r];
         }
+      } else {
+        load_pass(m0, col0, row0, crs, ajs, tjs, sls, scol, srow);
       }
-      if (rel_slot >= 0) {  // the last commit's stores have completed with these loads
+      pf = false;
+      if (rel_slot >= 0 && !from_pf) {  // the last commit's stores have completed with these loads
         wait_mem();
         if (lane == 0) {
           strict_rel<SC>(lp.strict);
@@ -949,7 +989,7 @@ __device__ void chain_events(const Dev &D, const Geo &g, const LegP &lp, int32_t
       }
       bool refine[W::SPL];
 #pragma unroll
-      for (int r = 0; r < W::SPL; ++r) refine[r] = sls[r] >= 0 && crs[r].id >= 0 && sls[r] != s;
+      for (int r = 0; r < W::SPL; ++r) refine[r] = sls[r] >= 0 && crs[r].id >= 0 && sls[r] != s && sls[r] != xs;
       if constexpr (F32) {
         // binary32 intervals; a lane's upper bound is the smallest upper end
         // over slots certainly in that lane (and certainly not behind)
@@ -1033,6 +1073,15 @@ __device__ void chain_events(const Dev &D, const Geo &g, const LegP &lp, int32_t
       if (lb > lim) break;
     }
     lane_scanned += scanned;
+    if (rel_slot >= 0) {  // a prefetched first pass: release once the commit's stores completed
+      wait_mem();
+      if (lane == 0) {
+        strict_rel<SC>(lp.strict);
+        __hip_atomic_store(&D.REF[c].ver, rel_ver, __ATOMIC_RELAXED, SC);
+        __hip_atomic_store(&D.TAG[rel_slot], TAG_STATIC, __ATOMIC_RELAXED, SC);  // 17
+      }
+      rel_slot = -1;
+    }
     ab = bcast<G>(ab, 0);
     if (ab) break;
 
@@ -1317,6 +1366,18 @@ __device__ void chain_events(const Dev &D, const Geo &g, const LegP &lp, int32_t
       spin_site = SP_ACTIVE_TARGET;
       continue;
     }
+    // the claim holds: load the next scan's first pass beside the post-claim
+    // reads (whole wavefronts; with several slots per lane the registers
+    // would spill)
+    if constexpr (PREFETCH) {
+      const int tcell = ts >> 2;
+      const int trow = tcell / g.nc, tcol = tcell - trow * g.nc;
+      load_pass(0, tcol, trow, pf_crs, pf_a, pf_t, pf_sl, pf_col, pf_row);
+      if (lane == 0) {
+        pf_ab = __hip_atomic_load(&D.ctl->abort, __ATOMIC_RELAXED, SC);
+        pf_hclk = ld_a<SC>(&D.ctl->clock);
+      }
+    }
     aj2 = bcast<G>(aj2, 0);
     tj2 = bcast<G>(tj2, 0);
     stale = bcast<G>(stale, 0);
@@ -1408,6 +1469,7 @@ __device__ void chain_events(const Dev &D, const Geo &g, const LegP &lp, int32_t
     cnt[C_EVENTS] += 1;
     ref_ver = cnt[C_EVENTS];
     sumb = sumb + t_b;
+    xs = s;
     s = ts;  // 19: continue with j
     a = aj2;
     p = t_p;
@@ -1415,6 +1477,7 @@ __device__ void chain_events(const Dev &D, const Geo &g, const LegP &lp, int32_t
     t_pub = tn;
     retries = 0;
     spins = 0;
+    pf = PREFETCH;
   }
   // group-wide sum of per-lane scan counts
   long long sc = lane_scanned, rf = lane_refined;
