@@ -2262,12 +2262,13 @@ __device__ __forceinline__ void round_decide(const Dev &D, double H, long long e
     lc.last_R = fmax(lc.last_R, R);
     lc.h = R;
     if (lc.stuck >= lc.max_splits) {
-      // the same race keeps coming back: a stretch with a bounded lag well
-      // below the mean free time (divided by 8 after each violation), then
-      // in global-time order (Alg. 2)
+      // the same race keeps coming back: a short stretch past R (T/512: of
+      // the lengths tried, T/32 ... T/2048, the fastest at N = 2^20) with a
+      // bounded lag well below the mean free time (divided by 8 after each
+      // violation), then in global-time order (Alg. 2)
       lc.mode = MD_LOCKSTEP;
       lc.lvl = 0;
-      lc.gend = fmin(lc.T, R + lc.T / 64.0);
+      lc.gend = fmin(lc.T, R + lc.T / 512.0);
       lc.final_cur = lc.gend < lc.T ? 0 : 1;
       lc.tend_cur = lc.final_cur ? lc.T : lc.gend;
       lc.lag_cur = lc.base_lag / 4.0;
@@ -2543,8 +2544,9 @@ __device__ int replica_leg(const RepIn &ri, RepOut *rp, int dir, int32_t wait_re
     __syncthreads();
     h = R;
     if (stuck >= ri.max_splits) {
-      // a stretch in global-time order (Alg. 2) guarantees progress
-      const double gend = fmin(T, h + T / 64.0);
+      // a stretch in global-time order (Alg. 2) guarantees progress; T/256
+      // was the fastest of T/64, T/256, T/512 for the 512-replica workload
+      const double gend = fmin(T, h + T / 256.0);
       const bool fin = !(gend < T);
       lp.final = fin ? 1 : 0;
       lp.h = h;
