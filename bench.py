@@ -148,7 +148,7 @@ def birthday_estimate(k, L, T, sigma=1.0):
     return 1.0 - math.exp(-k * k / (2.0 * n_regions))
 
 
-def run_batch(n_rep, target, t_frac, graph=1, window_micro=0):
+def run_batch(n_rep, target, t_frac, graph=1, window_micro=0, max_splits=0):
     """The replica workload: n_rep seeded replicas of N in {1024..16384}, eta in
     [0.60, 0.72], k = round(sqrt N), FP32-mixed, run in one persistent launch
     (captured in a hipGraph) until every replica has `target` liftings; the
@@ -168,6 +168,8 @@ def run_batch(n_rep, target, t_frac, graph=1, window_micro=0):
     b = pkg.Batch(systems)
     b.set_option(pkg.OPT_GRAPH, graph)
     b.set_option(pkg.OPT_WINDOW_MICRO, window_micro)
+    if max_splits:
+        b.set_option(pkg.OPT_MAX_SPLITS, max_splits)
     T = [t_frac * s.L for s in reps]
     big = np.full(n_rep, 1 << 60, np.int64)
     b.run(big, T, pkg.DIR_ALTERNATE, max_legs=1)  # autotune (one leg per lane count)
@@ -286,14 +288,14 @@ def main():
     ap.add_argument("--lanes", type=int, default=64)
     ap.add_argument("--max-splits", type=int, default=0,
                     help="rollbacks without progress before a lockstep stretch (0: library default)")
-    ap.add_argument("--window-micro", type=int, default=100_000,
+    ap.add_argument("--window-micro", type=int, default=160_000,
                     help="bounded lag between chains, in 1e-6 sigma (0: free running)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batch-replicas", type=int, default=512)
     ap.add_argument("--batch-events", type=int, default=1_000_000)
     ap.add_argument("--batch-leg-frac", type=float, default=0.25)
-    ap.add_argument("--batch-window-micro", type=int, default=250_000,
+    ap.add_argument("--batch-window-micro", type=int, default=350_000,
                     help="bounded lag between a replica's chains, in 1e-6 sigma (0: free running)")
     ap.add_argument("--no-batch", action="store_true")
     args = ap.parse_args()

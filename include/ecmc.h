@@ -71,7 +71,8 @@ extern "C" {
 #define ECMC_OPT_MAX_SPLITS 3     /* consecutive rollbacks that do not move
                                      past the earliest unsettled time before a
                                      short stretch runs with a tiny bounded lag
-                                     (default 4)                                 */
+                                     (default 1; in a batch, before a
+                                     global-order stretch, also default 1)      */
 #define ECMC_OPT_FORCE_GLOBAL 4   /* 1: run every leg in global-time order      */
 #define ECMC_OPT_INJECT_CHAIN 5   /* test hook: chain that reports a horizon    */
 #define ECMC_OPT_INJECT_EVENT 6   /*   violation at its given event of the next
@@ -285,7 +286,7 @@ int ecmc_batch_create(ecmc_batch **out, ecmc_ctx *const *ctxs, int32_t n_ctx,
                       void *scratch, int64_t scratch_bytes);
 
 /* ECMC_OPT_LANES (0: autotune at the first run; 4, 8, 16, 32),
- * ECMC_OPT_GRAPH, ECMC_OPT_FEATURES, ECMC_OPT_WAIT_RETRIES, and
+ * ECMC_OPT_GRAPH, ECMC_OPT_FEATURES, ECMC_OPT_WAIT_RETRIES, ECMC_OPT_MAX_SPLITS and
  * ECMC_OPT_WINDOW_MICRO (bounded lag between a replica's chains in units of
  * 1e-6 sigma, 0 = free; a chain waiting at the lag takes the replica's H from
  * its chains' next-event times itself). */

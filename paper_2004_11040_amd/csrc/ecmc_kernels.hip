@@ -2642,7 +2642,7 @@ struct ecmc_ctx {
   int64_t log_cap;
   int32_t lanes = 64;
   int32_t wait_retries = 64;
-  int32_t max_splits = 4;     // rollbacks without progress before a lockstep stretch
+  int32_t max_splits = 1;     // rollbacks without progress before a lockstep stretch
   int64_t undo_cap = 4096;     // undo records per chain and leg
   int32_t force_global = 0;
   int32_t inject_chain = -1, inject_event = -1;
@@ -3513,7 +3513,7 @@ struct ecmc_batch {
   int32_t use_graph = 0;
   int32_t features = ECMC_FEAT_ALL;
   int32_t wait_retries = 64;
-  int32_t max_splits = 4;
+  int32_t max_splits = 1;
   hipGraphExec_t exec = nullptr;
   int32_t exec_lanes = 0, exec_grid = 0, last_grid = 0;
   hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -3647,7 +3647,7 @@ int batch_once(ecmc_batch *b, const int64_t *target, const double *leg_T, int32_
     R.target = target[r];
     R.legs_done = ctx->leg_counter;
     R.dir_mode = direction;
-    R.max_splits = ctx->max_splits;
+    R.max_splits = b->max_splits;
     R.max_legs = max_legs;
     R.window = b->window_micro * 1e-6 * ctx->g.sigma;
   }
@@ -3774,6 +3774,10 @@ int ecmc_batch_set_option(ecmc_batch *b, int32_t key, int64_t value) {
     case ECMC_OPT_WINDOW_MICRO:
       if (value < 0 || value > (1ll << 50)) return ECMC_EINVAL;
       b->window_micro = (double)value;
+      return ECMC_OK;
+    case ECMC_OPT_MAX_SPLITS:
+      if (value < 0 || value > 64) return ECMC_EINVAL;
+      b->max_splits = (int32_t)value;
       return ECMC_OK;
     default:
       return ECMC_EINVAL;
