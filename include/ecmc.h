@@ -9,9 +9,8 @@
  * tau_ij = forward distance - b_ij, b_ij = sqrt((2 sigma)^2 - dp^2), Sec. 2.2),
  * checks the horizon condition t_i + tau_ij > t_j (Eq. 2) on the nearest disk
  * of each of its three lanes (Sec. 3.1, the out-arrows of the constraint graph
- * G(3)), claims the target with a compare-and-swap on its tag (Alg. 5
- * statement 10), re-checks the target's position and local time (statement
- * 13), and lifts (statements 14-19; Eq. 1).  A horizon violation stops
+ * G(3)), claims the target with a compare-and-swap on its tag (Alg. 5),
+ * re-checks the target's position and local time, and lifts (Eq. 1).  A horizon violation stops
  * every chain; the liftings at or after the earliest time that is not settled
  * (min of the violation times and of the chains' pending event times) are
  * taken back from per-chain undo records and the leg resumes from there

@@ -38,15 +38,15 @@
  * design notes):
  *  - sigma is the disk radius; contact at centre distance d = 2 sigma (Sec. 1).
  *  - tau_ij = (forward distance along v from i to j) - b_ij with
- *    b_ij = sqrt(d^2 - dp^2) (Sec. 2.2; the text's "+ b" contradicts Alg. 5's
- *    statement 4 and Eq. 3; the minus sign is used).
+ *    b_ij = sqrt(d^2 - dp^2) (Sec. 2.2; the text's "+ b" contradicts the time
+ *    of flight used in Alg. 5 and Eq. 3; the minus sign is used).
  *  - periodic box: dp is the minimum image, the forward distance lies in
  *    [0, L), and a computed tau below zero (contact within rounding) is 0.
  *  - a disk is in the corridor iff dp^2 < d^2 (grazing contact: no lifting,
  *    consistent with tau = infinity in the footnote to Alg. 2).
  *  - ties: within a chain the smaller (tau, disk id) wins; between chains the
  *    smaller (event time, chain id) wins (the paper assumes generic times).
- *  - a lifting is admissible iff tau < h' - t_c (Alg. 5 statement 12).
+ *  - a lifting is admissible iff tau < h' - t_c (Alg. 5: before the breakpoint).
  *
  * Floating point: IEEE binary64, round to nearest, no contraction
  * (compile with -ffp-contract=off), correctly rounded sqrt.
@@ -78,7 +78,7 @@ typedef struct {
 } Sys;
 
 /* ------------------------------------------------------------------------ */
-/* Time of flight (Sec. 2.2, Eq. 2 context; Alg. 5 statements 3-4).          */
+/* Time of flight (Sec. 2.2, Eq. 2 context; Alg. 5).                          */
 /* Returns +inf if j is outside the corridor |dp| < d.  *b_out = b_ij.        */
 /* ------------------------------------------------------------------------ */
 static double tof(const Sys *s, double ai, double pi, double aj, double pj,

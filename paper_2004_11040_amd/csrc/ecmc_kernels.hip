@@ -33,14 +33,14 @@
 // (measured ~7 ns each, i.e. ~7 us per fence with 1024 waves in flight).  The
 // completion-wait protocol was validated on gfx950 with a cross-XCD
 // message-passing litmus test (0 reordered observations in 1.2e8, against
-// 0.5 % without the waits) and is re-checked by ecmc_selftest_ordering().
+// 0.5 % without the waits).
 // A chain claims its target with a compare-and-swap on the target's tag; after
-// the claim it re-reads the target's position and local time and the local
-// times of the other lane minima, so the re-check of Alg. 5 statement 13 and
-// the horizon test use data no older than the claim.  The commit writes the
+// the claim it re-reads the target's position and local time and the records
+// of the other lane minima, so the re-check of the target (Alg. 5) and the
+// horizon test use data no older than the claim.  The commit writes the
 // target's local time, the moving disk's local time and then its position
-// (statements 14-16; local time before position, Remark on memory order),
-// waits for completion, and releases the moving disk's tag (statement 17).
+// (local time before position, Remark on memory-order directives), waits for
+// completion, and releases the moving disk's tag.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -480,8 +480,9 @@ __global__ void k_ctl_reset(Dev D, double h) {
 // ------------------------------------------------------------------------
 // a3-a7: the event kernel.  One chain per group of G lanes (G = 64: one
 // wavefront per chain).  Each iteration is one attempt at one event of Alg. 5
-// (statements 1-19) for the group's chain; a wait on an active target is a
-// retry in the next iteration, never a spin inside the iteration.
+// (scan, horizon check, claim, re-check, commit) for the group's chain; a wait
+// on an active target is a retry in the next iteration, never a spin inside
+// the iteration.
 // ------------------------------------------------------------------------
 template <int G>
 struct Win {
@@ -850,9 +851,9 @@ __device__ void chain_events(const Dev &D, const Geo &g, const LegP &lp, int32_t
   // lane would always win)
   int yield_slot = -1;
   unsigned long long yield_key = RES_EMPTY;
-  // statement 17 of the last lifting (release of the disk that stopped) and
-  // the new version of the activation record wait for the next completion
-  // wait, instead of a round trip of their own
+  // the release of the disk that stopped at the last lifting and the new
+  // version of the activation record wait for the next completion wait,
+  // instead of a round trip of their own
   int rel_slot = -1;
   long long rel_ver = 0;
   // rounds of scan and claim since the last lifting, and the retry path taken last
@@ -938,7 +939,7 @@ __device__ void chain_events(const Dev &D, const Geo &g, const LegP &lp, int32_t
       break;
     }
 
-    // ---- statements 1-9: corridor scan over home columns ----
+    // ---- corridor scan over home columns (time of flight, Sec. 2.2) ----
     const int cell0 = s >> 2;
     const int row0 = cell0 / g.nc, col0 = cell0 - row0 * g.nc;
     double u = a - col0 * g.c;  // distance from the home column's trailing edge
@@ -983,7 +984,7 @@ __device__ void chain_events(const Dev &D, const Geo &g, const LegP &lp, int32_t
         if (lane == 0) {
           strict_rel<SC>(lp.strict);
           __hip_atomic_store(&D.REF[c].ver, rel_ver, __ATOMIC_RELAXED, SC);
-          __hip_atomic_store(&D.TAG[rel_slot], TAG_STATIC, __ATOMIC_RELAXED, SC);  // 17
+          __hip_atomic_store(&D.TAG[rel_slot], TAG_STATIC, __ATOMIC_RELAXED, SC);  // release
         }
         rel_slot = -1;
       }
@@ -1078,7 +1079,7 @@ __device__ void chain_events(const Dev &D, const Geo &g, const LegP &lp, int32_t
       if (lane == 0) {
         strict_rel<SC>(lp.strict);
         __hip_atomic_store(&D.REF[c].ver, rel_ver, __ATOMIC_RELAXED, SC);
-        __hip_atomic_store(&D.TAG[rel_slot], TAG_STATIC, __ATOMIC_RELAXED, SC);  // 17
+        __hip_atomic_store(&D.TAG[rel_slot], TAG_STATIC, __ATOMIC_RELAXED, SC);  // release
       }
       rel_slot = -1;
     }
@@ -1194,7 +1195,7 @@ __device__ void chain_events(const Dev &D, const Geo &g, const LegP &lp, int32_t
       }
     }
 
-    // ---- statement 5: horizon condition on the lane minima (scanned times) ----
+    // ---- horizon condition (Eq. 2) on the lane minima (scanned times) ----
     bool viol = false;
     double vtj = 0.0, vta = 0.0;
     int vid = -1;
@@ -1225,8 +1226,8 @@ __device__ void chain_events(const Dev &D, const Geo &g, const LegP &lp, int32_t
       viol = false;
     }
 
-    // ---- no admissible lifting before the breakpoint: stall (statements
-    // 21-24) or pause; both publish the point reached at the breakpoint ----
+    // ---- no admissible lifting before the breakpoint: stall (Remark on
+    // stalled spheres) or pause; both publish the point reached there ----
     if (!(tau < trem)) {
       const double an = fwd_move(a, trem, g);
       if (lane == 0) {
@@ -1241,7 +1242,7 @@ __device__ void chain_events(const Dev &D, const Geo &g, const LegP &lp, int32_t
       break;  // the reference stays: a rollback may resume this chain
     }
 
-    // ---- statement 10: claim the target ----
+    // ---- claim the target (Alg. 5) ----
     if (yield_slot >= 0) {
       int live = 0;
       if (yield_slot == ts && lane == 0) {
@@ -1267,10 +1268,10 @@ __device__ void chain_events(const Dev &D, const Geo &g, const LegP &lp, int32_t
     const double t_prev = t_pub;
     if (lane == 0) {
       // the activation record is rewritten if the claim succeeds: mark it
-      // invalid first; statement 15 (the local time of the disk that will
-      // stop) is written ahead of the claim.  The wait after the claim
-      // completes both, so the position (statement 16) needs no wait of its
-      // own.  If the lifting does not happen the local time is put back.
+      // invalid first; the local time of the disk that will stop is written
+      // ahead of the claim.  The wait after the claim completes both, so its
+      // position needs no wait of its own.  If the lifting does not happen the
+      // local time is put back.
       __hip_atomic_store(&D.REF[c].ver, -1ll, __ATOMIC_RELAXED, SC);
       st_a<SC>(&D.MUT[s].t, t + tau);
       won = __hip_atomic_compare_exchange_strong(&D.TAG[ts], &old, (uint32_t)c, __ATOMIC_RELAXED,
@@ -1280,7 +1281,7 @@ __device__ void chain_events(const Dev &D, const Geo &g, const LegP &lp, int32_t
       fence_acq();
       strict_acq<SC>(lp.strict);
       if (won) {
-        // statement 13 (extended to the local time): reads issued after the claim completed
+        // the target's re-check (extended to the local time): reads issued after the claim completed
         aj2 = ld_a<SC>(&D.MUT[ts].a);
         tj2 = ld_a<SC>(&D.MUT[ts].t);
         double acl[3], tcl[3];
@@ -1290,7 +1291,7 @@ __device__ void chain_events(const Dev &D, const Geo &g, const LegP &lp, int32_t
           tcl[q] = (gt[q] < trem) ? ld_a<SC>(&D.MUT[gsl[q]].t) : 0.0;
         }
         rk = __hip_atomic_load(&D.RES[ts], __ATOMIC_RELAXED, SC);
-        // statement 5 again on records read after the claim: a lane minimum
+        // Eq. 2 again on records read after the claim: a lane minimum
         // whose record changed must still pass Eq. 2 and stay behind the
         // target, else the chain scans again
 #pragma unroll
@@ -1390,14 +1391,14 @@ __device__ void chain_events(const Dev &D, const Geo &g, const LegP &lp, int32_t
       flag_violation<G, SC>(D, c, t > h ? t : h, lane, VK_CLAIM, 0.0, tau, t_id);
       break;
     }
-    // statement 13: the target must not have moved (nor been stamped) since
+    // the re-check: the target must not have moved (nor been stamped) since
     // the scan, and no lane minimum may have moved into question
     if (aj2 != t_aj || tj2 != t_tj || stale) {
       if (lane == 0) {
         __hip_atomic_store(&D.REF[c].ver, ref_ver, __ATOMIC_RELAXED, SC);
         st_a<SC>(&D.MUT[s].t, t_prev);
         strict_rel<SC>(lp.strict);
-        st_rel<SC>(&D.TAG[ts], TAG_STATIC);  // statement 20
+        st_rel<SC>(&D.TAG[ts], TAG_STATIC);  // give the target back
       }
       cnt[C_CASFAIL] += (lane == 0);
       spin_site = SP_CHANGED;
@@ -1431,7 +1432,7 @@ __device__ void chain_events(const Dev &D, const Geo &g, const LegP &lp, int32_t
         continue;
       }
     }
-    // ---- statements 14-19: commit the lifting ----
+    // ---- commit the lifting (Eq. 1) ----
     const double tn = t + tau;
     const double an = fwd_move(a, tau, g);
     if (lane == 0) {
@@ -1448,8 +1449,8 @@ __device__ void chain_events(const Dev &D, const Geo &g, const LegP &lp, int32_t
       } else {
         __hip_atomic_store(&D.ctl->undo_overflow, 1, __ATOMIC_RELAXED, SC);
       }
-      st_a<SC>(&D.MUT[ts].t, tn);  // 14: t_j
-      // 15 (t_i = tn) was written before the claim and has completed
+      st_a<SC>(&D.MUT[ts].t, tn);  // t_j
+      // t_i = tn was written before the claim and has completed
       __hip_atomic_store(&D.REF[c].slot, ts, __ATOMIC_RELAXED, SC);
       st_a<SC>(&D.REF[c].a, aj2);
       st_a<SC>(&D.REF[c].t_act, tn);
@@ -1457,10 +1458,10 @@ __device__ void chain_events(const Dev &D, const Geo &g, const LegP &lp, int32_t
       unsigned long long used = mykey;  // the reservation is used
       __hip_atomic_compare_exchange_strong(&D.RES[ts], &used, RES_EMPTY, __ATOMIC_RELAXED, __ATOMIC_RELAXED, SC);
       strict_rel<SC>(lp.strict);
-      st_a<SC>(&D.MUT[s].a, an);   // 16: x_i
+      st_a<SC>(&D.MUT[s].a, an);   // x_i
       D.LOG[(int64_t)c * D.log_cap + (loglen % D.log_cap)] = t_id;
     }
-    // 17 (release of i) and the activation record's new version follow the
+    // the release of i and the activation record's new version follow the
     // next completion wait (the next scan's loads, or the exit)
     rel_slot = s;
     rel_ver = cnt[C_EVENTS] + 1;
@@ -1470,7 +1471,7 @@ __device__ void chain_events(const Dev &D, const Geo &g, const LegP &lp, int32_t
     ref_ver = cnt[C_EVENTS];
     sumb = sumb + t_b;
     xs = s;
-    s = ts;  // 19: continue with j
+    s = ts;  // continue with j
     a = aj2;
     p = t_p;
     t = tn;
@@ -1491,7 +1492,7 @@ __device__ void chain_events(const Dev &D, const Geo &g, const LegP &lp, int32_t
     if (lane == 0) {
       strict_rel<SC>(lp.strict);
       __hip_atomic_store(&D.REF[c].ver, rel_ver, __ATOMIC_RELAXED, SC);
-      __hip_atomic_store(&D.TAG[rel_slot], TAG_STATIC, __ATOMIC_RELAXED, SC);  // 17
+      __hip_atomic_store(&D.TAG[rel_slot], TAG_STATIC, __ATOMIC_RELAXED, SC);  // release
     }
   }
   if (lane == 0) {
@@ -1975,7 +1976,7 @@ __device__ __forceinline__ void global_order(const Dev &D, const Geo &g, const L
         l_b[w] = bb;
       }
     } else if (tid == 64) {
-      // the commit (statements 14-19 of Alg. 2 for chain w)
+      // the commit of chain w's lifting (Alg. 2)
       const int cw = s_w;
       const long long un = D.UNDO_N[cw];
       const MutRec mj = D.MUT[sj];
