@@ -466,6 +466,162 @@ __device__ __forceinline__ void rb_reset_one(const Dev &D, const Geo &g, double 
   D.TAG[s] = (uint32_t)c;
 }
 
+// The same rollback for at most one chain per thread, in one block, with
+// fewer dependent round trips to memory: each thread reads its chain's last
+// RB_U undo records at once and keeps them in registers through the four
+// phases (mark, mark the old times, restore, reset); records past those are
+// walked as above.
+constexpr int RB_U = 4;
+__device__ __forceinline__ void rollback_block(const Dev &D, const Geo &g, double R) {
+  const int c = threadIdx.x;
+  const bool act = c < D.k;
+  UndoRec u[RB_U];
+  long long n = 0;
+  int cnt = 0;
+  bool more = false;
+  const UndoRec *base = nullptr;
+  int ch_s = 0;
+  double ch_a = 0.0, ch_t = 0.0;
+  if (act) {
+    n = D.UNDO_N[c];
+    ch_s = D.CH_SLOT[c];
+    ch_a = D.CH_A[c];
+    ch_t = D.CH_T[c];
+    base = D.UNDO + (int64_t)c * D.undo_cap;
+#pragma unroll
+    for (int j = 0; j < RB_U; ++j)
+      if (n - 1 - j >= 0) u[j] = base[n - 1 - j];
+#pragma unroll
+    for (int j = 0; j < RB_U; ++j)
+      if (cnt == j && n - 1 - j >= 0 && u[j].e >= R) cnt = j + 1;
+    more = cnt == RB_U && n - RB_U > 0;
+    D.UNDO_N_OLD[c] = n;
+#pragma unroll
+    for (int j = 0; j < RB_U; ++j)
+      if (j < cnt) atomicMin(&D.RKEY[u[j].sj], (unsigned long long)__double_as_longlong(u[j].e));
+    if (more)
+      for (long long m = n - 1 - RB_U; m >= 0; --m) {
+        const UndoRec &v = base[m];
+        if (!(v.e >= R)) break;
+        atomicMin(&D.RKEY[v.sj], (unsigned long long)__double_as_longlong(v.e));
+      }
+  }
+  __syncthreads();
+  if (act) {
+    unsigned long long rk[RB_U];
+#pragma unroll
+    for (int j = 0; j < RB_U; ++j) rk[j] = j < cnt ? D.RKEY[u[j].sj] : 0ull;
+#pragma unroll
+    for (int j = 0; j < RB_U; ++j)
+      if (j < cnt && rk[j] == (unsigned long long)__double_as_longlong(u[j].e))
+        atomicMin(&D.RKEY2[u[j].sj], (unsigned long long)__double_as_longlong(u[j].tj));
+    if (more)
+      for (long long m = n - 1 - RB_U; m >= 0; --m) {
+        const UndoRec &v = base[m];
+        if (!(v.e >= R)) break;
+        if (D.RKEY[v.sj] == (unsigned long long)__double_as_longlong(v.e))
+          atomicMin(&D.RKEY2[v.sj], (unsigned long long)__double_as_longlong(v.tj));
+      }
+  }
+  __syncthreads();
+  long long nu = 0;
+  if (act) {
+    unsigned long long rk[RB_U], rk2[RB_U];
+#pragma unroll
+    for (int j = 0; j < RB_U; ++j) {
+      rk[j] = j < cnt ? D.RKEY[u[j].sj] : 0ull;
+      rk2[j] = j < cnt ? D.RKEY2[u[j].sj] : 0ull;
+    }
+#pragma unroll
+    for (int j = 0; j < RB_U; ++j) {
+      if (j < cnt) {
+        D.TAG[u[j].si] = TAG_STATIC;
+        if (rk[j] == (unsigned long long)__double_as_longlong(u[j].e) &&
+            rk2[j] == (unsigned long long)__double_as_longlong(u[j].tj)) {
+          MutRec r;
+          r.a = u[j].aj;
+          r.t = u[j].tj;
+          D.MUT[u[j].sj] = r;
+          D.TAG[u[j].sj] = TAG_STATIC;
+        }
+      }
+    }
+    long long m = n - 1 - cnt;  // the latest record kept
+    if (more)
+      for (; m >= 0; --m) {
+        const UndoRec &v = base[m];
+        if (!(v.e >= R)) break;
+        D.TAG[v.si] = TAG_STATIC;
+        if (D.RKEY[v.sj] == (unsigned long long)__double_as_longlong(v.e) &&
+            D.RKEY2[v.sj] == (unsigned long long)__double_as_longlong(v.tj)) {
+          MutRec r;
+          r.a = v.aj;
+          r.t = v.tj;
+          D.MUT[v.sj] = r;
+          D.TAG[v.sj] = TAG_STATIC;
+        }
+      }
+    nu = n - 1 - m;  // liftings taken back
+    if (nu > 0) {
+      // the earliest record taken back holds the reference the chain had at R
+      int e_si;
+      double e_ai, e_ti, e_sumb;
+      if (!more) {
+        e_si = u[0].si;
+        e_ai = u[0].ai;
+        e_ti = u[0].ti;
+        e_sumb = u[0].sumb;
+#pragma unroll
+        for (int j = 1; j < RB_U; ++j)
+          if (j == cnt - 1) {
+            e_si = u[j].si;
+            e_ai = u[j].ai;
+            e_ti = u[j].ti;
+            e_sumb = u[j].sumb;
+          }
+      } else {
+        const UndoRec &v = base[m + 1];
+        e_si = v.si;
+        e_ai = v.ai;
+        e_ti = v.ti;
+        e_sumb = v.sumb;
+      }
+      ch_s = e_si;
+      ch_a = e_ai;
+      ch_t = e_ti;
+      D.CH_SLOT[c] = e_si;
+      D.CH_A[c] = e_ai;
+      D.CH_T[c] = e_ti;
+      D.SUMB_W[c] = e_sumb;
+      D.CNT_W[c * NCNT + C_EVENTS] -= nu;
+      D.LOGLEN_W[c] -= nu;
+      D.UNDO_N[c] = n - nu;
+    }
+  }
+  __syncthreads();
+  if (act) {
+#pragma unroll
+    for (int j = 0; j < RB_U; ++j)
+      if (j < cnt) {
+        D.RKEY[u[j].sj] = 0x7FF0000000000000ull;
+        D.RKEY2[u[j].sj] = 0x7FF0000000000000ull;
+      }
+    if (more)
+      for (long long m = n - nu; m < n - RB_U; ++m) {
+        const UndoRec &v = base[m];
+        D.RKEY[v.sj] = 0x7FF0000000000000ull;
+        D.RKEY2[v.sj] = 0x7FF0000000000000ull;
+      }
+    D.REF[c].ver = -1;  // the activation may have been taken back
+    MutRec r;  // the chain's disk at R: a pause there
+    r.a = fwd_move(ch_a, R - ch_t, g);
+    r.t = R;
+    D.MUT[ch_s] = r;
+    D.TAG[ch_s] = (uint32_t)c;
+  }
+  __syncthreads();
+}
+
 __global__ void k_ctl_reset(Dev D, double h) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     D.ctl->tstar_bits = 0x7FF0000000000000ull;  // +inf
@@ -989,8 +1145,12 @@ __device__ void chain_events(const Dev &D, const Geo &g, const LegP &lp, int32_t
         rel_slot = -1;
       }
       bool refine[W::SPL];
+      unsigned candq[W::SPL];  // FP32-mixed: lanes of the corridor a refined slot may undercut (bit q)
 #pragma unroll
-      for (int r = 0; r < W::SPL; ++r) refine[r] = sls[r] >= 0 && crs[r].id >= 0 && sls[r] != s && sls[r] != xs;
+      for (int r = 0; r < W::SPL; ++r) {
+        refine[r] = sls[r] >= 0 && crs[r].id >= 0 && sls[r] != s && sls[r] != xs;
+        candq[r] = 0;
+      }
       if constexpr (F32) {
         // binary32 intervals; a lane's upper bound is the smallest upper end
         // over slots certainly in that lane (and certainly not behind)
@@ -1020,11 +1180,12 @@ __device__ void chain_events(const Dev &D, const Geo &g, const LegP &lp, int32_t
 #pragma unroll
         for (int r = 0; r < W::SPL; ++r) {
           if (refine[r]) {
-            bool need = false;
+            unsigned cm = 0;
 #pragma unroll
             for (int q = 0; q < 3; ++q)
-              if (((fc[r].cls_mask >> q) & 1) && fc[r].lo <= ub[q]) need = true;
-            refine[r] = need;
+              if (((fc[r].cls_mask >> q) & 1) && fc[r].lo <= ub[q]) cm |= 1u << q;
+            candq[r] = cm;
+            refine[r] = cm != 0;
           }
         }
       }
@@ -1062,9 +1223,35 @@ __device__ void chain_events(const Dev &D, const Geo &g, const LegP &lp, int32_t
       double lim = 0.0;
 #pragma unroll
       for (int q = 0; q < 3; ++q) {
-        gt[q] = bl.tau[q];
-        gi[q] = bl.id[q];
-        grp_min<G>(gt[q], gi[q]);
+        bool reduced = false;
+        if constexpr (F32 && G == 64 && W::SPL == 1) {
+          // After the filter a lane of the corridor has mostly one candidate
+          // slot or none.  Every other slot's key is above the binary32 upper
+          // bound, which the candidates or the earlier passes' minimum
+          // undercut, so the minimum is the earlier one or that slot's: read
+          // it from its lane instead of reducing over the wavefront.
+          const unsigned long long mq = __ballot((candq[0] >> q) & 1u);
+          if (__popcll(mq) <= 1) {
+            if (mq) {
+              const int l = __ffsll((long long)mq) - 1;
+              const unsigned long long kb = (unsigned long long)__double_as_longlong(bl.tau[q]);
+              const unsigned lo32 = __builtin_amdgcn_readlane((int)(unsigned)kb, l);
+              const unsigned hi32 = __builtin_amdgcn_readlane((int)(unsigned)(kb >> 32), l);
+              const double tl = __longlong_as_double((long long)(((unsigned long long)hi32 << 32) | lo32));
+              const int il = __builtin_amdgcn_readlane(bl.id[q], l);
+              if (key_less(tl, il, gt[q], gi[q])) {
+                gt[q] = tl;
+                gi[q] = il;
+              }
+            }
+            reduced = true;
+          }
+        }
+        if (!reduced) {
+          gt[q] = bl.tau[q];
+          gi[q] = bl.id[q];
+          grp_min<G>(gt[q], gi[q]);
+        }
         const double lq = gt[q] < trem ? gt[q] : trem;
         lim = lq > lim ? lq : lim;
       }
@@ -2310,7 +2497,9 @@ __global__ void __launch_bounds__(1024) k_round_end(Dev D, Geo g, LegP lp0) {
     s_run = D.ctl->lc.phase == PH_RUN;
   }
   __syncthreads();
-  if (s_rb) {
+  if (s_rb && D.k <= (int)blockDim.x) {
+    rollback_block(D, g, s_R);
+  } else if (s_rb) {
     const double R = s_R;
     for (int c = threadIdx.x; c < D.k; c += blockDim.x) rb_mark_one(D, R, c);
     __syncthreads();
@@ -2644,6 +2833,7 @@ struct ecmc_ctx {
   int32_t lanes = 64;
   int32_t wait_retries = 64;
   int32_t max_splits = 1;     // rollbacks without progress before a lockstep stretch
+  int32_t last_rounds = 0;    // rounds the previous leg took (sizes the first batch of rounds)
   int64_t undo_cap = 4096;     // undo records per chain and leg
   int32_t force_global = 0;
   int32_t inject_chain = -1, inject_event = -1;
@@ -3003,7 +3193,10 @@ int run_leg(ecmc_ctx *ctx, int dir, double T) {
     lp0.features = ctx->features;
     lp0.self_clock = 0;
     Ctl hc;
-    int nspec = 2;
+    // the first batch covers as many rounds as the previous leg took, and a
+    // few more, so that a leg mostly costs one wait on the host; rounds past
+    // the end of the leg return at once
+    int nspec = std::min(std::max(ctx->last_rounds + 4, 2), 64);
     for (int64_t batch = 0;; ++batch) {
       for (int r = 0; r < nspec; ++r) {
         rc = enqueue_round(ctx, lp0);
@@ -3012,13 +3205,14 @@ int run_leg(ecmc_ctx *ctx, int dir, double T) {
       rc = read_ctl(ctx, &hc);
       if (rc) return rc;
       if (hc.lc.phase != PH_RUN) break;
-      nspec = std::min(nspec * 2, 16);
+      nspec = batch == 0 ? 4 : std::min(nspec * 2, 16);
       if (batch > (int64_t)1 << 22) {
         ctx->err = "rollbacks exhausted";
         return ECMC_EHANG;
       }
     }
     const LegCtl &lc = hc.lc;
+    ctx->last_rounds = (int)std::min<long long>(lc.rounds, 1 << 20);
     ctx->attempts += lc.attempts;
     ctx->reruns += lc.reruns;
     ctx->lockstep_runs += lc.lockstep_runs;
