@@ -466,160 +466,201 @@ __device__ __forceinline__ void rb_reset_one(const Dev &D, const Geo &g, double 
   D.TAG[s] = (uint32_t)c;
 }
 
-// The same rollback for at most one chain per thread, in one block, with
-// fewer dependent round trips to memory: each thread reads its chain's last
-// RB_U undo records at once and keeps them in registers through the four
-// phases (mark, mark the old times, restore, reset); records past those are
-// walked as above.
-constexpr int RB_U = 4;
-__device__ __forceinline__ void rollback_block(const Dev &D, const Geo &g, double R) {
+// The same rollback for at most one chain per thread, in one block, with a
+// fixed number of dependent round trips to memory whatever the number of
+// liftings a chain takes back: each thread counts its chain's liftings at or
+// after R from their times (the newest two, then RB_E at a time), a
+// block-wide prefix sum lays the records taken back out in LDS, and each of
+// the four phases (mark, mark the old times, restore, reset) handles them
+// spread over all threads, RB_PER per thread kept in registers.  The block
+// runs on one CU, whose own load throughput bounds these scattered reads, so
+// each phase reads as few lines as it can.  With prep set it also prepares
+// the next attempt from R (what round_prep does, from the values it holds).
+// Returns false, having changed nothing, when more than RB_LIST records are
+// taken back (the caller then walks them chain by chain).
+constexpr int RB_E = 8;
+constexpr int RB_LIST = 4096;
+constexpr int RB_PER = RB_LIST / 1024;
+__device__ __forceinline__ bool rollback_block(const Dev &D, const Geo &g, double R, bool prep) {
+  __shared__ int2 s_list[RB_LIST];
+  __shared__ int s_wsum[16], s_total;
   const int c = threadIdx.x;
   const bool act = c < D.k;
-  UndoRec u[RB_U];
   long long n = 0;
   int cnt = 0;
-  bool more = false;
-  const UndoRec *base = nullptr;
   int ch_s = 0;
   double ch_a = 0.0, ch_t = 0.0;
+  long long ev_c = 0, sl_c = 0;  // the chain's lifting and scan counters
+  const UndoRec *base = nullptr;
   if (act) {
     n = D.UNDO_N[c];
     ch_s = D.CH_SLOT[c];
     ch_a = D.CH_A[c];
     ch_t = D.CH_T[c];
+    ev_c = D.CNT_W[c * NCNT + C_EVENTS];
+    sl_c = D.CNT_W[c * NCNT + C_SCANNED];
     base = D.UNDO + (int64_t)c * D.undo_cap;
+    const double e0 = n >= 1 ? base[n - 1].e : -INFINITY, e1 = n >= 2 ? base[n - 2].e : -INFINITY;
+    cnt = (e0 >= R ? 1 : 0) + (e0 >= R && e1 >= R ? 1 : 0);
+    if (cnt == 2)
+      for (long long m = n - 3; m >= 0; m -= RB_E) {
+        double ev[RB_E];
 #pragma unroll
-    for (int j = 0; j < RB_U; ++j)
-      if (n - 1 - j >= 0) u[j] = base[n - 1 - j];
+        for (int j = 0; j < RB_E; ++j) ev[j] = m - j >= 0 ? base[m - j].e : -INFINITY;
+        int run = 0;
 #pragma unroll
-    for (int j = 0; j < RB_U; ++j)
-      if (cnt == j && n - 1 - j >= 0 && u[j].e >= R) cnt = j + 1;
-    more = cnt == RB_U && n - RB_U > 0;
+        for (int j = 0; j < RB_E; ++j)
+          if (run == j && ev[j] >= R) run = j + 1;
+        cnt += run;
+        if (run < RB_E) break;
+      }
+  }
+  // exclusive prefix sum of the counts over the block
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  int incl = cnt;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const int y = __shfl_up(incl, off, 64);
+    if (lane >= off) incl += y;
+  }
+  if (lane == 63) s_wsum[wv] = incl;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int acc = 0;
+    for (int q = 0; q < (int)((blockDim.x + 63) >> 6); ++q) {
+      const int w = s_wsum[q];
+      s_wsum[q] = acc;
+      acc += w;
+    }
+    s_total = acc;
+  }
+  __syncthreads();
+  const int total = s_total;
+  if (total > RB_LIST || total > RB_PER * (int)blockDim.x) return false;
+  const int first = s_wsum[wv] + incl - cnt;
+  for (int j = 0; j < cnt; ++j) s_list[first + j] = make_int2(c, (int)(n - 1 - j));
+  __syncthreads();
+  // mark: the earliest undone claim of each slot
+  UndoRec u[RB_PER];
+  bool has[RB_PER];
+#pragma unroll
+  for (int r = 0; r < RB_PER; ++r) {
+    const int i = threadIdx.x + r * (int)blockDim.x;
+    has[r] = i < total;
+    if (has[r]) {
+      const int2 cm = s_list[i];
+      u[r] = D.UNDO[(int64_t)cm.x * D.undo_cap + cm.y];
+    }
+  }
+  UndoRec early;  // the chain's earliest lifting taken back: its reference at R
+  if (act && cnt > 0) early = base[n - cnt];
+#pragma unroll
+  for (int r = 0; r < RB_PER; ++r)
+    if (has[r]) atomicMin(&D.RKEY[u[r].sj], (unsigned long long)__double_as_longlong(u[r].e));
+  __syncthreads();
+  // among those, the smallest old local time
+  {
+    unsigned long long rk[RB_PER];
+#pragma unroll
+    for (int r = 0; r < RB_PER; ++r) rk[r] = has[r] ? D.RKEY[u[r].sj] : 0ull;
+#pragma unroll
+    for (int r = 0; r < RB_PER; ++r)
+      if (has[r] && rk[r] == (unsigned long long)__double_as_longlong(u[r].e))
+        atomicMin(&D.RKEY2[u[r].sj], (unsigned long long)__double_as_longlong(u[r].tj));
+  }
+  __syncthreads();
+  // restore the slots and the chains' references
+  {
+    unsigned long long rk[RB_PER], rk2[RB_PER];
+#pragma unroll
+    for (int r = 0; r < RB_PER; ++r) {
+      rk[r] = has[r] ? D.RKEY[u[r].sj] : 0ull;
+      rk2[r] = has[r] ? D.RKEY2[u[r].sj] : 0ull;
+    }
+#pragma unroll
+    for (int r = 0; r < RB_PER; ++r) {
+      if (!has[r]) continue;
+      D.TAG[u[r].si] = TAG_STATIC;
+      if (rk[r] == (unsigned long long)__double_as_longlong(u[r].e) &&
+          rk2[r] == (unsigned long long)__double_as_longlong(u[r].tj)) {
+        MutRec m;
+        m.a = u[r].aj;
+        m.t = u[r].tj;
+        D.MUT[u[r].sj] = m;
+        D.TAG[u[r].sj] = TAG_STATIC;
+      }
+    }
+  }
+  if (act) {
     D.UNDO_N_OLD[c] = n;
-#pragma unroll
-    for (int j = 0; j < RB_U; ++j)
-      if (j < cnt) atomicMin(&D.RKEY[u[j].sj], (unsigned long long)__double_as_longlong(u[j].e));
-    if (more)
-      for (long long m = n - 1 - RB_U; m >= 0; --m) {
-        const UndoRec &v = base[m];
-        if (!(v.e >= R)) break;
-        atomicMin(&D.RKEY[v.sj], (unsigned long long)__double_as_longlong(v.e));
-      }
-  }
-  __syncthreads();
-  if (act) {
-    unsigned long long rk[RB_U];
-#pragma unroll
-    for (int j = 0; j < RB_U; ++j) rk[j] = j < cnt ? D.RKEY[u[j].sj] : 0ull;
-#pragma unroll
-    for (int j = 0; j < RB_U; ++j)
-      if (j < cnt && rk[j] == (unsigned long long)__double_as_longlong(u[j].e))
-        atomicMin(&D.RKEY2[u[j].sj], (unsigned long long)__double_as_longlong(u[j].tj));
-    if (more)
-      for (long long m = n - 1 - RB_U; m >= 0; --m) {
-        const UndoRec &v = base[m];
-        if (!(v.e >= R)) break;
-        if (D.RKEY[v.sj] == (unsigned long long)__double_as_longlong(v.e))
-          atomicMin(&D.RKEY2[v.sj], (unsigned long long)__double_as_longlong(v.tj));
-      }
-  }
-  __syncthreads();
-  long long nu = 0;
-  if (act) {
-    unsigned long long rk[RB_U], rk2[RB_U];
-#pragma unroll
-    for (int j = 0; j < RB_U; ++j) {
-      rk[j] = j < cnt ? D.RKEY[u[j].sj] : 0ull;
-      rk2[j] = j < cnt ? D.RKEY2[u[j].sj] : 0ull;
-    }
-#pragma unroll
-    for (int j = 0; j < RB_U; ++j) {
-      if (j < cnt) {
-        D.TAG[u[j].si] = TAG_STATIC;
-        if (rk[j] == (unsigned long long)__double_as_longlong(u[j].e) &&
-            rk2[j] == (unsigned long long)__double_as_longlong(u[j].tj)) {
-          MutRec r;
-          r.a = u[j].aj;
-          r.t = u[j].tj;
-          D.MUT[u[j].sj] = r;
-          D.TAG[u[j].sj] = TAG_STATIC;
-        }
-      }
-    }
-    long long m = n - 1 - cnt;  // the latest record kept
-    if (more)
-      for (; m >= 0; --m) {
-        const UndoRec &v = base[m];
-        if (!(v.e >= R)) break;
-        D.TAG[v.si] = TAG_STATIC;
-        if (D.RKEY[v.sj] == (unsigned long long)__double_as_longlong(v.e) &&
-            D.RKEY2[v.sj] == (unsigned long long)__double_as_longlong(v.tj)) {
-          MutRec r;
-          r.a = v.aj;
-          r.t = v.tj;
-          D.MUT[v.sj] = r;
-          D.TAG[v.sj] = TAG_STATIC;
-        }
-      }
-    nu = n - 1 - m;  // liftings taken back
-    if (nu > 0) {
-      // the earliest record taken back holds the reference the chain had at R
-      int e_si;
-      double e_ai, e_ti, e_sumb;
-      if (!more) {
-        e_si = u[0].si;
-        e_ai = u[0].ai;
-        e_ti = u[0].ti;
-        e_sumb = u[0].sumb;
-#pragma unroll
-        for (int j = 1; j < RB_U; ++j)
-          if (j == cnt - 1) {
-            e_si = u[j].si;
-            e_ai = u[j].ai;
-            e_ti = u[j].ti;
-            e_sumb = u[j].sumb;
-          }
-      } else {
-        const UndoRec &v = base[m + 1];
-        e_si = v.si;
-        e_ai = v.ai;
-        e_ti = v.ti;
-        e_sumb = v.sumb;
-      }
-      ch_s = e_si;
-      ch_a = e_ai;
-      ch_t = e_ti;
-      D.CH_SLOT[c] = e_si;
-      D.CH_A[c] = e_ai;
-      D.CH_T[c] = e_ti;
-      D.SUMB_W[c] = e_sumb;
-      D.CNT_W[c * NCNT + C_EVENTS] -= nu;
-      D.LOGLEN_W[c] -= nu;
-      D.UNDO_N[c] = n - nu;
+    if (cnt > 0) {
+      ch_s = early.si;
+      ch_a = early.ai;
+      ch_t = early.ti;
+      D.CH_SLOT[c] = early.si;
+      D.CH_A[c] = early.ai;
+      D.CH_T[c] = early.ti;
+      D.SUMB_W[c] = early.sumb;
+      D.CNT_W[c * NCNT + C_EVENTS] -= cnt;
+      D.LOGLEN_W[c] -= cnt;
+      D.UNDO_N[c] = n - cnt;
     }
   }
   __syncthreads();
-  if (act) {
+  // reset the rollback keys; every chain republishes its disk at R (a pause)
 #pragma unroll
-    for (int j = 0; j < RB_U; ++j)
-      if (j < cnt) {
-        D.RKEY[u[j].sj] = 0x7FF0000000000000ull;
-        D.RKEY2[u[j].sj] = 0x7FF0000000000000ull;
-      }
-    if (more)
-      for (long long m = n - nu; m < n - RB_U; ++m) {
-        const UndoRec &v = base[m];
-        D.RKEY[v.sj] = 0x7FF0000000000000ull;
-        D.RKEY2[v.sj] = 0x7FF0000000000000ull;
-      }
+  for (int r = 0; r < RB_PER; ++r)
+    if (has[r]) {
+      D.RKEY[u[r].sj] = 0x7FF0000000000000ull;
+      D.RKEY2[u[r].sj] = 0x7FF0000000000000ull;
+    }
+  if (act) {
     D.REF[c].ver = -1;  // the activation may have been taken back
-    MutRec r;  // the chain's disk at R: a pause there
-    r.a = fwd_move(ch_a, R - ch_t, g);
-    r.t = R;
-    D.MUT[ch_s] = r;
+    MutRec m;
+    m.a = fwd_move(ch_a, R - ch_t, g);
+    m.t = R;
+    D.MUT[ch_s] = m;
     D.TAG[ch_s] = (uint32_t)c;
+    if (prep) {  // the next attempt starts at R (chains_attempt_one)
+      D.NEXT[c] = ch_t > R ? ch_t : R;
+      D.FLAG[c] = INFINITY;
+    }
+  }
+  if (prep) {
+    // the work counters before the next launch (round_prep)
+    __shared__ long long s_e[16], s_sl[16];
+    long long e = act ? ev_c - cnt : 0, sl = act ? sl_c : 0;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      e += __shfl_xor(e, off, 64);
+      sl += __shfl_xor(sl, off, 64);
+    }
+    if (lane == 0) {
+      s_e[wv] = e;
+      s_sl[wv] = sl;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      for (int q = 1; q < (int)((blockDim.x + 63) >> 6); ++q) {
+        e += s_e[q];
+        sl += s_sl[q];
+      }
+      Ctl &C = *D.ctl;
+      C.lc.do_rb = 0;
+      C.tstar_bits = 0x7FF0000000000000ull;
+      C.abort = 0;
+      C.clock = R;
+      C.done = 0;
+      C.vkind_first = -1;
+      for (int q = 0; q < NVK; ++q) C.vkind_cnt[q] = 0ull;
+      C.t_start = ~0ull;
+      C.t_end = 0ull;
+      C.tot_events[0] = e;
+      C.tot_slots[0] = sl;
+    }
   }
   __syncthreads();
+  return true;
 }
 
 __global__ void k_ctl_reset(Dev D, double h) {
@@ -2497,21 +2538,25 @@ __global__ void __launch_bounds__(1024) k_round_end(Dev D, Geo g, LegP lp0) {
     s_run = D.ctl->lc.phase == PH_RUN;
   }
   __syncthreads();
-  if (s_rb && D.k <= (int)blockDim.x) {
-    rollback_block(D, g, s_R);
-  } else if (s_rb) {
-    const double R = s_R;
-    for (int c = threadIdx.x; c < D.k; c += blockDim.x) rb_mark_one(D, R, c);
-    __syncthreads();
-    for (int c = threadIdx.x; c < D.k; c += blockDim.x) rb_mark2_one(D, R, c);
-    __syncthreads();
-    for (int c = threadIdx.x; c < D.k; c += blockDim.x) rb_apply_one(D, g, R, c);
-    __syncthreads();
-    for (int c = threadIdx.x; c < D.k; c += blockDim.x) rb_reset_one(D, g, R, c);
-    __syncthreads();
+  // the fast rollback prepares the next attempt itself (h = R after a rollback)
+  bool prepared = false;
+  if (s_rb) {
+    const bool fast = D.k <= (int)blockDim.x && rollback_block(D, g, s_R, s_run != 0);
+    if (!fast) {
+      const double R = s_R;
+      for (int c = threadIdx.x; c < D.k; c += blockDim.x) rb_mark_one(D, R, c);
+      __syncthreads();
+      for (int c = threadIdx.x; c < D.k; c += blockDim.x) rb_mark2_one(D, R, c);
+      __syncthreads();
+      for (int c = threadIdx.x; c < D.k; c += blockDim.x) rb_apply_one(D, g, R, c);
+      __syncthreads();
+      for (int c = threadIdx.x; c < D.k; c += blockDim.x) rb_reset_one(D, g, R, c);
+      __syncthreads();
+    }
+    prepared = fast;
   }
   if (!s_run) return;
-  round_prep(D);
+  if (!prepared) round_prep(D);
 }
 
 
@@ -3196,7 +3241,7 @@ int run_leg(ecmc_ctx *ctx, int dir, double T) {
     // the first batch covers as many rounds as the previous leg took, and a
     // few more, so that a leg mostly costs one wait on the host; rounds past
     // the end of the leg return at once
-    int nspec = std::min(std::max(ctx->last_rounds + 4, 2), 64);
+    int nspec = std::min(std::max(ctx->last_rounds + 2, 2), 64);
     for (int64_t batch = 0;; ++batch) {
       for (int r = 0; r < nspec; ++r) {
         rc = enqueue_round(ctx, lp0);
