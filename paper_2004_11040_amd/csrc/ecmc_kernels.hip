@@ -3207,7 +3207,7 @@ int enqueue_round(ecmc_ctx *ctx, const LegP &lp0) {
 // resumes from R with every chain paused there (restart strategy 2, Sec. 3.4).
 // If rollbacks stop making progress, a short stretch runs with a small
 // bounded lag, then in global-time order (Alg. 2), which cannot violate.  The
-// decisions are taken on the device (k_round_post); the host enqueues rounds
+// decisions are taken on the device (k_round_end); the host enqueues rounds
 // ahead and reads the outcome once per batch of rounds.
 int run_leg(ecmc_ctx *ctx, int dir, double T) {
   Dev &D = ctx->D;
