@@ -124,16 +124,18 @@ def test_bounded_lag_window_is_pure_scheduling(window_micro):
     print("window", window_micro, "attempts", st["attempts"], "reruns", st["reruns"])
 
 
+@pytest.mark.parametrize("window_micro", [200_000, 0])
 @pytest.mark.parametrize("lanes", [64, 32, 16])
-def test_window_with_many_chains(lanes):
+def test_window_with_many_chains(lanes, window_micro):
     """With fewer lanes a wavefront runs several chains; a chain waiting at
-    the lag must not keep the others of its wavefront from running."""
+    the lag must not keep the others of its wavefront from running.  Also
+    free-running chains (no lag) at the same sizes."""
     x, y, L, act = _square(161, 32, 0.70, 128)
     T = 0.2 * L
     dirs = [0, 1, 0, 1]
-    e = gpu_run(x, y, L, act, dirs, T, lanes=lanes, opts=((pkg.OPT_WINDOW_MICRO, 200_000),))
+    e = gpu_run(x, y, L, act, dirs, T, lanes=lanes, opts=((pkg.OPT_WINDOW_MICRO, window_micro),))
     ref = oracle.run(x, y, 1.0, L, act, dirs, T)
-    check_parity(e, ref, L, 128, f"window k=128 lanes={lanes}")
+    check_parity(e, ref, L, 128, f"window={window_micro} k=128 lanes={lanes}")
 
 
 def test_contact_moves_keep_exact_arithmetic():
