@@ -2878,7 +2878,7 @@ struct ecmc_ctx {
   int32_t lanes = 64;
   int32_t wait_retries = 64;
   int32_t max_splits = 1;     // rollbacks without progress before a lockstep stretch
-  int32_t last_rounds = 0;    // rounds the previous leg took (sizes the first batch of rounds)
+  int32_t last_rounds[2] = {0, 0};  // rounds the last leg along +x / +y took (sizes the first batch)
   int64_t undo_cap = 4096;     // undo records per chain and leg
   int32_t force_global = 0;
   int32_t inject_chain = -1, inject_event = -1;
@@ -3238,10 +3238,12 @@ int run_leg(ecmc_ctx *ctx, int dir, double T) {
     lp0.features = ctx->features;
     lp0.self_clock = 0;
     Ctl hc;
-    // the first batch covers as many rounds as the previous leg took, and a
-    // few more, so that a leg mostly costs one wait on the host; rounds past
-    // the end of the leg return at once
-    int nspec = std::min(std::max(ctx->last_rounds + 2, 2), 64);
+    // the first batch covers as many rounds as the last leg along the same
+    // direction took (the lattice is not isotropic: legs along +x take about
+    // twice as many at N = 2^20), and two more, so that a leg mostly costs
+    // one wait on the host; rounds past the end of the leg return at once
+    int &last_rounds = ctx->last_rounds[dir & 1];
+    int nspec = std::min(std::max(last_rounds + 2, 2), 64);
     for (int64_t batch = 0;; ++batch) {
       for (int r = 0; r < nspec; ++r) {
         rc = enqueue_round(ctx, lp0);
@@ -3257,7 +3259,7 @@ int run_leg(ecmc_ctx *ctx, int dir, double T) {
       }
     }
     const LegCtl &lc = hc.lc;
-    ctx->last_rounds = (int)std::min<long long>(lc.rounds, 1 << 20);
+    last_rounds = (int)std::min<long long>(lc.rounds, 1 << 20);
     ctx->attempts += lc.attempts;
     ctx->reruns += lc.reruns;
     ctx->lockstep_runs += lc.lockstep_runs;
