@@ -1725,9 +1725,15 @@ __device__ void chain_events(const Dev &D, const Geo &g, const LegP &lp, int32_t
   }
   if (lane == 0) {
     // a chain stopped by an abort keeps its last next-event time: a lower
-    // bound of every lifting it has still to make
-    if (finished) st_a<SC>(&D.NEXT[c], INFINITY);
-    __hip_atomic_fetch_add(&D.ctl->done, 1, __ATOMIC_RELAXED, SC);
+    // bound of every lifting it has still to make.  Only finished chains
+    // count themselves: the clock stops on an abort anyway, and a thousand
+    // chains leaving an aborted attempt together would otherwise queue on
+    // the one counter (an atomic on one address is serialized, ~5 ns each),
+    // which held the end of every aborted launch back by ~5 us.
+    if (finished) {
+      st_a<SC>(&D.NEXT[c], INFINITY);
+      __hip_atomic_fetch_add(&D.ctl->done, 1, __ATOMIC_RELAXED, SC);
+    }
     cnt[C_SCANNED] += sc;
     cnt[C_REFINES] += rf;
     for (int q = 0; q < NCNT; ++q) D.CNT_W[c * NCNT + q] = cnt[q];
