@@ -105,7 +105,8 @@ struct Ctl {
   int32_t error;                  // ECMC_E* raised by a kernel
   unsigned long long overlaps;
   int32_t inject_chain, inject_event;
-  int32_t pad[2];
+  int32_t ev_blocks;  // workgroups of the last event launch (their stamps are in TS)
+  int32_t pad1;
   long long tot_events[2], tot_slots[2];  // work counters before / after the last launch
   double clock;     // H: smallest next-event time published by the chains
   int32_t done;     // chains that finished the attempt
@@ -154,6 +155,7 @@ struct Dev {
   // rollback keys per slot (earliest undone claim of the slot)
   unsigned long long *RKEY, *RKEY2;
   double *NEXT;  // per chain: time of the event it is about to commit (+inf: done)
+  unsigned long long *TS;  // per event workgroup: s_memrealtime at its start and end
   struct RefRec *REF;   // per chain: current activation
   unsigned long long *RES;  // per slot: earliest (time, chain) that targets the disk
   Ctl *ctl;
@@ -1759,9 +1761,11 @@ __global__ void __launch_bounds__(256) k_event(Dev D, Geo g, LegP lp, int32_t wa
     lp.tend = lc.tend_cur;
     lp.window = lc.lag_cur;
   }
+  // device timing: each workgroup stamps its own start and end (a min and a
+  // max over one word from every workgroup would queue on that word)
   if (threadIdx.x == 0) {
-    const unsigned long long now = __builtin_amdgcn_s_memrealtime();
-    __hip_atomic_fetch_min(&D.ctl->t_start, now, __ATOMIC_RELAXED, SCA);
+    D.TS[2 * blockIdx.x] = __builtin_amdgcn_s_memrealtime();
+    if (blockIdx.x == 0) D.ctl->ev_blocks = (int32_t)gridDim.x;
   }
   if (blockIdx.x == gridDim.x - 1) {  // the clock workgroup (idle without a bounded lag)
     if (lp.window > 0.0) clock_loop(D, iter_cap);
@@ -1769,10 +1773,7 @@ __global__ void __launch_bounds__(256) k_event(Dev D, Geo g, LegP lp, int32_t wa
     chain_events<G, F32, SCA>(D, g, lp, wait_retries, iter_cap, c, lane);
   }
   __syncthreads();
-  if (threadIdx.x == 0) {
-    const unsigned long long now = __builtin_amdgcn_s_memrealtime();
-    __hip_atomic_fetch_max(&D.ctl->t_end, now, __ATOMIC_RELAXED, SCA);
-  }
+  if (threadIdx.x == 0) D.TS[2 * blockIdx.x + 1] = __builtin_amdgcn_s_memrealtime();
 }
 
 // ------------------------------------------------------------------------
@@ -2368,6 +2369,39 @@ __device__ __forceinline__ void round_reduce(const Dev &D, double *m_out, long l
   *sl_out = sl;
 }
 
+// The last event launch's span on the device: the first workgroup's start to
+// the last one's end, from the workgroups' own stamps (into ctl t_start, t_end).
+__device__ __forceinline__ void launch_span(const Dev &D) {
+  __shared__ unsigned long long s_t0[16], s_t1[16];
+  const int nb = D.ctl->ev_blocks;
+  unsigned long long t0 = ~0ull, t1 = 0ull;
+  for (int b = threadIdx.x; b < nb; b += blockDim.x) {
+    const unsigned long long a = D.TS[2 * b], z = D.TS[2 * b + 1];
+    t0 = a < t0 ? a : t0;
+    t1 = z > t1 ? z : t1;
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    const unsigned long long a = __shfl_xor(t0, off, 64), z = __shfl_xor(t1, off, 64);
+    t0 = a < t0 ? a : t0;
+    t1 = z > t1 ? z : t1;
+  }
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) {
+    s_t0[threadIdx.x >> 6] = t0;
+    s_t1[threadIdx.x >> 6] = t1;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int q = 1; q < (int)((blockDim.x + 63) >> 6); ++q) {
+      t0 = s_t0[q] < t0 ? s_t0[q] : t0;
+      t1 = s_t1[q] > t1 ? s_t1[q] : t1;
+    }
+    D.ctl->t_start = t0;
+    D.ctl->t_end = t1;
+  }
+  __syncthreads();
+}
+
 // Prepare an attempt from lc.h: reset the attempt's flags, tag every chain's
 // disk, seed next-event times, record the work counters before the launch.
 __device__ __forceinline__ void round_prep(const Dev &D) {
@@ -2537,6 +2571,7 @@ __global__ void __launch_bounds__(1024) k_round_end(Dev D, Geo g, LegP lp0) {
   double H;
   long long e, sl;
   round_reduce(D, &H, &e, &sl);
+  launch_span(D);
   if (threadIdx.x == 0) {
     round_decide(D, H, e, sl);
     s_rb = D.ctl->lc.do_rb;
@@ -2952,7 +2987,7 @@ Layout make_layout(int64_t n, int32_t nc, int32_t kmax, int64_t log_cap, uint32_
       S * 16,                 // 6 MUT
       S * 16,                 // 7 CST
       S * 4,                  // 8 TAG
-      0,                      // 9 (unused)
+      ((int64_t)kmax / 4 + 2) * 16,  // 9 TS (event workgroups: 64 lanes per chain, 256 threads each, + clock)
       (int64_t)kmax * 4,      // 10 CH_SLOT
       (int64_t)kmax * NCNT * 8,  // 11 CNT_W
       (int64_t)kmax * NCNT * 8,  // 12 CNT_C
@@ -3394,6 +3429,7 @@ int ecmc_init(ecmc_ctx **out, const double *positions_xy, int64_t n, double sigm
   D.UNDO_N_OLD = (long long *)(b + Lo.off[30]);
   D.undo_cap = UNDO_CAP;
   D.NEXT = (double *)(b + Lo.off[32]);
+  D.TS = (unsigned long long *)(b + Lo.off[9]);
   D.REF = (RefRec *)(b + Lo.off[31]);
   D.RES = (unsigned long long *)(b + Lo.off[33]);
   D.n = n;
