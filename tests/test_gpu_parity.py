@@ -138,6 +138,56 @@ def test_window_with_many_chains(lanes, window_micro):
     check_parity(e, ref, L, 128, f"window={window_micro} k=128 lanes={lanes}")
 
 
+def _cells(L, sigma=1.0):
+    """Home cells per side the library picks by default: the most cells whose
+    side is at least the diameter (restated here, not imported)."""
+    d = 2.0 * sigma
+    nc = int(math.floor(L / d))
+    while nc > 1 and L / nc < d * (1.0 + 1e-9):
+        nc -= 1
+    return nc
+
+
+@pytest.mark.parametrize("flags", [pkg.FP64, pkg.FP32_MIXED])
+def test_longest_legal_leg(flags):
+    """Legs as long as the library allows (box - 4 cells - d): the scans reach
+    their farthest columns and the disk that stopped at the last lifting is
+    closest to coming back into reach."""
+    x, y, L, act = _square(171, 12, 0.62, 12)
+    T = (L - 4.0 * (L / _cells(L)) - 2.0) * (1.0 - 1e-12)
+    dirs = [0, 1, 0, 1]
+    e = gpu_run(x, y, L, act, dirs, T, flags=flags)
+    ref = oracle.run(x, y, 1.0, L, act, dirs, T)
+    check_parity(e, ref, L, 12, f"longest leg flags={flags}")
+
+
+@pytest.mark.parametrize("flags", [pkg.FP64, pkg.FP32_MIXED])
+@pytest.mark.parametrize("tfrac", [1e-4, 1.0])
+def test_smallest_box(tfrac, flags):
+    """5 x 5 disks at eta 0.58 in a box of 5 x 5 home cells, the fewest the
+    library accepts, with a leg far shorter than a flight (no lifting) and the
+    longest legal one (19 liftings in the oracle)."""
+    x, y, L, act = _square(173, 5, 0.58, 4)
+    assert _cells(L) == 5
+    T = (L - 4.0 * (L / 5) - 2.0) * (1.0 - 1e-12) * tfrac
+    dirs = [0, 1, 0, 1, 0, 1]
+    e = gpu_run(x, y, L, act, dirs, T, flags=flags)
+    ref = oracle.run(x, y, 1.0, L, act, dirs, T)
+    if tfrac == 1.0:
+        assert ref.n_events > 0
+    check_parity(e, ref, L, 4, f"smallest box T={T} flags={flags}")
+
+
+def test_zero_chain_time_is_a_no_op():
+    s = W.config(0)
+    e = gpu_run(s.x, s.y, s.L, s.active, [], s.T)
+    e.run(0.0, s.T)
+    st = e.stats()
+    assert st["events"] == 0 and st["legs"] == 0
+    pos = e.positions()
+    assert np.array_equal(pos[:, 0], s.x) and np.array_equal(pos[:, 1], s.y)
+
+
 def test_contact_moves_keep_exact_arithmetic():
     """One failed claim on an active target is enough to publish a move up to
     contact: many moves, still the oracle's liftings and bits."""
