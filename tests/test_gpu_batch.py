@@ -157,3 +157,32 @@ def test_batch_replica_workload_sample():
     for s, e in zip(reps, systems):
         ref = oracle.run(s.x, s.y, 1.0, s.L, s.active, [0], s.T, log_cap=1 << 20)
         _check(e, ref, s.k, s.name)
+
+
+def test_batch_one_replica_one_chain():
+    """The smallest batch: one replica with one chain (the rest of the
+    workgroup idle), three alternating legs."""
+    x, y, L, act, T = _small_replicas(1, 23)[0]
+    act = act[:1]
+    e = pkg.Ecmc(np.stack([x, y], 1), 1.0, L, max_chains=1, log_cap=1 << 14)
+    e.set_active(act)
+    b = pkg.Batch([e])
+    b.set_option(pkg.OPT_LANES, 4)
+    b.run(np.array([1 << 60], np.int64), [T], pkg.DIR_ALTERNATE, max_legs=3)
+    ref = oracle.run(x, y, 1.0, L, act, [0, 1, 0], T)
+    _check(e, ref, 1, "one replica, one chain")
+
+
+def test_batch_replica_at_the_chain_limit():
+    """A replica with 128 chains at 4 lanes fills its workgroup's 512 threads
+    (the largest k of the 512-replica workload, N = 16384), one leg."""
+    s = W.replica_batch(512)[230]
+    assert s.k == 128
+    e = pkg.Ecmc(np.stack([s.x, s.y], 1), 1.0, s.L, flags=pkg.FP32_MIXED, max_chains=s.k, log_cap=1 << 12)
+    e.set_active(s.active)
+    b = pkg.Batch([e])
+    b.set_option(pkg.OPT_LANES, 4)
+    b.set_option(pkg.OPT_WINDOW_MICRO, 350_000)
+    b.run(np.array([1 << 60], np.int64), [s.T], pkg.DIR_ALTERNATE, max_legs=1)
+    ref = oracle.run(s.x, s.y, 1.0, s.L, s.active, [0], s.T, log_cap=1 << 20)
+    _check(e, ref, s.k, s.name)
