@@ -313,54 +313,50 @@ __global__ void k_bin(Dev D, Geo g, int32_t dir) {
   if (i < D.n) bin_one(D, g, dir, i);
 }
 
-// One thread per cell: order the cell's disks by id (deterministic layout) and
-// write their slot records.
-__device__ void cellfill_one(const Dev &D, const Geo &g, int32_t dir, int64_t cell) {
+// One thread per slot: slot q of a cell gets the cell's q-th disk in
+// increasing id order (a deterministic layout), empty slots after them.  The
+// CAP threads of a cell lie in one wavefront and each rewrites its record
+// from the ids of all CAP slots, so every id is read before any record of the
+// cell is rewritten; consecutive threads write consecutive records.
+__device__ void cellfill_slot(const Dev &D, const Geo &g, int32_t dir, int64_t s) {
+  const int64_t cell = s / CAP;
+  const int q = (int)(s - cell * CAP);
   int cnt = D.CELL_CNT[cell];
   cnt = cnt > CAP ? CAP : cnt;
   int ids[CAP];
-  for (int q = 0; q < CAP; ++q) ids[q] = q < cnt ? D.CST[cell * CAP + q].id : 0x7fffffff;
-  for (int q = 1; q < CAP; ++q)  // insertion sort of <= 4 ids
-    for (int r = q; r > 0 && ids[r] < ids[r - 1]; --r) {
-      int tmp = ids[r];
-      ids[r] = ids[r - 1];
-      ids[r - 1] = tmp;
+  for (int r = 0; r < CAP; ++r) ids[r] = r < cnt ? D.CST[cell * CAP + r].id : 0x7fffffff;
+  for (int r = 1; r < CAP; ++r)  // insertion sort of <= 4 ids
+    for (int v = r; v > 0 && ids[v] < ids[v - 1]; --v) {
+      const int tmp = ids[v];
+      ids[v] = ids[v - 1];
+      ids[v - 1] = tmp;
     }
-  int row = (int)(cell / g.nc), col = (int)(cell % g.nc);
-  for (int q = 0; q < CAP; ++q) {
-    int64_t s = cell * CAP + q;
-    if (q < cnt) {
-      int i = ids[q];
-      double a = dir ? D.Y[i] : D.X[i];
-      double p = dir ? D.X[i] : D.Y[i];
-      CstRec cr;
-      cr.p = p;
-      cr.id = i;
-      cr.pad = 0;
-      D.CST[s] = cr;
-      MutRec mr;
-      mr.a = a;
-      mr.t = D.STAMP[i];
-      D.MUT[s] = mr;
-      D.TAG[s] = TAG_STATIC;
-      D.SLOT_OF[i] = (int32_t)s;
-    } else {
-      CstRec cr;
-      cr.p = 0.0;
-      cr.id = -1;
-      cr.pad = 0;
-      D.CST[s] = cr;
-      MutRec mr;
-      mr.a = 0.0;
-      mr.t = 0.0;
-      D.MUT[s] = mr;
-      D.TAG[s] = TAG_STATIC;
-    }
+  int mine = ids[0];
+  for (int r = 1; r < CAP; ++r)
+    if (r == q) mine = ids[r];
+  CstRec cr;
+  MutRec mr;
+  cr.pad = 0;
+  if (q < cnt) {
+    const int i = mine;
+    cr.p = dir ? D.X[i] : D.Y[i];
+    cr.id = i;
+    mr.a = dir ? D.Y[i] : D.X[i];
+    mr.t = D.STAMP[i];
+    D.SLOT_OF[i] = (int32_t)s;
+  } else {
+    cr.p = 0.0;
+    cr.id = -1;
+    mr.a = 0.0;
+    mr.t = 0.0;
   }
+  D.CST[s] = cr;
+  D.MUT[s] = mr;
+  D.TAG[s] = TAG_STATIC;
 }
 __global__ void k_cellfill(Dev D, Geo g, int32_t dir) {
-  int64_t cell = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (cell < (int64_t)g.nc * g.nc) cellfill_one(D, g, dir, cell);
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s < (int64_t)g.nc * g.nc * CAP) cellfill_slot(D, g, dir, s);
 }
 
 // Once per leg, after the home-cell build: attach each chain to its disk's slot.
@@ -2712,7 +2708,9 @@ __device__ __noinline__ void replica_build(const Dev &D, const Geo &g, int dir) 
   __syncthreads();
   for (int64_t i = tid; i < D.n; i += nt) bin_one(D, g, dir, i);
   __syncthreads();
-  for (int64_t i = tid; i < ncell; i += nt) cellfill_one(D, g, dir, i);
+  // slots strided by the workgroup size (a multiple of CAP): a cell's CAP
+  // slots fall into one iteration and one wavefront, as cellfill_slot needs
+  for (int64_t sl = tid; sl < ncell * CAP; sl += nt) cellfill_slot(D, g, dir, sl);
   __syncthreads();
   for (int c = tid; c < D.k; c += nt) chains_leg_one(D, ncell * CAP, c);
   __syncthreads();
@@ -3071,7 +3069,7 @@ int build_cells(ecmc_ctx *ctx, int dir) {
   if (rc) return rc;
   k_bin<<<blocks_for(D.n, 256), 256, 0, ctx->stream>>>(D, ctx->g, dir);
   HIPCHK(hipGetLastError());
-  k_cellfill<<<blocks_for((int64_t)ctx->g.nc * ctx->g.nc, 256), 256, 0, ctx->stream>>>(D, ctx->g, dir);
+  k_cellfill<<<blocks_for((int64_t)ctx->g.nc * ctx->g.nc * CAP, 256), 256, 0, ctx->stream>>>(D, ctx->g, dir);
   HIPCHK(hipGetLastError());
   return ECMC_OK;
 }
