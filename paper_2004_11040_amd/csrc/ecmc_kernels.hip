@@ -318,7 +318,7 @@ __global__ void k_bin(Dev D, Geo g, int32_t dir) {
 // CAP threads of a cell lie in one wavefront and each rewrites its record
 // from the ids of all CAP slots, so every id is read before any record of the
 // cell is rewritten; consecutive threads write consecutive records.
-__device__ void cellfill_slot(const Dev &D, const Geo &g, int32_t dir, int64_t s) {
+__device__ void cellfill_slot(const Dev &D, int32_t dir, int64_t s) {
   const int64_t cell = s / CAP;
   const int q = (int)(s - cell * CAP);
   int cnt = D.CELL_CNT[cell];
@@ -356,7 +356,7 @@ __device__ void cellfill_slot(const Dev &D, const Geo &g, int32_t dir, int64_t s
 }
 __global__ void k_cellfill(Dev D, Geo g, int32_t dir) {
   const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (s < (int64_t)g.nc * g.nc * CAP) cellfill_slot(D, g, dir, s);
+  if (s < (int64_t)g.nc * g.nc * CAP) cellfill_slot(D, dir, s);
 }
 
 // Once per leg, after the home-cell build: attach each chain to its disk's slot.
@@ -420,7 +420,7 @@ __device__ __forceinline__ void rb_mark2_one(const Dev &D, double R, int c) {
       atomicMin(&D.RKEY2[u.sj], (unsigned long long)__double_as_longlong(u.tj));
   }
 }
-__device__ __forceinline__ void rb_apply_one(const Dev &D, const Geo &g, double R, int c) {
+__device__ __forceinline__ void rb_apply_one(const Dev &D, double R, int c) {
   const long long n = D.UNDO_N_OLD[c];
   long long m = n - 1;
   for (; m >= 0; --m) {
@@ -793,7 +793,7 @@ __device__ __forceinline__ float grp_min_f32(float v) {
 }
 
 template <int G>
-__device__ __forceinline__ int grp_owner(bool mine, int lane) {
+__device__ __forceinline__ int grp_owner(bool mine) {
   unsigned long long m = __ballot(mine);
   if constexpr (G == 64) {
     return m ? (__ffsll((long long)m) - 1) : 0;
@@ -1317,7 +1317,7 @@ __device__ void chain_events(const Dev &D, const Geo &g, const LegP &lp, int32_t
     int gsl[3];
 #pragma unroll
     for (int q = 0; q < 3; ++q) {
-      const int own = grp_owner<G>(bl.tau[q] == gt[q] && bl.id[q] == gi[q] && gt[q] < INFINITY, lane);
+      const int own = grp_owner<G>(bl.tau[q] == gt[q] && bl.id[q] == gi[q] && gt[q] < INFINITY);
       gtj[q] = bcast<G>(bl.t[q], own);
       gaj[q] = bcast<G>(bl.a[q], own);
       gbj[q] = bcast<G>(bl.b[q], own);
@@ -2080,7 +2080,7 @@ __device__ __forceinline__ void g_scan_wave(const Dev &D, const Geo &g, int s, i
     int mi = id;
     grp_min<64>(mt, mi);
     if (key_less(mt, mi, btau, bid)) {
-      const int own = grp_owner<64>(tau == mt && id == mi, lane);
+      const int own = grp_owner<64>(tau == mt && id == mi);
       btau = mt;
       bid = mi;
       bslot = __shfl(sl, own, 64);
@@ -2586,7 +2586,7 @@ __global__ void __launch_bounds__(1024) k_round_end(Dev D, Geo g, LegP lp0) {
       __syncthreads();
       for (int c = threadIdx.x; c < D.k; c += blockDim.x) rb_mark2_one(D, R, c);
       __syncthreads();
-      for (int c = threadIdx.x; c < D.k; c += blockDim.x) rb_apply_one(D, g, R, c);
+      for (int c = threadIdx.x; c < D.k; c += blockDim.x) rb_apply_one(D, R, c);
       __syncthreads();
       for (int c = threadIdx.x; c < D.k; c += blockDim.x) rb_reset_one(D, g, R, c);
       __syncthreads();
@@ -2710,7 +2710,7 @@ __device__ __noinline__ void replica_build(const Dev &D, const Geo &g, int dir) 
   __syncthreads();
   // slots strided by the workgroup size (a multiple of CAP): a cell's CAP
   // slots fall into one iteration and one wavefront, as cellfill_slot needs
-  for (int64_t sl = tid; sl < ncell * CAP; sl += nt) cellfill_slot(D, g, dir, sl);
+  for (int64_t sl = tid; sl < ncell * CAP; sl += nt) cellfill_slot(D, dir, sl);
   __syncthreads();
   for (int c = tid; c < D.k; c += nt) chains_leg_one(D, ncell * CAP, c);
   __syncthreads();
@@ -2813,7 +2813,7 @@ __device__ int replica_leg(const RepIn &ri, RepOut *rp, int dir, int32_t wait_re
     __syncthreads();
     for (int c = tid; c < D.k; c += nt) rb_mark2_one(D, R, c);
     __syncthreads();
-    for (int c = tid; c < D.k; c += nt) rb_apply_one(D, g, R, c);
+    for (int c = tid; c < D.k; c += nt) rb_apply_one(D, R, c);
     __syncthreads();
     for (int c = tid; c < D.k; c += nt) rb_reset_one(D, g, R, c);
     __syncthreads();
@@ -2973,7 +2973,7 @@ bool cells_ok(double sigma, double box, int32_t nc) {
 }
 
 // workspace layout; order matters only for alignment
-Layout make_layout(int64_t n, int32_t nc, int32_t kmax, int64_t log_cap, uint32_t flags) {
+Layout make_layout(int64_t n, int32_t nc, int32_t kmax, int64_t log_cap) {
   Layout L;
   int64_t S = (int64_t)nc * nc * CAP;
   int64_t sizes[] = {
@@ -3361,7 +3361,7 @@ int64_t ecmc_workspace_bytes(int64_t n, double sigma, double box, int32_t cells,
   const int32_t nc = cells == 0 ? default_cells(sigma, box) : cells;
   if (!cells_ok(sigma, box, nc)) return ECMC_EINVAL;
   if ((int64_t)nc * nc * CAP < n) return ECMC_EINVAL;
-  return make_layout(n, nc, max_chains, log_cap, flags).total;
+  return make_layout(n, nc, max_chains, log_cap).total;
 }
 
 int ecmc_init(ecmc_ctx **out, const double *positions_xy, int64_t n, double sigma, double box,
@@ -3394,7 +3394,7 @@ int ecmc_init(ecmc_ctx **out, const double *positions_xy, int64_t n, double sigm
   g.L32 = (float)box;
   g.d2_32 = (float)g.d2;
   g.sigma32 = (float)sigma;
-  Layout Lo = make_layout(n, nc, max_chains, log_cap, flags);
+  Layout Lo = make_layout(n, nc, max_chains, log_cap);
   char *b = (char *)workspace;
   Dev &D = ctx->D;
   D.X = (double *)(b + Lo.off[0]);
@@ -3616,7 +3616,7 @@ int ecmc_stats(ecmc_ctx *ctx, ecmc_stats_t *out) {
 int ecmc_get_positions(ecmc_ctx *ctx, double *out_xy) {
   if (!ctx || !out_xy) return ECMC_EINVAL;
   Dev &D = ctx->D;
-  Layout Lo = make_layout(D.n, ctx->g.nc, ctx->kmax, ctx->log_cap, ctx->flags);
+  Layout Lo = make_layout(D.n, ctx->g.nc, ctx->kmax, ctx->log_cap);
   double *stage = (double *)((char *)D.X - Lo.off[0] + Lo.off[23]);
   k_join_xy<<<blocks_for(D.n, 256), 256, 0, ctx->stream>>>(D, stage);
   HIPCHK(hipGetLastError());
