@@ -4,7 +4,7 @@
  *
  * Method: Li, Todo, Maggs, Krauth, "Multithreaded event-chain Monte Carlo with
  * local times".  Between two breakpoints h and h' (a "leg"), k active disks
- * ("chains") move with one common velocity v (+x or +y).  Each chain advances
+ * ("chains") move with one common velocity v (+x, +y, -x or -y).  Each chain advances
  * on its own local time: it finds the next disk it would hit (time of flight
  * tau_ij = forward distance - b_ij, b_ij = sqrt((2 sigma)^2 - dp^2), Sec. 2.2),
  * checks the horizon condition t_i + tau_ij > t_j (Eq. 2) on the nearest disk
@@ -157,7 +157,9 @@ typedef struct {
                                     4 active target, 5 changed records, 6 yield) */
 } ecmc_stats_t;
 
-/* Bytes of device workspace for a context.  n disks of radius sigma in a box of
+/* Bytes of device workspace for a context (the storage of the lifted
+ * configuration {C, A} of Sec. 2.1 with the per-leg home cells, local times
+ * and tags of Sec. 2.2-2.3).  n disks of radius sigma in a box of
  * side box; cells per side (0: floor(box / (2 sigma)) reduced until the cell is
  * at least 2 sigma wide); max_chains >= the k later passed to ecmc_set_active;
  * log_cap = number of target ids kept per chain (a ring: the last log_cap
@@ -190,9 +192,18 @@ int ecmc_init(ecmc_ctx **out, const double *positions_xy, int64_t n,
 int ecmc_set_active(ecmc_ctx *ctx, const int32_t *idx, int32_t k);
 
 /* Run chain_time / breakpoint_interval legs (that ratio must be an integer
- * within 1e-9) of length T = breakpoint_interval each.
- * direction: 0 +x, 1 +y, 4 alternate +x/+y (the first leg of the context is
- * +x, and the alternation continues across calls).
+ * within 1e-9) of length T = breakpoint_interval each.  A leg is the interval
+ * between two breakpoints h and h' = h + T: the multithreaded local-time
+ * algorithm (Alg. 5 / Alg. 6, Sec. 2.3-2.4) takes the lifted configuration
+ * {C_h, A_h} to {C_h', A_h'} and adds the leg's liftings to L; without a
+ * horizon violation this is the output of global-time ECMC, Alg. 2 (Lemma 2,
+ * Lemma 3), and violations are undone by restarts (Sec. 3.4).
+ * direction: 0 +x, 1 +y, 2 -x, 3 -y, 4 alternate +x/+y (the first leg of the
+ * context is +x, and the alternation continues across calls).  -x and -y run
+ * the leg on the reflected coordinate L - x (or L - y), so a leg followed by
+ * the opposite leg of the same length returns the configuration (Remark on
+ * time-reversal invariance) up to the rounding of the reflection, a few ulps
+ * of the box.
  * n_chains must equal the k given to ecmc_set_active.  T must satisfy
  * 0 <= T <= box - 4 (box/cells) - 2 sigma.  Horizon violations are absorbed by
  * rollbacks and counted in the statistics.  Synchronises the stream once per
@@ -201,23 +212,36 @@ int ecmc_set_active(ecmc_ctx *ctx, const int32_t *idx, int32_t k);
 int ecmc_run(ecmc_ctx *ctx, int32_t n_chains, double chain_time,
              double breakpoint_interval, int32_t direction);
 
-/* Statistics accumulated since ecmc_set_active.  Synchronises the stream. */
+/* Statistics accumulated since ecmc_set_active.  events counts elements of
+ * the lifting set L (Alg. 1 output); sum_b and pressure are the ECMC pressure
+ * estimator, beta P / rho = 1 + sum of b_ij over liftings / chain time (the
+ * lifting distance b_ij of Sec. 2.2 summed per chain in lifting order, then
+ * over chains); the other counters describe the horizon protocol (Eq. 2,
+ * Alg. 5) and its restarts (Sec. 3.4).  Synchronises the stream. */
 int ecmc_stats(ecmc_ctx *ctx, ecmc_stats_t *out);
 
-/* Copy the current configuration to HOST memory: out_xy n x 2 doubles. */
+/* Copy the current configuration C (Sec. 2.1) to HOST memory: out_xy n x 2
+ * doubles, row-major (x0,y0,x1,y1,...).  Synchronises the stream. */
 int ecmc_get_positions(ecmc_ctx *ctx, double *out_xy);
 
-/* Local times at the end of the last leg (HOST, n doubles; leg-relative). */
+/* Local times t_i at the end of the last leg (HOST, n doubles, relative to
+ * the leg's breakpoint h; Remark on the meaning of local times: the last time
+ * disk i was active, h' for the stalled active disks, Remark on stalled
+ * spheres).  Synchronises the stream. */
 int ecmc_get_stamps(ecmc_ctx *ctx, double *out);
 
-/* Current active set (HOST, k int32: disk of chain c). */
+/* Current active set A (Sec. 2.1; HOST, k int32: disk of chain c).
+ * Synchronises the stream. */
 int ecmc_get_active(ecmc_ctx *ctx, int32_t *out);
 
 /* Per-chain results since ecmc_set_active (HOST, k entries each; either may
- * be NULL): sum of b_ij in the chain's lifting order, and lifting count. */
+ * be NULL): sum of the lifting distances b_ij (Sec. 2.2) in the chain's
+ * lifting order, and its number of liftings.  Synchronises the stream. */
 int ecmc_get_chain_sums(ecmc_ctx *ctx, double *sum_b, int64_t *events);
 
-/* Lifting log of one chain: the target disk ids of its liftings, in order.
+/* Lifting log of one chain: the target disk ids j of its liftings i -> j,
+ * in order (the chain's part of the lifting set L output by Alg. 1 and
+ * Alg. 2; consecutive entries are the disks the chain moved).
  * Writes min(count, log_cap, cap) most recent entries to the HOST array
  * targets and the chain's total lifting count to *n_out.  ECMC_EINVAL if
  * chain is out of range or cap < min(count, log_cap). */
@@ -226,22 +250,31 @@ int ecmc_get_log(ecmc_ctx *ctx, int32_t chain, int32_t *targets, int64_t cap,
 
 /* Count pairs closer than 2 sigma - 4 ulp(box) in the current configuration
  * (binary64, minimum image; zero tolerance beyond rounding of contact
- * positions).  Writes the count to *count and into the statistics. */
+ * positions).  Hard disks may not overlap (Sec. 1, the hard-disk model; a
+ * valid run keeps every pair at distance >= 2 sigma, Eq. 1 moves a disk up
+ * to contact only).  Writes the count to *count and into the statistics.
+ * Synchronises the stream. */
 int ecmc_overlaps(ecmc_ctx *ctx, int64_t *count);
 
-/* Tuning and test options (ECMC_OPT_*).  ECMC_EINVAL for unknown keys or
- * values. */
+/* Tuning and test options (ECMC_OPT_*): scheduling of the horizon protocol
+ * (Alg. 5), the necklace retries (Remark on active-sphere necklaces), the
+ * restart ladder (Sec. 3.4) and test hooks.  None changes results.
+ * ECMC_EINVAL for unknown keys or values. */
 int ecmc_set_option(ecmc_ctx *ctx, int32_t key, int64_t value);
 
-/* Static description of the last error on this context (never NULL). */
+/* Static description of the last error on this context (never NULL; the
+ * caller must not free it).  Bookkeeping of the C ABI, no paper passage. */
 const char *ecmc_last_error(const ecmc_ctx *ctx);
 
 /* Release the context (host memory only; the workspace stays the caller's).
- * Accepts NULL. */
+ * Accepts NULL.  Bookkeeping of the C ABI, no paper passage. */
 void ecmc_free(ecmc_ctx *ctx);
 
 /* ---- batched replicas -----------------------------------------------------
- * Many independent systems ("replicas"), each a context set up as usual
+ * Many independent systems ("replicas"), each the problem of Sec. 2.1 (one
+ * lifted configuration advanced leg by leg between breakpoints; running many
+ * of them at once is a systems pattern, not part of the paper), each a
+ * context set up as usual
  * (ecmc_init, ecmc_set_active), run together in ONE persistent launch: a
  * workgroup takes a replica from a device queue and runs its legs, with the
  * breakpoint synchronisation, rollbacks (Sec. 3.4, strategy 2) and the
@@ -273,7 +306,9 @@ typedef struct {
 } ecmc_batch_info_t;
 
 /* Bytes of device scratch for a batch of n_ctx contexts (descriptors, the
- * work queue and its order, longest expected replica first).  Negative ECMC_EINVAL for n_ctx outside [1, 2^20]. */
+ * work queue and its order, longest expected replica first; bookkeeping of
+ * the batch, no paper passage).  Negative ECMC_EINVAL for n_ctx outside
+ * [1, 2^20]. */
 int64_t ecmc_batch_scratch_bytes(int32_t n_ctx);
 
 /* Group n_ctx distinct contexts (HOST array of handles; the contexts must
@@ -301,13 +336,16 @@ int ecmc_batch_set_option(ecmc_batch *b, int32_t key, int64_t value);
 int ecmc_batch_run(ecmc_batch *b, const int64_t *target_events,
                    const double *leg_T, int32_t direction, int32_t max_legs);
 
-/* Details of the last ecmc_batch_run. */
+/* Details of the last ecmc_batch_run (liftings as for ecmc_stats, restarts
+ * of Sec. 3.4, global-order stretches of Alg. 2, and the autotuner's rates). */
 int ecmc_batch_info(const ecmc_batch *b, ecmc_batch_info_t *out);
 
-/* Static description of the last error of the batch (never NULL). */
+/* Static description of the last error of the batch (never NULL; bookkeeping
+ * of the C ABI, no paper passage). */
 const char *ecmc_batch_last_error(const ecmc_batch *b);
 
-/* Release the batch (host memory and the captured graph).  Accepts NULL. */
+/* Release the batch (host memory and the captured graph).  Accepts NULL.
+ * Bookkeeping of the C ABI, no paper passage. */
 void ecmc_batch_free(ecmc_batch *b);
 
 #ifdef __cplusplus

@@ -15,6 +15,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libecmc.so")
+PROBE_LIB_PATH = os.path.join(_HERE, "libecmc_probe.so")
 
 OK = 0
 EINVAL, EOVERLAP, EDEVICE, ECELL, EHANG, ESTATE = -1, -2, -3, -4, -5, -6
@@ -25,9 +26,12 @@ OPT_WINDOW_MICRO = 9
 OPT_FEATURES = 10
 OPT_GRAPH = 11
 FEAT_SCREEN, FEAT_RESERVE, FEAT_REREAD, FEAT_FRESH, FEAT_ALL = 1, 2, 4, 8, 15
-DIR_X, DIR_Y, DIR_ALTERNATE = 0, 1, 4
+DIR_X, DIR_Y, DIR_MX, DIR_MY, DIR_ALTERNATE = 0, 1, 2, 3, 4
 
-# every symbol the header declares
+# every symbol include/ecmc_probe.h declares (libecmc_probe.so)
+PROBE_EXPORTS = ("ecmc_probe_chase", "ecmc_probe_gather")
+
+# every symbol include/ecmc.h declares
 EXPORTS = (
     "ecmc_workspace_bytes", "ecmc_init", "ecmc_set_active", "ecmc_run", "ecmc_stats",
     "ecmc_get_positions", "ecmc_get_stamps", "ecmc_get_active", "ecmc_get_chain_sums",
@@ -130,6 +134,54 @@ def load_library(path: str = LIB_PATH):
     lib.ecmc_batch_free.argtypes = [P]
     _lib = lib
     return lib
+
+
+_probe_lib = None
+
+
+def load_probe_library(path: str = PROBE_LIB_PATH):
+    """Load libecmc_probe.so, the memory microbenchmarks (raises if missing)."""
+    global _probe_lib
+    if _probe_lib is not None:
+        return _probe_lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is not built; run __graft_entry__.build() first")
+    lib = ctypes.CDLL(path)
+    P, I32, I64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+    lib.ecmc_probe_chase.restype = ctypes.c_int
+    lib.ecmc_probe_chase.argtypes = [P, I64, I64, I32, P, ctypes.POINTER(ctypes.c_double)]
+    lib.ecmc_probe_gather.restype = ctypes.c_int
+    lib.ecmc_probe_gather.argtypes = [P, I64, I32, I32, I32, P, ctypes.POINTER(ctypes.c_double)]
+    _probe_lib = lib
+    return lib
+
+
+def probe_chase(lines, hops, scope=1) -> float:
+    """Mean dependent-load latency in ns over a device uint8/uint32 tensor of
+    64-byte lines whose first word holds the next line's index."""
+    import torch
+    lib = load_probe_library()
+    out = ctypes.c_double(0.0)
+    n_lines = lines.numel() * lines.element_size() // 64
+    rc = lib.ecmc_probe_chase(ctypes.c_void_p(lines.data_ptr()), n_lines, int(hops), int(scope),
+                              ctypes.c_void_p(torch.cuda.current_stream().cuda_stream), ctypes.byref(out))
+    if rc:
+        raise EcmcError(rc, "ecmc_probe_chase failed")
+    return out.value
+
+
+def probe_gather(lines, blocks, loads_per_thread, scope=1) -> float:
+    """Random-line gather bandwidth (64 B per load) in GB/s over a device tensor."""
+    import torch
+    lib = load_probe_library()
+    out = ctypes.c_double(0.0)
+    n_lines = lines.numel() * lines.element_size() // 64
+    rc = lib.ecmc_probe_gather(ctypes.c_void_p(lines.data_ptr()), n_lines, int(blocks), int(loads_per_thread),
+                               int(scope), ctypes.c_void_p(torch.cuda.current_stream().cuda_stream),
+                               ctypes.byref(out))
+    if rc:
+        raise EcmcError(rc, "ecmc_probe_gather failed")
+    return out.value
 
 
 def workspace_bytes(n, sigma, box, cells=0, max_chains=1, log_cap=1, flags=FP64) -> int:

@@ -165,7 +165,7 @@ struct Dev {
 };
 
 struct LegP {
-  int32_t dir;     // 0: v = +x, 1: v = +y
+  int32_t dir;     // 0: v = +x, 1: +y, 2: -x, 3: -y
   int32_t final;   // 1: tend is the leg's breakpoint h' (stall); 0: intermediate (pause)
   double h;        // start of this attempt (leg-relative time)
   double tend;     // end of this attempt
@@ -294,9 +294,34 @@ __global__ void k_fill(T *p, T v, int64_t n) {
 // ------------------------------------------------------------------------
 // a1: home-cell build.  Bin every disk by its (a, p) at the breakpoint.
 // ------------------------------------------------------------------------
+// Leg coordinates.  Every leg moves the active disks towards larger a.  For
+// v = +x (dir 0) or +y (1), a is x or y; for -x (2) or -y (3), a is the
+// reflection L - x or L - y (0 stays 0), so one event code serves all four
+// directions (running a leg backwards, Remark on time-reversal invariance).
+// p is the other coordinate.
+__device__ __forceinline__ double reflect(double x, double L) {
+  const double r = L - x;
+  return r >= L ? r - L : r;
+}
+__device__ __forceinline__ double leg_a(const Dev &D, int32_t dir, int64_t i, double L) {
+  const double x = (dir & 1) ? D.Y[i] : D.X[i];
+  return dir >= 2 ? reflect(x, L) : x;
+}
+__device__ __forceinline__ double leg_p(const Dev &D, int32_t dir, int64_t i) {
+  return (dir & 1) ? D.X[i] : D.Y[i];
+}
+// write a position along v back to the canonical arrays
+__device__ __forceinline__ void put_a(const Dev &D, int32_t dir, int64_t i, double a, double L) {
+  const double x = dir >= 2 ? reflect(a, L) : a;
+  if (dir & 1)
+    D.Y[i] = x;
+  else
+    D.X[i] = x;
+}
+
 __device__ void bin_one(const Dev &D, const Geo &g, int32_t dir, int64_t i) {
-  double a = dir ? D.Y[i] : D.X[i];
-  double p = dir ? D.X[i] : D.Y[i];
+  double a = leg_a(D, dir, i, g.L);
+  double p = leg_p(D, dir, i);
   int col = (int)(a * g.inv_c), row = (int)(p * g.inv_c);
   col = col < 0 ? 0 : (col >= g.nc ? g.nc - 1 : col);
   row = row < 0 ? 0 : (row >= g.nc ? g.nc - 1 : row);
@@ -318,7 +343,7 @@ __global__ void k_bin(Dev D, Geo g, int32_t dir) {
 // CAP threads of a cell lie in one wavefront and each rewrites its record
 // from the ids of all CAP slots, so every id is read before any record of the
 // cell is rewritten; consecutive threads write consecutive records.
-__device__ void cellfill_slot(const Dev &D, int32_t dir, int64_t s) {
+__device__ void cellfill_slot(const Dev &D, double L, int32_t dir, int64_t s) {
   const int64_t cell = s / CAP;
   const int q = (int)(s - cell * CAP);
   int cnt = D.CELL_CNT[cell];
@@ -339,9 +364,9 @@ __device__ void cellfill_slot(const Dev &D, int32_t dir, int64_t s) {
   cr.pad = 0;
   if (q < cnt) {
     const int i = mine;
-    cr.p = dir ? D.X[i] : D.Y[i];
+    cr.p = leg_p(D, dir, i);
     cr.id = i;
-    mr.a = dir ? D.Y[i] : D.X[i];
+    mr.a = leg_a(D, dir, i, L);
     mr.t = D.STAMP[i];
     D.SLOT_OF[i] = (int32_t)s;
   } else {
@@ -356,7 +381,7 @@ __device__ void cellfill_slot(const Dev &D, int32_t dir, int64_t s) {
 }
 __global__ void k_cellfill(Dev D, Geo g, int32_t dir) {
   const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (s < (int64_t)g.nc * g.nc * CAP) cellfill_slot(D, dir, s);
+  if (s < (int64_t)g.nc * g.nc * CAP) cellfill_slot(D, g.L, dir, s);
 }
 
 // Once per leg, after the home-cell build: attach each chain to its disk's slot.
@@ -1785,10 +1810,7 @@ __global__ void k_writeback(Dev D, Geo g, int32_t dir) {
   const int id = D.CST[s].id;
   if (id < 0) return;
   const MutRec m = D.MUT[s];
-  if (dir)
-    D.Y[id] = m.a;
-  else
-    D.X[id] = m.a;
+  put_a(D, dir, id, m.a, g.L);
   D.STAMP[id] = m.t;
 }
 
@@ -2663,7 +2685,7 @@ struct RepIn {
   double T;              // leg length
   int64_t target;        // run legs until the committed liftings reach this
   int64_t legs_done;     // legs completed before this run (direction parity)
-  int32_t dir_mode;      // 0 +x, 1 +y, 4 alternate
+  int32_t dir_mode;      // 0 +x, 1 +y, 2 -x, 3 -y, 4 alternate +x/+y
   int32_t max_splits;
   int32_t max_legs;      // at most this many legs in this run (0: no limit)
   int32_t pad;
@@ -2710,7 +2732,7 @@ __device__ __noinline__ void replica_build(const Dev &D, const Geo &g, int dir) 
   __syncthreads();
   // slots strided by the workgroup size (a multiple of CAP): a cell's CAP
   // slots fall into one iteration and one wavefront, as cellfill_slot needs
-  for (int64_t sl = tid; sl < ncell * CAP; sl += nt) cellfill_slot(D, dir, sl);
+  for (int64_t sl = tid; sl < ncell * CAP; sl += nt) cellfill_slot(D, g.L, dir, sl);
   __syncthreads();
   for (int c = tid; c < D.k; c += nt) chains_leg_one(D, ncell * CAP, c);
   __syncthreads();
@@ -2846,10 +2868,7 @@ __device__ int replica_leg(const RepIn &ri, RepOut *rp, int dir, int32_t wait_re
     const int id = D.CST[sl].id;
     if (id >= 0) {
       const MutRec mr = D.MUT[sl];
-      if (dir)
-        D.Y[id] = mr.a;
-      else
-        D.X[id] = mr.a;
+      put_a(D, dir, id, mr.a, g.L);
       D.STAMP[id] = mr.t;
     }
   }
@@ -3529,8 +3548,8 @@ int ecmc_run(ecmc_ctx *ctx, int32_t n_chains, double chain_time, double breakpoi
     ctx->err = "leg length outside [0, box - 4 cell - 2 sigma]";
     return ECMC_EINVAL;
   }
-  if (direction != 0 && direction != 1 && direction != 4) {
-    ctx->err = "direction must be 0 (+x), 1 (+y) or 4 (alternate)";
+  if (direction < 0 || direction > 4) {
+    ctx->err = "direction must be 0 (+x), 1 (+y), 2 (-x), 3 (-y) or 4 (alternate +x/+y)";
     return ECMC_EINVAL;
   }
   int64_t n_legs = 0;
@@ -4070,8 +4089,8 @@ int ecmc_batch_set_option(ecmc_batch *b, int32_t key, int64_t value) {
 int ecmc_batch_run(ecmc_batch *b, const int64_t *target_events, const double *leg_T, int32_t direction,
                    int32_t max_legs) {
   if (!b || !target_events || !leg_T || max_legs < 0) return ECMC_EINVAL;
-  if (direction != 0 && direction != 1 && direction != 4) {
-    b->err = "direction must be 0 (+x), 1 (+y) or 4 (alternate)";
+  if (direction < 0 || direction > 4) {
+    b->err = "direction must be 0 (+x), 1 (+y), 2 (-x), 3 (-y) or 4 (alternate +x/+y)";
     return ECMC_EINVAL;
   }
   int kmax = 1;
