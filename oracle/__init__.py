@@ -14,9 +14,11 @@ Contents
                    explicit periodic images, pure numpy: pins ``run`` on tiny
                    systems.
 ``enumerate_alg5`` (module) exact enumeration of every interleaving of the
-                   sequential-consistency multithreaded algorithm (Alg. 5, Sec.
-                   2.3) as an absorbing Markov chain: pins the lock-less
-                   protocol against ``run``.
+                   multithreaded algorithm on tiny suites as an absorbing Markov
+                   chain (Sec. 2.3, Alg. 5, Lemma 3), for the paper's
+                   sequential-consistency program and for the gfx950 kernel's
+                   protocol: every terminate state is compared with ``run``, and
+                   single-statement mutations must break a check.
 """
 from __future__ import annotations
 
