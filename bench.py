@@ -1,17 +1,26 @@
 """Benchmark: ECMC events/s on one MI355X for hard disks, N = 2^20, eta = 0.708.
 
 One step = one leg (breakpoint interval) of the whole hot path: home-cell build,
-1024 chains running the event kernel to the breakpoint (reruns included),
+1024 chains running the event kernel to the breakpoint (restarts included),
 breakpoint reduction and write-back.  Directions alternate +x/+y.  Inputs are
 seeded synthetic lattices resident in HBM before the timed region starts.
 
-Prints ONE JSON line (see the repository's design notes for the fields).
+The headline value is measured after an untimed, labelled burn-in of at least
+10 liftings per disk (the lattice start is a transient: its first legs run
+faster); the figure from the lattice (warm-up legs only) is reported beside it.
+
+Prints ONE JSON line.  Besides the headline it carries both forms, the other
+workloads (256, 4096 and 65536 disks), the violation probability per
+breakpoint against the generalized birthday estimate (Sec. 3.4) over a sweep
+of leg lengths, the roofline of the event kernel with the measured gather and
+latency bounds, the replica batch, and the oracle timed on the host.
 """
 from __future__ import annotations
 
 import argparse
 import hashlib
 import json
+import math
 import os
 import sys
 import time
@@ -21,14 +30,39 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0        # MI355X HBM3E, published
-# Algorithmic bytes of the event kernel.  Per scanned cell slot: the fixed
-# record (p, id; 16 B) and the mutable record (a, t; 16 B).  Per lifting:
+# Algorithmic bytes per lifting: what the method has to move, per lifting, with
+# about 7.5 cells of 0.9 disks scanned: per scanned cell 4 B of cell header
+# plus 20 B per disk record (binary64 a, p, id) or 8 B (binary32 cell-relative
+# offsets); 3 local-time reads of the horizon set 24 B, claim 8 B, target
+# re-read 16 B, commit writes 32 B, tag release 4 B, log 4 B; FP32-mixed adds
+# the winner's id 4 B and its binary64 refinement 16 B.
+ALG_BYTES_PER_EVENT = {"fp64": 250.0, "fp32": 190.0}
+# The same at 64-byte line granularity (rows of cells padded to lines, about 8
+# further scattered lines per lifting).
+LINE_BYTES_PER_EVENT = {"fp64": 1500.0, "fp32": 1050.0}
+# Bytes this implementation moves (reported separately): per scanned slot the
+# fixed record (p, id; 16 B) and the mutable record (a, t; 16 B); per lifting
 # next-event time 8, reservation 8, activation-record invalidation 8, claim 4,
 # target re-read 16, lane-minima re-read 48, reservation read 8, undo record
-# 60, commit (t_j, t_i, a_i) 24, activation record 36, reservation release 8,
-# tag release 4, log 4: 236 B.
-BYTES_PER_SLOT = 32
-BYTES_PER_EVENT = 236
+# 60, commit 24, activation record 36, reservation release 8, tag release 4,
+# log 4: 236 B.
+IMPL_BYTES_PER_SLOT = 32
+IMPL_BYTES_PER_EVENT = 236
+# the scanned working set of the 2^20-disk workload: fixed and mutable slot
+# records and tags of 1078^2 cells x 4 slots
+WORKING_SET_BYTES = 1078 * 1078 * 4 * (16 + 16 + 4)
+PAPER_CONTEXT = {
+    "x86": "Alg. 6 (C++/OpenMP, constraint graph G256, k=80, N=65536, eta=0.708, runs continue through "
+           "horizon violations): ~1.7e12 events/hour (~4.7e8 events/s) at 40 threads on one Intel Xeon "
+           "Gold 6230 (20 cores, 2.1-3.9 GHz); x12 over 1 thread at 20 threads, x16 at 40",
+    "arm": "NVIDIA Jetson (ARM Cortex-A57, 4 cores, 1.43 GHz): x4.0 at 4 threads, about 7x below x86 "
+           "at a comparable thread count",
+    "cell_serial": "cell-based serial production code: ~3e10 events/hour (~8.3e6 events/s)",
+}
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 def _src_hash():
@@ -42,110 +76,342 @@ def pmc_summary_path(form):
     return os.path.join(ROOT, "profiles", f"event_kernel_N1048576_{form}_pmc.json")
 
 
-def _traffic(form, events_per_launch):
-    """HBM bytes per event-kernel launch: the bytes per lifting measured by the
-    committed rocprofv3 counter summary (FETCH_SIZE + WRITE_SIZE, calibrated on
-    a copy of known size) times this run's liftings per launch.  None if the
-    summary is missing or was taken on another kernel source."""
+def _pmc(form):
     try:
         with open(pmc_summary_path(form)) as f:
             d = json.load(f)
     except (OSError, ValueError):
         return None
-    if d.get("source_sha256_16") != _src_hash() or not d.get("hbm_bytes_per_event"):
+    if d.get("source_sha256_16") != _src_hash():
+        return None
+    return d
+
+
+def _traffic(form, events_per_launch):
+    """HBM bytes per event-kernel launch: the bytes per lifting measured by the
+    committed rocprofv3 counter summary (FETCH_SIZE + WRITE_SIZE, calibrated on
+    a copy of known size) times this run's liftings per launch.  None if the
+    summary is missing or was taken on another kernel source."""
+    d = _pmc(form)
+    if not d or not d.get("hbm_bytes_per_event"):
         return None
     return d["hbm_bytes_per_event"] * events_per_launch
 
 
+# ---------------------------------------------------------------------------
+# the oracle on the host (runs before anything touches the GPU)
+# ---------------------------------------------------------------------------
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
 def cpu_baseline(seconds: float):
-    """The oracle, as it stands, on a bounded sample of the same workload."""
+    """The oracle, as it stands, on a bounded sample of the headline workload,
+    pinned to one host core."""
     import oracle
     import workloads as W
-    s = W.config(4)
-    x, y, act = s.x, s.y, s.active
-    events, t_used, legs = 0, 0.0, 0
-    while t_used < seconds and legs < 8:
-        t0 = time.perf_counter()
-        r = oracle.run(x, y, s.sigma, s.L, act, [legs % 2], s.T, log=False)
-        t_used += time.perf_counter() - t0
-        print(f"[bench] cpu baseline: leg {legs} done, {t_used:.1f} s", file=sys.stderr, flush=True)
-        events += r.n_events
-        x, y, act = r.x, r.y, r.active
-        legs += 1
+    avail = sorted(os.sched_getaffinity(0))
+    os.sched_setaffinity(0, {avail[0]})
+    try:
+        s = W.config(4)
+        x, y, act = s.x, s.y, s.active
+        events, t_used, legs = 0, 0.0, 0
+        while t_used < seconds and legs < 8:
+            t0 = time.perf_counter()
+            r = oracle.run(x, y, s.sigma, s.L, act, [legs % 2], s.T, log=False)
+            t_used += time.perf_counter() - t0
+            log(f"cpu baseline: leg {legs} done, {t_used:.1f} s")
+            events += r.n_events
+            x, y, act = r.x, r.y, r.active
+            legs += 1
+    finally:
+        os.sched_setaffinity(0, set(avail))
     return {"value": events / t_used, "unit": "events/s", "cores": 1, "kind": "oracle",
             "sample": f"first {legs} legs ({events} liftings) of the N=1048576 eta=0.708 k=1024 "
-                      f"workload, serial C global-time event queue, 1 host thread"}
+                      f"workload from the lattice, serial C global-time event queue, pinned to one core",
+            "cpu_model": _cpu_model(), "host_cores": os.cpu_count(), "cores_available": len(avail)}
 
 
+def _oracle_replica(args):
+    import oracle
+    x, y, L, act, T, target = args
+    t0 = time.perf_counter()
+    ev, leg = 0, 0
+    while ev < target:
+        r = oracle.run(x, y, 1.0, L, act, [leg % 2], T, log=False)
+        ev += r.n_events
+        x, y, act = r.x, r.y, r.active
+        leg += 1
+    return ev, time.perf_counter() - t0
+
+
+def cpu_baseline_batch(n_rep, per_replica, max_procs=16):
+    """The oracle on the replica workload on all usable host cores (one
+    process per core, replicas handed out one at a time)."""
+    import multiprocessing as mp
+
+    import workloads as W
+    reps = W.replica_batch(n_rep)
+    tasks = [(s.x, s.y, s.L, s.active, s.T, per_replica) for s in reps]
+    procs = max(1, min(max_procs, len(os.sched_getaffinity(0))))
+    t0 = time.perf_counter()
+    with mp.get_context("fork").Pool(procs) as pool:
+        res = pool.map(_oracle_replica, tasks, chunksize=1)
+    wall = time.perf_counter() - t0
+    ev = sum(r[0] for r in res)
+    log(f"cpu baseline batch: {ev} liftings on {procs} processes in {wall:.1f} s")
+    return {"value": ev / wall, "unit": "events/s", "cores": procs, "kind": "oracle",
+            "sample": f"{n_rep} replicas, whole legs until >= {per_replica} liftings each, "
+                      f"one process per core", "cpu_model": _cpu_model()}
+
+
+# ---------------------------------------------------------------------------
+# GPU measurements
+# ---------------------------------------------------------------------------
 def _stats_delta(st0, st1):
     d = {k: st1[k] - st0[k] for k in st1 if isinstance(st1[k], (int, float))}
     d["violations_by_kind"] = [b - a for a, b in zip(st0["violations_by_kind"], st1["violations_by_kind"])]
     return d
 
 
-def run_form(form, steps, warmup, lanes, window_micro, max_splits=0):
+def _make(s, form, lanes, window_micro, log_cap=1 << 12, max_splits=0):
     import numpy as np
-    import torch
 
     import paper_2004_11040_amd as pkg
-    import workloads as W
-
-    s = W.config(4)
     flags = pkg.FP32_MIXED if form == "fp32" else pkg.FP64
-    e = pkg.Ecmc(np.stack([s.x, s.y], 1), s.sigma, s.L, flags=flags, max_chains=s.k, log_cap=1 << 12)
+    e = pkg.Ecmc(np.stack([s.x, s.y], 1), s.sigma, s.L, flags=flags, max_chains=s.k, log_cap=log_cap)
     e.set_option(pkg.OPT_LANES, lanes)
     e.set_option(pkg.OPT_KERNEL_TIMING, 1)
     e.set_option(pkg.OPT_WINDOW_MICRO, window_micro)
     if max_splits:
         e.set_option(pkg.OPT_MAX_SPLITS, max_splits)
     e.set_active(s.active)
-    if warmup:
-        e.run(warmup * s.T, s.T, pkg.DIR_ALTERNATE)
+    return e
+
+
+def timed_legs(e, s, n_legs=None, target_events=None, label="", chunk=10):
+    """Run whole legs (alternating when the workload alternates) in one timed
+    region: n_legs of them, or until target_events more liftings."""
+    import torch
+
+    import paper_2004_11040_amd as pkg
+    direction = pkg.DIR_ALTERNATE if s.alternate else pkg.DIR_X
     st0 = e.stats()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    done = 0
-    while done < steps:  # chunks only to report progress; one timed region
-        n = min(10, steps - done)
-        e.run(n * s.T, s.T, pkg.DIR_ALTERNATE)
-        done += n
-        print(f"[bench] {form}: {done}/{steps} legs", file=sys.stderr, flush=True)
+    legs, ev0 = 0, st0["events"]
+    while True:
+        if n_legs is not None and legs >= n_legs:
+            break
+        n = chunk if n_legs is None else min(chunk, n_legs - legs)
+        e.run(n * s.T, s.T, direction)
+        legs += n
+        if target_events is not None:
+            if e.stats()["events"] - ev0 >= target_events:
+                break
     torch.cuda.synchronize()
-    t1 = time.perf_counter()
+    wall = time.perf_counter() - t0
     st1 = e.stats()
     d = _stats_delta(st0, st1)
-    wall = t1 - t0
+    log(f"{label}: {legs} legs, {d['events']} liftings, {d['events'] / wall / 1e6:.2f} M/s")
+    return d, wall
+
+
+def _summary(d, wall, form):
     launches = max(d["event_launches"], 1)
-    kbytes = (d["timed_slots"] * BYTES_PER_SLOT + d["timed_events"] * BYTES_PER_EVENT) / launches
     kdur = d["event_kernel_ms"] / launches / 1e3
-    achieved = kbytes / kdur / 1e9 if kdur > 0 else 0.0
-    overlaps = e.overlaps()
-    res = {
+    epl = d["timed_events"] / launches
+    alg = ALG_BYTES_PER_EVENT[form] * epl
+    impl = (d["timed_slots"] * IMPL_BYTES_PER_SLOT + d["timed_events"] * IMPL_BYTES_PER_EVENT) / launches
+    return {
         "events": d["events"], "wall_s": wall, "events_per_s": d["events"] / wall,
         "legs": d["legs"], "legs_violated": d["legs_violated"], "reruns": d["reruns"],
         "global_legs": d["global_legs"], "lockstep_runs": d["lockstep_runs"],
         "violations_screened": d["violations_screened"], "claim_yields": d["claim_yields"],
-        "spin_aborts": d["spin_aborts"],
-        "violations_by_kind": d["violations_by_kind"], "attempts": d["attempts"],
-        "slots_per_event": d["slots_scanned"] / max(d["events"], 1),
-        "events_per_launch": d["timed_events"] / launches,
-        "kernel_ms_avg": kdur * 1e3, "kernel_bytes_per_launch": kbytes, "achieved_gbs": achieved,
-        "kernel_time_frac": d["event_kernel_ms"] / 1e3 / wall, "overlaps": overlaps,
+        "spin_aborts": d["spin_aborts"], "violations_by_kind": d["violations_by_kind"],
+        "attempts": d["attempts"], "slots_per_event": d["slots_scanned"] / max(d["events"], 1),
+        "events_per_launch": epl, "kernel_ms_avg": kdur * 1e3,
+        "alg_bytes_per_launch": alg, "implementation_bytes_per_launch": impl,
+        "achieved_gbs": alg / kdur / 1e9 if kdur > 0 else 0.0,
+        "kernel_time_frac": d["event_kernel_ms"] / 1e3 / wall if wall > 0 else 0.0,
         "pressure_raw": 1.0 + d["sum_b"] / d["chain_time"] if d["chain_time"] else None,
         "violation_probability_per_breakpoint": d["legs_violated"] / max(d["legs"], 1),
     }
+
+
+def burn_in(e, s, per_disk=10.0):
+    """Untimed legs until at least per_disk liftings per disk since set-up."""
+    import paper_2004_11040_amd as pkg
+    direction = pkg.DIR_ALTERNATE if s.alternate else pkg.DIR_X
+    legs = 0
+    while e.stats()["events"] < per_disk * s.n:
+        e.run(10 * s.T, s.T, direction)
+        legs += 10
+    return legs
+
+
+def violation_sweep(e, s, Ts, n_legs, window_micro):
+    """Violation probability per breakpoint (legs whose first attempt saw a
+    horizon violation / legs) for each leg length T, with the same bounded lag
+    at every size so that the sizes compare."""
+    import paper_2004_11040_amd as pkg
+    e.set_option(pkg.OPT_WINDOW_MICRO, window_micro)
+    out = {}
+    direction = pkg.DIR_ALTERNATE if s.alternate else pkg.DIR_X
+    for T in Ts:
+        st0 = e.stats()
+        e.run(n_legs * T, T, direction)
+        st1 = e.stats()
+        out[f"{T:g}"] = (st1["legs_violated"] - st0["legs_violated"]) / max(st1["legs"] - st0["legs"], 1)
+    return out
+
+
+def run_form(form, steps, warmup, lanes, window_micro, max_splits=0, sweep_Ts=(), sweep_legs=40):
+    """The headline workload in one form: `warmup` untimed legs and `steps`
+    timed legs from the lattice, then a burn-in to >= 10 liftings per disk and
+    `steps` timed legs again (the headline), then the violation sweep."""
+    import workloads as W
+    s = W.config(4)
+    e = _make(s, form, lanes, window_micro, max_splits=max_splits)
+    if warmup:
+        e.run(warmup * s.T, s.T, 4)
+    d0, w0 = timed_legs(e, s, n_legs=steps, label=f"{form} from the lattice")
+    bl = burn_in(e, s)
+    d1, w1 = timed_legs(e, s, n_legs=steps, label=f"{form} after burn-in")
+    res = _summary(d1, w1, form)
+    res["burn_in_legs"] = bl + warmup + steps
+    res["liftings_per_disk_before_timing"] = (e.stats()["events"] - d1["events"]) / s.n
+    res["from_lattice"] = _summary(d0, w0, form)
+    res["overlaps"] = e.overlaps()
+    if sweep_Ts:
+        res["violation_sweep"] = violation_sweep(e, s, sweep_Ts, sweep_legs, window_micro)
     e.close()
     return res
 
 
-def birthday_estimate(k, L, T, sigma=1.0):
-    """Generalized birthday estimate of the violation probability per
-    breakpoint (Sec. 3.4): k chains, each confined during a leg to a region of
-    area about T x 4 sigma (its path along v and the corridor around it), in a
-    box of area L^2 cut into L^2 / (4 sigma T) such regions; p = 1 - exp(-k^2 / 2 n)."""
-    import math
-    n_regions = L * L / (4.0 * sigma * T)
-    return 1.0 - math.exp(-k * k / (2.0 * n_regions))
+def run_small_configs(lanes, sweep_Ts, sweep_legs, window_micro):
+    """The 256-disk (FP64, +x, 1e5 liftings) and 4096-disk (FP64, alternating,
+    1e7 liftings, violation rate per breakpoint) workloads."""
+    import workloads as W
+    out = {}
+    s = W.config(0)
+    e = _make(s, "fp64", lanes, 0)
+    d, w = timed_legs(e, s, target_events=s.target_events, label="N=256", chunk=50)
+    out["N256"] = {"workload": "N=256 eta=0.60 square lattice, k=4, +x, T=0.5 L, FP64",
+                   **_summary(d, w, "fp64"), "overlaps": e.overlaps()}
+    e.close()
+    s = W.config(1)
+    e = _make(s, "fp64", lanes, 0)
+    d, w = timed_legs(e, s, target_events=s.target_events, label="N=4096", chunk=50)
+    r = {"workload": "N=4096 eta=0.70 centred-rectangular lattice, k=64, alternating +x/+y, T=0.25 L, FP64",
+         **_summary(d, w, "fp64"), "overlaps": e.overlaps()}
+    if sweep_Ts:
+        r["violation_sweep"] = violation_sweep(e, s, sweep_Ts, sweep_legs, window_micro)
+    out["N4096"] = r
+    e.close()
+    return out
+
+
+def run_precision_config(lanes, window_micro, target, prefix_events, sweep_Ts, sweep_legs):
+    """The 65536-disk workload in both forms: the error of each form against
+    the binary64 oracle over the legs that cover the first prefix_events
+    liftings, then timed legs up to `target` liftings, and the pressure."""
+    import numpy as np
+
+    import oracle
+    import workloads as W
+    s = W.config(2)
+    out = {"workload": "N=65536 eta=0.708 centred-rectangular lattice, k=256, alternating +x/+y, T=33.896"}
+    # the oracle over the prefix
+    t0 = time.perf_counter()
+    legs, ref_ev = 0, 0
+    while ref_ev < prefix_events:
+        legs += 1
+        ref = oracle.run(s.x, s.y, s.sigma, s.L, s.active, s.leg_dirs(legs), s.T, log_cap=1 << 23)
+        ref_ev = ref.n_events
+    log(f"N=65536 oracle prefix: {legs} legs, {ref_ev} liftings, {time.perf_counter() - t0:.1f} s")
+    for form in ("fp64", "fp32"):
+        e = _make(s, form, lanes, window_micro, log_cap=1 << 14)
+        e.run(legs * s.T, s.T, 4)
+        pos = e.positions()
+        dx = np.abs((pos[:, 0] - ref.x + s.L / 2) % s.L - s.L / 2).max()
+        dy = np.abs((pos[:, 1] - ref.y + s.L / 2) % s.L - s.L / 2).max()
+        bad_chains = sum(not np.array_equal(e.log(c).targets, ref.targets(c)) for c in range(s.k))
+        sb, _ = e.chain_sums()
+        err = {"legs": legs, "liftings": int(e.stats()["events"]), "oracle_liftings": int(ref_ev),
+               "chains_with_other_targets": int(bad_chains),
+               "max_abs_position_error": float(max(dx, dy)),
+               "max_abs_local_time_error": float(np.abs(e.stamps() - ref.stamps).max()),
+               "max_abs_sum_b_error": float(np.abs(sb - ref.sum_b).max()),
+               "active_set_equal": bool(np.array_equal(e.active(), ref.active))}
+        d, w = timed_legs(e, s, target_events=target, label=f"N=65536 {form}", chunk=20)
+        r = {"error_vs_fp64_oracle": err, **_summary(d, w, form), "overlaps": e.overlaps()}
+        if form == "fp64" and sweep_Ts:
+            r["violation_sweep"] = violation_sweep(e, s, sweep_Ts, sweep_legs, window_micro)
+        out[form] = r
+        e.close()
+    out["fp32_over_fp64"] = out["fp32"]["events_per_s"] / out["fp64"]["events_per_s"]
+    return out
+
+
+def birthday(sweeps):
+    """Generalized birthday estimate (Sec. 3.4): p = 1 - exp(-k^2 / (2 N')),
+    with N' = N / alpha cells of constant area; alpha fitted per leg length on
+    the 4096-disk workload, then predicted for the larger ones."""
+    fit_n, fit_k = 4096, 64
+    out = {"model": "p = 1 - exp(-alpha k^2 / (2 N)), alpha fitted at N=4096, k=64; every size with "
+                    "the headline's bounded lag, after >= 1000 liftings per disk (N=4096, 65536) or "
+                    "the burn-in (N=2^20)", "by_T": {}}
+    for T, p1 in sweeps["N4096"].items():
+        n_legs = sweeps["legs"]
+        pc = min(max(p1, 0.5 / n_legs), 1.0 - 0.5 / n_legs)
+        alpha = -2.0 * fit_n * math.log(1.0 - pc) / (fit_k * fit_k)
+        row = {"alpha": alpha, "alpha_is_bound": p1 in (0.0, 1.0), "N4096_measured": p1}
+        for name, n, k in (("N65536", 65536, 256), ("N1048576", 1 << 20, 1024)):
+            if T in sweeps.get(name, {}):
+                row[f"{name}_measured"] = sweeps[name][T]
+                row[f"{name}_predicted"] = 1.0 - math.exp(-alpha * k * k / (2.0 * n))
+        out["by_T"][T] = row
+    return out
+
+
+def run_probes(k):
+    """Dependent-load latency and random-line gather bandwidth over a buffer of
+    the headline working-set size (and of 2 GiB, beyond the Infinity Cache)."""
+    import numpy as np
+    import torch
+
+    import paper_2004_11040_amd as pkg
+    out = {}
+    for name, nbytes in (("working_set", WORKING_SET_BYTES), ("2GiB", 2 << 30)):
+        n_lines = nbytes // 64
+        rng = np.random.Generator(np.random.PCG64(7))
+        perm = rng.permutation(n_lines).astype(np.uint32)
+        nxt = np.empty(n_lines, np.uint32)
+        nxt[perm] = np.roll(perm, -1)          # one cycle through every line
+        host = np.zeros((n_lines, 16), np.uint32)
+        host[:, 0] = nxt
+        buf = torch.from_numpy(host.reshape(-1)).to("cuda")
+        del host
+        r = {"bytes": int(n_lines * 64)}
+        for scope, tag in ((1, "agent_scope"), (0, "plain")):
+            r[f"chase_ns_{tag}"] = pkg.probe_chase(buf, 200_000, scope)
+            r[f"gather_gbs_{tag}"] = pkg.probe_gather(buf, 2048, 256, scope)
+        out[name] = r
+        del buf
+        torch.cuda.empty_cache()
+    lat = out["working_set"]["chase_ns_agent_scope"] * 1e-9
+    out["littles_law_events_per_s"] = k / (3.0 * lat)
+    log(f"probes: latency {lat * 1e9:.0f} ns, gather {out['working_set']['gather_gbs_agent_scope']:.0f} GB/s")
+    return out
 
 
 def run_batch(n_rep, target, t_frac, graph=1, window_micro=0, max_splits=0):
@@ -172,7 +438,7 @@ def run_batch(n_rep, target, t_frac, graph=1, window_micro=0, max_splits=0):
         b.set_option(pkg.OPT_MAX_SPLITS, max_splits)
     T = [t_frac * s.L for s in reps]
     big = np.full(n_rep, 1 << 60, np.int64)
-    b.run(big, T, pkg.DIR_ALTERNATE, max_legs=1)  # autotune (one leg per lane count)
+    b.run(big, T, pkg.DIR_ALTERNATE, max_legs=1)  # autotune (one leg per candidate)
     tune = b.info()
     ev0 = sum(e.stats()["events"] for e in systems)
     torch.cuda.synchronize()
@@ -182,7 +448,7 @@ def run_batch(n_rep, target, t_frac, graph=1, window_micro=0, max_splits=0):
     wall = time.perf_counter() - t0
     info = b.info()
     ev1 = sum(e.stats()["events"] for e in systems)
-    print(f"[bench] batch: {ev1 - ev0} liftings in {wall:.2f} s", file=sys.stderr, flush=True)
+    log(f"batch: {ev1 - ev0} liftings in {wall:.2f} s")
     overlaps = sum(e.overlaps() for e in systems)
     out = {"workload": f"{n_rep} replicas, N in 64*[16,256], eta in [0.60,0.72], k=round(sqrt N), "
                        f"legs of {t_frac} L alternating +x/+y, FP32-mixed, {target} liftings per replica, "
@@ -190,7 +456,10 @@ def run_batch(n_rep, target, t_frac, graph=1, window_micro=0, max_splits=0):
            "events": ev1 - ev0, "wall_s": wall, "events_per_s": (ev1 - ev0) / wall,
            "device_ms": info["device_ms"], "lanes": info["lanes"], "graph": info["graph"],
            "workgroups": info["workgroups"], "legs": info["legs"], "rollbacks": info["rollbacks"],
-           "global_runs": info["global_runs"], "autotune_events_per_ms": tune["tune_events_per_ms"],
+           "global_runs": info["global_runs"],
+           "rollbacks_per_replica_leg": info["rollbacks"] / max(info["legs"], 1),
+           "global_runs_per_replica_leg": info["global_runs"] / max(info["legs"], 1),
+           "autotune_events_per_ms": tune["tune_events_per_ms"],
            "replica_ms_max": info["replica_ms_max"],
            "load_balance": info["replica_ms_sum"] / max(info["workgroups"] * info["device_ms"], 1e-9),
            "overlaps": overlaps, "total_disks": int(sum(s.n for s in reps)),
@@ -202,27 +471,23 @@ def run_batch(n_rep, target, t_frac, graph=1, window_micro=0, max_splits=0):
 
 
 def profile_run(legs, lanes, window_micro, form):
-    """Short run for hardware-counter collection: a few legs of the workload,
-    then a device copy of 256 MiB (read 256 MiB, write 256 MiB) whose counter
-    readings calibrate the bytes the counters report."""
-    import numpy as np
+    """Short run for hardware-counter collection: a few legs of the workload
+    after the burn-in, then a device copy of 256 MiB (read 256 MiB, write
+    256 MiB) whose counter readings calibrate the bytes the counters report."""
     import torch
 
-    import paper_2004_11040_amd as pkg
     import workloads as W
     s = W.config(4)
-    flags = pkg.FP32_MIXED if form == "fp32" else pkg.FP64
-    e = pkg.Ecmc(np.stack([s.x, s.y], 1), s.sigma, s.L, max_chains=s.k, log_cap=1 << 12, flags=flags)
-    e.set_option(pkg.OPT_LANES, lanes)
-    e.set_option(pkg.OPT_WINDOW_MICRO, window_micro)
-    e.set_option(pkg.OPT_KERNEL_TIMING, 1)
-    e.set_active(s.active)
-    e.run(legs * s.T, s.T, pkg.DIR_ALTERNATE)
-    st = e.stats()
-    print(json.dumps({"profile_run": True, "form": form, "lanes": lanes,
-                      "events": st["events"], "attempts": st["attempts"],
-                      "event_launches": st["event_launches"], "timed_events": st["timed_events"],
-                      "slots_scanned": st["slots_scanned"]}), flush=True)
+    e = _make(s, form, lanes, window_micro)
+    burn_in(e, s)
+    st0 = e.stats()
+    e.run(legs * s.T, s.T, 4)
+    d = _stats_delta(st0, e.stats())
+    print(json.dumps({"profile_run": True, "form": form, "lanes": lanes, "legs": legs,
+                      "events": d["events"], "attempts": d["attempts"],
+                      "event_launches": d["event_launches"], "timed_events": d["timed_events"],
+                      "slots_scanned": d["slots_scanned"], "burn_in_launches": st0["event_launches"]}),
+          flush=True)
     a = torch.ones(256 << 20, dtype=torch.uint8, device="cuda")
     b = torch.empty_like(a)
     torch.cuda.synchronize()
@@ -232,44 +497,66 @@ def profile_run(legs, lanes, window_micro, form):
 
 def _pmc_values(path, counter):
     """Per-dispatch values of one counter from a rocprofv3 counter_collection
-    CSV: list of (kernel name, value)."""
+    CSV: list of (dispatch id, kernel name, value)."""
     import csv
     out = []
     with open(path, newline="") as f:
         for row in csv.DictReader(f):
             if row.get("Counter_Name") == counter:
-                out.append((row.get("Kernel_Name", ""), float(row["Counter_Value"])))
+                out.append((int(row.get("Dispatch_Id", 0) or 0), row.get("Kernel_Name", ""),
+                            float(row["Counter_Value"])))
     return out
 
 
-def pmc_summary(fetch_csv, write_csv, profile_log):
-    """Turn two counter runs of --profile-run (FETCH_SIZE, then WRITE_SIZE) into
-    the committed summary: bytes per event-kernel dispatch and per lifting,
-    each counter calibrated by its reading on the 256 MiB device copy."""
+def pmc_summary(fetch_csv, write_csv, profile_log, extra_csvs=()):
+    """Turn the counter runs of --profile-run (FETCH_SIZE, then WRITE_SIZE, and
+    optionally L2 hit/miss and VALU counters) into the committed summary.
+    Only the event-kernel dispatches after the burn-in count: the last
+    `event_launches` dispatches that did work, plus the rounds that returned
+    at once, are taken as the dispatches after the burn-in's."""
     copy_bytes = 256 << 20
-    fe, wr = _pmc_values(fetch_csv, "FETCH_SIZE"), _pmc_values(write_csv, "WRITE_SIZE")
-    ev_f = [v for n, v in fe if "k_event" in n]
-    ev_w = [v for n, v in wr if "k_event" in n]
-    cp_f = max(v for n, v in fe if "copy" in n.lower() or "elementwise" in n.lower())
-    cp_w = max(v for n, v in wr if "copy" in n.lower() or "elementwise" in n.lower())
-    f_cal = copy_bytes / (cp_f * 1024.0)  # counters are in KiB
-    w_cal = copy_bytes / (cp_w * 1024.0)
     with open(profile_log) as f:
         run = next(json.loads(line) for line in f if line.startswith("{") and "profile_run" in line)
-    # rounds enqueued past the end of a leg are dispatched but return at once:
-    # totals over every dispatch, per launch that ran an attempt
-    total = sum(ev_f) * 1024.0 * f_cal + sum(ev_w) * 1024.0 * w_cal
-    per_launch = total / max(run["event_launches"], 1)
-    events_per_launch = run["timed_events"] / max(run["event_launches"], 1)
+
+    def event_vals(csv_path, counter):
+        vals = [(i, v) for i, n, v in _pmc_values(csv_path, counter) if "k_event" in n]
+        vals.sort()
+        return vals
+
+    def copy_val(csv_path, counter):
+        return max(v for _, n, v in _pmc_values(csv_path, counter)
+                   if "copy" in n.lower() or "elementwise" in n.lower())
+
+    fe, wr = event_vals(fetch_csv, "FETCH_SIZE"), event_vals(write_csv, "WRITE_SIZE")
+    # dispatches of the profiled legs: those after the burn-in's dispatches
+    n_burn = run.get("burn_in_dispatches")
+    cp_f, cp_w = copy_val(fetch_csv, "FETCH_SIZE"), copy_val(write_csv, "WRITE_SIZE")
+    f_cal = copy_bytes / (cp_f * 1024.0)  # counters are in KiB
+    w_cal = copy_bytes / (cp_w * 1024.0)
+    launches = max(run["event_launches"], 1)
+    events_per_launch = run["timed_events"] / launches
+    # the burn-in's dispatches come first; the profiled legs' dispatches are the
+    # tail whose count matches the launches that ran plus the at-once returns
+    tail_f = fe[-run["event_launches"] * 3:] if n_burn is None else fe[n_burn:]
+    tail_w = wr[-run["event_launches"] * 3:] if n_burn is None else wr[n_burn:]
+    total = sum(v for _, v in tail_f) * 1024.0 * f_cal + sum(v for _, v in tail_w) * 1024.0 * w_cal
+    per_launch = total / launches
     form = run.get("form", "fp64")
     d = {"source_sha256_16": _src_hash(), "form": form,
          "kernel": f"k_event<{run.get('lanes', 64)}, {'true' if form == 'fp32' else 'false'}>",
-         "dispatches": len(ev_f),
-         "fetch_kib_mean": sum(ev_f) / max(len(ev_f), 1), "write_kib_mean": sum(ev_w) / max(len(ev_w), 1),
-         "copy_fetch_kib": cp_f, "copy_write_kib": cp_w, "fetch_calibration": f_cal, "write_calibration": w_cal,
+         "dispatches_counted": len(tail_f), "copy_fetch_kib": cp_f, "copy_write_kib": cp_w,
+         "fetch_calibration": f_cal, "write_calibration": w_cal,
          "launches_that_ran": run["event_launches"], "liftings": run["timed_events"],
          "hbm_bytes_per_launch": per_launch, "events_per_launch": events_per_launch,
-         "hbm_bytes_per_event": per_launch / events_per_launch if events_per_launch else None}
+         "hbm_bytes_per_event": per_launch / events_per_launch if events_per_launch else None,
+         "write_bytes_per_event": (sum(v for _, v in tail_w) * 1024.0 * w_cal / max(run["timed_events"], 1))}
+    for path in extra_csvs:
+        import csv
+        with open(path, newline="") as f:
+            names = sorted({row["Counter_Name"] for row in csv.DictReader(f)})
+        for c in names:
+            vals = event_vals(path, c)
+            d[f"{c}_per_launch"] = sum(v for _, v in vals) / launches
     with open(pmc_summary_path(form), "w") as f:
         json.dump(d, f, indent=1)
     print(json.dumps(d))
@@ -278,12 +565,12 @@ def pmc_summary(fetch_csv, write_csv, profile_log):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--profile-run", type=int, default=0, metavar="LEGS",
-                    help="only run LEGS legs and a 256 MiB copy (for rocprofv3 counters)")
-    ap.add_argument("--pmc-summary", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "PROFILE_LOG"),
-                    help="write the counter summary from two --profile-run counter runs")
+                    help="only burn in, run LEGS legs and a 256 MiB copy (for rocprofv3 counters)")
+    ap.add_argument("--pmc-summary", nargs="+", metavar="CSV",
+                    help="FETCH_CSV WRITE_CSV PROFILE_LOG [EXTRA_CSV ...]: write the counter summary")
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200, help="timed legs")
-    ap.add_argument("--warmup", type=int, default=4, help="untimed legs")
+    ap.add_argument("--steps", type=int, default=20, help="timed legs")
+    ap.add_argument("--warmup", type=int, default=5, help="untimed legs before the lattice timing")
     ap.add_argument("--form", choices=["fp64", "fp32", "both"], default="both")
     ap.add_argument("--lanes", type=int, default=64)
     ap.add_argument("--max-splits", type=int, default=0,
@@ -291,6 +578,8 @@ def main():
     ap.add_argument("--window-micro", type=int, default=160_000,
                     help="bounded lag between chains, in 1e-6 sigma (0: free running)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--cpu-batch-events", type=int, default=20_000,
+                    help="liftings per replica for the all-cores oracle run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batch-replicas", type=int, default=512)
     ap.add_argument("--batch-events", type=int, default=1_000_000)
@@ -298,37 +587,58 @@ def main():
     ap.add_argument("--batch-window-micro", type=int, default=350_000,
                     help="bounded lag between a replica's chains, in 1e-6 sigma (0: free running)")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-configs", action="store_true", help="skip the 256/4096/65536-disk workloads")
+    ap.add_argument("--precision-events", type=int, default=100_000_000)
+    ap.add_argument("--sweep-legs", type=int, default=40)
+    ap.add_argument("--no-sweep", action="store_true")
+    ap.add_argument("--no-probes", action="store_true")
     args = ap.parse_args()
     if args.pmc_summary:
-        pmc_summary(*args.pmc_summary)
+        a = args.pmc_summary
+        pmc_summary(a[0], a[1], a[2], a[3:])
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
-    import torch
-    assert torch.cuda.is_available(), "bench.py needs a GPU"
-    torch.cuda.set_device(0)
     if args.profile_run:
+        import torch
+        assert torch.cuda.is_available(), "bench.py needs a GPU"
         profile_run(args.profile_run, args.lanes, args.window_micro,
                     "fp64" if args.form == "fp64" else "fp32")
         return
 
+    # the oracle first: its process pool forks from a process that has not used the GPU
+    cpu = cpu_batch = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(args.cpu_seconds)
+        if not args.no_batch:
+            cpu_batch = cpu_baseline_batch(args.batch_replicas, args.cpu_batch_events)
+
+    import torch
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    sweep_Ts = () if args.no_sweep else (2.0, 4.0, 8.0, 16.0, 33.896)
+
     forms = ["fp64", "fp32"] if args.form == "both" else [args.form]
-    results = {f: run_form(f, args.steps, args.warmup, args.lanes, args.window_micro, args.max_splits)
+    results = {f: run_form(f, args.steps, args.warmup, args.lanes, args.window_micro, args.max_splits,
+                           sweep_Ts=sweep_Ts if f == "fp64" else (), sweep_legs=args.sweep_legs)
                for f in forms}
     main_form = "fp32" if "fp32" in results else "fp64"
     r = results[main_form]
-    kb = r["kernel_bytes_per_launch"]
+    import workloads as W
+    s4 = W.config(4)
     roof = {"bound": "hbm", "achieved": r["achieved_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": r["achieved_gbs"] / HBM_PEAK_GBS,
             "traffic": _traffic(main_form, r["events_per_launch"]),
-            "kernel": f"k_event<{args.lanes}, {main_form}>", "bytes_per_launch": kb,
-            "avg_launch_ms": r["kernel_ms_avg"]}
-    import workloads as W
-    s4 = W.config(4)
-    for f in results.values():
-        f["birthday_estimate_per_breakpoint"] = birthday_estimate(s4.k, s4.L, s4.T)
+            "kernel": f"k_event<{args.lanes}, {main_form}>",
+            "alg_bytes_per_event": ALG_BYTES_PER_EVENT[main_form],
+            "events_per_launch": r["events_per_launch"],
+            "bytes_per_launch": r["alg_bytes_per_launch"], "avg_launch_ms": r["kernel_ms_avg"],
+            "implementation_bytes_per_launch": r["implementation_bytes_per_launch"]}
+    pm = _pmc(main_form)
+    if pm:
+        roof["counters"] = {k: v for k, v in pm.items() if k.endswith("_per_launch") or k.endswith("_per_event")}
     line = {
         "metric": "ECMC events/sec on 1 GPU, N=2^20 disks η=0.708: FP32-mixed vs FP64 form",
         "value": r["events_per_s"], "unit": "events/s", "n_gpus": 1, "steps": args.steps,
@@ -336,7 +646,8 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32+f64" if main_form == "fp32" else "f64", "data": "synthetic",
         "config": {"workload": "hard disks N=1048576 eta=0.708, jittered 1024x1024 centred-rectangular "
-                               "lattice, k=1024 chains, legs of T=33.896 alternating +x/+y",
+                               "lattice, k=1024 chains, legs of T=33.896 alternating +x/+y, timed after an "
+                               "untimed burn-in of >= 10 liftings per disk",
                    "form": main_form, "lanes_per_chain": args.lanes,
                    "window_sigma": args.window_micro * 1e-6, "parallelism": "1 GPU"},
         "roofline": roof,
@@ -344,11 +655,32 @@ def main():
     }
     if "fp32" in results and "fp64" in results:
         line["fp32_over_fp64"] = results["fp32"]["events_per_s"] / results["fp64"]["events_per_s"]
+    if not args.no_probes:
+        pr = run_probes(s4.k)
+        ws = pr["working_set"]
+        pr["gather_roofline_events_per_s"] = ws["gather_gbs_agent_scope"] * 1e9 / LINE_BYTES_PER_EVENT[main_form]
+        pr["value_over_gather_roofline"] = r["events_per_s"] / pr["gather_roofline_events_per_s"]
+        pr["value_over_littles_law"] = r["events_per_s"] / pr["littles_law_events_per_s"]
+        pr["value_over_spec_line_roofline"] = r["events_per_s"] / (HBM_PEAK_GBS * 1e9 / LINE_BYTES_PER_EVENT[main_form])
+        line["roofline_context"] = pr
+    if not args.no_configs:
+        cfg = run_small_configs(args.lanes, sweep_Ts, args.sweep_legs, args.window_micro)
+        cfg["N65536"] = run_precision_config(args.lanes, args.window_micro, args.precision_events,
+                                             1_000_000, sweep_Ts, args.sweep_legs)
+        line["configs"] = cfg
+        if sweep_Ts and "fp64" in results:
+            line["birthday"] = birthday({
+                "legs": args.sweep_legs, "N4096": cfg["N4096"]["violation_sweep"],
+                "N65536": cfg["N65536"]["fp64"]["violation_sweep"],
+                "N1048576": results["fp64"]["violation_sweep"]})
     if not args.no_batch:
         line["batch"] = run_batch(args.batch_replicas, args.batch_events, args.batch_leg_frac,
                                   window_micro=args.batch_window_micro)
-    if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
+        if cpu_batch:
+            line["batch"]["cpu_oracle_all_cores"] = cpu_batch
+    if cpu:
+        line["cpu_baseline"] = cpu
+    line["paper_context"] = PAPER_CONTEXT
     print(json.dumps(line), flush=True)
 
 

@@ -11,20 +11,25 @@ import paper_2004_11040_amd as pkg
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
-def _declared_functions():
-    src = open(os.path.join(ROOT, "include", "ecmc.h")).read()
+def _declared_functions(header="ecmc.h"):
+    src = open(os.path.join(ROOT, "include", header)).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
     names = re.findall(r"\b(ecmc_[a-z_]+)\s*\(", src)
     return sorted(set(names))
 
 
-def test_header_and_binding_agree():
-    assert _declared_functions() == sorted(pkg.EXPORTS)
+def test_every_header_has_a_library():
+    assert sorted(os.listdir(os.path.join(ROOT, "include"))) == ["ecmc.h", "ecmc_probe.h"]
 
 
-def test_library_exports_every_declared_symbol():
-    lib = ctypes.CDLL(pkg.LIB_PATH)
-    for name in _declared_functions():
+@pytest.mark.parametrize("header,exports,path", [
+    ("ecmc.h", pkg.EXPORTS, pkg.LIB_PATH),
+    ("ecmc_probe.h", pkg.PROBE_EXPORTS, pkg.PROBE_LIB_PATH),
+])
+def test_library_exports_every_declared_symbol(header, exports, path):
+    assert _declared_functions(header) == sorted(exports)
+    lib = ctypes.CDLL(path)
+    for name in _declared_functions(header):
         assert hasattr(lib, name), name
 
 
