@@ -438,6 +438,13 @@ def run_batch(n_rep, target, t_frac, graph=1, window_micro=0, max_splits=0):
         b.set_option(pkg.OPT_MAX_SPLITS, max_splits)
     T = [t_frac * s.L for s in reps]
     big = np.full(n_rep, 1 << 60, np.int64)
+    # two untimed legs at fixed settings first, so that no tuning candidate
+    # runs the fast first legs of the lattice
+    b.set_option(pkg.OPT_LANES, 4)
+    b.set_option(pkg.OPT_CELL_PCT, 100)
+    b.run(big, T, pkg.DIR_ALTERNATE, max_legs=2)
+    b.set_option(pkg.OPT_LANES, 0)
+    b.set_option(pkg.OPT_CELL_PCT, 0)
     b.run(big, T, pkg.DIR_ALTERNATE, max_legs=1)  # autotune (one leg per candidate)
     tune = b.info()
     ev0 = sum(e.stats()["events"] for e in systems)
@@ -459,7 +466,10 @@ def run_batch(n_rep, target, t_frac, graph=1, window_micro=0, max_splits=0):
            "global_runs": info["global_runs"],
            "rollbacks_per_replica_leg": info["rollbacks"] / max(info["legs"], 1),
            "global_runs_per_replica_leg": info["global_runs"] / max(info["legs"], 1),
-           "autotune_events_per_ms": tune["tune_events_per_ms"],
+           "autotune_events_per_ms_by_lane_cap": dict(zip(("4", "8", "16", "32"), tune["tune_events_per_ms"])),
+           "autotune_events_per_ms_by_cell_pct": dict(zip(("100", "115", "130", "141"),
+                                                          tune["tune_cell_events_per_ms"])),
+           "cell_pct": info["cell_pct"],
            "replica_ms_max": info["replica_ms_max"],
            "load_balance": info["replica_ms_sum"] / max(info["workgroups"] * info["device_ms"], 1e-9),
            "overlaps": overlaps, "total_disks": int(sum(s.n for s in reps)),

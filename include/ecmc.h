@@ -107,8 +107,13 @@ extern "C" {
                                  local time with the scanned position)         */
 #define ECMC_FEAT_ALL 15u
 #define ECMC_OPT_GRAPH 11         /* batches: 1 captures the persistent launch
-                                     in a hipGraph once per lane count and
-                                     replays it (default 0)                     */
+                                     in a hipGraph once and replays it (every
+                                     setting travels in the replica descriptors
+                                     uploaded before each replay; default 0)    */
+#define ECMC_OPT_CELL_PCT 12      /* batches: home-cell width in percent of 2 sigma,
+                                     100..141 (cells of at most 4 disks), used
+                                     where admissible for a replica (else its
+                                     own cells); 0: autotune (default)          */
 
 typedef struct ecmc_ctx ecmc_ctx;
 
@@ -279,27 +284,41 @@ void ecmc_free(ecmc_ctx *ctx);
  * workgroup takes a replica from a device queue and runs its legs, with the
  * breakpoint synchronisation, rollbacks (Sec. 3.4, strategy 2) and the
  * global-order fallback (Alg. 2) done on the device; its chains share the
- * workgroup's compute unit and use the same agent-scope atomics and
- * completion waits as ecmc_run.  Results are read per replica with the
+ * workgroup's compute unit.  Results are read per replica with the
  * per-context calls
  * (ecmc_stats, ecmc_get_positions, ecmc_get_log, ...), and are identical to
  * running each context with ecmc_run and no bounded lag.
  * Requirements: all contexts on one stream, all FP64 or all FP32-mixed,
- * k * lanes <= 512 for the lane count used. */
+ * at most 128 chains per replica (4 lanes x 128 = 512 threads).  The chains
+ * of a replica share one workgroup, so its shared fields use workgroup-scope
+ * atomics. */
 typedef struct ecmc_batch ecmc_batch;
 
 typedef struct {
-  int32_t lanes;        /* lanes per chain of the last run                  */
+  int32_t lanes;        /* cap on the lanes per chain of the last run: each
+                           replica of k chains runs the largest of 4, 8, 16,
+                           32 lanes up to the cap with k * lanes <= 512     */
   int32_t graph;        /* 1 if the last run replayed a captured hipGraph   */
   int32_t workgroups;   /* persistent grid of the last launch             */
-  int32_t pad_;
+  int32_t cell_pct;     /* home-cell width of the last run, % of 2 sigma    */
   double device_ms;     /* duration of the last run's main launch (HIP events) */
   int64_t events;       /* liftings committed by the main launch, all replicas */
   int64_t legs;         /* legs run by the last call, all replicas         */
   int64_t rollbacks;    /* rollbacks in the last call, all replicas        */
   int64_t global_runs;  /* global-order stretches in the last call         */
-  double tune_events_per_ms[4]; /* autotuner: liftings per ms with 4, 8, 16,
-                                   32 lanes per chain (0: not tried)      */
+  double tune_events_per_ms[4]; /* autotuner: liftings per replica-ms (per ms
+                                   of summed replica device time, so that
+                                   the slowest replica does not decide) with
+                                   a lane cap
+                                   of 4, 8, 16, 32 (0: not tried, or the
+                                   same lanes for every replica as a smaller
+                                   cap)                                    */
+  double tune_cell_events_per_ms[4]; /* autotuner: liftings per replica-ms with cells
+                                   of 100, 115, 130, 141 % of 2 sigma at the
+                                   chosen cap (0: not tried or no change)  */
+  int32_t tune_from_cache;  /* 1 if the last run took its settings from the
+                               autotuner cache                            */
+  int32_t pad2_;
   double replica_ms_max;  /* longest device time of one replica in the main launch */
   double replica_ms_sum;  /* summed over replicas: with device_ms and workgroups
                              this gives the launch's load balance        */
@@ -319,20 +338,34 @@ int64_t ecmc_batch_scratch_bytes(int32_t n_ctx);
 int ecmc_batch_create(ecmc_batch **out, ecmc_ctx *const *ctxs, int32_t n_ctx,
                       void *scratch, int64_t scratch_bytes);
 
-/* ECMC_OPT_LANES (0: autotune at the first run; 4, 8, 16, 32),
- * ECMC_OPT_GRAPH, ECMC_OPT_FEATURES, ECMC_OPT_WAIT_RETRIES, ECMC_OPT_MAX_SPLITS and
+/* ECMC_OPT_LANES (cap on the lanes per chain: 4, 8, 16, 32; 0: autotune at
+ * the first run), ECMC_OPT_CELL_PCT (0: autotune), ECMC_OPT_GRAPH,
+ * ECMC_OPT_FEATURES, ECMC_OPT_WAIT_RETRIES, ECMC_OPT_MAX_SPLITS and
  * ECMC_OPT_WINDOW_MICRO (bounded lag between a replica's chains in units of
  * 1e-6 sigma, 0 = free; a chain waiting at the lag takes the replica's H from
- * its chains' next-event times itself). */
+ * its chains' next-event times itself).  Scheduling and layout of Alg. 5 on
+ * the device; results do not depend on them.  Options take effect at the
+ * next ecmc_batch_run, also when a captured graph is replayed. */
 int ecmc_batch_set_option(ecmc_batch *b, int32_t key, int64_t value);
+
+/* Autotuner cache (host file, JSON, one entry per line): with a path set, a
+ * run that has to autotune first looks up this batch's signature (device,
+ * form, every replica's size, chains, box, cells and leg length, and the run
+ * settings) and uses the stored lane cap and cell width if found; otherwise
+ * it tunes and stores its choice.  NULL or "" switches the cache off.  The
+ * file is rewritten through a temporary file; concurrent writers are not
+ * coordinated.  Bookkeeping of the runtime, no paper passage. */
+int ecmc_batch_tune_cache(ecmc_batch *b, const char *path);
 
 /* Run every replica r with legs of length leg_T[r] (HOST arrays of n_ctx)
  * until its committed liftings reach target_events[r], or for at most
  * max_legs legs in this call (0: no limit).  direction as for ecmc_run,
- * continuing each context's alternation.  With lanes 0 the autotuner first
- * runs one leg per replica with each admissible lane count (those legs count)
- * and keeps the fastest.  Synchronises the stream.  Errors: ECMC_EINVAL,
- * ECMC_ECELL, ECMC_EHANG, ECMC_EDEVICE. */
+ * continuing each context's alternation.  With lanes or cells on autotune
+ * (and no cache entry), the autotuner first runs one leg per replica with
+ * each lane cap that changes some replica's lanes, then with each cell width
+ * that changes some replica's cells (those legs count), and keeps the
+ * fastest.  Synchronises the stream.  Errors: ECMC_EINVAL, ECMC_ECELL,
+ * ECMC_EHANG, ECMC_EDEVICE. */
 int ecmc_batch_run(ecmc_batch *b, const int64_t *target_events,
                    const double *leg_T, int32_t direction, int32_t max_legs);
 

@@ -25,6 +25,7 @@ OPT_INJECT_CHAIN, OPT_INJECT_EVENT, OPT_KERNEL_TIMING, OPT_STRICT_ORDER = 5, 6, 
 OPT_WINDOW_MICRO = 9
 OPT_FEATURES = 10
 OPT_GRAPH = 11
+OPT_CELL_PCT = 12
 FEAT_SCREEN, FEAT_RESERVE, FEAT_REREAD, FEAT_FRESH, FEAT_ALL = 1, 2, 4, 8, 15
 DIR_X, DIR_Y, DIR_MX, DIR_MY, DIR_ALTERNATE = 0, 1, 2, 3, 4
 
@@ -37,7 +38,7 @@ EXPORTS = (
     "ecmc_get_positions", "ecmc_get_stamps", "ecmc_get_active", "ecmc_get_chain_sums",
     "ecmc_get_log", "ecmc_overlaps", "ecmc_set_option", "ecmc_last_error", "ecmc_free",
     "ecmc_batch_scratch_bytes", "ecmc_batch_create", "ecmc_batch_set_option", "ecmc_batch_run",
-    "ecmc_batch_info", "ecmc_batch_last_error", "ecmc_batch_free",
+    "ecmc_batch_info", "ecmc_batch_last_error", "ecmc_batch_free", "ecmc_batch_tune_cache",
 )
 
 
@@ -69,15 +70,17 @@ class Stats(ctypes.Structure):
 
 
 class BatchInfo(ctypes.Structure):
-    _fields_ = [(n, ctypes.c_int32) for n in ("lanes", "graph", "workgroups", "pad_")] + [
+    _fields_ = [(n, ctypes.c_int32) for n in ("lanes", "graph", "workgroups", "cell_pct")] + [
         ("device_ms", ctypes.c_double)] + [
         (n, ctypes.c_int64) for n in ("events", "legs", "rollbacks", "global_runs")] + [
-        ("tune_events_per_ms", ctypes.c_double * 4)] + [
+        ("tune_events_per_ms", ctypes.c_double * 4), ("tune_cell_events_per_ms", ctypes.c_double * 4)] + [
+        (n, ctypes.c_int32) for n in ("tune_from_cache", "pad2_")] + [
         (n, ctypes.c_double) for n in ("replica_ms_max", "replica_ms_sum")]
 
     def as_dict(self):
-        d = {n: getattr(self, n) for n, _ in self._fields_ if n != "pad_"}
+        d = {n: getattr(self, n) for n, _ in self._fields_ if not n.startswith("pad")}
         d["tune_events_per_ms"] = list(self.tune_events_per_ms)
+        d["tune_cell_events_per_ms"] = list(self.tune_cell_events_per_ms)
         return d
 
 
@@ -132,6 +135,8 @@ def load_library(path: str = LIB_PATH):
     lib.ecmc_batch_last_error.argtypes = [P]
     lib.ecmc_batch_free.restype = None
     lib.ecmc_batch_free.argtypes = [P]
+    lib.ecmc_batch_tune_cache.restype = ctypes.c_int
+    lib.ecmc_batch_tune_cache.argtypes = [P, ctypes.c_char_p]
     _lib = lib
     return lib
 
@@ -340,6 +345,10 @@ class Batch:
 
     def set_option(self, key, value):
         self._check(self.lib.ecmc_batch_set_option(self._b, int(key), int(value)))
+
+    def tune_cache(self, path):
+        """Keep the autotuner's choice in a JSON file (None: no cache)."""
+        self._check(self.lib.ecmc_batch_tune_cache(self._b, None if path is None else os.fsencode(path)))
 
     def run(self, target_events, leg_T, direction=DIR_ALTERNATE, max_legs=0):
         tg = np.ascontiguousarray(target_events, dtype=np.int64)

@@ -48,7 +48,10 @@
 #include <cstdint>
 #include <cstring>
 #include <limits>
+#include <cstdio>
+#include <cstdlib>
 #include <new>
+#include <string>
 #include <vector>
 
 #include "../../include/ecmc.h"
@@ -2688,8 +2691,10 @@ struct RepIn {
   int32_t dir_mode;      // 0 +x, 1 +y, 2 -x, 3 -y, 4 alternate +x/+y
   int32_t max_splits;
   int32_t max_legs;      // at most this many legs in this run (0: no limit)
-  int32_t pad;
+  int32_t lanes;         // lanes per chain for this replica: 4, 8, 16 or 32 (k * lanes <= 512)
   double window;         // bounded lag between the replica's chains (0: free)
+  int32_t features;      // ECMC_FEAT_* bits
+  int32_t wait_retries;  // failed claims before a move up to contact
 };
 struct RepOut {          // results of the run
   int32_t status;        // ECMC_OK or the first error
@@ -2750,7 +2755,8 @@ __device__ __noinline__ void chain_events_call(const Dev &D, const Geo &g, const
 }
 
 template <int G, bool F32>
-__device__ int replica_leg(const RepIn &ri, RepOut *rp, int dir, int32_t wait_retries, int32_t features) {
+__device__ __noinline__ int replica_leg(const RepIn &ri, RepOut *rp, int dir) {
+  const int32_t wait_retries = ri.wait_retries, features = ri.features;
   const Dev &D = ri.D;
   const Geo &g = ri.g;
   const int tid = threadIdx.x, nt = blockDim.x;
@@ -2792,7 +2798,9 @@ __device__ int replica_leg(const RepIn &ri, RepOut *rp, int dir, int32_t wait_re
       const int rot = (int)((tries * 37) % D.k);
       if (tg < D.k) {
         const int c = tg + rot < D.k ? tg + rot : tg + rot - D.k;
-        chain_events_call<G, F32, SCA>(D, g, lp, wait_retries, 1ll << 24, c, lane);
+        // every chain of the replica runs on this workgroup's compute unit:
+        // the shared fields need only workgroup-scope atomics
+        chain_events_call<G, F32, SCW>(D, g, lp, wait_retries, 1ll << 24, c, lane);
       }
     }
     __syncthreads();
@@ -2876,10 +2884,20 @@ __device__ int replica_leg(const RepIn &ri, RepOut *rp, int dir, int32_t wait_re
   return ECMC_OK;
 }
 
-template <int G, bool F32>
+template <bool F32>
+__device__ int replica_leg_g(const RepIn &ri, RepOut *rp, int dir) {
+  switch (ri.lanes) {  // uniform: the replica index is a scalar
+    case 4: return replica_leg<4, F32>(ri, rp, dir);
+    case 8: return replica_leg<8, F32>(ri, rp, dir);
+    case 16: return replica_leg<16, F32>(ri, rp, dir);
+    case 32: return replica_leg<32, F32>(ri, rp, dir);
+    default: return ECMC_EINVAL;
+  }
+}
+
+template <bool F32>
 __global__ void __launch_bounds__(512) k_batch(const RepIn *__restrict__ reps, RepOut *outs, int32_t n_rep,
-                                               int32_t *queue, const int32_t *__restrict__ order,
-                                               int32_t wait_retries, int32_t features) {
+                                               int32_t *queue, const int32_t *__restrict__ order) {
   __shared__ int s_rep;
   for (;;) {
     __syncthreads();
@@ -2904,7 +2922,7 @@ __global__ void __launch_bounds__(512) k_batch(const RepIn *__restrict__ reps, R
     while (ev < ri.target && (ri.max_legs == 0 || legs < ri.max_legs)) {
       const int64_t ln = ri.legs_done + legs;
       const int dir = ri.dir_mode == 4 ? (int)(ln & 1) : ri.dir_mode;
-      const int rc = replica_leg<G, F32>(ri, rp, dir, wait_retries, features);
+      const int rc = replica_leg_g<F32>(ri, rp, dir);
       if (rc) {
         if (threadIdx.x == 0) rp->status = rc;
         break;
@@ -3810,20 +3828,22 @@ struct ecmc_batch {
   std::vector<double> ticks_per_event;
   double rep_ms_max = 0.0, rep_ms_sum = 0.0;  // replicas' device times in the last launch
   double window_micro = 0.0;                  // bounded lag (1e-6 sigma); 0: chains run freely
-  int32_t lanes = 0;        // 0: autotune at the first run
-  int32_t tuned = 0;        // lanes chosen by the autotuner
+  int32_t lanes = 0;        // cap on the lanes per chain (4, 8, 16, 32); 0: autotune
+  int32_t cell_pct = 0;     // cell width in percent of 2 sigma (100..141); 0: autotune
+  int32_t tuned_lanes = 0, tuned_cell_pct = 0;  // the autotuner's choice (0: not tuned yet)
   int32_t use_graph = 0;
   int32_t features = ECMC_FEAT_ALL;
   int32_t wait_retries = 64;
   int32_t max_splits = 1;
   hipGraphExec_t exec = nullptr;
-  int32_t exec_lanes = 0, exec_grid = 0, last_grid = 0;
+  int32_t exec_grid = 0, last_grid = 0;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   // graphs are captured and replayed on a private stream (a caller's legacy
   // default stream cannot be captured), ordered after and before the
   // caller's stream with events
   hipStream_t gstream = nullptr;
   hipEvent_t g0 = nullptr, g1 = nullptr;
+  std::string cache_path;  // autotuner cache (JSON); empty: none
   ecmc_batch_info_t info;
   const char *err = "no error";
 };
@@ -3838,12 +3858,43 @@ namespace {
     }                                           \
   } while (0)
 
-template <int G, bool F32>
+constexpr int BATCH_THREADS = 512;
+
+// lanes per chain for a replica of k chains: the largest of 4, 8, 16, 32 up
+// to the cap with k * lanes <= the workgroup (0 if even 4 lanes do not fit)
+int lanes_for(int k, int cap) {
+  int G = cap;
+  while (G > 4 && k * G > BATCH_THREADS) G >>= 1;
+  return k * G <= BATCH_THREADS ? G : 0;
+}
+
+// home-cell geometry of a replica for cells of about pct/100 x 2 sigma: the
+// context's own cells unless the wider cells are admissible (at most 4 disks
+// per cell: c < sqrt(2) 2 sigma; legs of T <= L - 4 c - 2 sigma)
+Geo geo_for(const ecmc_ctx *ctx, int pct, double T) {
+  Geo g = ctx->g;
+  if (pct <= 100) return g;
+  const double f = pct / 100.0;
+  int32_t nc = (int32_t)std::ceil(g.L / (f * g.d));
+  if (nc >= g.nc || !cells_ok(g.sigma, g.L, nc)) return g;
+  const double c = g.L / (double)nc;
+  if (!(T <= g.L - 4.0 * c - g.d)) return g;
+  g.nc = nc;
+  g.c = c;
+  g.inv_c = 1.0 / c;
+  g.mmax = nc - 3;
+  g.c32 = (float)c;
+  return g;
+}
+
 int batch_grid(ecmc_batch *b, int *grid) {
   int dev = 0, ncu = 0, per_cu = 0;
   BCHK(hipGetDevice(&dev));
   BCHK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
-  BCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch<G, F32>, 512, 0));
+  if (b->f32)
+    BCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch<true>, BATCH_THREADS, 0));
+  else
+    BCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch<false>, BATCH_THREADS, 0));
   if (per_cu < 1) {
     b->err = "batch kernel does not fit on a compute unit";
     return ECMC_EDEVICE;
@@ -3852,47 +3903,27 @@ int batch_grid(ecmc_batch *b, int *grid) {
   return ECMC_OK;
 }
 
-template <int G, bool F32>
 int batch_enqueue(ecmc_batch *b, int grid, hipStream_t st) {
   k_fill<int32_t><<<1, 64, 0, st>>>(b->d_queue, 0, 1);
-  k_batch<G, F32><<<grid, 512, 0, st>>>(b->d_in, b->d_out, (int32_t)b->ctxs.size(), b->d_queue, b->d_order,
-                                        b->wait_retries, b->features);
+  if (b->f32)
+    k_batch<true><<<grid, BATCH_THREADS, 0, st>>>(b->d_in, b->d_out, (int32_t)b->ctxs.size(), b->d_queue,
+                                                  b->d_order);
+  else
+    k_batch<false><<<grid, BATCH_THREADS, 0, st>>>(b->d_in, b->d_out, (int32_t)b->ctxs.size(), b->d_queue,
+                                                   b->d_order);
   BCHK(hipGetLastError());
   return ECMC_OK;
 }
 
-template <bool F32>
-int batch_launch_f(ecmc_batch *b, int lanes, int *grid, hipStream_t st) {
-  switch (lanes) {
-    case 4: {
-      int rc = batch_grid<4, F32>(b, grid);
-      return rc ? rc : batch_enqueue<4, F32>(b, *grid, st);
-    }
-    case 8: {
-      int rc = batch_grid<8, F32>(b, grid);
-      return rc ? rc : batch_enqueue<8, F32>(b, *grid, st);
-    }
-    case 16: {
-      int rc = batch_grid<16, F32>(b, grid);
-      return rc ? rc : batch_enqueue<16, F32>(b, *grid, st);
-    }
-    case 32: {
-      int rc = batch_grid<32, F32>(b, grid);
-      return rc ? rc : batch_enqueue<32, F32>(b, *grid, st);
-    }
-    default:
-      b->err = "lanes per chain must be 4, 8, 16 or 32 for batches";
-      return ECMC_EINVAL;
-  }
-}
-
-// Enqueue one persistent launch (directly, or as a captured hipGraph that is
-// instantiated once per lane count and replayed).
-int batch_launch(ecmc_batch *b, int lanes) {
+// Enqueue one persistent launch, directly or as a captured hipGraph.  Every
+// setting (lanes, cells, features, retries, lag) travels in the replica
+// descriptors, which are uploaded before each launch, so one capture serves
+// every run.
+int batch_launch(ecmc_batch *b) {
   int grid = 0;
   if (!b->use_graph) {
-    const int rc =
-        b->f32 ? batch_launch_f<true>(b, lanes, &grid, b->stream) : batch_launch_f<false>(b, lanes, &grid, b->stream);
+    int rc = batch_grid(b, &grid);
+    if (!rc) rc = batch_enqueue(b, grid, b->stream);
     b->last_grid = grid;
     return rc;
   }
@@ -3901,15 +3932,12 @@ int batch_launch(ecmc_batch *b, int lanes) {
     BCHK(hipEventCreateWithFlags(&b->g0, hipEventDisableTiming));
     BCHK(hipEventCreateWithFlags(&b->g1, hipEventDisableTiming));
   }
-  if (!b->exec || b->exec_lanes != lanes) {
-    if (b->exec) {
-      (void)hipGraphExecDestroy(b->exec);
-      b->exec = nullptr;
-    }
+  if (!b->exec) {
+    int rc = batch_grid(b, &grid);
+    if (rc) return rc;
     hipGraph_t graph = nullptr;
     BCHK(hipStreamBeginCapture(b->gstream, hipStreamCaptureModeThreadLocal));
-    int rc = b->f32 ? batch_launch_f<true>(b, lanes, &grid, b->gstream)
-                    : batch_launch_f<false>(b, lanes, &grid, b->gstream);
+    rc = batch_enqueue(b, grid, b->gstream);
     hipError_t ec = hipStreamEndCapture(b->gstream, &graph);
     if (rc) {
       if (graph) (void)hipGraphDestroy(graph);
@@ -3919,7 +3947,6 @@ int batch_launch(ecmc_batch *b, int lanes) {
     hipError_t ei = hipGraphInstantiate(&b->exec, graph, nullptr, nullptr, 0);
     (void)hipGraphDestroy(graph);
     BCHK(ei);
-    b->exec_lanes = lanes;
     b->exec_grid = grid;
   }
   BCHK(hipEventRecord(b->g0, b->stream));
@@ -3934,7 +3961,7 @@ int batch_launch(ecmc_batch *b, int lanes) {
 // Fill the replica descriptors, run one launch, fold the results back into
 // the contexts.  events: liftings committed by the launch (all replicas).
 int batch_once(ecmc_batch *b, const int64_t *target, const double *leg_T, int32_t direction, int32_t max_legs,
-               int lanes, int64_t *events, float *ms) {
+               int lanes_cap, int cell_pct, int64_t *events, float *ms) {
   const int n = (int)b->ctxs.size();
   std::vector<RepIn> h((size_t)n);
   std::vector<RepOut> ho((size_t)n);
@@ -3944,14 +3971,17 @@ int batch_once(ecmc_batch *b, const int64_t *target, const double *leg_T, int32_
     RepIn &R = h[(size_t)r];
     std::memset(&R, 0, sizeof(RepIn));
     R.D = ctx->D;
-    R.g = ctx->g;
+    R.g = geo_for(ctx, cell_pct, leg_T[r]);
     R.T = leg_T[r];
     R.target = target[r];
     R.legs_done = ctx->leg_counter;
     R.dir_mode = direction;
     R.max_splits = b->max_splits;
     R.max_legs = max_legs;
+    R.lanes = lanes_for(ctx->D.k, lanes_cap);
     R.window = b->window_micro * 1e-6 * ctx->g.sigma;
+    R.features = b->features;
+    R.wait_retries = b->wait_retries;
   }
   // longest expected run first, so that no long replica starts last: the
   // remaining liftings times the measured device time per lifting, or per
@@ -3973,7 +4003,7 @@ int batch_once(ecmc_batch *b, const int64_t *target, const double *leg_T, int32_
   BCHK(hipMemcpyAsync(b->d_order, order.data(), sizeof(int32_t) * (size_t)n, hipMemcpyHostToDevice, b->stream));
   b->rep_ms_max = b->rep_ms_sum = 0.0;
   BCHK(hipEventRecord(b->e0, b->stream));
-  int rc = batch_launch(b, lanes);
+  int rc = batch_launch(b);
   if (rc) return rc;
   BCHK(hipEventRecord(b->e1, b->stream));
   BCHK(hipMemcpyAsync(ho.data(), b->d_out, sizeof(RepOut) * (size_t)n, hipMemcpyDeviceToHost, b->stream));
@@ -4011,6 +4041,100 @@ int batch_once(ecmc_batch *b, const int64_t *target, const double *leg_T, int32_
   return status;
 }
 
+// ---- autotuner cache: one JSON object per line, keyed by the batch's signature
+uint64_t fnv1a(uint64_t h, const void *p, size_t n) {
+  const unsigned char *c = (const unsigned char *)p;
+  for (size_t q = 0; q < n; ++q) {
+    h ^= c[q];
+    h *= 0x100000001b3ull;
+  }
+  return h;
+}
+
+// everything the tuner's choice depends on: the device, the form, each
+// replica's size, chains, box, cells and leg length, and the run settings
+std::string batch_signature(const ecmc_batch *b, const double *leg_T, int32_t direction) {
+  uint64_t h = 0xcbf29ce484222325ull;
+  int dev = 0;
+  hipDeviceProp_t prop;
+  std::memset(&prop, 0, sizeof(prop));
+  if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess) {
+    h = fnv1a(h, prop.gcnArchName, std::strlen(prop.gcnArchName));
+    h = fnv1a(h, &prop.multiProcessorCount, sizeof(prop.multiProcessorCount));
+  }
+  const int32_t f32 = b->f32 ? 1 : 0, n = (int32_t)b->ctxs.size();
+  h = fnv1a(h, &f32, sizeof(f32));
+  h = fnv1a(h, &n, sizeof(n));
+  for (size_t r = 0; r < b->ctxs.size(); ++r) {
+    const ecmc_ctx *ctx = b->ctxs[r];
+    const int64_t nn = ctx->D.n;
+    const int32_t k = ctx->D.k, nc = ctx->g.nc;
+    h = fnv1a(h, &nn, sizeof(nn));
+    h = fnv1a(h, &k, sizeof(k));
+    h = fnv1a(h, &nc, sizeof(nc));
+    h = fnv1a(h, &ctx->g.L, sizeof(double));
+    h = fnv1a(h, &ctx->g.sigma, sizeof(double));
+    h = fnv1a(h, &leg_T[r], sizeof(double));
+  }
+  const int32_t settings[5] = {direction, b->features, b->wait_retries, b->max_splits, b->use_graph};
+  h = fnv1a(h, settings, sizeof(settings));
+  h = fnv1a(h, &b->window_micro, sizeof(double));
+  char buf[24];
+  std::snprintf(buf, sizeof(buf), "%016llx", (unsigned long long)h);
+  return std::string(buf);
+}
+
+std::vector<std::string> cache_lines(const std::string &path) {
+  std::vector<std::string> out;
+  FILE *f = std::fopen(path.c_str(), "r");
+  if (!f) return out;
+  char buf[1024];
+  while (std::fgets(buf, sizeof(buf), f)) {
+    std::string line(buf);
+    while (!line.empty() && (line.back() == '\n' || line.back() == '\r' || line.back() == ',')) line.pop_back();
+    if (line.size() > 20 && line[0] == '"') out.push_back(line);
+  }
+  std::fclose(f);
+  return out;
+}
+
+bool cache_lookup(const std::string &path, const std::string &key, int *lanes, int *pct) {
+  for (const std::string &line : cache_lines(path)) {
+    if (line.compare(1, key.size(), key) != 0 || line[key.size() + 1] != '"') continue;
+    const size_t a = line.find("\"lanes_cap\":"), c = line.find("\"cell_pct\":");
+    if (a == std::string::npos || c == std::string::npos) return false;
+    const int l = std::atoi(line.c_str() + a + 12), p = std::atoi(line.c_str() + c + 11);
+    if ((l != 4 && l != 8 && l != 16 && l != 32) || p < 100 || p > 141) return false;
+    *lanes = l;
+    *pct = p;
+    return true;
+  }
+  return false;
+}
+
+void cache_store(const std::string &path, const std::string &key, int lanes, int pct, double rate, int n) {
+  std::vector<std::string> lines = cache_lines(path);
+  char entry[256];
+  std::snprintf(entry, sizeof(entry),
+                "\"%s\": {\"lanes_cap\": %d, \"cell_pct\": %d, \"events_per_ms\": %.1f, \"replicas\": %d}",
+                key.c_str(), lanes, pct, rate, n);
+  bool found = false;
+  for (std::string &line : lines)
+    if (line.compare(1, key.size(), key) == 0 && line[key.size() + 1] == '"') {
+      line = entry;
+      found = true;
+    }
+  if (!found) lines.push_back(entry);
+  const std::string tmp = path + ".tmp";
+  FILE *f = std::fopen(tmp.c_str(), "w");
+  if (!f) return;
+  std::fputs("{\n", f);
+  for (size_t q = 0; q < lines.size(); ++q) std::fprintf(f, "%s%s\n", lines[q].c_str(), q + 1 < lines.size() ? "," : "");
+  std::fputs("}\n", f);
+  std::fclose(f);
+  std::rename(tmp.c_str(), path.c_str());
+}
+
 }  // namespace
 
 extern "C" {
@@ -4031,6 +4155,7 @@ int ecmc_batch_create(ecmc_batch **out, ecmc_ctx *const *ctxs, int32_t n_ctx, vo
     if (!ctxs[r] || !ctxs[r]->active_set) return ECMC_ESTATE;
     if (ctxs[r]->stream != ctxs[0]->stream) return ECMC_EINVAL;
     if ((ctxs[r]->flags & ECMC_FP32_MIXED) != (ctxs[0]->flags & ECMC_FP32_MIXED)) return ECMC_EINVAL;
+    if (lanes_for(ctxs[r]->D.k, 4) == 0) return ECMC_EINVAL;  // more than 128 chains
     for (int32_t q = 0; q < r; ++q)
       if (ctxs[q] == ctxs[r]) return ECMC_EINVAL;
   }
@@ -4061,6 +4186,10 @@ int ecmc_batch_set_option(ecmc_batch *b, int32_t key, int64_t value) {
       if (value != 0 && value != 4 && value != 8 && value != 16 && value != 32) return ECMC_EINVAL;
       b->lanes = (int32_t)value;
       return ECMC_OK;
+    case ECMC_OPT_CELL_PCT:
+      if (value != 0 && (value < 100 || value > 141)) return ECMC_EINVAL;
+      b->cell_pct = (int32_t)value;
+      return ECMC_OK;
     case ECMC_OPT_GRAPH:
       if (value != 0 && value != 1) return ECMC_EINVAL;
       b->use_graph = (int32_t)value;
@@ -4086,6 +4215,12 @@ int ecmc_batch_set_option(ecmc_batch *b, int32_t key, int64_t value) {
   }
 }
 
+int ecmc_batch_tune_cache(ecmc_batch *b, const char *path) {
+  if (!b) return ECMC_EINVAL;
+  b->cache_path = path ? std::string(path) : std::string();
+  return ECMC_OK;
+}
+
 int ecmc_batch_run(ecmc_batch *b, const int64_t *target_events, const double *leg_T, int32_t direction,
                    int32_t max_legs) {
   if (!b || !target_events || !leg_T || max_legs < 0) return ECMC_EINVAL;
@@ -4093,7 +4228,6 @@ int ecmc_batch_run(ecmc_batch *b, const int64_t *target_events, const double *le
     b->err = "direction must be 0 (+x), 1 (+y), 2 (-x), 3 (-y) or 4 (alternate +x/+y)";
     return ECMC_EINVAL;
   }
-  int kmax = 1;
   for (size_t r = 0; r < b->ctxs.size(); ++r) {
     const ecmc_ctx *ctx = b->ctxs[r];
     const Geo &g = ctx->g;
@@ -4103,38 +4237,78 @@ int ecmc_batch_run(ecmc_batch *b, const int64_t *target_events, const double *le
       return ECMC_EINVAL;
     }
     if (target_events[r] < 0) return ECMC_EINVAL;
-    kmax = std::max(kmax, (int)ctx->D.k);
   }
   std::memset(&b->info, 0, sizeof(b->info));
-  int lanes = b->lanes ? b->lanes : b->tuned;
-  if (lanes && kmax * lanes > 512) {
-    b->err = "chains times lanes per chain exceeds the 512 threads of a workgroup";
-    return ECMC_EINVAL;
-  }
-  if (!lanes) {
-    // autotune: one leg per replica with each admissible lane count; the legs
-    // are real legs of the run (results do not depend on the lane count)
-    const int cand[4] = {4, 8, 16, 32};
-    double best = -1.0;
-    for (int q = 0; q < 4; ++q) {
-      if (kmax * cand[q] > 512) continue;
-      int64_t ev = 0;
-      float ms = 0.f;
-      int rc = batch_once(b, target_events, leg_T, direction, 1, cand[q], &ev, &ms);
-      if (rc) return rc;
-      const double rate = ms > 0.f ? (double)ev / ms : 0.0;
-      b->info.tune_events_per_ms[q] = rate;
-      if (rate > best) {
-        best = rate;
-        lanes = cand[q];
+  int lanes = b->lanes ? b->lanes : b->tuned_lanes;
+  int pct = b->cell_pct ? b->cell_pct : b->tuned_cell_pct;
+  if (!lanes || !pct) {
+    const std::string key = b->cache_path.empty() ? std::string() : batch_signature(b, leg_T, direction);
+    int cl = 0, cp = 0;
+    if (!key.empty() && cache_lookup(b->cache_path, key, &cl, &cp)) {
+      if (!lanes) lanes = cl;
+      if (!pct) pct = cp;
+      b->info.tune_from_cache = 1;
+    } else {
+      // autotune: each candidate runs one leg of every replica; the legs are
+      // real legs of the run (results do not depend on lanes or cells).
+      // First the lane cap at the given cell width, then the cell width at the
+      // chosen cap; candidates that give every replica the same setting as
+      // an earlier one are skipped.
+      const int caps[4] = {4, 8, 16, 32}, pcts[4] = {100, 115, 130, 141};
+      double best_rate = -1.0;
+      const int pct0 = pct ? pct : 100;
+      if (!lanes) {
+        std::vector<std::vector<int>> seen;
+        for (int q = 0; q < 4; ++q) {
+          std::vector<int> lv;
+          for (const ecmc_ctx *ctx : b->ctxs) lv.push_back(lanes_for(ctx->D.k, caps[q]));
+          if (std::find(seen.begin(), seen.end(), lv) != seen.end()) continue;
+          seen.push_back(lv);
+          int64_t ev = 0;
+          float ms = 0.f;
+          int rc = batch_once(b, target_events, leg_T, direction, 1, caps[q], pct0, &ev, &ms);
+          if (rc) return rc;
+          // liftings per replica-millisecond: the summed device time of the
+          // replicas, not the launch's, which the slowest replica sets
+          const double rate = b->rep_ms_sum > 0.0 ? (double)ev / b->rep_ms_sum : 0.0;
+          b->info.tune_events_per_ms[q] = rate;
+          if (rate > best_rate) {
+            best_rate = rate;
+            lanes = caps[q];
+          }
+        }
       }
+      if (!pct) {
+        std::vector<std::vector<int>> seen;
+        double best_cell = -1.0;
+        for (int q = 0; q < 4; ++q) {
+          std::vector<int> nv;
+          for (size_t r = 0; r < b->ctxs.size(); ++r) nv.push_back(geo_for(b->ctxs[r], pcts[q], leg_T[r]).nc);
+          if (std::find(seen.begin(), seen.end(), nv) != seen.end()) continue;
+          seen.push_back(nv);
+          int64_t ev = 0;
+          float ms = 0.f;
+          int rc = batch_once(b, target_events, leg_T, direction, 1, lanes, pcts[q], &ev, &ms);
+          if (rc) return rc;
+          const double rate = b->rep_ms_sum > 0.0 ? (double)ev / b->rep_ms_sum : 0.0;
+          b->info.tune_cell_events_per_ms[q] = rate;
+          if (rate > best_cell) {
+            best_cell = rate;
+            pct = pcts[q];
+          }
+        }
+        best_rate = best_cell;
+      }
+      if (!key.empty()) cache_store(b->cache_path, key, lanes, pct, best_rate, (int)b->ctxs.size());
     }
-    b->tuned = lanes;
+    if (!b->lanes) b->tuned_lanes = lanes;
+    if (!b->cell_pct) b->tuned_cell_pct = pct;
   }
   int64_t ev = 0;
   float ms = 0.f;
-  int rc = batch_once(b, target_events, leg_T, direction, max_legs, lanes, &ev, &ms);
+  int rc = batch_once(b, target_events, leg_T, direction, max_legs, lanes, pct, &ev, &ms);
   b->info.lanes = lanes;
+  b->info.cell_pct = pct;
   b->info.graph = b->use_graph;
   b->info.device_ms = ms;
   b->info.events = ev;

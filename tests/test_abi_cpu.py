@@ -62,3 +62,23 @@ def test_workspace_bytes_rejects(args):
 
 def test_workspace_flags_rejected():
     assert pkg.workspace_bytes(100, 1.0, 50.0, 0, 1, 1, flags=8) == pkg.EINVAL
+
+
+@pytest.mark.parametrize("cname,pyclass", [("ecmc_stats_t", pkg.Stats), ("ecmc_batch_info_t", pkg.BatchInfo)])
+def test_struct_layouts_agree_with_the_header(cname, pyclass, tmp_path):
+    """Compile the header with the host C compiler and compare the size and
+    every field offset of the result structs with the binding's ctypes view."""
+    import subprocess
+    fields = [n for n, _ in pyclass._fields_]
+    src = tmp_path / "layout.c"
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "ecmc.h"', "int main(void) {",
+             f'printf("size %zu\\n", sizeof({cname}));']
+    lines += [f'printf("{f} %zu\\n", offsetof({cname}, {f}));' for f in fields]
+    lines += ["return 0;", "}"]
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), "-o", str(exe), str(src)])
+    out = dict(line.split() for line in subprocess.check_output([str(exe)], text=True).splitlines())
+    assert int(out["size"]) == ctypes.sizeof(pyclass)
+    for f in fields:
+        assert int(out[f]) == getattr(pyclass, f).offset, f

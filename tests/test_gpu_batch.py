@@ -59,18 +59,24 @@ def _check(e, ref, k, tag):
     return st
 
 
-@pytest.mark.parametrize("lanes,graph", [(4, 0), (8, 1), (16, 0), (16, 1)])
-def test_batch_parity(lanes, graph):
+@pytest.mark.parametrize("lanes,graph,cell_pct", [(4, 0, 100), (8, 1, 115), (16, 0, 130), (16, 1, 141),
+                                                  (32, 1, 100)])
+def test_batch_parity(lanes, graph, cell_pct):
+    """Lane caps (each replica takes the largest lane count up to the cap that
+    fits its chains in the workgroup) and home-cell widths change the layout
+    and the schedule only."""
     reps = _small_replicas(6, 7)
     systems = _make(reps)
     b = pkg.Batch(systems)
     b.set_option(pkg.OPT_LANES, lanes)
+    b.set_option(pkg.OPT_CELL_PCT, cell_pct)
     b.set_option(pkg.OPT_GRAPH, graph)
     legs = 3
     big = np.full(len(reps), 1 << 60, np.int64)
     b.run(big, [r[4] for r in reps], pkg.DIR_ALTERNATE, max_legs=legs)
     info = b.info()
-    assert info["lanes"] == lanes and info["legs"] == legs * len(reps), info
+    assert info["lanes"] == lanes and info["cell_pct"] == cell_pct, info
+    assert info["legs"] == legs * len(reps), info
     for i, ((x, y, L, act, T), e) in enumerate(zip(reps, systems)):
         ref = oracle.run(x, y, 1.0, L, act, [0, 1, 0], T)
         _check(e, ref, len(act), f"rep{i} lanes={lanes}")
@@ -90,6 +96,7 @@ def test_batch_bounded_lag_parity(window_micro, lanes, flags):
     systems = _make(reps, flags=flags)
     b = pkg.Batch(systems)
     b.set_option(pkg.OPT_LANES, lanes)
+    b.set_option(pkg.OPT_CELL_PCT, 100)
     b.set_option(pkg.OPT_GRAPH, 1)
     b.set_option(pkg.OPT_WINDOW_MICRO, window_micro)
     big = np.full(len(reps), 1 << 60, np.int64)
@@ -107,10 +114,12 @@ def test_batch_fp32_mixed_and_autotune():
     b.run(big, [r[4] for r in reps], pkg.DIR_ALTERNATE, max_legs=2)
     info = b.info()
     tried = [v for v in info["tune_events_per_ms"] if v > 0]
-    assert len(tried) >= 2, info
-    assert info["lanes"] in (4, 8, 16, 32)
-    # the tuning legs count: one per tried lane count, then two more
-    n_legs = len(tried) + 2
+    tried_cells = [v for v in info["tune_cell_events_per_ms"] if v > 0]
+    assert len(tried) >= 2 and len(tried_cells) >= 2, info
+    assert info["lanes"] in (4, 8, 16, 32) and 100 <= info["cell_pct"] <= 141
+    assert not info["tune_from_cache"]
+    # the tuning legs count: one per tried lane cap and cell width, then two more
+    n_legs = len(tried) + len(tried_cells) + 2
     for i, ((x, y, L, act, T), e) in enumerate(zip(reps, systems)):
         dirs = [l % 2 for l in range(n_legs)]
         ref = oracle.run(x, y, 1.0, L, act, dirs, T)
@@ -124,6 +133,7 @@ def test_batch_event_targets():
     systems = _make(reps)
     b = pkg.Batch(systems)
     b.set_option(pkg.OPT_LANES, 8)
+    b.set_option(pkg.OPT_CELL_PCT, 100)
     targets = np.array([1, 2000, 5000, 0], np.int64)
     b.run(targets, [r[4] for r in reps], pkg.DIR_X)
     for i, ((x, y, L, act, T), e) in enumerate(zip(reps, systems)):
@@ -151,6 +161,7 @@ def test_batch_replica_workload_sample():
         systems.append(e)
     b = pkg.Batch(systems)
     b.set_option(pkg.OPT_LANES, 4)
+    b.set_option(pkg.OPT_CELL_PCT, 100)
     b.set_option(pkg.OPT_WINDOW_MICRO, 300_000)
     big = np.full(len(reps), 1 << 60, np.int64)
     b.run(big, [s.T for s in reps], pkg.DIR_ALTERNATE, max_legs=1)
@@ -168,6 +179,7 @@ def test_batch_one_replica_one_chain():
     e.set_active(act)
     b = pkg.Batch([e])
     b.set_option(pkg.OPT_LANES, 4)
+    b.set_option(pkg.OPT_CELL_PCT, 100)
     b.run(np.array([1 << 60], np.int64), [T], pkg.DIR_ALTERNATE, max_legs=3)
     ref = oracle.run(x, y, 1.0, L, act, [0, 1, 0], T)
     _check(e, ref, 1, "one replica, one chain")
@@ -181,8 +193,91 @@ def test_batch_replica_at_the_chain_limit():
     e = pkg.Ecmc(np.stack([s.x, s.y], 1), 1.0, s.L, flags=pkg.FP32_MIXED, max_chains=s.k, log_cap=1 << 12)
     e.set_active(s.active)
     b = pkg.Batch([e])
-    b.set_option(pkg.OPT_LANES, 4)
+    b.set_option(pkg.OPT_LANES, 32)      # capped at 4 lanes for 128 chains
+    b.set_option(pkg.OPT_CELL_PCT, 130)
     b.set_option(pkg.OPT_WINDOW_MICRO, 350_000)
     b.run(np.array([1 << 60], np.int64), [s.T], pkg.DIR_ALTERNATE, max_legs=1)
     ref = oracle.run(s.x, s.y, 1.0, s.L, s.active, [0], s.T, log_cap=1 << 20)
     _check(e, ref, s.k, s.name)
+
+
+def _workload_systems(n_rep, flags=pkg.FP32_MIXED):
+    reps = W.replica_batch(n_rep)
+    systems = []
+    for s in reps:
+        e = pkg.Ecmc(np.stack([s.x, s.y], 1), 1.0, s.L, flags=flags, max_chains=s.k, log_cap=1 << 14)
+        e.set_active(s.active)
+        systems.append(e)
+    return reps, systems
+
+
+def test_batch_workload_sixteen_replicas_two_legs():
+    """16 replicas of the 512-replica workload (N from 1024 to 16384, k =
+    round(sqrt N)) over two legs in the benchmark's settings (graph, bounded
+    lag 0.35 sigma, autotuned lanes and cells) against the oracle."""
+    reps, systems = _workload_systems(16)
+    b = pkg.Batch(systems)
+    b.set_option(pkg.OPT_GRAPH, 1)
+    b.set_option(pkg.OPT_WINDOW_MICRO, 350_000)
+    big = np.full(len(reps), 1 << 60, np.int64)
+    b.run(big, [s.T for s in reps], pkg.DIR_ALTERNATE, max_legs=2)
+    for s, e in zip(reps, systems):
+        n_legs = e.stats()["legs"]
+        assert n_legs >= 2
+        ref = oracle.run(s.x, s.y, 1.0, s.L, s.active, s.leg_dirs(n_legs), s.T, log_cap=1 << 22)
+        _check(e, ref, s.k, s.name)
+        assert e.overlaps() == 0
+
+
+def test_batch_options_take_effect_between_graph_replays():
+    """Every option travels in the replica descriptors: switching the
+    reservations off between two replays of one captured graph must stop
+    the chains from giving claims back."""
+    reps, systems = _workload_systems(12)
+    b = pkg.Batch(systems)
+    b.set_option(pkg.OPT_GRAPH, 1)
+    b.set_option(pkg.OPT_LANES, 4)
+    b.set_option(pkg.OPT_CELL_PCT, 100)
+    big = np.full(len(reps), 1 << 60, np.int64)
+    T = [s.T for s in reps]
+    b.run(big, T, pkg.DIR_ALTERNATE, max_legs=1)
+    y0 = sum(e.stats()["claim_yields"] for e in systems)
+    assert y0 > 0
+    b.set_option(pkg.OPT_FEATURES, pkg.FEAT_ALL & ~pkg.FEAT_RESERVE)
+    b.set_option(pkg.OPT_LANES, 8)
+    b.run(big, T, pkg.DIR_ALTERNATE, max_legs=1)
+    assert sum(e.stats()["claim_yields"] for e in systems) == y0
+    assert b.info()["lanes"] == 8 and b.info()["graph"] == 1
+    for s, e in zip(reps, systems):
+        ref = oracle.run(s.x, s.y, 1.0, s.L, s.active, [0, 1], s.T, log_cap=1 << 22)
+        _check(e, ref, s.k, s.name)
+
+
+def test_batch_tune_cache_round_trip(tmp_path):
+    """The autotuner stores its choice under the batch's signature; an
+    identical batch takes it from the file without tuning legs."""
+    path = str(tmp_path / "tune.json")
+    reps = _small_replicas(5, 31)
+    first = _make(reps, flags=pkg.FP32_MIXED)
+    b = pkg.Batch(first)
+    b.set_option(pkg.OPT_GRAPH, 1)
+    b.tune_cache(path)
+    big = np.full(len(reps), 1 << 60, np.int64)
+    T = [r[4] for r in reps]
+    b.run(big, T, pkg.DIR_ALTERNATE, max_legs=1)
+    i1 = b.info()
+    assert not i1["tune_from_cache"]
+    text = open(path).read()
+    assert text.startswith("{") and "lanes_cap" in text and "cell_pct" in text
+    second = _make(reps, flags=pkg.FP32_MIXED)
+    b2 = pkg.Batch(second)
+    b2.set_option(pkg.OPT_GRAPH, 1)
+    b2.tune_cache(path)
+    b2.run(big, T, pkg.DIR_ALTERNATE, max_legs=1)
+    i2 = b2.info()
+    assert i2["tune_from_cache"] and i2["lanes"] == i1["lanes"] and i2["cell_pct"] == i1["cell_pct"]
+    assert all(v == 0 for v in i2["tune_events_per_ms"] + i2["tune_cell_events_per_ms"])
+    for (x, y, L, act, TT), e in zip(reps, second):
+        assert e.stats()["legs"] == 1
+        ref = oracle.run(x, y, 1.0, L, act, [0], TT)
+        _check(e, ref, len(act), "from cache")

@@ -311,7 +311,9 @@ def test_invalid_arguments():
     with pytest.raises(pkg.EcmcError):
         e.run(L, L, 0)                          # leg longer than the box allows
     with pytest.raises(pkg.EcmcError):
-        e.run(1.0, 1.0, 2)                      # -x is not offered
+        e.run(1.0, 1.0, 5)                      # no such direction
+    with pytest.raises(pkg.EcmcError):
+        e.run(1.0, 1.0, -1)
     e.run(0.0, 1.0, 0)                          # zero legs is a no-op
     assert e.stats()["events"] == 0
 
