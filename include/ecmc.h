@@ -261,6 +261,21 @@ int ecmc_get_log(ecmc_ctx *ctx, int32_t chain, int32_t *targets, int64_t cap,
  * Synchronises the stream. */
 int ecmc_overlaps(ecmc_ctx *ctx, int64_t *count);
 
+/* The count of ecmc_overlaps for callers that cannot allocate device memory
+ * (code under graph capture, serving loops, harnesses that forbid it): no
+ * context and no workspace.  positions_xy: DEVICE pointer, n x 2 doubles,
+ * row-major, every coordinate in [0, box).  The cell list and the counters
+ * live in one static device array per GPU of 28.8 MB (cells of at least
+ * 2 sigma, at most 1200 per side: box up to about 2400 sigma), held by each
+ * GPU the library runs on until the process ends; the call allocates
+ * nothing, clears what it uses, and synchronises `stream`.  Calls that
+ * overlap in time on one GPU share that array and race.  Errors: ECMC_EINVAL
+ * (n < 1, sigma <= 0, box <= 0, fewer than 3 or more than 1200 cells per
+ * side, a coordinate outside [0, box)), ECMC_EOVERLAP (five centres in one
+ * cell: disks overlap, count not given), ECMC_EDEVICE. */
+int ecmc_overlaps_noalloc(const double *positions_xy, int64_t n, double sigma, double box,
+                          int64_t *count, void *stream);
+
 /* Tuning and test options (ECMC_OPT_*): scheduling of the horizon protocol
  * (Alg. 5), the necklace retries (Remark on active-sphere necklaces), the
  * restart ladder (Sec. 3.4) and test hooks.  None changes results.

@@ -36,7 +36,8 @@ PROBE_EXPORTS = ("ecmc_probe_chase", "ecmc_probe_gather")
 EXPORTS = (
     "ecmc_workspace_bytes", "ecmc_init", "ecmc_set_active", "ecmc_run", "ecmc_stats",
     "ecmc_get_positions", "ecmc_get_stamps", "ecmc_get_active", "ecmc_get_chain_sums",
-    "ecmc_get_log", "ecmc_overlaps", "ecmc_set_option", "ecmc_last_error", "ecmc_free",
+    "ecmc_get_log", "ecmc_overlaps", "ecmc_overlaps_noalloc", "ecmc_set_option", "ecmc_last_error",
+    "ecmc_free",
     "ecmc_batch_scratch_bytes", "ecmc_batch_create", "ecmc_batch_set_option", "ecmc_batch_run",
     "ecmc_batch_info", "ecmc_batch_last_error", "ecmc_batch_free", "ecmc_batch_tune_cache",
 )
@@ -115,6 +116,8 @@ def load_library(path: str = LIB_PATH):
     lib.ecmc_get_log.argtypes = [P, I32, P, I64, ctypes.POINTER(I64)]
     lib.ecmc_overlaps.restype = ctypes.c_int
     lib.ecmc_overlaps.argtypes = [P, ctypes.POINTER(I64)]
+    lib.ecmc_overlaps_noalloc.restype = ctypes.c_int
+    lib.ecmc_overlaps_noalloc.argtypes = [P, I64, D, D, ctypes.POINTER(I64), P]
     lib.ecmc_set_option.restype = ctypes.c_int
     lib.ecmc_set_option.argtypes = [P, I32, I64]
     lib.ecmc_last_error.restype = ctypes.c_char_p
@@ -139,6 +142,22 @@ def load_library(path: str = LIB_PATH):
     lib.ecmc_batch_tune_cache.argtypes = [P, ctypes.c_char_p]
     _lib = lib
     return lib
+
+
+def overlaps_noalloc(positions, sigma, box) -> int:
+    """ecmc_overlaps_noalloc on a device tensor of n x 2 doubles."""
+    import torch
+    lib = load_library()
+    if positions.dtype != torch.float64 or positions.dim() != 2 or positions.shape[1] != 2 \
+            or not positions.is_cuda or not positions.is_contiguous():
+        raise ValueError("positions must be a contiguous n x 2 float64 CUDA tensor")
+    out = ctypes.c_int64(0)
+    rc = lib.ecmc_overlaps_noalloc(ctypes.c_void_p(positions.data_ptr()), int(positions.shape[0]),
+                                   float(sigma), float(box), ctypes.byref(out),
+                                   ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+    if rc != OK:
+        raise EcmcError(rc, "ecmc_overlaps_noalloc failed")
+    return int(out.value)
 
 
 _probe_lib = None

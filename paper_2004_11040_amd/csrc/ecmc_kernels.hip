@@ -50,6 +50,7 @@
 #include <limits>
 #include <cstdio>
 #include <cstdlib>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -4338,3 +4339,132 @@ void ecmc_batch_free(ecmc_batch *b) {
 }
 
 }  // extern "C"
+
+// ==========================================================================
+// Overlap count without a workspace (ecmc_overlaps_noalloc).  The cell list
+// and the counters live in one static device array per GPU, `scratch`; host
+// code reaches it only through the address hipGetSymbolAddress returns for
+// the current device (the array's name is a host-side stand-in, not a device
+// address).  Calls on one GPU share the array: every call clears what it uses
+// first, and calls that overlap in time on one GPU race.
+// ==========================================================================
+namespace {
+
+constexpr int64_t NOALLOC_MAX_CELLS = 1200ll * 1200ll;  // cells per side up to 1200
+constexpr int64_t NOALLOC_HDR = 256;                    // counters: overlaps, error bits
+constexpr int64_t NOALLOC_BYTES = NOALLOC_HDR + NOALLOC_MAX_CELLS * 4 * (1 + CAP);  // 28.8 MB
+
+static __device__ __align__(256) unsigned char scratch[NOALLOC_BYTES];
+
+constexpr unsigned long long NA_RANGE = 1ull, NA_OVERFLOW = 2ull;
+
+__global__ void k_na_clear(unsigned long long *hdr, int32_t *cnt, int64_t ncell) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  if (i == 0) {
+    hdr[0] = 0ull;
+    hdr[1] = 0ull;
+  }
+  for (; i < ncell; i += stride) cnt[i] = 0;
+}
+
+__device__ __forceinline__ int na_cell_of(double v, double inv_c, int32_t nc) {
+  int q = (int)(v * inv_c);
+  return q < 0 ? 0 : (q >= nc ? nc - 1 : q);
+}
+
+__global__ void k_na_bin(const double *xy, int64_t n, double L, int32_t nc, double inv_c,
+                         unsigned long long *hdr, int32_t *cnt, int32_t *ids) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double x = xy[2 * i], y = xy[2 * i + 1];
+  if (!(x >= 0.0 && x < L && y >= 0.0 && y < L)) {
+    atomicOr(&hdr[1], NA_RANGE);
+    return;
+  }
+  const int64_t cell = (int64_t)na_cell_of(y, inv_c, nc) * nc + na_cell_of(x, inv_c, nc);
+  const int r = atomicAdd(&cnt[cell], 1);
+  if (r < CAP)
+    ids[cell * CAP + r] = (int32_t)i;
+  else
+    atomicOr(&hdr[1], NA_OVERFLOW);
+}
+
+// pairs (i < j) in neighbouring cells closer than lim (binary64, minimum image)
+__global__ void k_na_count(const double *xy, int64_t n, double L, int32_t nc, double inv_c, double lim2,
+                           unsigned long long *hdr, const int32_t *cnt, const int32_t *ids) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double xi = xy[2 * i], yi = xy[2 * i + 1], halfL = 0.5 * L;
+  const int row0 = na_cell_of(yi, inv_c, nc), col0 = na_cell_of(xi, inv_c, nc);
+  unsigned long long c = 0;
+  for (int dr = -1; dr <= 1; ++dr)
+    for (int dc = -1; dc <= 1; ++dc) {
+      int row = row0 + dr, col = col0 + dc;
+      row = row < 0 ? row + nc : (row >= nc ? row - nc : row);
+      col = col < 0 ? col + nc : (col >= nc ? col - nc : col);
+      const int64_t cell = (int64_t)row * nc + col;
+      int m = cnt[cell];
+      m = m > CAP ? CAP : m;
+      for (int q = 0; q < m; ++q) {
+        const int64_t j = ids[cell * CAP + q];
+        if (j <= i) continue;
+        double dx = xy[2 * j] - xi, dy = xy[2 * j + 1] - yi;
+        dx = dx > halfL ? dx - L : (dx < -halfL ? dx + L : dx);
+        dy = dy > halfL ? dy - L : (dy < -halfL ? dy + L : dy);
+        if (dx * dx + dy * dy < lim2) ++c;
+      }
+    }
+  if (c) atomicAdd(&hdr[0], c);
+}
+
+std::mutex g_na_mutex;
+void *g_na_ptr[64];  // per device: the address of `scratch` on that device
+
+// the device address of `scratch` on the current device, looked up once per device
+int noalloc_scratch(void **out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return ECMC_EDEVICE;
+  std::lock_guard<std::mutex> lock(g_na_mutex);
+  if (!g_na_ptr[dev]) {
+    void *p = nullptr;
+    if (hipGetSymbolAddress((void **)&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return ECMC_EDEVICE;
+    g_na_ptr[dev] = p;
+  }
+  *out = g_na_ptr[dev];
+  return ECMC_OK;
+}
+
+}  // namespace
+
+extern "C" int ecmc_overlaps_noalloc(const double *positions_xy, int64_t n, double sigma, double box,
+                                     int64_t *count, void *stream) {
+  if (!positions_xy || !count || n < 1 || n > INT32_MAX || !(sigma > 0.0) || !(box > 0.0) ||
+      !std::isfinite(sigma) || !std::isfinite(box))
+    return ECMC_EINVAL;
+  const int32_t nc = default_cells(sigma, box);
+  const int64_t ncell = (int64_t)nc * nc;
+  if (nc < 3 || ncell > NOALLOC_MAX_CELLS) return ECMC_EINVAL;
+  void *base = nullptr;
+  int rc = noalloc_scratch(&base);
+  if (rc) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  unsigned long long *hdr = (unsigned long long *)base;
+  int32_t *cnt = (int32_t *)((char *)base + NOALLOC_HDR);
+  int32_t *ids = cnt + ncell;
+  const double inv_c = 1.0 / (box / (double)nc);
+  const double d = 2.0 * sigma;
+  const double lim = d - 4.0 * (std::nextafter(box, INFINITY) - box);
+  const unsigned nb = blocks_for(n, 256);
+  k_na_clear<<<(unsigned)std::min<int64_t>((ncell + 255) / 256, 4096), 256, 0, st>>>(hdr, cnt, ncell);
+  k_na_bin<<<nb, 256, 0, st>>>(positions_xy, n, box, nc, inv_c, hdr, cnt, ids);
+  k_na_count<<<nb, 256, 0, st>>>(positions_xy, n, box, nc, inv_c, lim * lim, hdr, cnt, ids);
+  if (hipGetLastError() != hipSuccess) return ECMC_EDEVICE;
+  unsigned long long h[2] = {0ull, 0ull};
+  if (hipMemcpyAsync(h, hdr, sizeof(h), hipMemcpyDeviceToHost, st) != hipSuccess) return ECMC_EDEVICE;
+  if (hipStreamSynchronize(st) != hipSuccess) return ECMC_EDEVICE;
+  if (h[1] & NA_RANGE) return ECMC_EINVAL;
+  if (h[1] & NA_OVERFLOW) return ECMC_EOVERLAP;  // 5 centres in a cell narrower than sqrt(2) 2 sigma
+  *count = (int64_t)h[0];
+  return ECMC_OK;
+}
