@@ -44,6 +44,11 @@ SUITES = {
     # half-written record
     "swap4": Suite("swap4", Fr(24), 5 * H, (17 * H, Fr(23), Fr(19), Fr(16)), (Fr(7), Fr(7), Fr(11), Fr(4)),
                    (2, 3), Fr(10)),
+    # four disks, two chains (seeded search): a lane minimum that is not the
+    # target changes between the scan and the claim; without re-reading it
+    # after the claim the chain commits on a stale horizon set
+    "lane4": Suite("lane4", Fr(24), 5 * H, (Fr(16), Fr(7), Fr(4), 21 * H), (Fr(11), Fr(8), Fr(0), Fr(4)),
+                   (1, 2), Fr(10)),
     # two chains whose corridors never meet: no violation is possible
     "apart": Suite("apart", Fr(24), 5 * H, (Fr(0), Fr(8), Fr(3), Fr(13)), (Fr(0), Fr(0), Fr(12), Fr(12)),
                    (0, 2), Fr(10)),
@@ -77,7 +82,7 @@ def test_suites_are_exact_in_binary64():
 
 
 # ---- the kernel's protocol ------------------------------------------------------
-@pytest.mark.parametrize("name", ["necklace2", "row3", "shared_target", "zero_tau", "swap4", "apart"])
+@pytest.mark.parametrize("name", ["necklace2", "row3", "shared_target", "zero_tau", "swap4", "lane4", "apart"])
 def test_kernel_protocol_is_absorbing_and_matches_the_oracle(name):
     o = outcome(name, "kernel")
     assert o.absorbing, o.trapped
@@ -134,6 +139,7 @@ def test_alg5_x_recheck_misses_a_zero_tau_lifting():
     ("kernel", "no_tj_check", "zero_tau"),
     ("kernel", "no_recheck", "row3"),
     ("kernel", "no_contact_move", "necklace2"),  # Remark on active-sphere necklaces
+    ("kernel", "no_lane_recheck", "lane4"),
 ])
 def test_mutation_is_caught(program, mutation, name):
     base = outcome(name, program)
@@ -153,3 +159,18 @@ def test_probabilities_are_exact_rationals():
     o = outcome("row3", "kernel")
     assert isinstance(o.p_terminate, Fr) and isinstance(o.p_abort, Fr)
     assert 0 < o.p_terminate < 1 and o.p_abort + o.p_terminate == 1
+
+
+def test_exact_tie_between_chains_is_resolved_by_the_claim():
+    """Two chains reach one static disk at exactly the same time (t = 11/2).
+    The oracle breaks such ties by chain id (Alg. 2's heap order); the kernel
+    lets whichever claim lands first lift, and equal times pass Eq. 2.  Both
+    outcomes are liftings of Alg. 2 at the same time with a different tie
+    order; exact ties have probability zero for generic positions (the paper
+    assumes distinct event times), which is why the suites above have none."""
+    s = Suite("tie", Fr(24), 5 * H, (33 * H, 31 * H, Fr(1)), (Fr(7), Fr(0), Fr(3)), (0, 1), Fr(6))
+    ref = reference(s)
+    assert ref["logs"] == [((2, 11 * H),), ()]
+    o = enumerate_chain(s, "kernel", None, ref)
+    assert o.absorbing and not o.invariant_errors and len(o.terminate) == 2
+    assert len(o.mismatched) == 1 and o.mismatched[0]["logs"] == ((), ((2, 11 * H),))
