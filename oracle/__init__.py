@@ -19,6 +19,9 @@ Contents
                    sequential-consistency program and for the gfx950 kernel's
                    protocol: every terminate state is compared with ``run``, and
                    single-statement mutations must break a check.
+``constraint_graph`` (module) the constraint graph G(3), its first-order
+                   pruning and symmetrization (Sec. 3.1-3.2), and the check
+                   that every lifting of a leg is an arrow.
 """
 from __future__ import annotations
 
