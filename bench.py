@@ -182,6 +182,10 @@ def _stats_delta(st0, st1):
     return d
 
 
+NEIGHBOURS = {"cells": 0, "graph": 1}
+_neighbours = "graph"
+
+
 def _make(s, form, lanes, window_micro, log_cap=1 << 12, max_splits=0):
     import numpy as np
 
@@ -191,6 +195,7 @@ def _make(s, form, lanes, window_micro, log_cap=1 << 12, max_splits=0):
     e.set_option(pkg.OPT_LANES, lanes)
     e.set_option(pkg.OPT_KERNEL_TIMING, 1)
     e.set_option(pkg.OPT_WINDOW_MICRO, window_micro)
+    e.set_option(pkg.OPT_NEIGHBOURS, NEIGHBOURS[_neighbours])
     if max_splits:
         e.set_option(pkg.OPT_MAX_SPLITS, max_splits)
     e.set_active(s.active)
@@ -433,6 +438,7 @@ def run_batch(n_rep, target, t_frac, graph=1, window_micro=0, max_splits=0):
         systems.append(e)
     b = pkg.Batch(systems)
     b.set_option(pkg.OPT_GRAPH, graph)
+    b.set_option(pkg.OPT_NEIGHBOURS, NEIGHBOURS[_neighbours])
     b.set_option(pkg.OPT_WINDOW_MICRO, window_micro)
     if max_splits:
         b.set_option(pkg.OPT_MAX_SPLITS, max_splits)
@@ -602,7 +608,10 @@ def main():
     ap.add_argument("--sweep-legs", type=int, default=40)
     ap.add_argument("--no-sweep", action="store_true")
     ap.add_argument("--no-probes", action="store_true")
+    ap.add_argument("--neighbours", choices=sorted(NEIGHBOURS), default=_neighbours,
+                    help="candidates from the corridor scan over home cells, or from the constraint graph G(3)")
     args = ap.parse_args()
+    globals()["_neighbours"] = args.neighbours
     if args.pmc_summary:
         a = args.pmc_summary
         pmc_summary(a[0], a[1], a[2], a[3:])
@@ -658,7 +667,7 @@ def main():
         "config": {"workload": "hard disks N=1048576 eta=0.708, jittered 1024x1024 centred-rectangular "
                                "lattice, k=1024 chains, legs of T=33.896 alternating +x/+y, timed after an "
                                "untimed burn-in of >= 10 liftings per disk",
-                   "form": main_form, "lanes_per_chain": args.lanes,
+                   "form": main_form, "lanes_per_chain": args.lanes, "neighbours": args.neighbours,
                    "window_sigma": args.window_micro * 1e-6, "parallelism": "1 GPU"},
         "roofline": roof,
         "forms": results,

@@ -61,7 +61,10 @@ extern "C" {
 #define ECMC_FP32_MIXED 1u  /* collision search in binary32 on cell-relative
                                coordinates, winners and near-ties recomputed in
                                binary64; positions, local times and sums stay
-                               binary64 (results identical to ECMC_FP64)       */
+                               binary64 (results identical to ECMC_FP64).  It
+                               filters the corridor scan (ECMC_NEIGHBOURS_CELLS);
+                               graph candidates are three binary64 times of
+                               flight per scan in either form             */
 
 /* ---- options for ecmc_set_option --------------------------------------- */
 #define ECMC_OPT_LANES 1          /* lanes per chain: 16, 32 or 64 (default 64) */
@@ -110,6 +113,16 @@ extern "C" {
                                      in a hipGraph once and replays it (every
                                      setting travels in the replica descriptors
                                      uploaded before each replay; default 0)    */
+#define ECMC_OPT_NEIGHBOURS 13    /* where a chain finds its candidates (contexts
+                                     and batches): ECMC_NEIGHBOURS_GRAPH (the
+                                     three arrows of the constraint graph G(3),
+                                     built at every breakpoint, Sec. 3.1;
+                                     default) or ECMC_NEIGHBOURS_CELLS (the
+                                     corridor scan over home cells, where the
+                                     FP32-mixed form filters in binary32).
+                                     Same results.                              */
+#define ECMC_NEIGHBOURS_CELLS 0
+#define ECMC_NEIGHBOURS_GRAPH 1
 #define ECMC_OPT_CELL_PCT 12      /* batches: home-cell width in percent of 2 sigma,
                                      100..141 (cells of at most 4 disks), used
                                      where admissible for a replica (else its
@@ -275,6 +288,20 @@ int ecmc_overlaps(ecmc_ctx *ctx, int64_t *count);
  * cell: disks overlap, count not given), ECMC_EDEVICE. */
 int ecmc_overlaps_noalloc(const double *positions_xy, int64_t n, double sigma, double box,
                           int64_t *count, void *stream);
+
+/* Constraint graph G(3) of the current configuration for velocity
+ * `direction` (0 +x, 1 +y, 2 -x, 3 -y) (Sec. 3.1): for every disk i the disk
+ * with the smallest (time of flight, id) in each lane of its corridor,
+ * |dp| < sigma, sigma <= dp < 2 sigma and -2 sigma < dp <= -sigma, keeping
+ * only arrows with a time of flight below `horizon` (a leg of that length
+ * cannot reach further; 0 < horizon <= box - 4 cell - 2 sigma).  Writes
+ * arrows[3 i + q] = target disk id, or -1 for an empty lane (HOST array of
+ * 3 n int32).  Disks closer than 2 sigma across v cannot pass each other,
+ * so the arrows hold for a whole leg; they are the candidates the event
+ * kernel uses with ECMC_NEIGHBOURS_GRAPH.  Rebuilds the home cells (call
+ * between runs).  Synchronises the stream.  Errors: ECMC_EINVAL, ECMC_ECELL,
+ * ECMC_EDEVICE. */
+int ecmc_graph(ecmc_ctx *ctx, int32_t direction, double horizon, int32_t *arrows);
 
 /* Tuning and test options (ECMC_OPT_*): scheduling of the horizon protocol
  * (Alg. 5), the necklace retries (Remark on active-sphere necklaces), the

@@ -58,8 +58,9 @@ def _pair(a, p, sign, L, d, i, js):
     return dp, da, b
 
 
-def g3(x, y, sigma, L, direction=0, horizon=None):
-    """G(3): (arrows, b, tau), each (n, 3), lanes (0, +, -)."""
+def g3(x, y, sigma, L, direction=0, horizon=None, rows=None):
+    """G(3): (arrows, b, tau), each (n, 3), lanes (0, +, -).  With `rows`,
+    only those disks' arrows are computed (the others stay -1)."""
     a, p, sign = _axes(x, y, direction)
     n = a.shape[0]
     d = 2.0 * sigma
@@ -67,7 +68,7 @@ def g3(x, y, sigma, L, direction=0, horizon=None):
     bb = np.zeros((n, 3))
     tt = np.full((n, 3), np.inf)
     ids = np.arange(n)
-    for i in range(n):
+    for i in (range(n) if rows is None else rows):
         js = ids[ids != i]
         dp, da, b = _pair(a, p, sign, L, d, i, js)
         inside = dp * dp < d * d

@@ -26,6 +26,8 @@ OPT_WINDOW_MICRO = 9
 OPT_FEATURES = 10
 OPT_GRAPH = 11
 OPT_CELL_PCT = 12
+OPT_NEIGHBOURS = 13
+NEIGHBOURS_CELLS, NEIGHBOURS_GRAPH = 0, 1
 FEAT_SCREEN, FEAT_RESERVE, FEAT_REREAD, FEAT_FRESH, FEAT_ALL = 1, 2, 4, 8, 15
 DIR_X, DIR_Y, DIR_MX, DIR_MY, DIR_ALTERNATE = 0, 1, 2, 3, 4
 
@@ -36,7 +38,8 @@ PROBE_EXPORTS = ("ecmc_probe_chase", "ecmc_probe_gather")
 EXPORTS = (
     "ecmc_workspace_bytes", "ecmc_init", "ecmc_set_active", "ecmc_run", "ecmc_stats",
     "ecmc_get_positions", "ecmc_get_stamps", "ecmc_get_active", "ecmc_get_chain_sums",
-    "ecmc_get_log", "ecmc_overlaps", "ecmc_overlaps_noalloc", "ecmc_set_option", "ecmc_last_error",
+    "ecmc_get_log", "ecmc_overlaps", "ecmc_overlaps_noalloc", "ecmc_graph", "ecmc_set_option",
+    "ecmc_last_error",
     "ecmc_free",
     "ecmc_batch_scratch_bytes", "ecmc_batch_create", "ecmc_batch_set_option", "ecmc_batch_run",
     "ecmc_batch_info", "ecmc_batch_last_error", "ecmc_batch_free", "ecmc_batch_tune_cache",
@@ -116,6 +119,8 @@ def load_library(path: str = LIB_PATH):
     lib.ecmc_get_log.argtypes = [P, I32, P, I64, ctypes.POINTER(I64)]
     lib.ecmc_overlaps.restype = ctypes.c_int
     lib.ecmc_overlaps.argtypes = [P, ctypes.POINTER(I64)]
+    lib.ecmc_graph.restype = ctypes.c_int
+    lib.ecmc_graph.argtypes = [P, I32, D, P]
     lib.ecmc_overlaps_noalloc.restype = ctypes.c_int
     lib.ecmc_overlaps_noalloc.argtypes = [P, I64, D, D, ctypes.POINTER(I64), P]
     lib.ecmc_set_option.restype = ctypes.c_int
@@ -330,6 +335,13 @@ class Ecmc:
         self._check(self.lib.ecmc_get_log(self._ctx, int(chain), _np_ptr(buf), keep,
                                           ctypes.byref(n)))
         return ChainLog(count, buf)
+
+    def graph(self, direction, horizon) -> np.ndarray:
+        """Arrows of the constraint graph G(3), (n, 3) target ids (-1: none),
+        lanes (0, +, -), for the current configuration."""
+        out = np.empty(3 * self.n, np.int32)
+        self._check(self.lib.ecmc_graph(self._ctx, int(direction), float(horizon), _np_ptr(out)))
+        return out.reshape(self.n, 3)
 
     def overlaps(self) -> int:
         c = ctypes.c_int64(0)

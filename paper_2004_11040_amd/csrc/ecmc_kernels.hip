@@ -162,6 +162,7 @@ struct Dev {
   unsigned long long *TS;  // per event workgroup: s_memrealtime at its start and end
   struct RefRec *REF;   // per chain: current activation
   unsigned long long *RES;  // per slot: earliest (time, chain) that targets the disk
+  int4 *GARR;  // per slot: arrows of G(3), slots of the lane minima (0, +, -), -1 none
   Ctl *ctl;
   int64_t n;
   int32_t k;
@@ -425,6 +426,77 @@ __device__ void chains_attempt_one(const Dev &D, double h, int c) {
 __global__ void k_chains_attempt(Dev D, double h) {
   int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c < D.k) chains_attempt_one(D, h, c);
+}
+
+// The constraint graph G(3) of the leg (Sec. 3.1): for the disk in slot s,
+// the slot of the disk with the smallest (time of flight, id) in each lane of
+// its corridor (|dp| < sigma; sigma <= dp < 2 sigma; -2 sigma < dp <= -sigma),
+// from the home-cell records at the breakpoint; arrows whose time of flight is
+// T or more are left out (no chain can reach them within the leg).  Columns
+// are walked forward as in the corridor scan until no further column can
+// undercut any lane's minimum.
+__device__ void graph_slot(const Dev &D, const Geo &g, double T, int64_t s) {
+  int4 out = make_int4(-1, -1, -1, -1);
+  const CstRec cs = D.CST[s];
+  if (cs.id >= 0) {
+    const double a = D.MUT[s].a, p = cs.p;
+    const int cell0 = (int)(s >> 2);
+    const int row0 = cell0 / g.nc, col0 = cell0 - row0 * g.nc;
+    double u = a - col0 * g.c;
+    if (u < 0.0) u = u + g.L;
+    double bt[3] = {INFINITY, INFINITY, INFINITY};
+    int bid[3] = {0x7fffffff, 0x7fffffff, 0x7fffffff};
+    int bsl[3] = {-1, -1, -1};
+    for (int m = 0; m <= g.mmax; ++m) {
+      if (m > 0) {
+        double lim = 0.0;
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+          const double lq = bt[q] < T ? bt[q] : T;
+          lim = lq > lim ? lq : lim;
+        }
+        if (m * g.c - u - g.d - STOP_MARGIN > lim) break;
+      }
+      int col = col0 + m;
+      if (col >= g.nc) col -= g.nc;
+      for (int dr = -1; dr <= 1; ++dr) {
+        int row = row0 + dr;
+        row = row < 0 ? row + g.nc : (row >= g.nc ? row - g.nc : row);
+        for (int q4 = 0; q4 < CAP; ++q4) {
+          const int sl = ((row * g.nc + col) << 2) + q4;
+          if (sl == (int)s) continue;
+          const CstRec cj = D.CST[sl];
+          if (cj.id < 0) continue;
+          double b, dp;
+          const double tau = tof(a, p, D.MUT[sl].a, cj.p, g, b, dp);
+          if (!(tau < T)) continue;
+          const int cls = lane_class(dp, g);
+#pragma unroll
+          for (int q = 0; q < 3; ++q)
+            if (q == cls && key_less(tau, cj.id, bt[q], bid[q])) {
+              bt[q] = tau;
+              bid[q] = cj.id;
+              bsl[q] = sl;
+            }
+        }
+      }
+    }
+    out = make_int4(bsl[0], bsl[1], bsl[2], -1);
+  }
+  D.GARR[s] = out;
+}
+__global__ void k_graph(Dev D, Geo g, double T) {
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s < (int64_t)g.nc * g.nc * CAP) graph_slot(D, g, T, s);
+}
+// arrows as disk ids, in disk order: out[3 i + q] (-1: none)
+__global__ void k_graph_ids(Dev D, int32_t *out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= D.n) return;
+  const int4 ar = D.GARR[D.SLOT_OF[i]];
+  out[3 * i] = ar.x >= 0 ? D.CST[ar.x].id : -1;
+  out[3 * i + 1] = ar.y >= 0 ? D.CST[ar.y].id : -1;
+  out[3 * i + 2] = ar.z >= 0 ? D.CST[ar.z].id : -1;
 }
 
 // ---- rollback to time R: take back every lifting with time >= R ----------
@@ -1047,7 +1119,7 @@ __device__ void clock_loop(const Dev &D, long long iter_cap) {
 // exactly like a stalled one to the others, t = breakpoint).
 // One chain's events for one launch: from its reference to the breakpoint, an
 // abort, or an error.  Lanes `lane` of a group of G run it together.
-template <int G, bool F32, int SC>
+template <int G, bool F32, int SC, bool GR>
 __device__ void chain_events(const Dev &D, const Geo &g, const LegP &lp, int32_t wait_retries,
                              long long iter_cap, int c, int lane) {
   using W = Win<G>;
@@ -1093,6 +1165,13 @@ __device__ void chain_events(const Dev &D, const Geo &g, const LegP &lp, int32_t
   // reach of any leg (legs are shorter than L - 5d), so scans skip its slot.
   constexpr bool PREFETCH = G == 64;
   bool pf = false;
+  // constraint graph (GR): the arrows of the moving disk (slots of the nearest
+  // disk ahead in each lane, fixed for the leg), loaded once per activation,
+  // and the next scan's records, loaded beside the post-claim reads
+  int arr[3] = {-1, -1, -1};
+  int arr_slot = -1;
+  CstRec pf_gcr[3];
+  double pf_ga[3], pf_gt[3];
   CstRec pf_crs[W::SPL];
   double pf_a[W::SPL], pf_t[W::SPL];
   int pf_sl[W::SPL], pf_col[W::SPL], pf_row[W::SPL];
@@ -1163,47 +1242,178 @@ __device__ void chain_events(const Dev &D, const Geo &g, const LegP &lp, int32_t
       break;
     }
 
-    // ---- corridor scan over home columns (time of flight, Sec. 2.2) ----
-    const int cell0 = s >> 2;
-    const int row0 = cell0 / g.nc, col0 = cell0 - row0 * g.nc;
-    double u = a - col0 * g.c;  // distance from the home column's trailing edge
-    if (u < 0.0) u = u + g.L;
+    // ---- candidates: the lane minima of the corridor, from a scan over home
+    // columns or from the arrows of the constraint graph G(3) (time of
+    // flight, Sec. 2.2; graph, Sec. 3.1) ----
     const double trem = tend - t;
-
-    Cand bl;
-#pragma unroll
-    for (int q = 0; q < 3; ++q) {
-      bl.tau[q] = INFINITY;
-      bl.t[q] = bl.a[q] = bl.b[q] = bl.p[q] = 0.0;
-      bl.id[q] = 0x7fffffff;
-      bl.slot[q] = -1;
-    }
     double gt[3] = {INFINITY, INFINITY, INFINITY};
     int gi[3] = {0x7fffffff, 0x7fffffff, 0x7fffffff};
-    int scanned = 0;
-    // binary32 offsets of the moving disk inside its home cell (FP32-mixed)
-    const float rai = (float)u, rpi = (float)(p - row0 * g.c);
-    for (int m0 = 0;; m0 += W::M) {
-      // the slots of this pass, loaded once (records are reread only after a claim)
-      CstRec crs[W::SPL];
-      double ajs[W::SPL], tjs[W::SPL];
-      int sls[W::SPL], scol[W::SPL], srow[W::SPL];
-      const bool from_pf = pf && m0 == 0;
-      if (from_pf) {
+    double gtj[3], gaj[3], gbj[3], gpj[3];
+    int gsl[3];
+    if constexpr (!GR) {
+      const int cell0 = s >> 2;
+      const int row0 = cell0 / g.nc, col0 = cell0 - row0 * g.nc;
+      double u = a - col0 * g.c;  // distance from the home column's trailing edge
+      if (u < 0.0) u = u + g.L;
+
+      Cand bl;
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        bl.tau[q] = INFINITY;
+        bl.t[q] = bl.a[q] = bl.b[q] = bl.p[q] = 0.0;
+        bl.id[q] = 0x7fffffff;
+        bl.slot[q] = -1;
+      }
+      int scanned = 0;
+      // binary32 offsets of the moving disk inside its home cell (FP32-mixed)
+      const float rai = (float)u, rpi = (float)(p - row0 * g.c);
+      for (int m0 = 0;; m0 += W::M) {
+        // the slots of this pass, loaded once (records are reread only after a claim)
+        CstRec crs[W::SPL];
+        double ajs[W::SPL], tjs[W::SPL];
+        int sls[W::SPL], scol[W::SPL], srow[W::SPL];
+        const bool from_pf = pf && m0 == 0;
+        if (from_pf) {
+#pragma unroll
+          for (int r = 0; r < W::SPL; ++r) {
+            crs[r] = pf_crs[r];
+            ajs[r] = pf_a[r];
+            tjs[r] = pf_t[r];
+            sls[r] = pf_sl[r];
+            scol[r] = pf_col[r];
+            srow[r] = pf_row[r];
+          }
+        } else {
+          load_pass(m0, col0, row0, crs, ajs, tjs, sls, scol, srow);
+        }
+        pf = false;
+        if (rel_slot >= 0 && !from_pf) {  // the last commit's stores have completed with these loads
+          wait_mem();
+          if (lane == 0) {
+            strict_rel<SC>(lp.strict);
+            __hip_atomic_store(&D.REF[c].ver, rel_ver, __ATOMIC_RELAXED, SC);
+            __hip_atomic_store(&D.TAG[rel_slot], TAG_STATIC, __ATOMIC_RELAXED, SC);  // release
+          }
+          rel_slot = -1;
+        }
+        bool refine[W::SPL];
+        unsigned candq[W::SPL];  // FP32-mixed: lanes of the corridor a refined slot may undercut (bit q)
 #pragma unroll
         for (int r = 0; r < W::SPL; ++r) {
-          crs[r] = pf_crs[r];
-          ajs[r] = pf_a[r];
-          tjs[r] = pf_t[r];
-          sls[r] = pf_sl[r];
-          scol[r] = pf_col[r];
-          srow[r] = pf_row[r];
+          refine[r] = sls[r] >= 0 && crs[r].id >= 0 && sls[r] != s && sls[r] != xs;
+          candq[r] = 0;
         }
-      } else {
-        load_pass(m0, col0, row0, crs, ajs, tjs, sls, scol, srow);
+        if constexpr (F32) {
+          // binary32 intervals; a lane's upper bound is the smallest upper end
+          // over slots certainly in that lane (and certainly not behind)
+          F32Cand fc[W::SPL];
+          float ub[3] = {INFINITY, INFINITY, INFINITY};
+#pragma unroll
+          for (int r = 0; r < W::SPL; ++r) {
+            fc[r].lo = fc[r].hi = INFINITY;
+            fc[r].cls_mask = 0;
+            fc[r].cls = -1;
+            if (refine[r]) {
+              const float raj = (float)(ajs[r] - scol[r] * g.c), rpj = (float)(crs[r].p - srow[r] * g.c);
+              const int w = lane + r * G;
+              fc[r] = tof_f32(m0 + w / (ROWS * CAP), (w % (ROWS * CAP)) / CAP - 1, rai, rpi, raj, rpj, g);
+              const bool not_behind = (tjs[r] > h) || (t + (double)fc[r].lo >= tjs[r]);
+#pragma unroll
+              for (int q = 0; q < 3; ++q)
+                if (fc[r].cls == q && not_behind && fc[r].hi < ub[q]) ub[q] = fc[r].hi;
+            }
+          }
+#pragma unroll
+          for (int q = 0; q < 3; ++q) {
+            ub[q] = grp_min_f32<G>(ub[q]);
+            const float ex = gt[q] < INFINITY ? (float)gt[q] * (1.f + 1e-6f) + 1e-6f : INFINITY;
+            ub[q] = fminf(ub[q], ex);  // exact minimum of the earlier passes, rounded up
+          }
+#pragma unroll
+          for (int r = 0; r < W::SPL; ++r) {
+            if (refine[r]) {
+              unsigned cm = 0;
+#pragma unroll
+              for (int q = 0; q < 3; ++q)
+                if (((fc[r].cls_mask >> q) & 1) && fc[r].lo <= ub[q]) cm |= 1u << q;
+              candq[r] = cm;
+              refine[r] = cm != 0;
+            }
+          }
+        }
+#pragma unroll
+        for (int r = 0; r < W::SPL; ++r) {
+          if (sls[r] >= 0 && crs[r].id >= 0 && sls[r] != s) ++scanned;
+          if (refine[r]) {
+            const int sl = sls[r];
+            const CstRec cr = crs[r];
+            const double aj = ajs[r], tj = tjs[r];
+            if (F32) ++lane_refined;
+            double b, dp;
+            const double tau = tof(a, p, aj, cr.p, g, b, dp);
+            // a disk that came to rest behind the moving disk before this
+            // attempt began (its stamp <= h) is not ahead of it
+            const bool behind = (t + tau < tj) && (tj <= h);
+            if (tau < INFINITY && !behind) {
+              const int cls = lane_class(dp, g);
+#pragma unroll
+              for (int q = 0; q < 3; ++q) {  // unrolled: no dynamic indexing
+                if (q == cls && key_less(tau, cr.id, bl.tau[q], bl.id[q])) {
+                  bl.tau[q] = tau;
+                  bl.id[q] = cr.id;
+                  bl.slot[q] = sl;
+                  bl.t[q] = tj;
+                  bl.a[q] = aj;
+                  bl.b[q] = b;
+                  bl.p[q] = cr.p;
+                }
+              }
+            }
+          }
+        }
+        // group minima per lane-class
+        double lim = 0.0;
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+          bool reduced = false;
+          if constexpr (F32 && G == 64 && W::SPL == 1) {
+            // After the filter a lane of the corridor has mostly one candidate
+            // slot or none.  Every other slot's key is above the binary32 upper
+            // bound, which the candidates or the earlier passes' minimum
+            // undercut, so the minimum is the earlier one or that slot's: read
+            // it from its lane instead of reducing over the wavefront.
+            const unsigned long long mq = __ballot((candq[0] >> q) & 1u);
+            if (__popcll(mq) <= 1) {
+              if (mq) {
+                const int l = __ffsll((long long)mq) - 1;
+                const unsigned long long kb = (unsigned long long)__double_as_longlong(bl.tau[q]);
+                const unsigned lo32 = __builtin_amdgcn_readlane((int)(unsigned)kb, l);
+                const unsigned hi32 = __builtin_amdgcn_readlane((int)(unsigned)(kb >> 32), l);
+                const double tl = __longlong_as_double((long long)(((unsigned long long)hi32 << 32) | lo32));
+                const int il = __builtin_amdgcn_readlane(bl.id[q], l);
+                if (key_less(tl, il, gt[q], gi[q])) {
+                  gt[q] = tl;
+                  gi[q] = il;
+                }
+              }
+              reduced = true;
+            }
+          }
+          if (!reduced) {
+            gt[q] = bl.tau[q];
+            gi[q] = bl.id[q];
+            grp_min<G>(gt[q], gi[q]);
+          }
+          const double lq = gt[q] < trem ? gt[q] : trem;
+          lim = lq > lim ? lq : lim;
+        }
+        const int mnext = m0 + W::M;
+        if (mnext > g.mmax) break;
+        const double lb = mnext * g.c - u - g.d - STOP_MARGIN;
+        if (lb > lim) break;
       }
-      pf = false;
-      if (rel_slot >= 0 && !from_pf) {  // the last commit's stores have completed with these loads
+      lane_scanned += scanned;
+      if (rel_slot >= 0) {  // a prefetched first pass: release once the commit's stores completed
         wait_mem();
         if (lane == 0) {
           strict_rel<SC>(lp.strict);
@@ -1212,146 +1422,81 @@ __device__ void chain_events(const Dev &D, const Geo &g, const LegP &lp, int32_t
         }
         rel_slot = -1;
       }
-      bool refine[W::SPL];
-      unsigned candq[W::SPL];  // FP32-mixed: lanes of the corridor a refined slot may undercut (bit q)
-#pragma unroll
-      for (int r = 0; r < W::SPL; ++r) {
-        refine[r] = sls[r] >= 0 && crs[r].id >= 0 && sls[r] != s && sls[r] != xs;
-        candq[r] = 0;
-      }
-      if constexpr (F32) {
-        // binary32 intervals; a lane's upper bound is the smallest upper end
-        // over slots certainly in that lane (and certainly not behind)
-        F32Cand fc[W::SPL];
-        float ub[3] = {INFINITY, INFINITY, INFINITY};
-#pragma unroll
-        for (int r = 0; r < W::SPL; ++r) {
-          fc[r].lo = fc[r].hi = INFINITY;
-          fc[r].cls_mask = 0;
-          fc[r].cls = -1;
-          if (refine[r]) {
-            const float raj = (float)(ajs[r] - scol[r] * g.c), rpj = (float)(crs[r].p - srow[r] * g.c);
-            const int w = lane + r * G;
-            fc[r] = tof_f32(m0 + w / (ROWS * CAP), (w % (ROWS * CAP)) / CAP - 1, rai, rpi, raj, rpj, g);
-            const bool not_behind = (tjs[r] > h) || (t + (double)fc[r].lo >= tjs[r]);
-#pragma unroll
-            for (int q = 0; q < 3; ++q)
-              if (fc[r].cls == q && not_behind && fc[r].hi < ub[q]) ub[q] = fc[r].hi;
-          }
-        }
-#pragma unroll
-        for (int q = 0; q < 3; ++q) {
-          ub[q] = grp_min_f32<G>(ub[q]);
-          const float ex = gt[q] < INFINITY ? (float)gt[q] * (1.f + 1e-6f) + 1e-6f : INFINITY;
-          ub[q] = fminf(ub[q], ex);  // exact minimum of the earlier passes, rounded up
-        }
-#pragma unroll
-        for (int r = 0; r < W::SPL; ++r) {
-          if (refine[r]) {
-            unsigned cm = 0;
-#pragma unroll
-            for (int q = 0; q < 3; ++q)
-              if (((fc[r].cls_mask >> q) & 1) && fc[r].lo <= ub[q]) cm |= 1u << q;
-            candq[r] = cm;
-            refine[r] = cm != 0;
-          }
-        }
-      }
-#pragma unroll
-      for (int r = 0; r < W::SPL; ++r) {
-        if (sls[r] >= 0 && crs[r].id >= 0 && sls[r] != s) ++scanned;
-        if (refine[r]) {
-          const int sl = sls[r];
-          const CstRec cr = crs[r];
-          const double aj = ajs[r], tj = tjs[r];
-          if (F32) ++lane_refined;
-          double b, dp;
-          const double tau = tof(a, p, aj, cr.p, g, b, dp);
-          // a disk that came to rest behind the moving disk before this
-          // attempt began (its stamp <= h) is not ahead of it
-          const bool behind = (t + tau < tj) && (tj <= h);
-          if (tau < INFINITY && !behind) {
-            const int cls = lane_class(dp, g);
-#pragma unroll
-            for (int q = 0; q < 3; ++q) {  // unrolled: no dynamic indexing
-              if (q == cls && key_less(tau, cr.id, bl.tau[q], bl.id[q])) {
-                bl.tau[q] = tau;
-                bl.id[q] = cr.id;
-                bl.slot[q] = sl;
-                bl.t[q] = tj;
-                bl.a[q] = aj;
-                bl.b[q] = b;
-                bl.p[q] = cr.p;
-              }
-            }
-          }
-        }
-      }
-      // group minima per lane-class
-      double lim = 0.0;
+      ab = bcast<G>(ab, 0);
+      if (ab) break;
+
+      // broadcast the records of the minima
 #pragma unroll
       for (int q = 0; q < 3; ++q) {
-        bool reduced = false;
-        if constexpr (F32 && G == 64 && W::SPL == 1) {
-          // After the filter a lane of the corridor has mostly one candidate
-          // slot or none.  Every other slot's key is above the binary32 upper
-          // bound, which the candidates or the earlier passes' minimum
-          // undercut, so the minimum is the earlier one or that slot's: read
-          // it from its lane instead of reducing over the wavefront.
-          const unsigned long long mq = __ballot((candq[0] >> q) & 1u);
-          if (__popcll(mq) <= 1) {
-            if (mq) {
-              const int l = __ffsll((long long)mq) - 1;
-              const unsigned long long kb = (unsigned long long)__double_as_longlong(bl.tau[q]);
-              const unsigned lo32 = __builtin_amdgcn_readlane((int)(unsigned)kb, l);
-              const unsigned hi32 = __builtin_amdgcn_readlane((int)(unsigned)(kb >> 32), l);
-              const double tl = __longlong_as_double((long long)(((unsigned long long)hi32 << 32) | lo32));
-              const int il = __builtin_amdgcn_readlane(bl.id[q], l);
-              if (key_less(tl, il, gt[q], gi[q])) {
-                gt[q] = tl;
-                gi[q] = il;
-              }
-            }
-            reduced = true;
-          }
-        }
-        if (!reduced) {
-          gt[q] = bl.tau[q];
-          gi[q] = bl.id[q];
-          grp_min<G>(gt[q], gi[q]);
-        }
-        const double lq = gt[q] < trem ? gt[q] : trem;
-        lim = lq > lim ? lq : lim;
+        const int own = grp_owner<G>(bl.tau[q] == gt[q] && bl.id[q] == gi[q] && gt[q] < INFINITY);
+        gtj[q] = bcast<G>(bl.t[q], own);
+        gaj[q] = bcast<G>(bl.a[q], own);
+        gbj[q] = bcast<G>(bl.b[q], own);
+        gpj[q] = bcast<G>(bl.p[q], own);
+        gsl[q] = bcast<G>(bl.slot[q], own);
       }
-      const int mnext = m0 + W::M;
-      if (mnext > g.mmax) break;
-      const double lb = mnext * g.c - u - g.d - STOP_MARGIN;
-      if (lb > lim) break;
-    }
-    lane_scanned += scanned;
-    if (rel_slot >= 0) {  // a prefetched first pass: release once the commit's stores completed
-      wait_mem();
-      if (lane == 0) {
-        strict_rel<SC>(lp.strict);
-        __hip_atomic_store(&D.REF[c].ver, rel_ver, __ATOMIC_RELAXED, SC);
-        __hip_atomic_store(&D.TAG[rel_slot], TAG_STATIC, __ATOMIC_RELAXED, SC);  // release
+    } else {
+      // The lane minima are the arrows of G(3): the nearest disk ahead in each
+      // lane at the breakpoint stays the nearest for the whole leg (disks
+      // closer than 2 sigma across v cannot pass each other, Sec. 3.1), and
+      // an arrow whose time of flight was beyond the leg at the breakpoint
+      // stays beyond what is left of it.  Every lane computes all three.
+      if (arr_slot != s) {
+        const int4 ar = D.GARR[s];
+        arr[0] = ar.x;
+        arr[1] = ar.y;
+        arr[2] = ar.z;
+        arr_slot = s;
       }
-      rel_slot = -1;
-    }
-    ab = bcast<G>(ab, 0);
-    if (ab) break;
-
-    // broadcast the records of the minima
-    double gtj[3], gaj[3], gbj[3], gpj[3];
-    int gsl[3];
+      CstRec crs[3];
+      double ajs[3], tjs[3];
 #pragma unroll
-    for (int q = 0; q < 3; ++q) {
-      const int own = grp_owner<G>(bl.tau[q] == gt[q] && bl.id[q] == gi[q] && gt[q] < INFINITY);
-      gtj[q] = bcast<G>(bl.t[q], own);
-      gaj[q] = bcast<G>(bl.a[q], own);
-      gbj[q] = bcast<G>(bl.b[q], own);
-      gpj[q] = bcast<G>(bl.p[q], own);
-      gsl[q] = bcast<G>(bl.slot[q], own);
+      for (int q = 0; q < 3; ++q) {
+        if (pf) {
+          crs[q] = pf_gcr[q];
+          ajs[q] = pf_ga[q];
+          tjs[q] = pf_gt[q];
+        } else if (arr[q] >= 0) {
+          crs[q] = D.CST[arr[q]];
+          ajs[q] = ld_a<SC>(&D.MUT[arr[q]].a);
+          tjs[q] = ld_a<SC>(&D.MUT[arr[q]].t);
+        } else {
+          crs[q].id = -1;
+          crs[q].p = 0.0;
+          ajs[q] = tjs[q] = 0.0;
+        }
+      }
+      pf = false;
+      if (rel_slot >= 0) {  // the last commit's stores have completed with these loads
+        wait_mem();
+        if (lane == 0) {
+          strict_rel<SC>(lp.strict);
+          __hip_atomic_store(&D.REF[c].ver, rel_ver, __ATOMIC_RELAXED, SC);
+          __hip_atomic_store(&D.TAG[rel_slot], TAG_STATIC, __ATOMIC_RELAXED, SC);  // release
+        }
+        rel_slot = -1;
+      }
+      int scanned = 0;
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        gsl[q] = arr[q];
+        gtj[q] = tjs[q];
+        gaj[q] = ajs[q];
+        gpj[q] = crs[q].p;
+        gbj[q] = 0.0;
+        // the disk that stopped at the last lifting sits at contact behind:
+        // skipped as in the scan (its record may predate the commit)
+        if (arr[q] >= 0 && arr[q] != xs && crs[q].id >= 0) {
+          ++scanned;
+          double b, dp;
+          gt[q] = tof(a, p, ajs[q], crs[q].p, g, b, dp);
+          gi[q] = crs[q].id;
+          gbj[q] = b;
+        }
+      }
+      if (lane == 0) lane_scanned += scanned;
+      ab = bcast<G>(ab, 0);
+      if (ab) break;
     }
     // the target: smallest of the three minima (selects, not indexing, keep
     // everything in registers)
@@ -1368,7 +1513,6 @@ __device__ void chain_events(const Dev &D, const Geo &g, const LegP &lp, int32_t
         t_b = gbj[q];
         t_p = gpj[q];
       }
-
     // ---- bounded lag: the next event (a lifting, or the breakpoint) may be
     // committed only if its time is within `window` of the clock H, the
     // smallest next-event time of all chains.  While blocked, the disk
@@ -1515,6 +1659,15 @@ __device__ void chain_events(const Dev &D, const Geo &g, const LegP &lp, int32_t
       }
       yield_slot = -1;
     }
+    // the target's arrows, issued with the claim: if it holds they give the
+    // next scan's records, loaded beside the post-claim reads
+    int nar[3] = {-1, -1, -1};
+    if constexpr (GR) {
+      const int4 ar = D.GARR[ts];
+      nar[0] = ar.x;
+      nar[1] = ar.y;
+      nar[2] = ar.z;
+    }
     int won = 0;
     uint32_t old = TAG_STATIC;
     double aj2 = 0.0, tj2 = 0.0;
@@ -1625,7 +1778,24 @@ __device__ void chain_events(const Dev &D, const Geo &g, const LegP &lp, int32_t
     // the claim holds: load the next scan's first pass beside the post-claim
     // reads (whole wavefronts; with several slots per lane the registers
     // would spill)
-    if constexpr (PREFETCH) {
+    if constexpr (GR) {
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        if (nar[q] >= 0) {
+          pf_gcr[q] = D.CST[nar[q]];
+          pf_ga[q] = ld_a<SC>(&D.MUT[nar[q]].a);
+          pf_gt[q] = ld_a<SC>(&D.MUT[nar[q]].t);
+        } else {
+          pf_gcr[q].id = -1;
+          pf_gcr[q].p = 0.0;
+          pf_ga[q] = pf_gt[q] = 0.0;
+        }
+      }
+      if (lane == 0) {
+        pf_ab = __hip_atomic_load(&D.ctl->abort, __ATOMIC_RELAXED, SC);
+        pf_hclk = ld_a<SC>(&D.ctl->clock);
+      }
+    } else if constexpr (PREFETCH) {
       const int tcell = ts >> 2;
       const int trow = tcell / g.nc, tcol = tcell - trow * g.nc;
       load_pass(0, tcol, trow, pf_crs, pf_a, pf_t, pf_sl, pf_col, pf_row);
@@ -1733,7 +1903,12 @@ __device__ void chain_events(const Dev &D, const Geo &g, const LegP &lp, int32_t
     t_pub = tn;
     retries = 0;
     spins = 0;
-    pf = PREFETCH;
+    pf = PREFETCH || GR;
+    if constexpr (GR) {
+#pragma unroll
+      for (int q = 0; q < 3; ++q) arr[q] = nar[q];
+      arr_slot = ts;
+    }
   }
   // group-wide sum of per-lane scan counts
   long long sc = lane_scanned, rf = lane_refined;
@@ -1773,7 +1948,7 @@ __device__ void chain_events(const Dev &D, const Geo &g, const LegP &lp, int32_t
   }
 }
 
-template <int G, bool F32>
+template <int G, bool F32, bool GR>
 __global__ void __launch_bounds__(256) k_event(Dev D, Geo g, LegP lp, int32_t wait_retries,
                                                long long iter_cap) {
   const int lane = threadIdx.x & (G - 1);
@@ -1795,7 +1970,7 @@ __global__ void __launch_bounds__(256) k_event(Dev D, Geo g, LegP lp, int32_t wa
   if (blockIdx.x == gridDim.x - 1) {  // the clock workgroup (idle without a bounded lag)
     if (lp.window > 0.0) clock_loop(D, iter_cap);
   } else if (c < D.k && !D.ctl->error) {
-    chain_events<G, F32, SCA>(D, g, lp, wait_retries, iter_cap, c, lane);
+    chain_events<G, F32, SCA, GR>(D, g, lp, wait_retries, iter_cap, c, lane);
   }
   __syncthreads();
   if (threadIdx.x == 0) D.TS[2 * blockIdx.x + 1] = __builtin_amdgcn_s_memrealtime();
@@ -2696,6 +2871,8 @@ struct RepIn {
   double window;         // bounded lag between the replica's chains (0: free)
   int32_t features;      // ECMC_FEAT_* bits
   int32_t wait_retries;  // failed claims before a move up to contact
+  int32_t graph;         // 1: candidates from the constraint graph G(3), 0: corridor scan
+  int32_t pad2;
 };
 struct RepOut {          // results of the run
   int32_t status;        // ECMC_OK or the first error
@@ -2728,7 +2905,7 @@ __device__ long long block_sum_ll(long long v) {
 }
 
 // a1 for one replica: local times to zero, home cells, chains attached.
-__device__ __noinline__ void replica_build(const Dev &D, const Geo &g, int dir) {
+__device__ __noinline__ void replica_build(const Dev &D, const Geo &g, int dir, double T, int graph) {
   const int tid = threadIdx.x, nt = blockDim.x;
   const int64_t ncell = (int64_t)g.nc * g.nc;
   for (int64_t i = tid; i < D.n; i += nt) D.STAMP[i] = 0.0;
@@ -2741,6 +2918,8 @@ __device__ __noinline__ void replica_build(const Dev &D, const Geo &g, int dir) 
   for (int64_t sl = tid; sl < ncell * CAP; sl += nt) cellfill_slot(D, g.L, dir, sl);
   __syncthreads();
   for (int c = tid; c < D.k; c += nt) chains_leg_one(D, ncell * CAP, c);
+  if (graph)
+    for (int64_t sl = tid; sl < ncell * CAP; sl += nt) graph_slot(D, g, T, sl);
   __syncthreads();
 }
 
@@ -2749,10 +2928,10 @@ __device__ __noinline__ void replica_build(const Dev &D, const Geo &g, int dir) 
 // Out-of-line copy of a chain's events for the replica workgroups: called,
 // it keeps its own register budget apart from the leg and rollback code
 // around it (inlined there, the kernel runs out of registers).
-template <int G, bool F32, int SC>
+template <int G, bool F32, int SC, bool GR>
 __device__ __noinline__ void chain_events_call(const Dev &D, const Geo &g, const LegP &lp, int32_t wait_retries,
                                                long long iter_cap, int c, int lane) {
-  chain_events<G, F32, SC>(D, g, lp, wait_retries, iter_cap, c, lane);
+  chain_events<G, F32, SC, GR>(D, g, lp, wait_retries, iter_cap, c, lane);
 }
 
 template <int G, bool F32>
@@ -2765,7 +2944,7 @@ __device__ __noinline__ int replica_leg(const RepIn &ri, RepOut *rp, int dir) {
   const double T = ri.T;
   __shared__ int s_i[3];
   __shared__ double s_d[2];
-  replica_build(D, g, dir);
+  replica_build(D, g, dir, T, ri.graph);
   if (D.ctl->error) return D.ctl->error;
   double h = 0.0, last_R = -1.0;
   int stuck = 0;
@@ -2801,7 +2980,10 @@ __device__ __noinline__ int replica_leg(const RepIn &ri, RepOut *rp, int dir) {
         const int c = tg + rot < D.k ? tg + rot : tg + rot - D.k;
         // every chain of the replica runs on this workgroup's compute unit:
         // the shared fields need only workgroup-scope atomics
-        chain_events_call<G, F32, SCW>(D, g, lp, wait_retries, 1ll << 24, c, lane);
+        if (ri.graph)  // the candidates need no binary32 filter: three arrows
+          chain_events_call<G, false, SCW, true>(D, g, lp, wait_retries, 1ll << 24, c, lane);
+        else
+          chain_events_call<G, F32, SCW, false>(D, g, lp, wait_retries, 1ll << 24, c, lane);
       }
     }
     __syncthreads();
@@ -2829,7 +3011,7 @@ __device__ __noinline__ int replica_leg(const RepIn &ri, RepOut *rp, int dir) {
     first = false;
     if (tries > (1ll << 20)) return ECMC_EHANG;
     if (ovf) {  // the undo records do not reach back: the leg in global-time order
-      replica_build(D, g, dir);
+      replica_build(D, g, dir, T, ri.graph);
       if (D.ctl->error) return D.ctl->error;
       lp.h = 0.0;
       global_order_call(D, g, lp);
@@ -2965,6 +3147,7 @@ struct ecmc_ctx {
   int32_t kernel_timing = 0;
   int32_t strict_order = 0;
   int32_t features = ECMC_FEAT_ALL;
+  int32_t graph = 1;          // 1: candidates from the constraint graph G(3), 0: corridor scan
   unsigned resident_nb = 0;   // grid size whose residency was last verified
   int32_t resident_key = 0;   // lanes * 2 + FP32 flag of that check
   int64_t vkind[NVK] = {0, 0, 0, 0, 0};
@@ -3049,6 +3232,7 @@ Layout make_layout(int64_t n, int32_t nc, int32_t kmax, int64_t log_cap) {
       (int64_t)kmax * (int64_t)sizeof(RefRec),  // 31 REF
       (int64_t)kmax * 8,      // 32 NEXT
       S * 8,                  // 33 RES
+      S * 16,                 // 34 GARR
   };
   int64_t o = 0;
   int nsz = (int)(sizeof(sizes) / sizeof(sizes[0]));
@@ -3114,12 +3298,12 @@ int build_cells(ecmc_ctx *ctx, int dir) {
 
 // Every chain's group must be resident at once: a chain that never started
 // would keep its disk tagged active and others would wait on it.
-template <int G, bool F32>
+template <int G, bool F32, bool GR>
 int check_resident(ecmc_ctx *ctx, unsigned nb) {
   int dev = 0, ncu = 0, per_cu = 0;
   HIPCHK(hipGetDevice(&dev));
   HIPCHK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
-  HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_event<G, F32>, 256, 0));
+  HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_event<G, F32, GR>, 256, 0));
   if ((int64_t)per_cu * ncu < (int64_t)nb) {
     ctx->err = "too many chains for one resident launch at this lane count";
     return ECMC_EINVAL;
@@ -3135,33 +3319,44 @@ int launch_event(ecmc_ctx *ctx, LegP lp) {
   const int64_t threads = (int64_t)D.k * G;
   const unsigned nb = blocks_for(threads, 256) + 1u;  // + the clock workgroup
   const bool f32 = (ctx->flags & ECMC_FP32_MIXED) != 0;
+  const bool gr = ctx->graph != 0;  // three arrows per scan: no binary32 filter
   int rc = ECMC_OK;
-  const int32_t key = G * 2 + (f32 ? 1 : 0);
+  const int32_t key = G * 4 + (gr ? 2 : (f32 ? 1 : 0));
   if (ctx->resident_nb != nb || ctx->resident_key != key) {
-    if (f32)
-      rc = G == 64 ? check_resident<64, true>(ctx, nb)
-                   : (G == 32 ? check_resident<32, true>(ctx, nb) : check_resident<16, true>(ctx, nb));
+    if (gr)
+      rc = G == 64 ? check_resident<64, false, true>(ctx, nb)
+                   : (G == 32 ? check_resident<32, false, true>(ctx, nb) : check_resident<16, false, true>(ctx, nb));
+    else if (f32)
+      rc = G == 64 ? check_resident<64, true, false>(ctx, nb)
+                   : (G == 32 ? check_resident<32, true, false>(ctx, nb) : check_resident<16, true, false>(ctx, nb));
     else
-      rc = G == 64 ? check_resident<64, false>(ctx, nb)
-                   : (G == 32 ? check_resident<32, false>(ctx, nb) : check_resident<16, false>(ctx, nb));
+      rc = G == 64 ? check_resident<64, false, false>(ctx, nb)
+                   : (G == 32 ? check_resident<32, false, false>(ctx, nb) : check_resident<16, false, false>(ctx, nb));
     if (rc) return rc;
     ctx->resident_nb = nb;
     ctx->resident_key = key;
   }
-  if (f32) {
+  if (gr) {
     if (G == 64)
-      k_event<64, true><<<nb, 256, 0, ctx->stream>>>(D, ctx->g, lp, ctx->wait_retries, cap);
+      k_event<64, false, true><<<nb, 256, 0, ctx->stream>>>(D, ctx->g, lp, ctx->wait_retries, cap);
     else if (G == 32)
-      k_event<32, true><<<nb, 256, 0, ctx->stream>>>(D, ctx->g, lp, ctx->wait_retries, cap);
+      k_event<32, false, true><<<nb, 256, 0, ctx->stream>>>(D, ctx->g, lp, ctx->wait_retries, cap);
     else
-      k_event<16, true><<<nb, 256, 0, ctx->stream>>>(D, ctx->g, lp, ctx->wait_retries, cap);
+      k_event<16, false, true><<<nb, 256, 0, ctx->stream>>>(D, ctx->g, lp, ctx->wait_retries, cap);
+  } else if (f32) {
+    if (G == 64)
+      k_event<64, true, false><<<nb, 256, 0, ctx->stream>>>(D, ctx->g, lp, ctx->wait_retries, cap);
+    else if (G == 32)
+      k_event<32, true, false><<<nb, 256, 0, ctx->stream>>>(D, ctx->g, lp, ctx->wait_retries, cap);
+    else
+      k_event<16, true, false><<<nb, 256, 0, ctx->stream>>>(D, ctx->g, lp, ctx->wait_retries, cap);
   } else {
     if (G == 64)
-      k_event<64, false><<<nb, 256, 0, ctx->stream>>>(D, ctx->g, lp, ctx->wait_retries, cap);
+      k_event<64, false, false><<<nb, 256, 0, ctx->stream>>>(D, ctx->g, lp, ctx->wait_retries, cap);
     else if (G == 32)
-      k_event<32, false><<<nb, 256, 0, ctx->stream>>>(D, ctx->g, lp, ctx->wait_retries, cap);
+      k_event<32, false, false><<<nb, 256, 0, ctx->stream>>>(D, ctx->g, lp, ctx->wait_retries, cap);
     else
-      k_event<16, false><<<nb, 256, 0, ctx->stream>>>(D, ctx->g, lp, ctx->wait_retries, cap);
+      k_event<16, false, false><<<nb, 256, 0, ctx->stream>>>(D, ctx->g, lp, ctx->wait_retries, cap);
   }
   HIPCHK(hipGetLastError());
   return ECMC_OK;
@@ -3257,10 +3452,19 @@ int set_inject(ecmc_ctx *ctx, int32_t chain, int32_t ev) {
   return ECMC_OK;
 }
 
-int begin_leg(ecmc_ctx *ctx, int dir) {
+int build_graph(ecmc_ctx *ctx, double T) {
+  k_graph<<<blocks_for((int64_t)ctx->g.nc * ctx->g.nc * CAP, 256), 256, 0, ctx->stream>>>(ctx->D, ctx->g, T);
+  HIPCHK(hipGetLastError());
+  return ECMC_OK;
+}
+int begin_leg(ecmc_ctx *ctx, int dir, double T) {
   Dev &D = ctx->D;
   int rc = build_cells(ctx, dir);
   if (rc) return rc;
+  if (ctx->graph) {
+    rc = build_graph(ctx, T);
+    if (rc) return rc;
+  }
   k_chains_leg<<<blocks_for(D.k, 256), 256, 0, ctx->stream>>>(D, (int64_t)ctx->g.nc * ctx->g.nc * CAP);
   HIPCHK(hipGetLastError());
   return ECMC_OK;
@@ -3292,7 +3496,7 @@ int run_leg(ecmc_ctx *ctx, int dir, double T) {
   const int64_t S = (int64_t)ctx->g.nc * ctx->g.nc * CAP;
   int rc = fill<double>(ctx, D.STAMP, 0.0, D.n);  // Alg. 1: local times start at h
   if (rc) return rc;
-  rc = begin_leg(ctx, dir);
+  rc = begin_leg(ctx, dir, T);
   if (rc) return rc;
   rc = fill<unsigned long long>(ctx, D.RES, RES_EMPTY, S);  // no reservations yet
   if (rc) return rc;
@@ -3370,7 +3574,7 @@ int run_leg(ecmc_ctx *ctx, int dir, double T) {
       // the breakpoint, in global-time order
       rc = fill<double>(ctx, D.STAMP, 0.0, D.n);
       if (rc) return rc;
-      rc = begin_leg(ctx, dir);
+      rc = begin_leg(ctx, dir, T);
       if (rc) return rc;
       rc = attempt(ctx, dir, 0.0, T, true, true, 0.0, &v, &ts, &clk, &ovf);
       if (rc) return rc;
@@ -3469,6 +3673,7 @@ int ecmc_init(ecmc_ctx **out, const double *positions_xy, int64_t n, double sigm
   D.TS = (unsigned long long *)(b + Lo.off[9]);
   D.REF = (RefRec *)(b + Lo.off[31]);
   D.RES = (unsigned long long *)(b + Lo.off[33]);
+  D.GARR = (int4 *)(b + Lo.off[34]);
   D.n = n;
   D.k = 0;
   D.log_cap = log_cap;
@@ -3791,9 +3996,41 @@ int ecmc_set_option(ecmc_ctx *ctx, int32_t key, int64_t value) {
       if (value < -1 || value > (1 << 30)) return ECMC_EINVAL;
       ctx->inject_event = (int32_t)value;
       return set_inject(ctx, ctx->inject_chain, ctx->inject_event);
+    case ECMC_OPT_NEIGHBOURS:
+      if (value != ECMC_NEIGHBOURS_CELLS && value != ECMC_NEIGHBOURS_GRAPH) return ECMC_EINVAL;
+      ctx->graph = value == ECMC_NEIGHBOURS_GRAPH ? 1 : 0;
+      return ECMC_OK;
     default:
       return ECMC_EINVAL;
   }
+}
+
+int ecmc_graph(ecmc_ctx *ctx, int32_t direction, double horizon, int32_t *arrows) {
+  if (!ctx || !arrows) return ECMC_EINVAL;
+  const Geo &g = ctx->g;
+  if (direction < 0 || direction > 3 || !(horizon > 0.0) || !(horizon <= g.L - 4.0 * g.c - g.d)) {
+    ctx->err = "graph: direction must be 0..3 and 0 < horizon <= box - 4 cell - 2 sigma";
+    return ECMC_EINVAL;
+  }
+  Dev &D = ctx->D;
+  int rc = build_cells(ctx, direction);
+  if (rc) return rc;
+  Ctl h;
+  rc = read_ctl(ctx, &h);
+  if (rc) return rc;
+  if (h.error) {
+    ctx->err = "a cell received more than 4 disks";
+    return h.error;
+  }
+  rc = build_graph(ctx, horizon);
+  if (rc) return rc;
+  Layout Lo = make_layout(D.n, ctx->g.nc, ctx->kmax, ctx->log_cap);
+  int32_t *stage = (int32_t *)((char *)D.X - Lo.off[0] + Lo.off[23]);  // n x 16 B, 12 B used
+  k_graph_ids<<<blocks_for(D.n, 256), 256, 0, ctx->stream>>>(D, stage);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipMemcpyAsync(arrows, stage, sizeof(int32_t) * 3 * (size_t)D.n, hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  return ECMC_OK;
 }
 
 const char *ecmc_last_error(const ecmc_ctx *ctx) { return ctx ? ctx->err : "null context"; }
@@ -3836,6 +4073,7 @@ struct ecmc_batch {
   int32_t features = ECMC_FEAT_ALL;
   int32_t wait_retries = 64;
   int32_t max_splits = 1;
+  int32_t graph = 1;        // 1: candidates from the constraint graph G(3), 0: corridor scan
   hipGraphExec_t exec = nullptr;
   int32_t exec_grid = 0, last_grid = 0;
   hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -3983,6 +4221,7 @@ int batch_once(ecmc_batch *b, const int64_t *target, const double *leg_T, int32_
     R.window = b->window_micro * 1e-6 * ctx->g.sigma;
     R.features = b->features;
     R.wait_retries = b->wait_retries;
+    R.graph = b->graph;
   }
   // longest expected run first, so that no long replica starts last: the
   // remaining liftings times the measured device time per lifting, or per
@@ -4077,7 +4316,7 @@ std::string batch_signature(const ecmc_batch *b, const double *leg_T, int32_t di
     h = fnv1a(h, &ctx->g.sigma, sizeof(double));
     h = fnv1a(h, &leg_T[r], sizeof(double));
   }
-  const int32_t settings[5] = {direction, b->features, b->wait_retries, b->max_splits, b->use_graph};
+  const int32_t settings[6] = {direction, b->features, b->wait_retries, b->max_splits, b->use_graph, b->graph};
   h = fnv1a(h, settings, sizeof(settings));
   h = fnv1a(h, &b->window_micro, sizeof(double));
   char buf[24];
@@ -4210,6 +4449,10 @@ int ecmc_batch_set_option(ecmc_batch *b, int32_t key, int64_t value) {
     case ECMC_OPT_MAX_SPLITS:
       if (value < 0 || value > 64) return ECMC_EINVAL;
       b->max_splits = (int32_t)value;
+      return ECMC_OK;
+    case ECMC_OPT_NEIGHBOURS:
+      if (value != ECMC_NEIGHBOURS_CELLS && value != ECMC_NEIGHBOURS_GRAPH) return ECMC_EINVAL;
+      b->graph = value == ECMC_NEIGHBOURS_GRAPH ? 1 : 0;
       return ECMC_OK;
     default:
       return ECMC_EINVAL;

@@ -59,9 +59,10 @@ def _check(e, ref, k, tag):
     return st
 
 
-@pytest.mark.parametrize("lanes,graph,cell_pct", [(4, 0, 100), (8, 1, 115), (16, 0, 130), (16, 1, 141),
-                                                  (32, 1, 100)])
-def test_batch_parity(lanes, graph, cell_pct):
+@pytest.mark.parametrize("lanes,graph,cell_pct,neighbours", [
+    (4, 0, 100, pkg.NEIGHBOURS_CELLS), (8, 1, 115, pkg.NEIGHBOURS_GRAPH), (16, 0, 130, pkg.NEIGHBOURS_CELLS),
+    (16, 1, 141, pkg.NEIGHBOURS_GRAPH), (32, 1, 100, pkg.NEIGHBOURS_CELLS)])
+def test_batch_parity(lanes, graph, cell_pct, neighbours):
     """Lane caps (each replica takes the largest lane count up to the cap that
     fits its chains in the workgroup) and home-cell widths change the layout
     and the schedule only."""
@@ -71,6 +72,7 @@ def test_batch_parity(lanes, graph, cell_pct):
     b.set_option(pkg.OPT_LANES, lanes)
     b.set_option(pkg.OPT_CELL_PCT, cell_pct)
     b.set_option(pkg.OPT_GRAPH, graph)
+    b.set_option(pkg.OPT_NEIGHBOURS, neighbours)
     legs = 3
     big = np.full(len(reps), 1 << 60, np.int64)
     b.run(big, [r[4] for r in reps], pkg.DIR_ALTERNATE, max_legs=legs)
@@ -99,6 +101,8 @@ def test_batch_bounded_lag_parity(window_micro, lanes, flags):
     b.set_option(pkg.OPT_CELL_PCT, 100)
     b.set_option(pkg.OPT_GRAPH, 1)
     b.set_option(pkg.OPT_WINDOW_MICRO, window_micro)
+    # the FP32-mixed form on the corridor scan, where its binary32 filter acts
+    b.set_option(pkg.OPT_NEIGHBOURS, pkg.NEIGHBOURS_CELLS if flags == pkg.FP32_MIXED else pkg.NEIGHBOURS_GRAPH)
     big = np.full(len(reps), 1 << 60, np.int64)
     b.run(big, [r[4] for r in reps], pkg.DIR_ALTERNATE, max_legs=3)
     for i, ((x, y, L, act, T), e) in enumerate(zip(reps, systems)):

@@ -32,9 +32,15 @@ def _wrapdiff(a, b, L):
 
 def gpu_run(x, y, L, act, dirs, T, lanes=64, flags=pkg.FP64, log_cap=1 << 15, opts=(),
             sigma=1.0, cells=0):
+    """Run legs on the GPU.  The FP64 form takes its candidates from the
+    constraint graph (the default); the FP32-mixed form runs on the corridor
+    scan, where its binary32 filter acts (graph candidates are binary64 in
+    either form).  `opts` may override both."""
     e = pkg.Ecmc(np.stack([x, y], 1), sigma, L, cells=cells, flags=flags,
                  max_chains=len(act), log_cap=log_cap)
     e.set_option(pkg.OPT_LANES, lanes)
+    if flags == pkg.FP32_MIXED:
+        e.set_option(pkg.OPT_NEIGHBOURS, pkg.NEIGHBOURS_CELLS)
     for key, val in opts:
         e.set_option(key, val)
     e.set_active(act)
