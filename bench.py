@@ -486,24 +486,44 @@ def run_batch(n_rep, target, t_frac, graph=1, window_micro=0, max_splits=0):
     return out
 
 
-def profile_run(legs, lanes, window_micro, form):
-    """Short run for hardware-counter collection: a few legs of the workload
-    after the burn-in, then a device copy of 256 MiB (read 256 MiB, write
-    256 MiB) whose counter readings calibrate the bytes the counters report."""
+def save_state(path, lanes, window_micro):
+    """Burn the headline workload in (>= 10 liftings per disk) and save the
+    configuration, so that a profiled process can start from it and count
+    only the legs it measures."""
+    import numpy as np
+
+    import workloads as W
+    s = W.config(4)
+    e = _make(s, "fp64", lanes, window_micro)
+    legs = burn_in(e, s)
+    np.savez(path, x=e.positions()[:, 0], y=e.positions()[:, 1], active=e.active(), legs=legs,
+             liftings=e.stats()["events"])
+    log(f"saved the state after {legs} burn-in legs to {path}")
+
+
+def profile_run(legs, lanes, window_micro, form, state=None):
+    """Short run for hardware counters and kernel traces: `legs` legs of the
+    headline workload (from a state saved by --save-state, else from the
+    lattice), then a device copy of 256 MiB (read 256 MiB, write 256 MiB)
+    whose counter readings calibrate the bytes the counters report."""
+    import numpy as np
     import torch
 
     import workloads as W
     s = W.config(4)
+    if state:  # saved after an even number of legs: the next one is +x
+        z = np.load(state)
+        s.x, s.y, s.active = z["x"], z["y"], z["active"].astype(np.int32)
+        assert int(z["legs"]) % 2 == 0
     e = _make(s, form, lanes, window_micro)
-    burn_in(e, s)
     st0 = e.stats()
     e.run(legs * s.T, s.T, 4)
     d = _stats_delta(st0, e.stats())
     print(json.dumps({"profile_run": True, "form": form, "lanes": lanes, "legs": legs,
+                      "neighbours": _neighbours, "from_state": bool(state),
                       "events": d["events"], "attempts": d["attempts"],
                       "event_launches": d["event_launches"], "timed_events": d["timed_events"],
-                      "slots_scanned": d["slots_scanned"], "burn_in_launches": st0["event_launches"]}),
-          flush=True)
+                      "slots_scanned": d["slots_scanned"]}), flush=True)
     a = torch.ones(256 << 20, dtype=torch.uint8, device="cuda")
     b = torch.empty_like(a)
     torch.cuda.synchronize()
@@ -544,22 +564,20 @@ def pmc_summary(fetch_csv, write_csv, profile_log, extra_csvs=()):
                    if "copy" in n.lower() or "elementwise" in n.lower())
 
     fe, wr = event_vals(fetch_csv, "FETCH_SIZE"), event_vals(write_csv, "WRITE_SIZE")
-    # dispatches of the profiled legs: those after the burn-in's dispatches
-    n_burn = run.get("burn_in_dispatches")
     cp_f, cp_w = copy_val(fetch_csv, "FETCH_SIZE"), copy_val(write_csv, "WRITE_SIZE")
     f_cal = copy_bytes / (cp_f * 1024.0)  # counters are in KiB
     w_cal = copy_bytes / (cp_w * 1024.0)
     launches = max(run["event_launches"], 1)
     events_per_launch = run["timed_events"] / launches
-    # the burn-in's dispatches come first; the profiled legs' dispatches are the
-    # tail whose count matches the launches that ran plus the at-once returns
-    tail_f = fe[-run["event_launches"] * 3:] if n_burn is None else fe[n_burn:]
-    tail_w = wr[-run["event_launches"] * 3:] if n_burn is None else wr[n_burn:]
+    # every event-kernel dispatch of the process belongs to the profiled legs
+    # (rounds enqueued past the end of a leg return at once and add little)
+    tail_f, tail_w = fe, wr
     total = sum(v for _, v in tail_f) * 1024.0 * f_cal + sum(v for _, v in tail_w) * 1024.0 * w_cal
     per_launch = total / launches
     form = run.get("form", "fp64")
-    d = {"source_sha256_16": _src_hash(), "form": form,
-         "kernel": f"k_event<{run.get('lanes', 64)}, {'true' if form == 'fp32' else 'false'}>",
+    d = {"source_sha256_16": _src_hash(), "form": form, "neighbours": run.get("neighbours"),
+         "from_state": run.get("from_state"),
+         "kernel": f"k_event<{run.get('lanes', 64)}, {form}, {run.get('neighbours')}>",
          "dispatches_counted": len(tail_f), "copy_fetch_kib": cp_f, "copy_write_kib": cp_w,
          "fetch_calibration": f_cal, "write_calibration": w_cal,
          "launches_that_ran": run["event_launches"], "liftings": run["timed_events"],
@@ -581,7 +599,9 @@ def pmc_summary(fetch_csv, write_csv, profile_log, extra_csvs=()):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--profile-run", type=int, default=0, metavar="LEGS",
-                    help="only burn in, run LEGS legs and a 256 MiB copy (for rocprofv3 counters)")
+                    help="only run LEGS legs and a 256 MiB copy (for rocprofv3 counters and traces)")
+    ap.add_argument("--save-state", metavar="NPZ", help="burn the headline workload in and save it")
+    ap.add_argument("--load-state", metavar="NPZ", help="--profile-run starts from a saved state")
     ap.add_argument("--pmc-summary", nargs="+", metavar="CSV",
                     help="FETCH_CSV WRITE_CSV PROFILE_LOG [EXTRA_CSV ...]: write the counter summary")
     ap.add_argument("--gpus", type=int, default=1)
@@ -591,7 +611,7 @@ def main():
     ap.add_argument("--lanes", type=int, default=64)
     ap.add_argument("--max-splits", type=int, default=0,
                     help="rollbacks without progress before a lockstep stretch (0: library default)")
-    ap.add_argument("--window-micro", type=int, default=160_000,
+    ap.add_argument("--window-micro", type=int, default=250_000,
                     help="bounded lag between chains, in 1e-6 sigma (0: free running)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--cpu-batch-events", type=int, default=20_000,
@@ -620,11 +640,14 @@ def main():
         print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
-    if args.profile_run:
+    if args.save_state or args.profile_run:
         import torch
         assert torch.cuda.is_available(), "bench.py needs a GPU"
-        profile_run(args.profile_run, args.lanes, args.window_micro,
-                    "fp64" if args.form == "fp64" else "fp32")
+        if args.save_state:
+            save_state(args.save_state, args.lanes, args.window_micro)
+        else:
+            profile_run(args.profile_run, args.lanes, args.window_micro,
+                        "fp64" if args.form == "fp64" else "fp32", args.load_state)
         return
 
     # the oracle first: its process pool forks from a process that has not used the GPU

@@ -434,11 +434,12 @@ __global__ void k_chains_attempt(Dev D, double h) {
 // from the home-cell records at the breakpoint; arrows whose time of flight is
 // T or more are left out (no chain can reach them within the leg).  Columns
 // are walked forward as in the corridor scan until no further column can
-// undercut any lane's minimum.
+// undercut any lane's minimum; a column's 12 slots are loaded at once.  Only
+// occupied slots get arrows (empty slots never hold a moving disk).
 __device__ void graph_slot(const Dev &D, const Geo &g, double T, int64_t s) {
   int4 out = make_int4(-1, -1, -1, -1);
   const CstRec cs = D.CST[s];
-  if (cs.id >= 0) {
+  {
     const double a = D.MUT[s].a, p = cs.p;
     const int cell0 = (int)(s >> 2);
     const int row0 = cell0 / g.nc, col0 = cell0 - row0 * g.nc;
@@ -459,41 +460,60 @@ __device__ void graph_slot(const Dev &D, const Geo &g, double T, int64_t s) {
       }
       int col = col0 + m;
       if (col >= g.nc) col -= g.nc;
-      for (int dr = -1; dr <= 1; ++dr) {
-        int row = row0 + dr;
+      CstRec cj[ROWS * CAP];
+      double aj[ROWS * CAP];
+      int sls[ROWS * CAP];
+#pragma unroll
+      for (int dr = 0; dr < ROWS; ++dr) {
+        int row = row0 + dr - 1;
         row = row < 0 ? row + g.nc : (row >= g.nc ? row - g.nc : row);
+#pragma unroll
         for (int q4 = 0; q4 < CAP; ++q4) {
           const int sl = ((row * g.nc + col) << 2) + q4;
-          if (sl == (int)s) continue;
-          const CstRec cj = D.CST[sl];
-          if (cj.id < 0) continue;
-          double b, dp;
-          const double tau = tof(a, p, D.MUT[sl].a, cj.p, g, b, dp);
-          if (!(tau < T)) continue;
-          const int cls = lane_class(dp, g);
-#pragma unroll
-          for (int q = 0; q < 3; ++q)
-            if (q == cls && key_less(tau, cj.id, bt[q], bid[q])) {
-              bt[q] = tau;
-              bid[q] = cj.id;
-              bsl[q] = sl;
-            }
+          sls[dr * CAP + q4] = sl;
+          cj[dr * CAP + q4] = D.CST[sl];
+          aj[dr * CAP + q4] = D.MUT[sl].a;
         }
+      }
+#pragma unroll
+      for (int r = 0; r < ROWS * CAP; ++r) {
+        if (sls[r] == (int)s || cj[r].id < 0) continue;
+        double b, dp;
+        const double tau = tof(a, p, aj[r], cj[r].p, g, b, dp);
+        if (!(tau < T)) continue;
+        const int cls = lane_class(dp, g);
+#pragma unroll
+        for (int q = 0; q < 3; ++q)
+          if (q == cls && key_less(tau, cj[r].id, bt[q], bid[q])) {
+            bt[q] = tau;
+            bid[q] = cj[r].id;
+            bsl[q] = sls[r];
+          }
       }
     }
     out = make_int4(bsl[0], bsl[1], bsl[2], -1);
   }
   D.GARR[s] = out;
 }
-__global__ void k_graph(Dev D, Geo g, double T) {
-  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (s < (int64_t)g.nc * g.nc * CAP) graph_slot(D, g, T, s);
+// the slot of disk i from the home-cell build, or -1 if the build did not
+// place it (a cell overflowed: the build's error stops the leg)
+__device__ __forceinline__ int64_t placed_slot(const Dev &D, const Geo &g, int64_t i) {
+  const int64_t s = D.SLOT_OF[i];
+  return (s >= 0 && s < (int64_t)g.nc * g.nc * CAP && D.CST[s].id == (int32_t)i) ? s : -1;
 }
-// arrows as disk ids, in disk order: out[3 i + q] (-1: none)
-__global__ void k_graph_ids(Dev D, int32_t *out) {
+// one thread per disk
+__global__ void k_graph(Dev D, Geo g, double T) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= D.n) return;
-  const int4 ar = D.GARR[D.SLOT_OF[i]];
+  const int64_t s = placed_slot(D, g, i);
+  if (s >= 0) graph_slot(D, g, T, s);
+}
+// arrows as disk ids, in disk order: out[3 i + q] (-1: none)
+__global__ void k_graph_ids(Dev D, Geo g, int32_t *out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= D.n) return;
+  const int64_t s = placed_slot(D, g, i);
+  const int4 ar = s >= 0 ? D.GARR[s] : make_int4(-1, -1, -1, -1);
   out[3 * i] = ar.x >= 0 ? D.CST[ar.x].id : -1;
   out[3 * i + 1] = ar.y >= 0 ? D.CST[ar.y].id : -1;
   out[3 * i + 2] = ar.z >= 0 ? D.CST[ar.z].id : -1;
@@ -2918,8 +2938,13 @@ __device__ __noinline__ void replica_build(const Dev &D, const Geo &g, int dir, 
   for (int64_t sl = tid; sl < ncell * CAP; sl += nt) cellfill_slot(D, g.L, dir, sl);
   __syncthreads();
   for (int c = tid; c < D.k; c += nt) chains_leg_one(D, ncell * CAP, c);
-  if (graph)
-    for (int64_t sl = tid; sl < ncell * CAP; sl += nt) graph_slot(D, g, T, sl);
+  if (graph) {
+    __syncthreads();  // SLOT_OF of every disk is set by the cell fill
+    for (int64_t i = tid; i < D.n; i += nt) {
+      const int64_t s = placed_slot(D, g, i);
+      if (s >= 0) graph_slot(D, g, T, s);
+    }
+  }
   __syncthreads();
 }
 
@@ -3453,7 +3478,7 @@ int set_inject(ecmc_ctx *ctx, int32_t chain, int32_t ev) {
 }
 
 int build_graph(ecmc_ctx *ctx, double T) {
-  k_graph<<<blocks_for((int64_t)ctx->g.nc * ctx->g.nc * CAP, 256), 256, 0, ctx->stream>>>(ctx->D, ctx->g, T);
+  k_graph<<<blocks_for(ctx->D.n, 256), 256, 0, ctx->stream>>>(ctx->D, ctx->g, T);
   HIPCHK(hipGetLastError());
   return ECMC_OK;
 }
@@ -4026,7 +4051,7 @@ int ecmc_graph(ecmc_ctx *ctx, int32_t direction, double horizon, int32_t *arrows
   if (rc) return rc;
   Layout Lo = make_layout(D.n, ctx->g.nc, ctx->kmax, ctx->log_cap);
   int32_t *stage = (int32_t *)((char *)D.X - Lo.off[0] + Lo.off[23]);  // n x 16 B, 12 B used
-  k_graph_ids<<<blocks_for(D.n, 256), 256, 0, ctx->stream>>>(D, stage);
+  k_graph_ids<<<blocks_for(D.n, 256), 256, 0, ctx->stream>>>(D, ctx->g, stage);
   HIPCHK(hipGetLastError());
   HIPCHK(hipMemcpyAsync(arrows, stage, sizeof(int32_t) * 3 * (size_t)D.n, hipMemcpyDeviceToHost, ctx->stream));
   HIPCHK(hipStreamSynchronize(ctx->stream));
