@@ -32,7 +32,7 @@ FEAT_SCREEN, FEAT_RESERVE, FEAT_REREAD, FEAT_FRESH, FEAT_ALL = 1, 2, 4, 8, 15
 DIR_X, DIR_Y, DIR_MX, DIR_MY, DIR_ALTERNATE = 0, 1, 2, 3, 4
 
 # every symbol include/ecmc_probe.h declares (libecmc_probe.so)
-PROBE_EXPORTS = ("ecmc_probe_chase", "ecmc_probe_gather")
+PROBE_EXPORTS = ("ecmc_probe_chase", "ecmc_probe_gather", "ecmc_probe_litmus_mp", "ecmc_probe_litmus_cas")
 
 # every symbol include/ecmc.h declares
 EXPORTS = (
@@ -181,6 +181,10 @@ def load_probe_library(path: str = PROBE_LIB_PATH):
     lib.ecmc_probe_chase.argtypes = [P, I64, I64, I32, P, ctypes.POINTER(ctypes.c_double)]
     lib.ecmc_probe_gather.restype = ctypes.c_int
     lib.ecmc_probe_gather.argtypes = [P, I64, I32, I32, I32, P, ctypes.POINTER(ctypes.c_double)]
+    lib.ecmc_probe_litmus_mp.restype = ctypes.c_int
+    lib.ecmc_probe_litmus_mp.argtypes = [P, P, I32, I32, I32, I32, P, ctypes.POINTER(I64), ctypes.POINTER(I64)]
+    lib.ecmc_probe_litmus_cas.restype = ctypes.c_int
+    lib.ecmc_probe_litmus_cas.argtypes = [P, P, I32, I32, I32, I32, P, ctypes.POINTER(I64)]
     _probe_lib = lib
     return lib
 
@@ -211,6 +215,37 @@ def probe_gather(lines, blocks, loads_per_thread, scope=1) -> float:
     if rc:
         raise EcmcError(rc, "ecmc_probe_gather failed")
     return out.value
+
+
+def litmus_mp(pairs, iters, spin, waits=True):
+    """Message-passing litmus test; returns (seen, stale)."""
+    import torch
+    lib = load_probe_library()
+    data = torch.zeros(pairs * 64 * iters, dtype=torch.int32, device="cuda")
+    flag = torch.zeros_like(data)
+    seen, stale = ctypes.c_int64(0), ctypes.c_int64(0)
+    rc = lib.ecmc_probe_litmus_mp(ctypes.c_void_p(data.data_ptr()), ctypes.c_void_p(flag.data_ptr()), int(pairs),
+                                  int(iters), int(spin), int(bool(waits)),
+                                  ctypes.c_void_p(torch.cuda.current_stream().cuda_stream),
+                                  ctypes.byref(seen), ctypes.byref(stale))
+    if rc:
+        raise EcmcError(rc, "ecmc_probe_litmus_mp failed")
+    return seen.value, stale.value
+
+
+def litmus_cas(locs, blocks, rounds, tries):
+    """Compare-and-swap exclusivity litmus test; returns (acquired, counter sum)."""
+    import torch
+    lib = load_probe_library()
+    tag = torch.zeros(locs, dtype=torch.int32, device="cuda")
+    counter = torch.zeros_like(tag)
+    acquired = ctypes.c_int64(0)
+    rc = lib.ecmc_probe_litmus_cas(ctypes.c_void_p(tag.data_ptr()), ctypes.c_void_p(counter.data_ptr()), int(locs),
+                                   int(blocks), int(rounds), int(tries),
+                                   ctypes.c_void_p(torch.cuda.current_stream().cuda_stream), ctypes.byref(acquired))
+    if rc:
+        raise EcmcError(rc, "ecmc_probe_litmus_cas failed")
+    return acquired.value, int(counter.to(torch.int64).sum().item()), int(tag.abs().sum().item())
 
 
 def workspace_bytes(n, sigma, box, cells=0, max_chains=1, log_cap=1, flags=FP64) -> int:

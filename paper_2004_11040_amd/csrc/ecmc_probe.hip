@@ -1,7 +1,8 @@
 // ecmc_probe.hip -- memory microbenchmarks behind include/ecmc_probe.h: the
 // dependent-load latency and the random-line gather bandwidth that bound the
 // event kernel (latency: Little's law over k chains; bandwidth: line-granular
-// bytes per lifting).
+// bytes per lifting), and two litmus tests of the ordering discipline the
+// kernel relies on.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -60,7 +61,113 @@ __global__ void __launch_bounds__(256) k_gather(const uint64_t *lines, uint64_t 
   if (acc == 0x5bd1e995ull) probe_out[2] = acc;  // practically never taken; keeps the loads
 }
 
+// ---- litmus tests: the event kernel's discipline (relaxed agent-scope
+// atomics, order between locations from completion waits)
+__device__ __forceinline__ void lit_st(uint32_t *p, uint32_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint32_t lit_ld(uint32_t *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void lit_wait() { __builtin_amdgcn_s_waitcnt(0x0F70); }  // vmcnt(0)
+
+template <bool WAIT>
+__global__ void __launch_bounds__(64) k_litmus_mp(uint32_t *data, uint32_t *flag, int iters, int spin) {
+  const int pair = blockIdx.x >> 1, role = blockIdx.x & 1;
+  const int64_t base = ((int64_t)pair * 64 + threadIdx.x) * iters;
+  unsigned long long seen = 0, stale = 0;
+  for (int it = 0; it < iters; ++it) {
+    const int64_t k = base + it;
+    const uint32_t v = (uint32_t)it + 1u;
+    if (role == 0) {
+      lit_st(&data[k], v);
+      if (WAIT) lit_wait();
+      lit_st(&flag[k], v);
+    } else {
+      uint32_t f = 0;
+      for (int s = 0; s < spin && f != v; ++s) f = lit_ld(&flag[k]);
+      if (f == v) {
+        ++seen;
+        if (lit_ld(&data[k]) != v) ++stale;
+      }
+    }
+  }
+  if (role == 1) {
+    atomicAdd(&probe_out[0], seen);
+    atomicAdd(&probe_out[1], stale);
+  }
+}
+
+__global__ void __launch_bounds__(256) k_litmus_cas(uint32_t *tag, uint32_t *counter, int locs, int rounds,
+                                                    int tries) {
+  const uint64_t tid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const uint32_t me = (uint32_t)tid + 1u;
+  unsigned long long got = 0;
+  for (int r = 0; r < rounds; ++r) {
+    const int l = (int)(mix64(tid * 0x9e3779b97f4a7c15ull + (uint64_t)r) % (uint64_t)locs);
+    bool done = false;
+    for (int t = 0; t < tries && !done; ++t) {
+      uint32_t old = 0u;
+      if (__hip_atomic_compare_exchange_strong(&tag[l], &old, me, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_AGENT)) {
+        lit_wait();  // the claim completes before the reads that depend on it
+        const uint32_t v = lit_ld(&counter[l]);
+        lit_st(&counter[l], v + 1u);
+        lit_wait();  // the data store completes before the release
+        lit_st(&tag[l], 0u);
+        done = true;
+      }
+    }
+    if (done) ++got;
+  }
+  atomicAdd(&probe_out[2], got);
+}
+
 }  // namespace
+
+extern "C" int ecmc_probe_litmus_mp(void *data, void *flag, int32_t pairs, int32_t iters, int32_t spin,
+                                    int32_t waits, void *stream, int64_t *seen, int64_t *stale) {
+  if (!data || !flag || pairs < 1 || pairs > 4096 || iters < 1 || iters > 4096 || spin < 1 || spin > 4096 ||
+      !seen || !stale)
+    return -1;
+  hipStream_t st = (hipStream_t)stream;
+  unsigned long long zero[3] = {0, 0, 0};
+  if (hipMemcpyToSymbolAsync(HIP_SYMBOL(probe_out), zero, sizeof(zero), 0, hipMemcpyHostToDevice, st) !=
+      hipSuccess)
+    return -3;
+  if (waits)
+    k_litmus_mp<true><<<2 * pairs, 64, 0, st>>>((uint32_t *)data, (uint32_t *)flag, iters, spin);
+  else
+    k_litmus_mp<false><<<2 * pairs, 64, 0, st>>>((uint32_t *)data, (uint32_t *)flag, iters, spin);
+  if (hipGetLastError() != hipSuccess) return -3;
+  unsigned long long out[3] = {0, 0, 0};
+  if (hipMemcpyFromSymbolAsync(out, HIP_SYMBOL(probe_out), sizeof(out), 0, hipMemcpyDeviceToHost, st) != hipSuccess)
+    return -3;
+  if (hipStreamSynchronize(st) != hipSuccess) return -3;
+  *seen = (int64_t)out[0];
+  *stale = (int64_t)out[1];
+  return 0;
+}
+
+extern "C" int ecmc_probe_litmus_cas(void *tag, void *counter, int32_t locs, int32_t blocks, int32_t rounds,
+                                     int32_t tries, void *stream, int64_t *acquired) {
+  if (!tag || !counter || locs < 1 || locs > (1 << 20) || blocks < 1 || blocks > 4096 || rounds < 1 ||
+      rounds > 4096 || tries < 1 || tries > 4096 || !acquired)
+    return -1;
+  hipStream_t st = (hipStream_t)stream;
+  unsigned long long zero[3] = {0, 0, 0};
+  if (hipMemcpyToSymbolAsync(HIP_SYMBOL(probe_out), zero, sizeof(zero), 0, hipMemcpyHostToDevice, st) !=
+      hipSuccess)
+    return -3;
+  k_litmus_cas<<<blocks, 256, 0, st>>>((uint32_t *)tag, (uint32_t *)counter, locs, rounds, tries);
+  if (hipGetLastError() != hipSuccess) return -3;
+  unsigned long long out[3] = {0, 0, 0};
+  if (hipMemcpyFromSymbolAsync(out, HIP_SYMBOL(probe_out), sizeof(out), 0, hipMemcpyDeviceToHost, st) != hipSuccess)
+    return -3;
+  if (hipStreamSynchronize(st) != hipSuccess) return -3;
+  *acquired = (int64_t)out[2];
+  return 0;
+}
 
 extern "C" int ecmc_probe_chase(const void *lines, int64_t n_lines, int64_t hops, int32_t scope,
                                 void *stream, double *ns_per_hop) {

@@ -135,3 +135,45 @@ def test_fp32_filter_interval_contains_binary64(mode, nudge):
     sure = inside & (cls >= 0)
     assert np.array_equal(cls[sure], lane[sure])
     assert np.all((mask[inside] >> lane[inside]) & 1)
+
+
+@pytest.mark.parametrize("nudge", [-1, 0, 1])
+def test_fp32_filter_with_disks_moved_past_their_home_cells(nudge):
+    """During a leg the records keep their home slots while the disks move on:
+    the kernel passes raj = a_j - (home column of j) c with a_j the current
+    position (up to T past the home column, wrapping past L, so raj ranges
+    over (-L, c + T)), and u = a_i - (home column of i) c for the moving
+    disk's reference, up to c + T.  The interval must still hold the binary64
+    time of flight computed from the absolute positions."""
+    rng = np.random.Generator(np.random.PCG64(9500 + nudge))
+    k = _cases(rng, 300_000, "random")
+    m = k["keep"]
+    k = {key: v[m] for key, v in k.items() if key != "keep"}
+    c, L = k["c"], k["L"]
+    T = np.minimum(L - 4.0 * c - 2.0, 40.0) * rng.uniform(0.0, 1.0, c.shape[0])
+    ok = T > 0
+    k = {key: v[ok] for key, v in k.items()}
+    c, L, T = k["c"], k["L"], T[ok]
+    n = c.shape[0]
+    # both disks advance along v; the records stay in their home slots
+    k["ai"] = np.mod(k["ai"] + rng.uniform(0.0, 1.0, n) * T, L)
+    k["aj"] = np.mod(k["aj"] + rng.uniform(0.0, 1.0, n) * T, L)
+    col0, row0 = k["col0"], k["row0"]
+    u = k["ai"] - col0 * c
+    u = np.where(u < 0, u + L, u)
+    rai = u.astype(F)
+    rpi = (k["pi"] - row0 * c).astype(F)
+    raj = (k["aj"] - k["colj"] * c).astype(F)
+    rpj = (k["pj"] - k["rowj"] * c).astype(F)
+    assert (raj < 0).any() and (u > 2 * c).any()   # the ranges this test is about do occur
+    lo, hi, cls, mask = _filter(k["mc"], k["dr"], rai, rpi, raj, rpj, c.astype(F), L.astype(F),
+                                F(4.0), F(1.0), nudge)
+    tau, lane, inside = _tau64(k)
+    assert inside.sum() > 1000
+    assert np.all(lo[inside] < np.inf)
+    ti, li, hi_i = tau[inside], lo[inside].astype(np.float64), hi[inside].astype(np.float64)
+    assert not (li > ti).any(), (ti[li > ti][:5], li[li > ti][:5])
+    assert not (hi_i < ti).any(), (ti[hi_i < ti][:5], hi_i[hi_i < ti][:5])
+    sure = inside & (cls >= 0)
+    assert np.array_equal(cls[sure], lane[sure])
+    assert np.all((mask[inside] >> lane[inside]) & 1)

@@ -1,0 +1,72 @@
+"""Parity at the states the benchmark times, against the oracle (Lemma 2).
+
+* N = 2^20, k = 1024: six alternating legs from the lattice (+x and +y; the
+  lattice disorders and violations become frequent), in the benchmark's
+  launch configuration for both forms: FP64 with graph candidates, and
+  FP32-mixed on the corridor scan with its binary32 filter.
+* N = 65536, k = 256: the legs that cover the first 10^6 liftings, both
+  forms, every per-chain result compared (the per-result error is zero).
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_2004_11040_amd as pkg  # noqa: E402
+from test_gpu_parity import check_parity  # noqa: E402
+
+FORMS = [(pkg.FP64, pkg.NEIGHBOURS_GRAPH, 250_000), (pkg.FP32_MIXED, pkg.NEIGHBOURS_CELLS, 160_000)]
+
+
+def _run(s, flags, neighbours, window_micro, legs, log_cap):
+    e = pkg.Ecmc(np.stack([s.x, s.y], 1), s.sigma, s.L, flags=flags, max_chains=s.k, log_cap=log_cap)
+    e.set_option(pkg.OPT_LANES, 64)
+    e.set_option(pkg.OPT_NEIGHBOURS, neighbours)
+    e.set_option(pkg.OPT_WINDOW_MICRO, window_micro)
+    e.set_active(s.active)
+    e.run(legs * s.T, s.T, pkg.DIR_ALTERNATE)
+    return e
+
+
+@pytest.fixture(scope="module")
+def headline_ref():
+    s = W.config(4)
+    print("[states] oracle: 6 legs at N=2^20", flush=True)
+    return s, oracle.run(s.x, s.y, s.sigma, s.L, s.active, s.leg_dirs(6), s.T, log_cap=1 << 24)
+
+
+@pytest.mark.parametrize("flags,neighbours,window_micro", FORMS)
+def test_headline_six_alternating_legs(headline_ref, flags, neighbours, window_micro):
+    s, ref = headline_ref
+    print(f"[states] N=2^20 flags={flags} neighbours={neighbours}", flush=True)
+    e = _run(s, flags, neighbours, window_micro, 6, 1 << 12)
+    st = check_parity(e, ref, s.L, s.k, f"headline 6 legs flags={flags}")
+    assert st["legs_violated"] >= 3 and st["reruns"] > 0   # the race-heavy regime
+    assert e.overlaps() == 0
+    print(f"[states] ok: {st['events']} liftings, {st['legs_violated']} violated legs, "
+          f"{st['reruns']} rollbacks", flush=True)
+
+
+@pytest.fixture(scope="module")
+def precision_ref():
+    s = W.config(2)
+    legs, ref = 0, None
+    while ref is None or ref.n_events < 1_000_000:
+        legs += 1
+        ref = oracle.run(s.x, s.y, s.sigma, s.L, s.active, s.leg_dirs(legs), s.T, log_cap=1 << 23)
+    return s, legs, ref
+
+
+@pytest.mark.parametrize("flags,neighbours,window_micro", FORMS)
+def test_precision_workload_first_million_liftings(precision_ref, flags, neighbours, window_micro):
+    s, legs, ref = precision_ref
+    assert ref.n_events >= 1_000_000
+    e = _run(s, flags, neighbours, window_micro, legs, 1 << 14)
+    check_parity(e, ref, s.L, s.k, f"N=65536 first {ref.n_events} liftings flags={flags}")
+    assert e.overlaps() == 0

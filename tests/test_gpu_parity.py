@@ -106,13 +106,16 @@ def test_alternating_parity(seed, n_side, eta, k, tfrac):
     check_parity(e, ref, L, k, f"seed={seed}")
 
 
-def test_many_chains_with_violations():
+@pytest.mark.parametrize("strict", [0, 1])
+def test_many_chains_with_violations(strict):
     """k = 4 sqrt(N) and long legs: horizon violations do happen; reruns and
-    the global-order fallback must still reproduce the oracle's liftings."""
+    the global-order fallback must still reproduce the oracle's liftings,
+    with the completion waits alone and with the formal agent-scope
+    release/acquire fences added."""
     x, y, L, act = _square(111, 32, 0.70, 128)
     T = 0.2 * L
     dirs = [0, 1, 0, 1]
-    e = gpu_run(x, y, L, act, dirs, T)
+    e = gpu_run(x, y, L, act, dirs, T, opts=((pkg.OPT_STRICT_ORDER, strict),))
     ref = oracle.run(x, y, 1.0, L, act, dirs, T)
     st = check_parity(e, ref, L, 128, "k=128")
     print("violated legs", st["legs_violated"], "reruns", st["reruns"], "global", st["global_legs"])
