@@ -184,6 +184,7 @@ def _stats_delta(st0, st1):
 
 NEIGHBOURS = {"cells": 0, "graph": 1}
 _neighbours = "graph"
+_cooperative = False
 
 
 def _make(s, form, lanes, window_micro, log_cap=1 << 12, max_splits=0):
@@ -196,6 +197,7 @@ def _make(s, form, lanes, window_micro, log_cap=1 << 12, max_splits=0):
     e.set_option(pkg.OPT_KERNEL_TIMING, 1)
     e.set_option(pkg.OPT_WINDOW_MICRO, window_micro)
     e.set_option(pkg.OPT_NEIGHBOURS, NEIGHBOURS[_neighbours])
+    e.set_option(pkg.OPT_COOPERATIVE, 1 if _cooperative else 0)
     if max_splits:
         e.set_option(pkg.OPT_MAX_SPLITS, max_splits)
     e.set_active(s.active)
@@ -242,6 +244,7 @@ def _summary(d, wall, form):
         "global_legs": d["global_legs"], "lockstep_runs": d["lockstep_runs"],
         "violations_screened": d["violations_screened"], "claim_yields": d["claim_yields"],
         "spin_aborts": d["spin_aborts"], "violations_by_kind": d["violations_by_kind"],
+        "nonresident_launches": d["nonresident_launches"],
         "attempts": d["attempts"], "slots_per_event": d["slots_scanned"] / max(d["events"], 1),
         "events_per_launch": epl, "kernel_ms_avg": kdur * 1e3,
         "alg_bytes_per_launch": alg, "implementation_bytes_per_launch": impl,
@@ -630,8 +633,12 @@ def main():
     ap.add_argument("--no-probes", action="store_true")
     ap.add_argument("--neighbours", choices=sorted(NEIGHBOURS), default=_neighbours,
                     help="candidates from the corridor scan over home cells, or from the constraint graph G(3)")
+    ap.add_argument("--cooperative-launch", action="store_true",
+                    help="launch the event kernel cooperatively (the runtime guarantees co-residency) "
+                         "instead of the plain launch that checks it itself")
     args = ap.parse_args()
     globals()["_neighbours"] = args.neighbours
+    globals()["_cooperative"] = args.cooperative_launch
     if args.pmc_summary:
         a = args.pmc_summary
         pmc_summary(a[0], a[1], a[2], a[3:])
@@ -690,7 +697,7 @@ def main():
         "config": {"workload": "hard disks N=1048576 eta=0.708, jittered 1024x1024 centred-rectangular "
                                "lattice, k=1024 chains, legs of T=33.896 alternating +x/+y, timed after an "
                                "untimed burn-in of >= 10 liftings per disk",
-                   "form": main_form, "lanes_per_chain": args.lanes, "neighbours": args.neighbours,
+                   "form": main_form, "lanes_per_chain": args.lanes, "neighbours": args.neighbours, "cooperative_launch": args.cooperative_launch,
                    "window_sigma": args.window_micro * 1e-6, "parallelism": "1 GPU"},
         "roofline": roof,
         "forms": results,

@@ -123,6 +123,21 @@ extern "C" {
                                      Same results.                              */
 #define ECMC_NEIGHBOURS_CELLS 0
 #define ECMC_NEIGHBOURS_GRAPH 1
+#define ECMC_OPT_COOPERATIVE 14   /* contexts: chains wait on each other and
+                                     on a clock workgroup, so all workgroups of
+                                     an event launch must be resident at once.
+                                     0 (default): plain launch; each workgroup
+                                     counts itself in when it starts, and a
+                                     chain that has waited 1 ms checks the
+                                     count: if part of the grid has not started,
+                                     the attempt is taken back and run again and
+                                     the context switches to 1 for good.
+                                     1: cooperative launch, the runtime
+                                     guarantees co-residency                    */
+#define ECMC_OPT_TEST_NONRESIDENT 15 /* test hook (contexts): a plain launch
+                                     expects this many workgroups beyond its
+                                     grid (0..4; default 0) and checks at the
+                                     first wait, so the fallback runs           */
 #define ECMC_OPT_CELL_PCT 12      /* batches: home-cell width in percent of 2 sigma,
                                      100..141 (cells of at most 4 disks), used
                                      where admissible for a replica (else its
@@ -173,6 +188,9 @@ typedef struct {
                                     last_violation_disk then names the retry path:
                                     1 rescan, 2 yield wait, 3 contact check,
                                     4 active target, 5 changed records, 6 yield) */
+  int64_t nonresident_launches;  /* plain event launches whose co-residency
+                                    handshake timed out (taken back, rerun)   */
+  int64_t cooperative;           /* 1 once event launches are cooperative      */
 } ecmc_stats_t;
 
 /* Bytes of device workspace for a context (the storage of the lifted

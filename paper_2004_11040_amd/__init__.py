@@ -27,6 +27,8 @@ OPT_FEATURES = 10
 OPT_GRAPH = 11
 OPT_CELL_PCT = 12
 OPT_NEIGHBOURS = 13
+OPT_COOPERATIVE = 14
+OPT_TEST_NONRESIDENT = 15
 NEIGHBOURS_CELLS, NEIGHBOURS_GRAPH = 0, 1
 FEAT_SCREEN, FEAT_RESERVE, FEAT_REREAD, FEAT_FRESH, FEAT_ALL = 1, 2, 4, 8, 15
 DIR_X, DIR_Y, DIR_MX, DIR_MY, DIR_ALTERNATE = 0, 1, 2, 3, 4
@@ -65,7 +67,7 @@ class Stats(ctypes.Structure):
         (n, ctypes.c_double) for n in ("last_violation_t", "last_violation_tj",
                                        "last_violation_tau", "last_violation_h")] + [
         (n, ctypes.c_int64) for n in ("lockstep_runs", "violations_screened", "claim_yields",
-                                      "spin_aborts")]
+                                      "spin_aborts", "nonresident_launches", "cooperative")]
 
     def as_dict(self):
         d = {n: getattr(self, n) for n, _ in self._fields_ if n != "pad_"}

@@ -100,6 +100,7 @@ struct LegCtl {
   double T, h, last_R, R, gend, tend_cur, lag_cur, window, base_lag;
   long long attempts, reruns, lockstep_runs, global_runs, legs_violated;
   long long timed_events, timed_slots, event_launches, event_ticks, rounds;
+  long long nonresident;  // launches retried because not every workgroup became resident
   unsigned long long vkind[NVK];
 };
 
@@ -110,7 +111,7 @@ struct Ctl {
   unsigned long long overlaps;
   int32_t inject_chain, inject_event;
   int32_t ev_blocks;  // workgroups of the last event launch (their stamps are in TS)
-  int32_t pad1;
+  int32_t arrived;    // workgroups of the current event launch that have started
   long long tot_events[2], tot_slots[2];  // work counters before / after the last launch
   double clock;     // H: smallest next-event time published by the chains
   int32_t done;     // chains that finished the attempt
@@ -123,6 +124,8 @@ struct Ctl {
   int32_t hang_site;      // which loop ran out of iterations (HS_*), with ECMC_EHANG
   // device timing of the last event launch (s_memrealtime ticks)
   unsigned long long t_start, t_end;
+  int32_t not_resident;   // part of the launch's grid had not started after a long wait (grid_not_resident)
+  int32_t pad2;
   LegCtl lc;
 };
 // loops bounded by an iteration limit (reported with ECMC_EHANG)
@@ -179,6 +182,7 @@ struct LegP {
   int32_t features;  // ECMC_FEAT_* bits
   int32_t self_clock;  // 1: a chain waiting at the lag takes H from the chains' next-event
                        // times itself (no clock workgroup: the replica workgroups)
+  int32_t resident_hook;  // test hook: arrivals the handshake expects beyond the grid (0)
 };
 
 // One committed lifting, as needed to take it back (restart from the earliest
@@ -768,6 +772,8 @@ __device__ __forceinline__ bool rollback_block(const Dev &D, const Geo &g, doubl
       C.lc.do_rb = 0;
       C.tstar_bits = 0x7FF0000000000000ull;
       C.abort = 0;
+      C.arrived = 0;
+      C.not_resident = 0;
       C.clock = R;
       C.done = 0;
       C.vkind_first = -1;
@@ -786,6 +792,8 @@ __global__ void k_ctl_reset(Dev D, double h) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     D.ctl->tstar_bits = 0x7FF0000000000000ull;  // +inf
     D.ctl->abort = 0;
+    D.ctl->arrived = 0;
+    D.ctl->not_resident = 0;
     D.ctl->clock = h;
     D.ctl->done = 0;
     D.ctl->vkind_first = -1;
@@ -1090,11 +1098,30 @@ __device__ __forceinline__ void flag_violation(const Dev &D, int c, double t, in
 // chain has finished (or the attempt aborts).  H never decreases.  One
 // iteration is a round of independent loads, a wavefront butterfly, and two
 // barriers: chains at the edge of the bounded lag wait on it.
-__device__ void clock_loop(const Dev &D, long long iter_cap) {
+// Co-residency of an event launch.  Chains wait on each other and on the
+// clock workgroup, which is only safe once every workgroup of the grid runs.
+// Each workgroup counts itself in when it starts (ctl.arrived) and goes on at
+// once; a wait at the bounded lag, or the clock, that has lasted longer than
+// RESIDENT_TICKS of the device clock checks the count, and if part of the
+// grid has still not started it marks the launch not resident and aborts it.
+// The attempt is then taken back and run again, and the host launches
+// cooperatively from then on.  (The test hook, expect above the grid, checks
+// at the first wait.)
+constexpr unsigned long long RESIDENT_TICKS = 100000;  // 1 ms at 100 MHz
+__device__ __forceinline__ bool grid_not_resident(const Dev &D, int expect, unsigned long long waited) {
+  if (waited <= (expect > (int)gridDim.x ? 0ull : RESIDENT_TICKS)) return false;
+  if (__hip_atomic_load(&D.ctl->arrived, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= expect) return false;
+  __hip_atomic_store(&D.ctl->not_resident, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store(&D.ctl->abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return true;
+}
+
+__device__ void clock_loop(const Dev &D, long long iter_cap, int expect) {
   __shared__ double red[16];
   __shared__ int s_quit;
   double hc = ld_a(&D.ctl->clock);
   const int nw = (int)((blockDim.x + 63) >> 6);
+  const unsigned long long t0 = __builtin_amdgcn_s_memrealtime();
   for (long long it = 0;; ++it) {
     double m = INFINITY;
 #pragma unroll 4
@@ -1116,6 +1143,7 @@ __device__ void clock_loop(const Dev &D, long long iter_cap) {
         st_a(&D.ctl->clock, hc);
       }
       int quit = (done >= D.k || ab || er) ? 1 : 0;
+      if (!quit && grid_not_resident(D, expect, __builtin_amdgcn_s_memrealtime() - t0)) quit = 1;
       if (!quit && it >= iter_cap) {
         atomicExch(&D.ctl->hang_site, (int32_t)HS_CLOCK);
         atomicExch(&D.ctl->error, ECMC_EHANG);
@@ -1551,6 +1579,7 @@ __device__ void chain_events(const Dev &D, const Geo &g, const LegP &lp, int32_t
     if (lp.window > 0.0) {
       double hc = bcast<G>(hclk, 0);
       bool stop = false, requeue = false;
+      const unsigned long long tw0 = __builtin_amdgcn_s_memrealtime();
       while (e_next > hc + lp.window) {
         const double tw = hc + lp.window;
         if (tw > t_pub) {
@@ -1577,6 +1606,11 @@ __device__ void chain_events(const Dev &D, const Geo &g, const LegP &lp, int32_t
         if (lane == 0) {
           ab2 = __hip_atomic_load(&D.ctl->abort, __ATOMIC_RELAXED, SC);
           h2 = ld_a<SC>(&D.ctl->clock);
+          // the event launch (not a replica workgroup) checks that its whole
+          // grid runs before it waits on for long
+          if (!ab2 && !lp.self_clock &&
+              grid_not_resident(D, (int)gridDim.x + lp.resident_hook, __builtin_amdgcn_s_memrealtime() - tw0))
+            ab2 = 1;
         }
         if (bcast<G>(ab2, 0)) {
           stop = true;
@@ -1986,9 +2020,11 @@ __global__ void __launch_bounds__(256) k_event(Dev D, Geo g, LegP lp, int32_t wa
   if (threadIdx.x == 0) {
     D.TS[2 * blockIdx.x] = __builtin_amdgcn_s_memrealtime();
     if (blockIdx.x == 0) D.ctl->ev_blocks = (int32_t)gridDim.x;
+    // count this workgroup in (see grid_not_resident)
+    __hip_atomic_fetch_add(&D.ctl->arrived, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
   if (blockIdx.x == gridDim.x - 1) {  // the clock workgroup (idle without a bounded lag)
-    if (lp.window > 0.0) clock_loop(D, iter_cap);
+    if (lp.window > 0.0) clock_loop(D, iter_cap, (int)gridDim.x + lp.resident_hook);
   } else if (c < D.k && !D.ctl->error) {
     chain_events<G, F32, SCA, GR>(D, g, lp, wait_retries, iter_cap, c, lane);
   }
@@ -2629,6 +2665,8 @@ __device__ __forceinline__ void round_prep(const Dev &D) {
     C.lc.do_rb = 0;
     C.tstar_bits = 0x7FF0000000000000ull;
     C.abort = 0;
+    C.arrived = 0;
+    C.not_resident = 0;
     C.clock = h;
     C.done = 0;
     C.vkind_first = -1;
@@ -2670,6 +2708,7 @@ __global__ void __launch_bounds__(1024) k_leg_init(Dev D, double T, double windo
     lc.base_lag = base_lag;
     lc.attempts = lc.reruns = lc.lockstep_runs = lc.global_runs = lc.legs_violated = 0;
     lc.timed_events = lc.timed_slots = lc.event_launches = lc.event_ticks = lc.rounds = 0;
+    lc.nonresident = 0;
     for (int q = 0; q < NVK; ++q) lc.vkind[q] = 0ull;
   }
   __syncthreads();
@@ -2710,6 +2749,22 @@ __device__ __forceinline__ void round_decide(const Dev &D, double H, long long e
   }
   for (int q = 0; q < NVK; ++q) lc.vkind[q] += C.vkind_cnt[q];
   if (lc.mode == MD_LOCKSTEP) lc.lockstep_runs++;
+  if (C.not_resident) {
+    // not every workgroup ran: take back what was committed from H (or the
+    // earliest violation) on and run the attempt again; not a violation
+    lc.nonresident++;
+    const double tstar = __longlong_as_double((long long)C.tstar_bits);
+    const double R = fmax(fmin(tstar, H), lc.h);
+    lc.R = R;
+    lc.do_rb = 1;
+    lc.h = R;
+    if (lc.rounds > (1ll << 20)) {
+      C.hang_site = HS_ROUNDS;
+      C.error = ECMC_EHANG;
+      lc.phase = PH_FAILED;
+    }
+    return;
+  }
   if (!C.abort) {
     if (lc.mode == MD_LOCKSTEP && !lc.final_cur) {
       lc.h = lc.gend;
@@ -2995,6 +3050,7 @@ __device__ __noinline__ int replica_leg(const RepIn &ri, RepOut *rp, int dir) {
     lp.window = ri.window;
     lp.features = features;
     lp.self_clock = 1;
+    lp.resident_hook = 0;
     {
       // chains rotate over the lane groups from one attempt to the next: the
       // lanes of a wavefront issue their claims in one instruction with a fixed
@@ -3174,7 +3230,11 @@ struct ecmc_ctx {
   int32_t features = ECMC_FEAT_ALL;
   int32_t graph = 1;          // 1: candidates from the constraint graph G(3), 0: corridor scan
   unsigned resident_nb = 0;   // grid size whose residency was last verified
-  int32_t resident_key = 0;   // lanes * 2 + FP32 flag of that check
+  int32_t resident_key = 0;   // lanes * 4 + form of that check
+  int32_t cooperative = 0;    // 1: event kernel launched cooperatively (co-residency guaranteed
+                              // by the runtime); 0: plain launch checked by the arrival handshake
+  int32_t resident_hook = 0;  // test hook: extra arrivals a plain launch's handshake expects
+  int64_t nonresident = 0;    // plain launches whose handshake timed out
   int64_t vkind[NVK] = {0, 0, 0, 0, 0};
   int32_t last_v_kind = -1, last_v_chain = -1, last_v_id = -1;
   double last_v_t = 0.0, last_v_tj = 0.0, last_v_tau = 0.0, last_v_h = 0.0;
@@ -3336,55 +3396,56 @@ int check_resident(ecmc_ctx *ctx, unsigned nb) {
   return ECMC_OK;
 }
 
-int launch_event(ecmc_ctx *ctx, LegP lp) {
-  Dev &D = ctx->D;
-  // attempts per chain before the kernel gives up (a leg needs a few hundred)
-  const long long cap = 1ll << 24;
-  const int G = ctx->lanes;
-  const int64_t threads = (int64_t)D.k * G;
-  const unsigned nb = blocks_for(threads, 256) + 1u;  // + the clock workgroup
-  const bool f32 = (ctx->flags & ECMC_FP32_MIXED) != 0;
-  const bool gr = ctx->graph != 0;  // three arrows per scan: no binary32 filter
-  int rc = ECMC_OK;
-  const int32_t key = G * 4 + (gr ? 2 : (f32 ? 1 : 0));
+// One event-kernel launch.  Chains wait on each other (bounded lag, active
+// targets) and on the clock workgroup, so every workgroup of the grid must be
+// resident at once.  The occupancy check says the grid fits an idle device; a
+// plain launch then verifies it wherever a chain waits long (grid_not_resident),
+// and a cooperative launch has the runtime guarantee it (it refuses a grid that
+// cannot be co-resident, and keeps other work off the device meanwhile, which
+// costs about a tenth of the throughput at N = 2^20).
+template <int G, bool F32, bool GR>
+int launch_event_t(ecmc_ctx *ctx, unsigned nb, LegP lp) {
+  const int32_t key = G * 4 + (GR ? 2 : (F32 ? 1 : 0));
   if (ctx->resident_nb != nb || ctx->resident_key != key) {
-    if (gr)
-      rc = G == 64 ? check_resident<64, false, true>(ctx, nb)
-                   : (G == 32 ? check_resident<32, false, true>(ctx, nb) : check_resident<16, false, true>(ctx, nb));
-    else if (f32)
-      rc = G == 64 ? check_resident<64, true, false>(ctx, nb)
-                   : (G == 32 ? check_resident<32, true, false>(ctx, nb) : check_resident<16, true, false>(ctx, nb));
-    else
-      rc = G == 64 ? check_resident<64, false, false>(ctx, nb)
-                   : (G == 32 ? check_resident<32, false, false>(ctx, nb) : check_resident<16, false, false>(ctx, nb));
+    const int rc = check_resident<G, F32, GR>(ctx, nb);
     if (rc) return rc;
     ctx->resident_nb = nb;
     ctx->resident_key = key;
   }
-  if (gr) {
-    if (G == 64)
-      k_event<64, false, true><<<nb, 256, 0, ctx->stream>>>(D, ctx->g, lp, ctx->wait_retries, cap);
-    else if (G == 32)
-      k_event<32, false, true><<<nb, 256, 0, ctx->stream>>>(D, ctx->g, lp, ctx->wait_retries, cap);
-    else
-      k_event<16, false, true><<<nb, 256, 0, ctx->stream>>>(D, ctx->g, lp, ctx->wait_retries, cap);
-  } else if (f32) {
-    if (G == 64)
-      k_event<64, true, false><<<nb, 256, 0, ctx->stream>>>(D, ctx->g, lp, ctx->wait_retries, cap);
-    else if (G == 32)
-      k_event<32, true, false><<<nb, 256, 0, ctx->stream>>>(D, ctx->g, lp, ctx->wait_retries, cap);
-    else
-      k_event<16, true, false><<<nb, 256, 0, ctx->stream>>>(D, ctx->g, lp, ctx->wait_retries, cap);
-  } else {
-    if (G == 64)
-      k_event<64, false, false><<<nb, 256, 0, ctx->stream>>>(D, ctx->g, lp, ctx->wait_retries, cap);
-    else if (G == 32)
-      k_event<32, false, false><<<nb, 256, 0, ctx->stream>>>(D, ctx->g, lp, ctx->wait_retries, cap);
-    else
-      k_event<16, false, false><<<nb, 256, 0, ctx->stream>>>(D, ctx->g, lp, ctx->wait_retries, cap);
+  Dev D = ctx->D;
+  Geo g = ctx->g;
+  int32_t wr = ctx->wait_retries;
+  long long cap = 1ll << 24;  // attempts per chain before the kernel gives up (a leg needs a few hundred)
+  if (ctx->cooperative) {
+    lp.resident_hook = 0;
+    void *args[] = {&D, &g, &lp, &wr, &cap};
+    const hipError_t e = hipLaunchCooperativeKernel(reinterpret_cast<const void *>(&k_event<G, F32, GR>),
+                                                    dim3(nb), dim3(256), args, 0, ctx->stream);
+    if (e != hipSuccess) {
+      ctx->err = "cooperative launch of the event kernel refused (grid not co-resident)";
+      (void)hipGetLastError();
+      return ECMC_EDEVICE;
+    }
+    return ECMC_OK;
   }
+  k_event<G, F32, GR><<<nb, 256, 0, ctx->stream>>>(D, g, lp, wr, cap);
   HIPCHK(hipGetLastError());
   return ECMC_OK;
+}
+
+int launch_event(ecmc_ctx *ctx, LegP lp) {
+  const int G = ctx->lanes;
+  const int64_t threads = (int64_t)ctx->D.k * G;
+  const unsigned nb = blocks_for(threads, 256) + 1u;  // + the clock workgroup
+  const bool f32 = (ctx->flags & ECMC_FP32_MIXED) != 0;
+  if (ctx->graph)  // three arrows per scan: no binary32 filter
+    return G == 64 ? launch_event_t<64, false, true>(ctx, nb, lp)
+                   : (G == 32 ? launch_event_t<32, false, true>(ctx, nb, lp) : launch_event_t<16, false, true>(ctx, nb, lp));
+  if (f32)
+    return G == 64 ? launch_event_t<64, true, false>(ctx, nb, lp)
+                   : (G == 32 ? launch_event_t<32, true, false>(ctx, nb, lp) : launch_event_t<16, true, false>(ctx, nb, lp));
+  return G == 64 ? launch_event_t<64, false, false>(ctx, nb, lp)
+                 : (G == 32 ? launch_event_t<32, false, false>(ctx, nb, lp) : launch_event_t<16, false, false>(ctx, nb, lp));
 }
 
 // One attempt over [h, tend) of the current leg (home cells already built and
@@ -3410,6 +3471,7 @@ int attempt(ecmc_ctx *ctx, int dir, double h, double tend, bool final, bool glob
   lp.features = ctx->features;
   lp.window = window;
   lp.self_clock = 0;
+  lp.resident_hook = 0;
   const bool timed = !global && ctx->kernel_timing && ctx->kevents_ok;
   k_count_delta<<<1, 256, 0, ctx->stream>>>(D, 0);
   HIPCHK(hipGetLastError());
@@ -3544,6 +3606,7 @@ int run_leg(ecmc_ctx *ctx, int dir, double T) {
     lp0.window = 0.0;
     lp0.features = ctx->features;
     lp0.self_clock = 0;
+    lp0.resident_hook = ctx->cooperative ? 0 : ctx->resident_hook;
     Ctl hc;
     // the first batch covers as many rounds as the last leg along the same
     // direction took (the lattice is not isotropic: legs along +x take about
@@ -3558,6 +3621,12 @@ int run_leg(ecmc_ctx *ctx, int dir, double T) {
       }
       rc = read_ctl(ctx, &hc);
       if (rc) return rc;
+      if (hc.lc.nonresident > 0 && !ctx->cooperative) {
+        // a plain launch did not get the whole grid resident: from now on
+        // the runtime guarantees it (cooperative launches)
+        ctx->cooperative = 1;
+        lp0.resident_hook = 0;
+      }
       if (hc.lc.phase != PH_RUN) break;
       nspec = batch == 0 ? 4 : std::min(nspec * 2, 16);
       if (batch > (int64_t)1 << 22) {
@@ -3572,6 +3641,7 @@ int run_leg(ecmc_ctx *ctx, int dir, double T) {
     ctx->lockstep_runs += lc.lockstep_runs;
     ctx->global_legs += lc.global_runs;
     ctx->legs_violated += lc.legs_violated;
+    ctx->nonresident += lc.nonresident;
     for (int q = 0; q < NVK; ++q) ctx->vkind[q] += (int64_t)lc.vkind[q];
     if (hc.vkind_first >= 0) {
       ctx->last_v_kind = hc.vkind_first;
@@ -3871,6 +3941,8 @@ int ecmc_stats(ecmc_ctx *ctx, ecmc_stats_t *out) {
   out->timed_slots = ctx->timed_slots;
   for (int q = 0; q < 4; ++q) out->violations_by_kind[q] = ctx->vkind[q];
   out->spin_aborts = ctx->vkind[VK_SPIN];
+  out->nonresident_launches = ctx->nonresident;
+  out->cooperative = ctx->cooperative;
   out->last_violation_kind = ctx->last_v_kind;
   out->last_violation_chain = ctx->last_v_chain;
   out->last_violation_disk = ctx->last_v_id;
@@ -4024,6 +4096,14 @@ int ecmc_set_option(ecmc_ctx *ctx, int32_t key, int64_t value) {
     case ECMC_OPT_NEIGHBOURS:
       if (value != ECMC_NEIGHBOURS_CELLS && value != ECMC_NEIGHBOURS_GRAPH) return ECMC_EINVAL;
       ctx->graph = value == ECMC_NEIGHBOURS_GRAPH ? 1 : 0;
+      return ECMC_OK;
+    case ECMC_OPT_COOPERATIVE:
+      if (value != 0 && value != 1) return ECMC_EINVAL;
+      ctx->cooperative = (int32_t)value;
+      return ECMC_OK;
+    case ECMC_OPT_TEST_NONRESIDENT:
+      if (value < 0 || value > 4) return ECMC_EINVAL;
+      ctx->resident_hook = (int32_t)value;
       return ECMC_OK;
     default:
       return ECMC_EINVAL;

@@ -121,6 +121,36 @@ def test_many_chains_with_violations(strict):
     print("violated legs", st["legs_violated"], "reruns", st["reruns"], "global", st["global_legs"])
 
 
+@pytest.mark.parametrize("cooperative", [0, 1])
+def test_cooperative_and_plain_launch_agree(cooperative):
+    """The event kernel launched cooperatively (co-residency guaranteed by the
+    runtime, the default) and as a plain launch after the occupancy check:
+    the same liftings, bit for bit, with the bounded-lag clock running."""
+    s = W.config(1)
+    dirs = s.leg_dirs(2)
+    e = gpu_run(s.x, s.y, s.L, s.active, dirs, s.T, log_cap=1 << 14,
+                opts=((pkg.OPT_COOPERATIVE, cooperative), (pkg.OPT_WINDOW_MICRO, 200_000)))
+    ref = oracle.run(s.x, s.y, 1.0, s.L, s.active, dirs, s.T)
+    st = check_parity(e, ref, s.L, s.k, f"cooperative={cooperative}")
+    assert st["nonresident_launches"] == 0 and st["cooperative"] == cooperative
+
+
+def test_failed_residency_handshake_falls_back_to_cooperative_launches():
+    """The host makes every plain launch expect one workgroup more than its
+    grid holds (a test hook that checks at the first wait; every kernel still
+    ends): the attempts are taken back, the context switches to cooperative
+    launches, and the liftings are the oracle's."""
+    s = W.config(1)
+    dirs = s.leg_dirs(2)
+    e = gpu_run(s.x, s.y, s.L, s.active, dirs, s.T, log_cap=1 << 14,
+                opts=((pkg.OPT_COOPERATIVE, 0), (pkg.OPT_TEST_NONRESIDENT, 1),
+                      (pkg.OPT_WINDOW_MICRO, 200_000)))
+    ref = oracle.run(s.x, s.y, 1.0, s.L, s.active, dirs, s.T)
+    st = check_parity(e, ref, s.L, s.k, "handshake fallback")
+    print("non-resident launches", st["nonresident_launches"], flush=True)
+    assert st["nonresident_launches"] >= 1 and st["cooperative"] == 1
+
+
 @pytest.mark.parametrize("window_micro", [50_000, 300_000])
 def test_bounded_lag_window_is_pure_scheduling(window_micro):
     """The bounded-lag clock only delays commits: same liftings, same bits."""
