@@ -439,7 +439,9 @@ __global__ void k_chains_attempt(Dev D, double h) {
 // T or more are left out (no chain can reach them within the leg).  Columns
 // are walked forward as in the corridor scan until no further column can
 // undercut any lane's minimum; a column's 12 slots are loaded at once.  Only
-// occupied slots get arrows (empty slots never hold a moving disk).
+// occupied slots get arrows (empty slots never hold a moving disk).  The
+// replica workgroups build their graphs disk by disk with it; a context
+// builds it tile by tile through LDS (k_graph_tile).
 __device__ void graph_slot(const Dev &D, const Geo &g, double T, int64_t s) {
   int4 out = make_int4(-1, -1, -1, -1);
   const CstRec cs = D.CST[s];
@@ -504,13 +506,6 @@ __device__ void graph_slot(const Dev &D, const Geo &g, double T, int64_t s) {
 __device__ __forceinline__ int64_t placed_slot(const Dev &D, const Geo &g, int64_t i) {
   const int64_t s = D.SLOT_OF[i];
   return (s >= 0 && s < (int64_t)g.nc * g.nc * CAP && D.CST[s].id == (int32_t)i) ? s : -1;
-}
-// one thread per disk
-__global__ void k_graph(Dev D, Geo g, double T) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= D.n) return;
-  const int64_t s = placed_slot(D, g, i);
-  if (s >= 0) graph_slot(D, g, T, s);
 }
 // arrows as disk ids, in disk order: out[3 i + q] (-1: none)
 __global__ void k_graph_ids(Dev D, Geo g, int32_t *out) {
@@ -981,6 +976,162 @@ __device__ __forceinline__ F32Cand tof_f32(int mc, int dr, float rai, float rpi,
   r.cls = !in ? -1 : (c0 ? 0 : (c1 ? 1 : (c2 ? 2 : -1)));
   r.cls_mask = !in ? 0 : (c0 ? 1 : (c1 ? 2 : (c2 ? 4 : (dp > 0.f ? 3 : 5))));
   return r;
+}
+
+// The same graph built tile by tile through LDS: a workgroup takes
+// GT_ROWS x GT_COLS home cells, stages their records with one row above and
+// below and GT_HALO columns ahead (every record is loaded once per tile
+// instead of once per disk that scans it), lists the tile's occupied slots,
+// and walks each of them over LDS columns; a walk that runs past the halo
+// continues on global memory.  Both forms build it in binary64: a binary32
+// stage (the corridor scan's interval filter, or only a screen of slots
+// certainly outside the corridor or beyond every lane's bound) made the
+// build 2.6 and 1.8 times slower.  Unpacked binary32 arithmetic issues at
+// the binary64 rate here, so a binary32 stage only adds work.
+constexpr int GT_ROWS = 8, GT_COLS = 32, GT_HALO = 8;
+constexpr int GT_LR = GT_ROWS + 2, GT_LC = GT_COLS + GT_HALO;
+constexpr int GT_SLOTS = GT_LR * GT_LC * CAP;  // 1600
+
+__global__ void __launch_bounds__(256) k_graph_tile(Dev D, Geo g, double T, int tiles_x) {
+  __shared__ double l_a[GT_SLOTS], l_p[GT_SLOTS];
+  __shared__ int l_id[GT_SLOTS];
+  __shared__ short l_list[GT_ROWS * GT_COLS * CAP];
+  __shared__ int l_wsum[4], l_total;
+  const int nc = g.nc;
+  const int ty = (int)blockIdx.x / tiles_x, tx = (int)blockIdx.x - ty * tiles_x;
+  const int r0 = ty * GT_ROWS, c0 = tx * GT_COLS;
+  // stage records: LDS slot li = ((lr * GT_LC) + lc) * CAP + q, cell (r0 - 1 + lr, c0 + lc) wrapped
+  for (int li = threadIdx.x; li < GT_SLOTS; li += blockDim.x) {
+    const int cell = li / CAP, q = li - cell * CAP;
+    const int lr = cell / GT_LC, lc = cell - lr * GT_LC;
+    const int row = ((r0 - 1 + lr) % nc + nc) % nc, col = (c0 + lc) % nc;
+    const int sl = ((row * nc + col) << 2) + q;
+    const CstRec cr = D.CST[sl];
+    const double aj = D.MUT[sl].a;
+    l_id[li] = cr.id;
+    l_p[li] = cr.p;
+    l_a[li] = aj;
+  }
+  // occupied slots of the tile's own cells (thread t: cell t of the tile)
+  int mine = 0, lsl[CAP];
+  {
+    const int tr = (int)threadIdx.x / GT_COLS, tc = (int)threadIdx.x - tr * GT_COLS;
+    const bool in_box = r0 + tr < nc && c0 + tc < nc;
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < CAP; ++q) {
+      const int li = (((tr + 1) * GT_LC) + tc) * CAP + q;
+      lsl[q] = li;
+      if (in_box && l_id[li] >= 0) ++mine;
+    }
+    if (!in_box) mine = 0;
+  }
+  // block-wide exclusive prefix sum of the counts (4 wavefronts)
+  int incl = mine;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const int v = __shfl_up(incl, off, 64);
+    if (__lane_id() >= (unsigned)off) incl += v;
+  }
+  if (__lane_id() == 63) l_wsum[threadIdx.x >> 6] = incl;
+  __syncthreads();
+  int base = 0;
+  for (int w = 0; w < (int)(threadIdx.x >> 6); ++w) base += l_wsum[w];
+  if (threadIdx.x == 0) l_total = l_wsum[0] + l_wsum[1] + l_wsum[2] + l_wsum[3];
+  int pos = base + incl - mine;
+#pragma unroll
+  for (int q = 0; q < CAP; ++q)
+    if (mine && l_id[lsl[q]] >= 0) l_list[pos++] = (short)lsl[q];
+  __syncthreads();
+  const int total = l_total;
+  // slots of the tile's cells that hold no disk get no arrows
+  {
+    const int tr = (int)threadIdx.x / GT_COLS, tc = (int)threadIdx.x - tr * GT_COLS;
+    if (r0 + tr < nc && c0 + tc < nc) {
+#pragma unroll
+      for (int q = 0; q < CAP; ++q)
+        if (l_id[lsl[q]] < 0) D.GARR[(((r0 + tr) * nc + c0 + tc) << 2) + q] = make_int4(-1, -1, -1, -1);
+    }
+  }
+  for (int e = threadIdx.x; e < total; e += blockDim.x) {
+    const int li = l_list[e];
+    const int cell = li / CAP, q0 = li - cell * CAP;
+    const int lr = cell / GT_LC, lc = cell - lr * GT_LC;  // lr in [1, GT_ROWS], lc < GT_COLS
+    const int row0 = r0 + lr - 1, col0 = c0 + lc;
+    const int64_t s = ((int64_t)(row0 * nc + col0) << 2) + q0;
+    const double a = l_a[li], p = l_p[li];
+    double u = a - col0 * g.c;
+    if (u < 0.0) u = u + g.L;
+    double bt[3] = {INFINITY, INFINITY, INFINITY};
+    int bid[3] = {0x7fffffff, 0x7fffffff, 0x7fffffff};
+    int bsl[3] = {-1, -1, -1};
+    for (int m = 0; m <= g.mmax; ++m) {
+      if (m > 0) {
+        double lim = 0.0;
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+          const double lq = bt[q] < T ? bt[q] : T;
+          lim = lq > lim ? lq : lim;
+        }
+        if (m * g.c - u - g.d - STOP_MARGIN > lim) break;
+      }
+      double aj[ROWS * CAP], pj[ROWS * CAP];
+      int idj[ROWS * CAP], slj[ROWS * CAP];
+      int col = col0 + m;
+      if (col >= nc) col -= nc;
+      if (lc + m < GT_LC) {
+#pragma unroll
+        for (int dr = 0; dr < ROWS; ++dr) {
+          int row = row0 + dr - 1;
+          row = row < 0 ? row + nc : (row >= nc ? row - nc : row);
+#pragma unroll
+          for (int q4 = 0; q4 < CAP; ++q4) {
+            const int r = dr * CAP + q4;
+            const int lj = (((lr + dr - 1) * GT_LC) + lc + m) * CAP + q4;
+            aj[r] = l_a[lj];
+            pj[r] = l_p[lj];
+            idj[r] = l_id[lj];
+            slj[r] = ((row * nc + col) << 2) + q4;
+          }
+        }
+      } else {
+#pragma unroll
+        for (int dr = 0; dr < ROWS; ++dr) {
+          int row = row0 + dr - 1;
+          row = row < 0 ? row + nc : (row >= nc ? row - nc : row);
+#pragma unroll
+          for (int q4 = 0; q4 < CAP; ++q4) {
+            const int r = dr * CAP + q4;
+            const int sl = ((row * nc + col) << 2) + q4;
+            const CstRec cr = D.CST[sl];
+            aj[r] = D.MUT[sl].a;
+            pj[r] = cr.p;
+            idj[r] = cr.id;
+            slj[r] = sl;
+          }
+        }
+      }
+      bool refine[ROWS * CAP];
+#pragma unroll
+      for (int r = 0; r < ROWS * CAP; ++r) refine[r] = idj[r] >= 0 && slj[r] != (int)s;
+#pragma unroll
+      for (int r = 0; r < ROWS * CAP; ++r) {
+        if (!refine[r]) continue;
+        double b, dp;
+        const double tau = tof(a, p, aj[r], pj[r], g, b, dp);
+        if (!(tau < T)) continue;
+        const int cls = lane_class(dp, g);
+#pragma unroll
+        for (int q = 0; q < 3; ++q)
+          if (q == cls && key_less(tau, idj[r], bt[q], bid[q])) {
+            bt[q] = tau;
+            bid[q] = idj[r];
+            bsl[q] = slj[r];
+          }
+      }
+    }
+    D.GARR[s] = make_int4(bsl[0], bsl[1], bsl[2], -1);
+  }
 }
 
 // Per-lane candidates: the nearest disk in each of the three lanes of the
@@ -3540,7 +3691,10 @@ int set_inject(ecmc_ctx *ctx, int32_t chain, int32_t ev) {
 }
 
 int build_graph(ecmc_ctx *ctx, double T) {
-  k_graph<<<blocks_for(ctx->D.n, 256), 256, 0, ctx->stream>>>(ctx->D, ctx->g, T);
+  const int nc = ctx->g.nc;
+  const int tiles_x = (nc + GT_COLS - 1) / GT_COLS, tiles_y = (nc + GT_ROWS - 1) / GT_ROWS;
+  const unsigned nb = (unsigned)(tiles_x * tiles_y);
+  k_graph_tile<<<nb, 256, 0, ctx->stream>>>(ctx->D, ctx->g, T, tiles_x);
   HIPCHK(hipGetLastError());
   return ECMC_OK;
 }

@@ -27,20 +27,43 @@ CELLS = ((pkg.OPT_NEIGHBOURS, pkg.NEIGHBOURS_CELLS),)
 MODES = pytest.mark.parametrize("mode", [GRAPH, CELLS], ids=["graph", "cells"])
 
 
-@pytest.mark.parametrize("cfg,direction", [(0, 0), (0, 3), (1, 0), (1, 1), (1, 2), (1, 3), (2, 1)])
-def test_device_graph_equals_the_oracle(cfg, direction):
+FORMS = pytest.mark.parametrize("flags", [pkg.FP64, pkg.FP32_MIXED], ids=["fp64", "fp32"])
+
+
+@pytest.mark.parametrize("cfg,direction", [(0, 0), (0, 3), (1, 0), (1, 1), (1, 2), (1, 3), (2, 1), (4, 0)])
+@FORMS
+def test_device_graph_equals_the_oracle(cfg, direction, flags):
+    """The tiled build (FP64, and FP32-mixed with its binary32 filter) against
+    brute force; at 2^20 disks on a sample of 150."""
     s = W.config(cfg)
-    e = pkg.Ecmc(np.stack([s.x, s.y], 1), s.sigma, s.L, max_chains=s.k, log_cap=16)
+    e = pkg.Ecmc(np.stack([s.x, s.y], 1), s.sigma, s.L, flags=flags, max_chains=s.k, log_cap=16)
     e.set_active(s.active)
     got = e.graph(direction, s.T)
     rows = None
     if s.n > 5000:
-        rows = np.random.Generator(np.random.PCG64(3)).choice(s.n, 1500, replace=False)
+        rows = np.random.Generator(np.random.PCG64(3)).choice(s.n, 1500 if s.n < 100_000 else 150, replace=False)
     want, _, _ = CG.g3(s.x, s.y, s.sigma, s.L, direction, horizon=s.T, rows=rows)
     if rows is not None:
         got, want = got[rows], want[rows]
     assert np.array_equal(got, want), (cfg, direction, np.argwhere(got != want)[:5])
     print(f"[graph] cfg={cfg} dir={direction}: out-degree {np.mean((got >= 0).sum(1)):.3f}")
+
+
+@pytest.mark.parametrize("direction", [0, 1, 2, 3])
+@FORMS
+def test_device_graph_dilute_walks_past_the_halo(direction, flags):
+    """A dilute square lattice (eta = 0.03, spacing ~10 sigma) with a long
+    horizon: the off-centre lanes are mostly empty, so walks run far past the
+    staged tile and continue on global memory."""
+    x, y, L, act = _square(7, 64, 0.03, 64)
+    T = 0.4 * L
+    e = pkg.Ecmc(np.stack([x, y], 1), 1.0, L, flags=flags, max_chains=64, log_cap=16)
+    e.set_active(act)
+    got = e.graph(direction, T)
+    rows = np.random.Generator(np.random.PCG64(5)).choice(x.shape[0], 800, replace=False)
+    want, _, _ = CG.g3(x, y, 1.0, L, direction, horizon=T, rows=rows)
+    assert np.array_equal(got[rows], want[rows]), np.argwhere(got[rows] != want[rows])[:5]
+    print(f"[graph] dilute dir={direction}: out-degree {np.mean((got >= 0).sum(1)):.3f}")
 
 
 @pytest.mark.parametrize("lanes", [64, 32, 16])
