@@ -6,8 +6,9 @@ breakpoint reduction and write-back.  Directions alternate +x/+y.  Inputs are
 seeded synthetic lattices resident in HBM before the timed region starts.
 
 The headline value is measured after an untimed, labelled burn-in of at least
-10 liftings per disk (the lattice start is a transient: its first legs run
-faster); the figure from the lattice (warm-up legs only) is reported beside it.
+50 liftings per disk.  The lattice start is a transient: its first legs run
+faster, and the rate settles after about 40 liftings per disk.  The figure
+from the lattice (warm-up legs only) is reported beside it.
 
 Prints ONE JSON line.  Besides the headline it carries both forms, the other
 workloads (256, 4096 and 65536 disks), the violation probability per
@@ -255,7 +256,10 @@ def _summary(d, wall, form):
     }
 
 
-def burn_in(e, s, per_disk=10.0):
+BURN_IN_PER_DISK = 50.0
+
+
+def burn_in(e, s, per_disk=BURN_IN_PER_DISK):
     """Untimed legs until at least per_disk liftings per disk since set-up."""
     import paper_2004_11040_amd as pkg
     direction = pkg.DIR_ALTERNATE if s.alternate else pkg.DIR_X
@@ -284,7 +288,7 @@ def violation_sweep(e, s, Ts, n_legs, window_micro):
 
 def run_form(form, steps, warmup, lanes, window_micro, max_splits=0, sweep_Ts=(), sweep_legs=40, neighbours=None):
     """The headline workload in one form: `warmup` untimed legs and `steps`
-    timed legs from the lattice, then a burn-in to >= 10 liftings per disk and
+    timed legs from the lattice, then a burn-in to >= 50 liftings per disk and
     `steps` timed legs again (the headline), then the violation sweep."""
     import workloads as W
     s = W.config(4)
@@ -491,7 +495,7 @@ def run_batch(n_rep, target, t_frac, graph=1, window_micro=0, max_splits=0):
 
 
 def save_state(path, lanes, window_micro):
-    """Burn the headline workload in (>= 10 liftings per disk) and save the
+    """Burn the headline workload in (>= 50 liftings per disk) and save the
     configuration, so that a profiled process can start from it and count
     only the legs it measures."""
     import numpy as np
@@ -615,7 +619,7 @@ def main():
     ap.add_argument("--lanes", type=int, default=64)
     ap.add_argument("--max-splits", type=int, default=0,
                     help="rollbacks without progress before a lockstep stretch (0: library default)")
-    ap.add_argument("--window-micro", type=int, default=250_000,
+    ap.add_argument("--window-micro", type=int, default=160_000,
                     help="bounded lag between chains, in 1e-6 sigma (0: free running)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--cpu-batch-events", type=int, default=20_000,
@@ -705,7 +709,7 @@ def main():
         "dtype": "f32+f64" if main_form == "fp32" else "f64", "data": "synthetic",
         "config": {"workload": "hard disks N=1048576 eta=0.708, jittered 1024x1024 centred-rectangular "
                                "lattice, k=1024 chains, legs of T=33.896 alternating +x/+y, timed after an "
-                               "untimed burn-in of >= 10 liftings per disk",
+                               "untimed burn-in of >= 50 liftings per disk",
                    "form": main_form, "lanes_per_chain": args.lanes, "neighbours": plan[0][2],
                    "cooperative_launch": args.cooperative_launch,
                    "window_sigma": args.window_micro * 1e-6, "parallelism": "1 GPU"},

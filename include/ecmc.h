@@ -108,7 +108,10 @@ extern "C" {
 #define ECMC_FEAT_FRESH 8u    /* after a claim, lane minima whose records changed
                                  are checked on the new records (else the new
                                  local time with the scanned position)         */
-#define ECMC_FEAT_ALL 15u
+#define ECMC_FEAT_UNRESERVE 16u /* with RESERVE: a chain takes its reservation
+                                 back when it changes target or time, and when
+                                 it leaves the attempt                        */
+#define ECMC_FEAT_ALL 31u
 #define ECMC_OPT_GRAPH 11         /* batches: 1 captures the persistent launch
                                      in a hipGraph once and replays it (every
                                      setting travels in the replica descriptors

@@ -1346,6 +1346,8 @@ __device__ void chain_events(const Dev &D, const Geo &g, const LegP &lp, int32_t
   // lane would always win)
   int yield_slot = -1;
   unsigned long long yield_key = RES_EMPTY;
+  int res_slot = -1;                     // lane 0: the slot this chain has reserved, and its key
+  unsigned long long res_held = RES_EMPTY;
   // the release of the disk that stopped at the last lifting and the new
   // version of the activation record wait for the next completion wait,
   // instead of a round trip of their own
@@ -1723,9 +1725,24 @@ __device__ void chain_events(const Dev &D, const Geo &g, const LegP &lp, int32_t
         st_a<SC>(&D.NEXT[c], e_next);
         nxt_pub = e_next;
       }
-      // reserve the target: a chain with a later lifting on it yields
-      if (tau < trem && (lp.features & ECMC_FEAT_RESERVE))
+      // reserve the target: a chain with a later lifting on it yields.  A
+      // reservation the chain no longer stands behind (another target or
+      // another time) is taken back first: a chain yielding to it would
+      // wait on a lifting that is not coming
+      if (tau < trem && (lp.features & ECMC_FEAT_RESERVE)) {
+        if (res_slot >= 0 && (res_slot != ts || res_held != mykey) && (lp.features & ECMC_FEAT_UNRESERVE)) {
+          unsigned long long o = res_held;
+          __hip_atomic_compare_exchange_strong(&D.RES[res_slot], &o, RES_EMPTY, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                               SC);
+        }
         __hip_atomic_fetch_min(&D.RES[ts], mykey, __ATOMIC_RELAXED, SC);
+        res_slot = ts;
+        res_held = mykey;
+      } else if (res_slot >= 0 && (lp.features & ECMC_FEAT_UNRESERVE)) {
+        unsigned long long o = res_held;
+        __hip_atomic_compare_exchange_strong(&D.RES[res_slot], &o, RES_EMPTY, __ATOMIC_RELAXED, __ATOMIC_RELAXED, SC);
+        res_slot = -1;
+      }
     }
     if (lp.window > 0.0) {
       double hc = bcast<G>(hclk, 0);
@@ -2087,6 +2104,7 @@ __device__ void chain_events(const Dev &D, const Geo &g, const LegP &lp, int32_t
       st_a<SC>(&D.REF[c].t_rest, tj2);
       unsigned long long used = mykey;  // the reservation is used
       __hip_atomic_compare_exchange_strong(&D.RES[ts], &used, RES_EMPTY, __ATOMIC_RELAXED, __ATOMIC_RELAXED, SC);
+      res_slot = -1;
       strict_rel<SC>(lp.strict);
       st_a<SC>(&D.MUT[s].a, an);   // x_i
       D.LOG[(int64_t)c * D.log_cap + (loglen % D.log_cap)] = t_id;
@@ -2129,6 +2147,10 @@ __device__ void chain_events(const Dev &D, const Geo &g, const LegP &lp, int32_t
       __hip_atomic_store(&D.REF[c].ver, rel_ver, __ATOMIC_RELAXED, SC);
       __hip_atomic_store(&D.TAG[rel_slot], TAG_STATIC, __ATOMIC_RELAXED, SC);  // release
     }
+  }
+  if (lane == 0 && res_slot >= 0 && (lp.features & ECMC_FEAT_UNRESERVE)) {  // not left behind for later attempts
+    unsigned long long o = res_held;
+    __hip_atomic_compare_exchange_strong(&D.RES[res_slot], &o, RES_EMPTY, __ATOMIC_RELAXED, __ATOMIC_RELAXED, SC);
   }
   if (lane == 0) {
     // a chain stopped by an abort keeps its last next-event time: a lower

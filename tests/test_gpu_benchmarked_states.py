@@ -4,8 +4,12 @@
   lattice disorders and violations become frequent), in the benchmark's
   launch configuration for both forms: FP64 with graph candidates, and
   FP32-mixed on the corridor scan with its binary32 filter.
-* N = 65536, k = 256: the legs that cover the first 10^6 liftings, both
-  forms, every per-chain result compared (the per-result error is zero).
+* N = 65536, k = 256 (the same density and k = sqrt N): the legs that take
+  the lattice past 50 liftings per disk, the burn-in the benchmark times
+  after (3.3e6 liftings, the first 10^6 among them), both forms, every
+  chain's whole lifting sequence and every per-chain result compared (the
+  per-result error is zero).  At N = 2^20 that many legs are beyond what the
+  oracle does in a test (about 200 s on one core).
 """
 import numpy as np
 import pytest
@@ -21,7 +25,7 @@ if not torch.cuda.is_available():
 import paper_2004_11040_amd as pkg  # noqa: E402
 from test_gpu_parity import check_parity  # noqa: E402
 
-FORMS = [(pkg.FP64, pkg.NEIGHBOURS_GRAPH, 250_000), (pkg.FP32_MIXED, pkg.NEIGHBOURS_CELLS, 160_000)]
+FORMS = [(pkg.FP64, pkg.NEIGHBOURS_GRAPH, 160_000), (pkg.FP32_MIXED, pkg.NEIGHBOURS_CELLS, 160_000)]
 
 
 def _run(s, flags, neighbours, window_micro, legs, log_cap):
@@ -56,17 +60,22 @@ def test_headline_six_alternating_legs(headline_ref, flags, neighbours, window_m
 @pytest.fixture(scope="module")
 def precision_ref():
     s = W.config(2)
-    legs, ref = 0, None
-    while ref is None or ref.n_events < 1_000_000:
-        legs += 1
-        ref = oracle.run(s.x, s.y, s.sigma, s.L, s.active, s.leg_dirs(legs), s.T, log_cap=1 << 23)
+    # legs of about 55,000 liftings each: start near the count, then top up
+    legs = 56
+    ref = oracle.run(s.x, s.y, s.sigma, s.L, s.active, s.leg_dirs(legs), s.T, log_cap=1 << 25)
+    while ref.n_events < 50 * s.n:
+        legs += 4
+        ref = oracle.run(s.x, s.y, s.sigma, s.L, s.active, s.leg_dirs(legs), s.T, log_cap=1 << 25)
+    print(f"[states] oracle: {legs} legs, {ref.n_events} liftings at N=65536", flush=True)
     return s, legs, ref
 
 
 @pytest.mark.parametrize("flags,neighbours,window_micro", FORMS)
-def test_precision_workload_first_million_liftings(precision_ref, flags, neighbours, window_micro):
+def test_precision_workload_burned_in(precision_ref, flags, neighbours, window_micro):
     s, legs, ref = precision_ref
-    assert ref.n_events >= 1_000_000
-    e = _run(s, flags, neighbours, window_micro, legs, 1 << 14)
-    check_parity(e, ref, s.L, s.k, f"N=65536 first {ref.n_events} liftings flags={flags}")
+    assert ref.n_events >= 50 * s.n >= 1_000_000
+    e = _run(s, flags, neighbours, window_micro, legs, 1 << 15)
+    st = check_parity(e, ref, s.L, s.k, f"N=65536 {ref.n_events} liftings flags={flags}")
     assert e.overlaps() == 0
+    print(f"[states] ok: {st['events']} liftings, {st['legs_violated']} violated legs, "
+          f"{st['reruns']} rollbacks", flush=True)

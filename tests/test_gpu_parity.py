@@ -124,8 +124,9 @@ def test_many_chains_with_violations(strict):
 @pytest.mark.parametrize("cooperative", [0, 1])
 def test_cooperative_and_plain_launch_agree(cooperative):
     """The event kernel launched cooperatively (co-residency guaranteed by the
-    runtime, the default) and as a plain launch after the occupancy check:
-    the same liftings, bit for bit, with the bounded-lag clock running."""
+    runtime) and as a plain launch that checks it at long waits (the
+    default): the same liftings, bit for bit, with the bounded-lag clock
+    running."""
     s = W.config(1)
     dirs = s.leg_dirs(2)
     e = gpu_run(s.x, s.y, s.L, s.active, dirs, s.T, log_cap=1 << 14,
@@ -411,9 +412,10 @@ def test_fp32_mixed_headline_size_first_leg():
     check_parity(e, ref, s.L, s.k, "fp32 cfg4-leg0")
 
 
-@pytest.mark.parametrize("features", [0, 1, 2, 4, 8])
+@pytest.mark.parametrize("features", [0, 1, 2, 4, 8, 18, 31])
 def test_protocol_refinements_are_scheduling_only(features):
-    """Each refinement of the horizon protocol switched on alone (and none):
+    """Each refinement of the horizon protocol switched on alone (and none;
+    reservations taken back together with reservations; all):
     violations, rollbacks and liftings must still match the oracle."""
     x, y, L, act = _square(161, 32, 0.70, 128)
     T = 0.2 * L
