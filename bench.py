@@ -270,6 +270,27 @@ def burn_in(e, s, per_disk=BURN_IN_PER_DISK):
     return legs
 
 
+def production_loop(e, s, n_legs, seed=11):
+    """Legs whose direction is drawn per leg, uniformly over +x, +y, -x, -y
+    (seeded), with the constraint graph rebuilt for every leg: the production
+    loop of the closing paragraph of Sec. 3.4."""
+    import numpy as np
+    import torch
+    dirs = np.random.Generator(np.random.PCG64(seed)).integers(0, 4, n_legs).astype(np.int32)
+    st0 = e.stats()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(0, n_legs, 10):
+        e.run_directions(s.T, dirs[i:i + 10])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    d = _stats_delta(st0, e.stats())
+    log(f"production loop: {n_legs} legs, {d['events']} liftings, {d['events'] / wall / 1e6:.2f} M/s")
+    return {"legs": n_legs, "directions": "drawn per leg, uniform over +x +y -x -y (PCG64 seed 11)",
+            "events": d["events"], "wall_s": wall, "events_per_s": d["events"] / wall,
+            "reruns": d["reruns"], "legs_violated": d["legs_violated"]}
+
+
 def violation_sweep(e, s, Ts, n_legs, window_micro):
     """Violation probability per breakpoint (legs whose first attempt saw a
     horizon violation / legs) for each leg length T, with the same bounded lag
@@ -303,6 +324,8 @@ def run_form(form, steps, warmup, lanes, window_micro, max_splits=0, sweep_Ts=()
     res["liftings_per_disk_before_timing"] = (e.stats()["events"] - d1["events"]) / s.n
     res["from_lattice"] = _summary(d0, w0, form)
     res["neighbours"] = neighbours or _neighbours
+    if form == "fp64" and (neighbours or _neighbours) == "graph":
+        res["production_loop"] = production_loop(e, s, steps)
     res["overlaps"] = e.overlaps()
     if sweep_Ts:
         res["violation_sweep"] = violation_sweep(e, s, sweep_Ts, sweep_legs, window_micro)

@@ -251,6 +251,19 @@ int ecmc_set_active(ecmc_ctx *ctx, const int32_t *idx, int32_t k);
 int ecmc_run(ecmc_ctx *ctx, int32_t n_chains, double chain_time,
              double breakpoint_interval, int32_t direction);
 
+/* n_legs legs of length T = breakpoint_interval, leg l along directions[l]
+ * (HOST array of n_legs int32: 0 +x, 1 +y, 2 -x, 3 -y).  A production loop
+ * changes v between breakpoints (Sec. 2.1: v is fixed within a leg; the
+ * constraint graph is rebuilt for each new v, Sec. 3.1 and the closing
+ * paragraph of Sec. 3.4 on production codes); the caller draws the
+ * directions, so the random numbers of the loop are inputs.  Everything else
+ * as ecmc_run with chain_time = n_legs T.  Errors: ECMC_EINVAL (n_legs < 0,
+ * directions NULL or T = 0 with n_legs > 0, a direction outside 0..3, and
+ * the checks of ecmc_run), ECMC_ESTATE, ECMC_ECELL, ECMC_EHANG,
+ * ECMC_EDEVICE. */
+int ecmc_run_directions(ecmc_ctx *ctx, int32_t n_chains, double breakpoint_interval, int64_t n_legs,
+                        const int32_t *directions);
+
 /* Statistics accumulated since ecmc_set_active.  events counts elements of
  * the lifting set L (Alg. 1 output); sum_b and pressure are the ECMC pressure
  * estimator, beta P / rho = 1 + sum of b_ij over liftings / chain time (the

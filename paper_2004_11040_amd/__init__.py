@@ -38,7 +38,7 @@ PROBE_EXPORTS = ("ecmc_probe_chase", "ecmc_probe_gather", "ecmc_probe_litmus_mp"
 
 # every symbol include/ecmc.h declares
 EXPORTS = (
-    "ecmc_workspace_bytes", "ecmc_init", "ecmc_set_active", "ecmc_run", "ecmc_stats",
+    "ecmc_workspace_bytes", "ecmc_init", "ecmc_set_active", "ecmc_run", "ecmc_run_directions", "ecmc_stats",
     "ecmc_get_positions", "ecmc_get_stamps", "ecmc_get_active", "ecmc_get_chain_sums",
     "ecmc_get_log", "ecmc_overlaps", "ecmc_overlaps_noalloc", "ecmc_graph", "ecmc_set_option",
     "ecmc_last_error",
@@ -110,6 +110,8 @@ def load_library(path: str = LIB_PATH):
     lib.ecmc_set_active.argtypes = [P, P, I32]
     lib.ecmc_run.restype = ctypes.c_int
     lib.ecmc_run.argtypes = [P, I32, D, D, I32]
+    lib.ecmc_run_directions.restype = ctypes.c_int
+    lib.ecmc_run_directions.argtypes = [P, I32, D, I64, P]
     lib.ecmc_stats.restype = ctypes.c_int
     lib.ecmc_stats.argtypes = [P, ctypes.POINTER(Stats)]
     for name in ("ecmc_get_positions", "ecmc_get_stamps", "ecmc_get_active"):
@@ -329,6 +331,12 @@ class Ecmc:
 
     def run_legs(self, n_legs, T, direction=DIR_ALTERNATE):
         self.run(n_legs * T, T, direction)
+
+    def run_directions(self, T, directions, n_chains=None):
+        """One leg of length T per entry of `directions` (0 +x, 1 +y, 2 -x, 3 -y)."""
+        d = np.ascontiguousarray(directions, dtype=np.int32)
+        self._check(self.lib.ecmc_run_directions(self._ctx, self.k if n_chains is None else int(n_chains),
+                                                 float(T), int(d.shape[0]), _np_ptr(d)))
 
     def set_option(self, key, value):
         self._check(self.lib.ecmc_set_option(self._ctx, int(key), int(value)))

@@ -4026,9 +4026,9 @@ int ecmc_set_active(ecmc_ctx *ctx, const int32_t *idx, int32_t k) {
   return ECMC_OK;
 }
 
-int ecmc_run(ecmc_ctx *ctx, int32_t n_chains, double chain_time, double breakpoint_interval,
-             int32_t direction) {
-  if (!ctx) return ECMC_EINVAL;
+namespace {
+// the checks shared by ecmc_run and ecmc_run_directions
+int check_run(ecmc_ctx *ctx, int32_t n_chains, double T) {
   if (!ctx->active_set) {
     ctx->err = "ecmc_set_active was not called";
     return ECMC_ESTATE;
@@ -4037,10 +4037,62 @@ int ecmc_run(ecmc_ctx *ctx, int32_t n_chains, double chain_time, double breakpoi
     ctx->err = "n_chains differs from the active set size";
     return ECMC_EINVAL;
   }
-  const double T = breakpoint_interval;
   const Geo &g = ctx->g;
-  if (!(T >= 0.0) || !(T <= g.L - 4.0 * g.c - g.d) || !(chain_time >= 0.0)) {
+  if (!(T >= 0.0) || !(T <= g.L - 4.0 * g.c - g.d)) {
     ctx->err = "leg length outside [0, box - 4 cell - 2 sigma]";
+    return ECMC_EINVAL;
+  }
+  return ECMC_OK;
+}
+
+// legs [0, n) of length T, leg l along dirs[l], or along `direction` (4:
+// alternate +x/+y, continuing across calls) when dirs is NULL
+int run_legs(ecmc_ctx *ctx, double T, int64_t n_legs, const int32_t *dirs, int32_t direction) {
+  if (ctx->events_ok) (void)hipEventRecord(ctx->ev0, ctx->stream);
+  for (int64_t l = 0; l < n_legs; ++l) {
+    const int dir = dirs ? (int)dirs[l] : (direction == 4 ? (int)(ctx->leg_counter & 1) : (int)direction);
+    int rc = run_leg(ctx, dir, T);
+    if (rc) return rc;
+    ctx->leg_counter++;
+    ctx->legs++;
+    ctx->chain_time += (double)ctx->D.k * T;
+  }
+  if (ctx->events_ok) {
+    (void)hipEventRecord(ctx->ev1, ctx->stream);
+    HIPCHK(hipEventSynchronize(ctx->ev1));
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1) == hipSuccess) ctx->device_ms += ms;
+  }
+  return ECMC_OK;
+}
+}  // namespace
+
+int ecmc_run_directions(ecmc_ctx *ctx, int32_t n_chains, double breakpoint_interval, int64_t n_legs,
+                        const int32_t *directions) {
+  if (!ctx) return ECMC_EINVAL;
+  const double T = breakpoint_interval;
+  int rc = check_run(ctx, n_chains, T);
+  if (rc) return rc;
+  if (n_legs < 0 || n_legs > (1ll << 40) || (n_legs > 0 && (!directions || !(T > 0.0)))) {
+    ctx->err = "n_legs < 0, or legs without directions or of zero length";
+    return ECMC_EINVAL;
+  }
+  for (int64_t l = 0; l < n_legs; ++l)
+    if (directions[l] < 0 || directions[l] > 3) {
+      ctx->err = "a leg direction is not 0 (+x), 1 (+y), 2 (-x) or 3 (-y)";
+      return ECMC_EINVAL;
+    }
+  return run_legs(ctx, T, n_legs, directions, 0);
+}
+
+int ecmc_run(ecmc_ctx *ctx, int32_t n_chains, double chain_time, double breakpoint_interval,
+             int32_t direction) {
+  if (!ctx) return ECMC_EINVAL;
+  const double T = breakpoint_interval;
+  int rc0 = check_run(ctx, n_chains, T);
+  if (rc0) return rc0;
+  if (!(chain_time >= 0.0)) {
+    ctx->err = "negative chain time";
     return ECMC_EINVAL;
   }
   if (direction < 0 || direction > 4) {
@@ -4057,22 +4109,7 @@ int ecmc_run(ecmc_ctx *ctx, int32_t n_chains, double chain_time, double breakpoi
       return ECMC_EINVAL;
     }
   }
-  if (ctx->events_ok) (void)hipEventRecord(ctx->ev0, ctx->stream);
-  for (int64_t l = 0; l < n_legs; ++l) {
-    const int dir = direction == 4 ? (int)(ctx->leg_counter & 1) : direction;
-    int rc = run_leg(ctx, dir, T);
-    if (rc) return rc;
-    ctx->leg_counter++;
-    ctx->legs++;
-    ctx->chain_time += (double)ctx->D.k * T;
-  }
-  if (ctx->events_ok) {
-    (void)hipEventRecord(ctx->ev1, ctx->stream);
-    HIPCHK(hipEventSynchronize(ctx->ev1));
-    float ms = 0.f;
-    if (hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1) == hipSuccess) ctx->device_ms += ms;
-  }
-  return ECMC_OK;
+  return run_legs(ctx, T, n_legs, nullptr, direction);
 }
 
 int ecmc_stats(ecmc_ctx *ctx, ecmc_stats_t *out) {
