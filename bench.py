@@ -575,6 +575,65 @@ def _pmc_values(path, counter):
     return out
 
 
+DERIVED_PCT = ("VALUBusy", "VALUUtilization", "OccupancyPercent")
+
+
+def trace_summary(trace_csv, bench_json, out_txt, command):
+    """Kernel statistics of a rocprofv3 kernel trace of a bench run, as text,
+    beside the bench's own device-timed mean duration of the event kernel per
+    form.  Event launches enqueued past the end of a leg return at once; the
+    launches that ran an attempt are told apart by their duration (over
+    RAN_US, a few times the empty launch's)."""
+    import csv
+    ran_us = 10.0
+    stats = {}
+    with open(trace_csv, newline="") as f:
+        for row in csv.DictReader(f):
+            name = row["Kernel_Name"]
+            dur = (int(row["End_Timestamp"]) - int(row["Start_Timestamp"])) * 1e-3  # us
+            st = stats.setdefault(name, [0, 0.0, 0, 0.0])
+            st[0] += 1
+            st[1] += dur
+            if dur > ran_us:
+                st[2] += 1
+                st[3] += dur
+    with open(bench_json) as f:
+        line = json.loads(next(ln for ln in f if ln.startswith("{")))
+    total = sum(v[1] for v in stats.values())
+
+    def short(n):
+        n = n.replace("(anonymous namespace)::", "")
+        return n.split("(")[0] if not n.startswith("void ") else n[5:].split("(")[0]
+
+    out = ["# rocprofv3 kernel statistics of a bench run (one MI355X)", "#",
+           "# command (from /tmp with TMPDIR=/tmp; <repo> = the repository root):"]
+    out += [f"#   {c}" for c in command]
+    out += [f"# source: paper_2004_11040_amd/csrc/ecmc_kernels.hip sha256[:16] = {_src_hash()}",
+            f"# bench line: value {line['value'] / 1e6:.2f} M liftings/s ({line['config']['form']}, "
+            f"{line['config']['neighbours']}), lag {line['config']['window_sigma']:g} sigma", "",
+            f"{'kernel':58s} {'calls':>7s} {'total_ms':>10s} {'avg_us':>9s} {'pct':>6s}  {'ran':>6s} {'avg_us_ran':>10s}"]
+    for name, (n, tot, nr, tr) in sorted(stats.items(), key=lambda kv: -kv[1][1])[:24]:
+        out.append(f"{short(name)[:58]:58s} {n:7d} {tot / 1e3:10.3f} {tot / n:9.2f} {100 * tot / total:6.2f}"
+                   f"  {nr:6d} {(tr / nr if nr else 0.0):10.2f}")
+    out += ["", "# event kernel: mean duration of the launches that ran an attempt",
+            "#   rocprofv3 (duration > 10 us) against the bench's device timing (s_memrealtime, first",
+            "#   workgroup start to last workgroup end)"]
+    tags = {"k_event<64, false, true>": "graph", "k_event<64, true, false>": "cells fp32",
+            "k_event<64, false, false>": "cells fp64"}
+    for kname, tag in tags.items():
+        hits = [v for n, v in stats.items() if short(n).replace(" ", "") == kname.replace(" ", "")]
+        if not hits:
+            continue
+        n, tot, nr, tr = hits[0]
+        out.append(f"  {kname:28s} rocprofv3 {tr / max(nr, 1):8.1f} us over {nr} launches")
+    for key, r in line.get("forms", {}).items():
+        out.append(f"  bench form {key:12s} ({r.get('neighbours')}): {r['kernel_ms_avg'] * 1e3:8.1f} us per launch, "
+                   f"{r['events_per_launch']:.0f} liftings per launch, {r['events_per_s'] / 1e6:.2f} M liftings/s")
+    with open(out_txt, "w") as f:
+        f.write("\n".join(out) + "\n")
+    print("\n".join(out))
+
+
 def pmc_summary(fetch_csv, write_csv, profile_log, extra_csvs=()):
     """Turn the counter runs of --profile-run (FETCH_SIZE, then WRITE_SIZE, and
     optionally L2 hit/miss and VALU counters) into the committed summary.
@@ -619,9 +678,20 @@ def pmc_summary(fetch_csv, write_csv, profile_log, extra_csvs=()):
         import csv
         with open(path, newline="") as f:
             names = sorted({row["Counter_Name"] for row in csv.DictReader(f)})
+        weight = dict(event_vals(path, "GRBM_GUI_ACTIVE")) if "GRBM_GUI_ACTIVE" in names else None
         for c in names:
             vals = event_vals(path, c)
-            d[f"{c}_per_launch"] = sum(v for _, v in vals) / launches
+            if c in DERIVED_PCT and weight:
+                # a percentage per dispatch: weighted by the dispatch's active cycles
+                wsum = sum(weight.get(i, 0.0) for i, _ in vals)
+                d[c] = sum(v * weight.get(i, 0.0) for i, v in vals) / wsum if wsum else None
+            else:
+                # other runs enqueue other numbers of rounds: sums, not per-launch values
+                d[f"{c}_sum"] = sum(v for _, v in vals)
+        if "TCC_HIT_sum" in names and "TCC_MISS_sum" in names:
+            hit = sum(v for _, v in event_vals(path, "TCC_HIT_sum"))
+            miss = sum(v for _, v in event_vals(path, "TCC_MISS_sum"))
+            d["L2_hit_rate"] = hit / (hit + miss) if hit + miss else None
     with open(pmc_summary_path(form), "w") as f:
         json.dump(d, f, indent=1)
     print(json.dumps(d))
@@ -633,6 +703,8 @@ def main():
                     help="only run LEGS legs and a 256 MiB copy (for rocprofv3 counters and traces)")
     ap.add_argument("--save-state", metavar="NPZ", help="burn the headline workload in and save it")
     ap.add_argument("--load-state", metavar="NPZ", help="--profile-run starts from a saved state")
+    ap.add_argument("--trace-summary", nargs="+", metavar="ARG",
+                    help="TRACE_CSV BENCH_JSON OUT_TXT COMMAND...: text summary of a kernel trace")
     ap.add_argument("--pmc-summary", nargs="+", metavar="CSV",
                     help="FETCH_CSV WRITE_CSV PROFILE_LOG [EXTRA_CSV ...]: write the counter summary")
     ap.add_argument("--gpus", type=int, default=1)
@@ -667,6 +739,10 @@ def main():
     args = ap.parse_args()
     globals()["_neighbours"] = args.neighbours
     globals()["_cooperative"] = args.cooperative_launch
+    if args.trace_summary:
+        a = args.trace_summary
+        trace_summary(a[0], a[1], a[2], a[3:])
+        return
     if args.pmc_summary:
         a = args.pmc_summary
         pmc_summary(a[0], a[1], a[2], a[3:])
@@ -723,7 +799,9 @@ def main():
             "implementation_bytes_per_launch": r["implementation_bytes_per_launch"]}
     pm = _pmc(main_form)
     if pm:
-        roof["counters"] = {k: v for k, v in pm.items() if k.endswith("_per_launch") or k.endswith("_per_event")}
+        roof["counters"] = {k: v for k, v in pm.items()
+                            if k.endswith("_per_launch") or k.endswith("_per_event") or k == "L2_hit_rate"
+                            or k in DERIVED_PCT}
     line = {
         "metric": "ECMC events/sec on 1 GPU, N=2^20 disks η=0.708: FP32-mixed vs FP64 form",
         "value": r["events_per_s"], "unit": "events/s", "n_gpus": 1, "steps": args.steps,
