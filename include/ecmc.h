@@ -93,8 +93,9 @@ extern "C" {
                                      scheduling: results do not depend on it.   */
 #define ECMC_OPT_FEATURES 10      /* bit set of the ECMC_FEAT_* refinements of the
                                      horizon protocol that are switched on
-                                     (default ECMC_FEAT_ALL); each only avoids
-                                     needless rollbacks                         */
+                                     (contexts: ECMC_FEAT_DEFAULT; batches:
+                                     ECMC_FEAT_ALL); each only avoids needless
+                                     rollbacks                                  */
 
 /* ---- refinements of the horizon protocol (ECMC_OPT_FEATURES) ------------ */
 #define ECMC_FEAT_SCREEN 1u   /* a lane minimum that fails Eq. 2 but is active on
@@ -112,6 +113,11 @@ extern "C" {
                                  back when it changes target or time, and when
                                  it leaves the attempt                        */
 #define ECMC_FEAT_ALL 31u
+#define ECMC_FEAT_DEFAULT 30u /* all but SCREEN: at N = 2^20 screening cleared a
+                                 few violations per 20 legs, for five stores
+                                 per lifting of the activation record that it
+                                 reads (about 200 B of HBM writes per lifting)
+                                 at no measurable gain in throughput          */
 #define ECMC_OPT_GRAPH 11         /* batches: 1 captures the persistent launch
                                      in a hipGraph once and replays it (every
                                      setting travels in the replica descriptors

@@ -31,6 +31,7 @@ OPT_COOPERATIVE = 14
 OPT_TEST_NONRESIDENT = 15
 NEIGHBOURS_CELLS, NEIGHBOURS_GRAPH = 0, 1
 FEAT_SCREEN, FEAT_RESERVE, FEAT_REREAD, FEAT_FRESH, FEAT_UNRESERVE, FEAT_ALL = 1, 2, 4, 8, 16, 31
+FEAT_DEFAULT = 30
 DIR_X, DIR_Y, DIR_MX, DIR_MY, DIR_ALTERNATE = 0, 1, 2, 3, 4
 
 # every symbol include/ecmc_probe.h declares (libecmc_probe.so)

@@ -1331,6 +1331,9 @@ __device__ void chain_events(const Dev &D, const Geo &g, const LegP &lp, int32_t
   double nxt_pub = -1.0;              // last next-event time published
   long long undo_n = D.UNDO_N[c];
   long long ref_ver = D.REF[c].ver;  // version of this chain's published activation
+  // the activation record serves the screening of false alarms only: without
+  // it nothing reads the record, and its five stores per lifting are skipped
+  const bool scr = (lp.features & ECMC_FEAT_SCREEN) != 0;
   long long cnt[NCNT];
   for (int q = 0; q < NCNT; ++q) cnt[q] = D.CNT_W[c * NCNT + q];
   double sumb = D.SUMB_W[c];
@@ -1492,7 +1495,7 @@ __device__ void chain_events(const Dev &D, const Geo &g, const LegP &lp, int32_t
           wait_mem();
           if (lane == 0) {
             strict_rel<SC>(lp.strict);
-            __hip_atomic_store(&D.REF[c].ver, rel_ver, __ATOMIC_RELAXED, SC);
+            if (scr) __hip_atomic_store(&D.REF[c].ver, rel_ver, __ATOMIC_RELAXED, SC);
             __hip_atomic_store(&D.TAG[rel_slot], TAG_STATIC, __ATOMIC_RELAXED, SC);  // release
           }
           rel_slot = -1;
@@ -1618,7 +1621,7 @@ __device__ void chain_events(const Dev &D, const Geo &g, const LegP &lp, int32_t
         wait_mem();
         if (lane == 0) {
           strict_rel<SC>(lp.strict);
-          __hip_atomic_store(&D.REF[c].ver, rel_ver, __ATOMIC_RELAXED, SC);
+          if (scr) __hip_atomic_store(&D.REF[c].ver, rel_ver, __ATOMIC_RELAXED, SC);
           __hip_atomic_store(&D.TAG[rel_slot], TAG_STATIC, __ATOMIC_RELAXED, SC);  // release
         }
         rel_slot = -1;
@@ -1672,7 +1675,7 @@ __device__ void chain_events(const Dev &D, const Geo &g, const LegP &lp, int32_t
         wait_mem();
         if (lane == 0) {
           strict_rel<SC>(lp.strict);
-          __hip_atomic_store(&D.REF[c].ver, rel_ver, __ATOMIC_RELAXED, SC);
+          if (scr) __hip_atomic_store(&D.REF[c].ver, rel_ver, __ATOMIC_RELAXED, SC);
           __hip_atomic_store(&D.TAG[rel_slot], TAG_STATIC, __ATOMIC_RELAXED, SC);  // release
         }
         rel_slot = -1;
@@ -1735,9 +1738,11 @@ __device__ void chain_events(const Dev &D, const Geo &g, const LegP &lp, int32_t
           __hip_atomic_compare_exchange_strong(&D.RES[res_slot], &o, RES_EMPTY, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
                                                SC);
         }
-        __hip_atomic_fetch_min(&D.RES[ts], mykey, __ATOMIC_RELAXED, SC);
-        res_slot = ts;
-        res_held = mykey;
+        if (res_slot != ts || res_held != mykey) {  // an unchanged reservation stands
+          __hip_atomic_fetch_min(&D.RES[ts], mykey, __ATOMIC_RELAXED, SC);
+          res_slot = ts;
+          res_held = mykey;
+        }
       } else if (res_slot >= 0 && (lp.features & ECMC_FEAT_UNRESERVE)) {
         unsigned long long o = res_held;
         __hip_atomic_compare_exchange_strong(&D.RES[res_slot], &o, RES_EMPTY, __ATOMIC_RELAXED, __ATOMIC_RELAXED, SC);
@@ -1902,7 +1907,7 @@ __device__ void chain_events(const Dev &D, const Geo &g, const LegP &lp, int32_t
       // ahead of the claim.  The wait after the claim completes both, so its
       // position needs no wait of its own.  If the lifting does not happen the
       // local time is put back.
-      __hip_atomic_store(&D.REF[c].ver, -1ll, __ATOMIC_RELAXED, SC);
+      if (scr) __hip_atomic_store(&D.REF[c].ver, -1ll, __ATOMIC_RELAXED, SC);
       st_a<SC>(&D.MUT[s].t, t + tau);
       won = __hip_atomic_compare_exchange_strong(&D.TAG[ts], &old, (uint32_t)c, __ATOMIC_RELAXED,
                                                  __ATOMIC_RELAXED, SC)
@@ -1940,7 +1945,7 @@ __device__ void chain_events(const Dev &D, const Geo &g, const LegP &lp, int32_t
           }
         }
       } else {
-        __hip_atomic_store(&D.REF[c].ver, ref_ver, __ATOMIC_RELAXED, SC);
+        if (scr) __hip_atomic_store(&D.REF[c].ver, ref_ver, __ATOMIC_RELAXED, SC);
         st_a<SC>(&D.MUT[s].t, t_prev);
       }
     }
@@ -2031,7 +2036,7 @@ __device__ void chain_events(const Dev &D, const Geo &g, const LegP &lp, int32_t
     stale = bcast<G>(stale, 0);
     if (stale == 2) {
       if (lane == 0) {
-        __hip_atomic_store(&D.REF[c].ver, ref_ver, __ATOMIC_RELAXED, SC);
+        if (scr) __hip_atomic_store(&D.REF[c].ver, ref_ver, __ATOMIC_RELAXED, SC);
         st_a<SC>(&D.MUT[s].t, t_prev);
         st_rel<SC>(&D.TAG[ts], TAG_STATIC);
       }
@@ -2042,7 +2047,7 @@ __device__ void chain_events(const Dev &D, const Geo &g, const LegP &lp, int32_t
     // the scan, and no lane minimum may have moved into question
     if (aj2 != t_aj || tj2 != t_tj || stale) {
       if (lane == 0) {
-        __hip_atomic_store(&D.REF[c].ver, ref_ver, __ATOMIC_RELAXED, SC);
+        if (scr) __hip_atomic_store(&D.REF[c].ver, ref_ver, __ATOMIC_RELAXED, SC);
         st_a<SC>(&D.MUT[s].t, t_prev);
         strict_rel<SC>(lp.strict);
         st_rel<SC>(&D.TAG[ts], TAG_STATIC);  // give the target back
@@ -2063,7 +2068,7 @@ __device__ void chain_events(const Dev &D, const Geo &g, const LegP &lp, int32_t
           live = __float_as_uint(__double2float_rd(nx)) == (uint32_t)(rk >> 32);
         }
         if (live) {
-          __hip_atomic_store(&D.REF[c].ver, ref_ver, __ATOMIC_RELAXED, SC);
+          if (scr) __hip_atomic_store(&D.REF[c].ver, ref_ver, __ATOMIC_RELAXED, SC);
           st_a<SC>(&D.MUT[s].t, t_prev);
           strict_rel<SC>(lp.strict);
           st_rel<SC>(&D.TAG[ts], TAG_STATIC);
@@ -2098,10 +2103,12 @@ __device__ void chain_events(const Dev &D, const Geo &g, const LegP &lp, int32_t
       }
       st_a<SC>(&D.MUT[ts].t, tn);  // t_j
       // t_i = tn was written before the claim and has completed
-      __hip_atomic_store(&D.REF[c].slot, ts, __ATOMIC_RELAXED, SC);
-      st_a<SC>(&D.REF[c].a, aj2);
-      st_a<SC>(&D.REF[c].t_act, tn);
-      st_a<SC>(&D.REF[c].t_rest, tj2);
+      if (scr) __hip_atomic_store(&D.REF[c].slot, ts, __ATOMIC_RELAXED, SC);
+      if (scr) {
+        st_a<SC>(&D.REF[c].a, aj2);
+        st_a<SC>(&D.REF[c].t_act, tn);
+        st_a<SC>(&D.REF[c].t_rest, tj2);
+      }
       unsigned long long used = mykey;  // the reservation is used
       __hip_atomic_compare_exchange_strong(&D.RES[ts], &used, RES_EMPTY, __ATOMIC_RELAXED, __ATOMIC_RELAXED, SC);
       res_slot = -1;
@@ -2144,7 +2151,7 @@ __device__ void chain_events(const Dev &D, const Geo &g, const LegP &lp, int32_t
     wait_mem();
     if (lane == 0) {
       strict_rel<SC>(lp.strict);
-      __hip_atomic_store(&D.REF[c].ver, rel_ver, __ATOMIC_RELAXED, SC);
+      if (scr) __hip_atomic_store(&D.REF[c].ver, rel_ver, __ATOMIC_RELAXED, SC);
       __hip_atomic_store(&D.TAG[rel_slot], TAG_STATIC, __ATOMIC_RELAXED, SC);  // release
     }
   }
@@ -3400,7 +3407,7 @@ struct ecmc_ctx {
   bool active_set = false;
   int32_t kernel_timing = 0;
   int32_t strict_order = 0;
-  int32_t features = ECMC_FEAT_ALL;
+  int32_t features = ECMC_FEAT_DEFAULT;
   int32_t graph = 1;          // 1: candidates from the constraint graph G(3), 0: corridor scan
   unsigned resident_nb = 0;   // grid size whose residency was last verified
   int32_t resident_key = 0;   // lanes * 4 + form of that check
