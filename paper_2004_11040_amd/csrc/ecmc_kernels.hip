@@ -599,7 +599,31 @@ __device__ __forceinline__ void rb_reset_one(const Dev &D, const Geo &g, double 
 constexpr int RB_E = 8;
 constexpr int RB_LIST = 4096;
 constexpr int RB_PER = RB_LIST / 1024;
-__device__ __forceinline__ bool rollback_block(const Dev &D, const Geo &g, double R, bool prep) {
+// One chain's values that the round end needs (the reductions, and the
+// rollback's inputs), loaded in one pass at the start of the round end: the
+// newest two lifting times are read beside the count they depend on, which
+// costs one more round trip for every chain at once instead of one per phase.
+struct RoundIn {
+  double next, a, t, e0, e1;
+  long long ev, sl, n;
+  int slot;
+};
+__device__ __forceinline__ RoundIn load_round_in(const Dev &D, int c) {
+  RoundIn r;
+  r.next = D.NEXT[c];
+  r.ev = D.CNT_W[c * NCNT + C_EVENTS];
+  r.sl = D.CNT_W[c * NCNT + C_SCANNED];
+  r.n = D.UNDO_N[c];
+  r.slot = D.CH_SLOT[c];
+  r.a = D.CH_A[c];
+  r.t = D.CH_T[c];
+  const UndoRec *base = D.UNDO + (int64_t)c * D.undo_cap;
+  r.e0 = r.n >= 1 ? base[r.n - 1].e : -INFINITY;
+  r.e1 = r.n >= 2 ? base[r.n - 2].e : -INFINITY;
+  return r;
+}
+
+__device__ __forceinline__ bool rollback_block(const Dev &D, const Geo &g, double R, bool prep, const RoundIn &ci) {
   __shared__ int2 s_list[RB_LIST];
   __shared__ int s_wsum[16], s_total;
   const int c = threadIdx.x;
@@ -611,14 +635,14 @@ __device__ __forceinline__ bool rollback_block(const Dev &D, const Geo &g, doubl
   long long ev_c = 0, sl_c = 0;  // the chain's lifting and scan counters
   const UndoRec *base = nullptr;
   if (act) {
-    n = D.UNDO_N[c];
-    ch_s = D.CH_SLOT[c];
-    ch_a = D.CH_A[c];
-    ch_t = D.CH_T[c];
-    ev_c = D.CNT_W[c * NCNT + C_EVENTS];
-    sl_c = D.CNT_W[c * NCNT + C_SCANNED];
+    n = ci.n;
+    ch_s = ci.slot;
+    ch_a = ci.a;
+    ch_t = ci.t;
+    ev_c = ci.ev;
+    sl_c = ci.sl;
     base = D.UNDO + (int64_t)c * D.undo_cap;
-    const double e0 = n >= 1 ? base[n - 1].e : -INFINITY, e1 = n >= 2 ? base[n - 2].e : -INFINITY;
+    const double e0 = ci.e0, e1 = ci.e1;
     cnt = (e0 >= R ? 1 : 0) + (e0 >= R && e1 >= R ? 1 : 0);
     if (cnt == 2)
       for (long long m = n - 3; m >= 0; m -= RB_E) {
@@ -2802,39 +2826,6 @@ __device__ __forceinline__ void round_reduce(const Dev &D, double *m_out, long l
   *sl_out = sl;
 }
 
-// The last event launch's span on the device: the first workgroup's start to
-// the last one's end, from the workgroups' own stamps (into ctl t_start, t_end).
-__device__ __forceinline__ void launch_span(const Dev &D) {
-  __shared__ unsigned long long s_t0[16], s_t1[16];
-  const int nb = D.ctl->ev_blocks;
-  unsigned long long t0 = ~0ull, t1 = 0ull;
-  for (int b = threadIdx.x; b < nb; b += blockDim.x) {
-    const unsigned long long a = D.TS[2 * b], z = D.TS[2 * b + 1];
-    t0 = a < t0 ? a : t0;
-    t1 = z > t1 ? z : t1;
-  }
-  for (int off = 32; off > 0; off >>= 1) {
-    const unsigned long long a = __shfl_xor(t0, off, 64), z = __shfl_xor(t1, off, 64);
-    t0 = a < t0 ? a : t0;
-    t1 = z > t1 ? z : t1;
-  }
-  __syncthreads();
-  if ((threadIdx.x & 63) == 0) {
-    s_t0[threadIdx.x >> 6] = t0;
-    s_t1[threadIdx.x >> 6] = t1;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    for (int q = 1; q < (int)((blockDim.x + 63) >> 6); ++q) {
-      t0 = s_t0[q] < t0 ? s_t0[q] : t0;
-      t1 = s_t1[q] > t1 ? s_t1[q] : t1;
-    }
-    D.ctl->t_start = t0;
-    D.ctl->t_end = t1;
-  }
-  __syncthreads();
-}
-
 // Prepare an attempt from lc.h: reset the attempt's flags, tag every chain's
 // disk, seed next-event times, record the work counters before the launch.
 __device__ __forceinline__ void round_prep(const Dev &D) {
@@ -2896,8 +2887,7 @@ __global__ void __launch_bounds__(1024) k_leg_init(Dev D, double T, double windo
 }
 
 // The decision after an attempt (thread 0): returns nothing; writes lc.
-__device__ __forceinline__ void round_decide(const Dev &D, double H, long long ev_after, long long sl_after) {
-  Ctl &C = *D.ctl;
+__device__ __forceinline__ void round_decide(Ctl &C, double H, long long ev_after, long long sl_after) {
   LegCtl &lc = C.lc;
   lc.rounds++;
   if (C.error) {
@@ -3021,21 +3011,79 @@ __global__ void __launch_bounds__(1024) k_round_end(Dev D, Geo g, LegP lp0) {
     global_order(D, g, lp);
     __syncthreads();
   }
-  double H;
-  long long e, sl;
-  round_reduce(D, &H, &e, &sl);
-  launch_span(D);
-  if (threadIdx.x == 0) {
-    round_decide(D, H, e, sl);
-    s_rb = D.ctl->lc.do_rb;
-    s_R = D.ctl->lc.R;
-    s_run = D.ctl->lc.phase == PH_RUN;
+  // the control block, the chains' values and the workgroups' stamps are
+  // loaded together; the decision is taken on a copy in LDS and written back
+  constexpr int NW = (int)(sizeof(Ctl) / 8);
+  static_assert(sizeof(Ctl) % 8 == 0, "the control block is copied in 8-byte words");
+  __shared__ unsigned long long s_ctl[NW];
+  __shared__ double s_m[16];
+  __shared__ long long s_e[16], s_sl[16];
+  __shared__ unsigned long long s_t0[16], s_t1[16];
+  for (int w = threadIdx.x; w < NW; w += blockDim.x) s_ctl[w] = ((const unsigned long long *)D.ctl)[w];
+  const bool fastk = D.k <= (int)blockDim.x;
+  RoundIn ci;
+  double H = INFINITY;
+  long long e = 0, sl = 0;
+  if (fastk) {
+    if ((int)threadIdx.x < D.k) {
+      ci = load_round_in(D, threadIdx.x);
+      H = ci.next;
+      e = ci.ev;
+      sl = ci.sl;
+    }
+  } else {
+    for (int c = threadIdx.x; c < D.k; c += blockDim.x) {
+      H = fmin(H, D.NEXT[c]);
+      e += D.CNT_W[c * NCNT + C_EVENTS];
+      sl += D.CNT_W[c * NCNT + C_SCANNED];
+    }
+  }
+  unsigned long long t0 = ~0ull, t1 = 0ull;
+  __syncthreads();  // s_ctl complete
+  for (int b = threadIdx.x; b < ((const Ctl *)s_ctl)->ev_blocks; b += blockDim.x) {
+    const unsigned long long a0 = D.TS[2 * b], z0 = D.TS[2 * b + 1];
+    t0 = a0 < t0 ? a0 : t0;
+    t1 = z0 > t1 ? z0 : t1;
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    H = fmin(H, __shfl_xor(H, off, 64));
+    e += __shfl_xor(e, off, 64);
+    sl += __shfl_xor(sl, off, 64);
+    const unsigned long long a0 = __shfl_xor(t0, off, 64), z0 = __shfl_xor(t1, off, 64);
+    t0 = a0 < t0 ? a0 : t0;
+    t1 = z0 > t1 ? z0 : t1;
+  }
+  if ((threadIdx.x & 63) == 0) {
+    s_m[threadIdx.x >> 6] = H;
+    s_e[threadIdx.x >> 6] = e;
+    s_sl[threadIdx.x >> 6] = sl;
+    s_t0[threadIdx.x >> 6] = t0;
+    s_t1[threadIdx.x >> 6] = t1;
   }
   __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int q = 1; q < (int)((blockDim.x + 63) >> 6); ++q) {
+      H = fmin(H, s_m[q]);
+      e += s_e[q];
+      sl += s_sl[q];
+      t0 = s_t0[q] < t0 ? s_t0[q] : t0;
+      t1 = s_t1[q] > t1 ? s_t1[q] : t1;
+    }
+    Ctl &C = *(Ctl *)s_ctl;
+    C.t_start = t0;
+    C.t_end = t1;
+    round_decide(C, H, e, sl);
+    s_rb = C.lc.do_rb;
+    s_R = C.lc.R;
+    s_run = C.lc.phase == PH_RUN;
+  }
+  __syncthreads();
+  for (int w = threadIdx.x; w < NW; w += blockDim.x) ((unsigned long long *)D.ctl)[w] = s_ctl[w];
+  __syncthreads();  // the writes below (rollback, preparation) follow the copy's
   // the fast rollback prepares the next attempt itself (h = R after a rollback)
   bool prepared = false;
   if (s_rb) {
-    const bool fast = D.k <= (int)blockDim.x && rollback_block(D, g, s_R, s_run != 0);
+    const bool fast = fastk && rollback_block(D, g, s_R, s_run != 0, ci);
     if (!fast) {
       const double R = s_R;
       for (int c = threadIdx.x; c < D.k; c += blockDim.x) rb_mark_one(D, R, c);
