@@ -503,6 +503,9 @@ def run_batch(n_rep, target, t_frac, graph=1, window_micro=0, max_splits=0):
            "global_runs": info["global_runs"],
            "rollbacks_per_replica_leg": info["rollbacks"] / max(info["legs"], 1),
            "global_runs_per_replica_leg": info["global_runs"] / max(info["legs"], 1),
+           # per-leg counts grow with the leg length; per lifting they do not
+           "rollbacks_per_1000_liftings": 1000.0 * info["rollbacks"] / max(ev1 - ev0, 1),
+           "global_runs_per_1000_liftings": 1000.0 * info["global_runs"] / max(ev1 - ev0, 1),
            "autotune_events_per_ms_by_lane_cap": dict(zip(("4", "8", "16", "32"), tune["tune_events_per_ms"])),
            "autotune_events_per_ms_by_cell_pct": dict(zip(("100", "115", "130", "141"),
                                                           tune["tune_cell_events_per_ms"])),
@@ -723,7 +726,7 @@ def main():
     ap.add_argument("--batch-replicas", type=int, default=512)
     ap.add_argument("--batch-events", type=int, default=1_000_000)
     ap.add_argument("--batch-leg-frac", type=float, default=0.25)
-    ap.add_argument("--batch-window-micro", type=int, default=350_000,
+    ap.add_argument("--batch-window-micro", type=int, default=200_000,
                     help="bounded lag between a replica's chains, in 1e-6 sigma (0: free running)")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-configs", action="store_true", help="skip the 256/4096/65536-disk workloads")
