@@ -200,6 +200,9 @@ typedef struct {
   int64_t nonresident_launches;  /* plain event launches whose co-residency
                                     handshake timed out (taken back, rerun)   */
   int64_t cooperative;           /* 1 once event launches are cooperative      */
+  int64_t clock_iters;           /* passes of the clock workgroup's loop over the
+                                    timed event launches (the clock's period is
+                                    event_kernel_ms / clock_iters)             */
 } ecmc_stats_t;
 
 /* Bytes of device workspace for a context (the storage of the lifted

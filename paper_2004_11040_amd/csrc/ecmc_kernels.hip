@@ -101,6 +101,7 @@ struct LegCtl {
   long long attempts, reruns, lockstep_runs, global_runs, legs_violated;
   long long timed_events, timed_slots, event_launches, event_ticks, rounds;
   long long nonresident;  // launches retried because not every workgroup became resident
+  long long clock_iters;  // passes of the clock loop over the attempts
   unsigned long long vkind[NVK];
 };
 
@@ -125,7 +126,7 @@ struct Ctl {
   // device timing of the last event launch (s_memrealtime ticks)
   unsigned long long t_start, t_end;
   int32_t not_resident;   // part of the launch's grid had not started after a long wait (grid_not_resident)
-  int32_t pad2;
+  int32_t clock_iters;    // passes of the clock workgroup's loop in the last event launch
   LegCtl lc;
 };
 // loops bounded by an iteration limit (reported with ECMC_EHANG)
@@ -799,6 +800,7 @@ __device__ __forceinline__ bool rollback_block(const Dev &D, const Geo &g, doubl
       for (int q = 0; q < NVK; ++q) C.vkind_cnt[q] = 0ull;
       C.t_start = ~0ull;
       C.t_end = 0ull;
+      C.clock_iters = 0;
       C.tot_events[0] = e;
       C.tot_slots[0] = sl;
     }
@@ -1291,33 +1293,74 @@ __device__ __forceinline__ bool grid_not_resident(const Dev &D, int expect, unsi
   return true;
 }
 
+// A workgroup barrier that waits for LDS traffic only: loads from global
+// memory issued before it stay in flight across it (a plain __syncthreads
+// waits for every outstanding load).
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// The clock: H = the smallest next-event time over the chains, published
+// while any chain runs.  Each pass reduces the values loaded by the pass
+// before and issues the next pass's loads first, so the loads of one pass
+// fly while the previous one is reduced and published (next-event times only
+// grow within a launch, so values one pass old give a lower bound of H, as H
+// must be; the stop words are read one pass late as well).
+constexpr int CLOCK_PER_THREAD = 4;
 __device__ void clock_loop(const Dev &D, long long iter_cap, int expect) {
   __shared__ double red[16];
   __shared__ int s_quit;
   double hc = ld_a(&D.ctl->clock);
   const int nw = (int)((blockDim.x + 63) >> 6);
   const unsigned long long t0 = __builtin_amdgcn_s_memrealtime();
+  const bool pipe = D.k <= CLOCK_PER_THREAD * (int)blockDim.x;
+  double nx[CLOCK_PER_THREAD];
+  int done = 0, ab = 0, er = 0;
+  if (pipe) {
+#pragma unroll
+    for (int j = 0; j < CLOCK_PER_THREAD; ++j) {
+      const int c = threadIdx.x + j * (int)blockDim.x;
+      nx[j] = c < D.k ? ld_a(&D.NEXT[c]) : INFINITY;
+    }
+  }
   for (long long it = 0;; ++it) {
     double m = INFINITY;
-#pragma unroll 4
-    for (int c = threadIdx.x; c < D.k; c += blockDim.x) m = fmin(m, ld_a(&D.NEXT[c]));
-    int done = 0, ab = 0, er = 0;
-    if (threadIdx.x == 0) {
-      done = __hip_atomic_load(&D.ctl->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      ab = __hip_atomic_load(&D.ctl->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      er = __hip_atomic_load(&D.ctl->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
+    int done_p = done, ab_p = ab, er_p = er;  // the stop words of the previous pass
+    if (pipe) {
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) m = fmin(m, __shfl_xor(m, off, 64));
+      for (int j = 0; j < CLOCK_PER_THREAD; ++j) m = fmin(m, nx[j]);
+      if (threadIdx.x == 0) {
+        done = __hip_atomic_load(&D.ctl->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        ab = __hip_atomic_load(&D.ctl->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        er = __hip_atomic_load(&D.ctl->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+#pragma unroll
+      for (int j = 0; j < CLOCK_PER_THREAD; ++j) {
+        const int c = threadIdx.x + j * (int)blockDim.x;
+        nx[j] = c < D.k ? ld_a(&D.NEXT[c]) : INFINITY;
+      }
+    } else {
+#pragma unroll 4
+      for (int c = threadIdx.x; c < D.k; c += blockDim.x) m = fmin(m, ld_a(&D.NEXT[c]));
+      if (threadIdx.x == 0) {
+        done_p = __hip_atomic_load(&D.ctl->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        ab_p = __hip_atomic_load(&D.ctl->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        er_p = __hip_atomic_load(&D.ctl->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+    }
+    // next-event times are >= 0 (or +inf): their bit patterns order as unsigned integers
+    m = __longlong_as_double((long long)wave_umin64((unsigned long long)__double_as_longlong(m + 0.0)));
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
-    __syncthreads();
+    lds_barrier();
     if (threadIdx.x == 0) {
       for (int q = 1; q < nw; ++q) m = fmin(m, red[q]);
       if (m > hc) {
         hc = m;
         st_a(&D.ctl->clock, hc);
       }
-      int quit = (done >= D.k || ab || er) ? 1 : 0;
+      int quit = (it > 0 || !pipe) && (done_p >= D.k || ab_p || er_p) ? 1 : 0;
       if (!quit && grid_not_resident(D, expect, __builtin_amdgcn_s_memrealtime() - t0)) quit = 1;
       if (!quit && it >= iter_cap) {
         atomicExch(&D.ctl->hang_site, (int32_t)HS_CLOCK);
@@ -1327,9 +1370,13 @@ __device__ void clock_loop(const Dev &D, long long iter_cap, int expect) {
       }
       s_quit = quit;
     }
-    __syncthreads();
-    if (s_quit) break;
+    lds_barrier();
+    if (s_quit) {
+      if (threadIdx.x == 0) D.ctl->clock_iters = (int32_t)(it + 1 < 0x7fffffff ? it + 1 : 0x7fffffff);
+      break;
+    }
   }
+  __syncthreads();  // the last pass's loads complete before the workgroup leaves
 }
 
 // Event arithmetic always starts from the chain's reference: the position a and
@@ -2844,6 +2891,7 @@ __device__ __forceinline__ void round_prep(const Dev &D) {
     for (int q = 0; q < NVK; ++q) C.vkind_cnt[q] = 0ull;
     C.t_start = ~0ull;
     C.t_end = 0ull;
+    C.clock_iters = 0;
   }
   for (int c = threadIdx.x; c < D.k; c += blockDim.x) chains_attempt_one(D, h, c);
   double m;
@@ -2880,6 +2928,7 @@ __global__ void __launch_bounds__(1024) k_leg_init(Dev D, double T, double windo
     lc.attempts = lc.reruns = lc.lockstep_runs = lc.global_runs = lc.legs_violated = 0;
     lc.timed_events = lc.timed_slots = lc.event_launches = lc.event_ticks = lc.rounds = 0;
     lc.nonresident = 0;
+    lc.clock_iters = 0;
     for (int q = 0; q < NVK; ++q) lc.vkind[q] = 0ull;
   }
   __syncthreads();
@@ -2916,6 +2965,7 @@ __device__ __forceinline__ void round_decide(Ctl &C, double H, long long ev_afte
   if (C.t_end > C.t_start) {
     lc.event_ticks += (long long)(C.t_end - C.t_start);
     lc.event_launches++;
+    lc.clock_iters += C.clock_iters;
   }
   for (int q = 0; q < NVK; ++q) lc.vkind[q] += C.vkind_cnt[q];
   if (lc.mode == MD_LOCKSTEP) lc.lockstep_runs++;
@@ -3463,6 +3513,7 @@ struct ecmc_ctx {
                               // by the runtime); 0: plain launch checked by the arrival handshake
   int32_t resident_hook = 0;  // test hook: extra arrivals a plain launch's handshake expects
   int64_t nonresident = 0;    // plain launches whose handshake timed out
+  int64_t clock_iters = 0;    // passes of the clock loop over all timed launches
   int64_t vkind[NVK] = {0, 0, 0, 0, 0};
   int32_t last_v_kind = -1, last_v_chain = -1, last_v_id = -1;
   double last_v_t = 0.0, last_v_tj = 0.0, last_v_tau = 0.0, last_v_h = 0.0;
@@ -3873,6 +3924,7 @@ int run_leg(ecmc_ctx *ctx, int dir, double T) {
     ctx->global_legs += lc.global_runs;
     ctx->legs_violated += lc.legs_violated;
     ctx->nonresident += lc.nonresident;
+    ctx->clock_iters += lc.clock_iters;
     for (int q = 0; q < NVK; ++q) ctx->vkind[q] += (int64_t)lc.vkind[q];
     if (hc.vkind_first >= 0) {
       ctx->last_v_kind = hc.vkind_first;
@@ -4210,6 +4262,7 @@ int ecmc_stats(ecmc_ctx *ctx, ecmc_stats_t *out) {
   for (int q = 0; q < 4; ++q) out->violations_by_kind[q] = ctx->vkind[q];
   out->spin_aborts = ctx->vkind[VK_SPIN];
   out->nonresident_launches = ctx->nonresident;
+  out->clock_iters = ctx->clock_iters;
   out->cooperative = ctx->cooperative;
   out->last_violation_kind = ctx->last_v_kind;
   out->last_violation_chain = ctx->last_v_chain;
