@@ -453,11 +453,12 @@ def run_probes(k):
     return out
 
 
-def run_batch(n_rep, target, t_frac, graph=1, window_micro=0, max_splits=0):
+def run_batch(n_rep, target, t_frac, graph=1, window_micro=0, max_splits=0, form="fp64", neighbours="graph"):
     """The replica workload: n_rep seeded replicas of N in {1024..16384}, eta in
-    [0.60, 0.72], k = round(sqrt N), FP32-mixed, run in one persistent launch
-    (captured in a hipGraph) until every replica has `target` liftings; the
-    autotuner's legs come first and are not timed."""
+    [0.60, 0.72], k = round(sqrt N), run in one persistent launch (captured in
+    a hipGraph) until every replica has `target` liftings; the autotuner's legs
+    come first and are not timed.  With graph candidates every time of flight
+    is binary64 (form fp64); FP32-mixed acts on the corridor scan."""
     import numpy as np
     import torch
 
@@ -466,13 +467,13 @@ def run_batch(n_rep, target, t_frac, graph=1, window_micro=0, max_splits=0):
     reps = W.replica_batch(n_rep)
     systems = []
     for s in reps:
-        e = pkg.Ecmc(np.stack([s.x, s.y], 1), s.sigma, s.L, flags=pkg.FP32_MIXED, max_chains=s.k,
-                     log_cap=1 << 8)
+        e = pkg.Ecmc(np.stack([s.x, s.y], 1), s.sigma, s.L, flags=pkg.FP32_MIXED if form == "fp32" else pkg.FP64,
+                     max_chains=s.k, log_cap=1 << 8)
         e.set_active(s.active)
         systems.append(e)
     b = pkg.Batch(systems)
     b.set_option(pkg.OPT_GRAPH, graph)
-    b.set_option(pkg.OPT_NEIGHBOURS, NEIGHBOURS[_neighbours])
+    b.set_option(pkg.OPT_NEIGHBOURS, NEIGHBOURS[neighbours])
     b.set_option(pkg.OPT_WINDOW_MICRO, window_micro)
     if max_splits:
         b.set_option(pkg.OPT_MAX_SPLITS, max_splits)
@@ -498,7 +499,8 @@ def run_batch(n_rep, target, t_frac, graph=1, window_micro=0, max_splits=0):
     log(f"batch: {ev1 - ev0} liftings in {wall:.2f} s")
     overlaps = sum(e.overlaps() for e in systems)
     out = {"workload": f"{n_rep} replicas, N in 64*[16,256], eta in [0.60,0.72], k=round(sqrt N), "
-                       f"legs of {t_frac} L alternating +x/+y, FP32-mixed, {target} liftings per replica, "
+                       f"legs of {t_frac} L alternating +x/+y, {form} with {neighbours} candidates, "
+                       f"{target} liftings per replica, "
                        f"bounded lag {window_micro * 1e-6:g} sigma",
            "events": ev1 - ev0, "wall_s": wall, "events_per_s": (ev1 - ev0) / wall,
            "device_ms": info["device_ms"], "lanes": info["lanes"], "graph": info["graph"],
@@ -848,6 +850,10 @@ def main():
     if not args.no_batch:
         line["batch"] = run_batch(args.batch_replicas, args.batch_events, args.batch_leg_frac,
                                   window_micro=args.batch_window_micro)
+        # the FP32-mixed batch: on the corridor scan, where the binary32 filter acts
+        line["batch_fp32_cells"] = run_batch(args.batch_replicas, args.batch_events, args.batch_leg_frac,
+                                             window_micro=args.batch_window_micro, form="fp32",
+                                             neighbours="cells")
         if cpu_batch:
             line["batch"]["cpu_oracle_all_cores"] = cpu_batch
     if cpu:
