@@ -734,6 +734,8 @@ def main():
     ap.add_argument("--batch-window-micro", type=int, default=200_000,
                     help="bounded lag between a replica's chains, in 1e-6 sigma (0: free running)")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--batch-only", action="store_true",
+                    help="run only the replica batch (FP64, graph candidates) and print its result")
     ap.add_argument("--no-configs", action="store_true", help="skip the 256/4096/65536-disk workloads")
     ap.add_argument("--precision-events", type=int, default=100_000_000)
     ap.add_argument("--sweep-legs", type=int, default=40)
@@ -759,6 +761,14 @@ def main():
         print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
+    if args.batch_only:
+        import torch
+        assert torch.cuda.is_available(), "bench.py needs a GPU"
+        torch.cuda.set_device(0)
+        r = run_batch(args.batch_replicas, args.batch_events, args.batch_leg_frac,
+                      window_micro=args.batch_window_micro)
+        print(json.dumps({"batch": r}), flush=True)
+        return
     if args.save_state or args.profile_run:
         import torch
         assert torch.cuda.is_available(), "bench.py needs a GPU"
