@@ -307,25 +307,31 @@ def violation_sweep(e, s, Ts, n_legs, window_micro):
     return out
 
 
+LATTICE_LEGS = 20      # timed legs from the lattice (the transient, reported beside the headline)
+PRODUCTION_LEGS = 20   # legs of the production loop (directions drawn per leg)
+
+
 def run_form(form, steps, warmup, lanes, window_micro, max_splits=0, sweep_Ts=(), sweep_legs=40, neighbours=None):
-    """The headline workload in one form: `warmup` untimed legs and `steps`
-    timed legs from the lattice, then a burn-in to >= 50 liftings per disk and
-    `steps` timed legs again (the headline), then the violation sweep."""
+    """The headline workload in one form: `warmup` untimed legs and
+    LATTICE_LEGS timed legs from the lattice, then a burn-in to >= 50
+    liftings per disk and `steps` timed legs (the headline), then the
+    production loop and the violation sweep."""
     import workloads as W
     s = W.config(4)
     e = _make(s, form, lanes, window_micro, max_splits=max_splits, neighbours=neighbours)
     if warmup:
         e.run(warmup * s.T, s.T, 4)
-    d0, w0 = timed_legs(e, s, n_legs=steps, label=f"{form} from the lattice")
+    d0, w0 = timed_legs(e, s, n_legs=LATTICE_LEGS, label=f"{form} from the lattice")
     bl = burn_in(e, s)
     d1, w1 = timed_legs(e, s, n_legs=steps, label=f"{form} after burn-in")
     res = _summary(d1, w1, form)
-    res["burn_in_legs"] = bl + warmup + steps
+    res["timed_legs"] = steps
+    res["burn_in_legs"] = bl + warmup + LATTICE_LEGS
     res["liftings_per_disk_before_timing"] = (e.stats()["events"] - d1["events"]) / s.n
     res["from_lattice"] = _summary(d0, w0, form)
     res["neighbours"] = neighbours or _neighbours
     if form == "fp64" and (neighbours or _neighbours) == "graph":
-        res["production_loop"] = production_loop(e, s, steps)
+        res["production_loop"] = production_loop(e, s, PRODUCTION_LEGS)
     res["overlaps"] = e.overlaps()
     if sweep_Ts:
         res["violation_sweep"] = violation_sweep(e, s, sweep_Ts, sweep_legs, window_micro)
@@ -716,7 +722,9 @@ def main():
     ap.add_argument("--pmc-summary", nargs="+", metavar="CSV",
                     help="FETCH_CSV WRITE_CSV PROFILE_LOG [EXTRA_CSV ...]: write the counter summary")
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20, help="timed legs")
+    ap.add_argument("--steps", type=int, default=4800,
+                    help="timed legs of the headline form after the burn-in (4800: just over 1e9 liftings "
+                         "at N=2^20, the workload's budget per form)")
     ap.add_argument("--warmup", type=int, default=5, help="untimed legs before the lattice timing")
     ap.add_argument("--form", choices=["fp64", "fp32", "both"], default="both")
     ap.add_argument("--lanes", type=int, default=64)
@@ -798,7 +806,10 @@ def main():
         plan = [("fp64", "fp64", args.neighbours), ("fp32", "fp32", "cells"), ("fp64_cells", "fp64", "cells")]
     else:
         plan = [(args.form, args.form, args.neighbours)]
-    results = {key: run_form(form, args.steps, args.warmup, args.lanes, args.window_micro, args.max_splits,
+    # FP64 on the corridor scan is a like-for-like reference for the FP32-mixed
+    # form: a tenth of the legs
+    results = {key: run_form(form, args.steps if key != "fp64_cells" else max(args.steps // 10, 20),
+                             args.warmup, args.lanes, args.window_micro, args.max_splits,
                              sweep_Ts=sweep_Ts if key == "fp64" else (), sweep_legs=args.sweep_legs,
                              neighbours=nb)
                for key, form, nb in plan}
