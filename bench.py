@@ -186,9 +186,10 @@ def _stats_delta(st0, st1):
 NEIGHBOURS = {"cells": 0, "graph": 1}
 _neighbours = "graph"
 _cooperative = False
+_clock_period_ns = 0   # pacing of the clock workgroup for the headline context (set from the command line)
 
 
-def _make(s, form, lanes, window_micro, log_cap=1 << 12, max_splits=0, neighbours=None):
+def _make(s, form, lanes, window_micro, log_cap=1 << 12, max_splits=0, neighbours=None, clock_period_ns=0):
     import numpy as np
 
     import paper_2004_11040_amd as pkg
@@ -199,6 +200,7 @@ def _make(s, form, lanes, window_micro, log_cap=1 << 12, max_splits=0, neighbour
     e.set_option(pkg.OPT_WINDOW_MICRO, window_micro)
     e.set_option(pkg.OPT_NEIGHBOURS, NEIGHBOURS[neighbours or _neighbours])
     e.set_option(pkg.OPT_COOPERATIVE, 1 if _cooperative else 0)
+    e.set_option(pkg.OPT_CLOCK_PERIOD_NS, clock_period_ns)
     if max_splits:
         e.set_option(pkg.OPT_MAX_SPLITS, max_splits)
     e.set_active(s.active)
@@ -294,9 +296,11 @@ def production_loop(e, s, n_legs, seed=11):
 def violation_sweep(e, s, Ts, n_legs, window_micro):
     """Violation probability per breakpoint (legs whose first attempt saw a
     horizon violation / legs) for each leg length T, with the same bounded lag
-    at every size so that the sizes compare."""
+    at every size so that the sizes compare (and the clock unpaced at every
+    size)."""
     import paper_2004_11040_amd as pkg
     e.set_option(pkg.OPT_WINDOW_MICRO, window_micro)
+    e.set_option(pkg.OPT_CLOCK_PERIOD_NS, 0)
     out = {}
     direction = pkg.DIR_ALTERNATE if s.alternate else pkg.DIR_X
     for T in Ts:
@@ -311,14 +315,16 @@ LATTICE_LEGS = 20      # timed legs from the lattice (the transient, reported be
 PRODUCTION_LEGS = 20   # legs of the production loop (directions drawn per leg)
 
 
-def run_form(form, steps, warmup, lanes, window_micro, max_splits=0, sweep_Ts=(), sweep_legs=40, neighbours=None):
+def run_form(form, steps, warmup, lanes, window_micro, max_splits=0, sweep_Ts=(), sweep_legs=40, neighbours=None,
+             clock_period_ns=0):
     """The headline workload in one form: `warmup` untimed legs and
     LATTICE_LEGS timed legs from the lattice, then a burn-in to >= 50
     liftings per disk and `steps` timed legs (the headline), then the
     production loop and the violation sweep."""
     import workloads as W
     s = W.config(4)
-    e = _make(s, form, lanes, window_micro, max_splits=max_splits, neighbours=neighbours)
+    e = _make(s, form, lanes, window_micro, max_splits=max_splits, neighbours=neighbours,
+              clock_period_ns=clock_period_ns)
     if warmup:
         e.run(warmup * s.T, s.T, 4)
     d0, w0 = timed_legs(e, s, n_legs=LATTICE_LEGS, label=f"{form} from the lattice")
@@ -330,6 +336,8 @@ def run_form(form, steps, warmup, lanes, window_micro, max_splits=0, sweep_Ts=()
     res["liftings_per_disk_before_timing"] = (e.stats()["events"] - d1["events"]) / s.n
     res["from_lattice"] = _summary(d0, w0, form)
     res["neighbours"] = neighbours or _neighbours
+    res["window_sigma"] = window_micro * 1e-6
+    res["clock_period_ns"] = clock_period_ns
     if form == "fp64" and (neighbours or _neighbours) == "graph":
         res["production_loop"] = production_loop(e, s, PRODUCTION_LEGS)
     res["overlaps"] = e.overlaps()
@@ -368,7 +376,10 @@ def run_small_configs(lanes, sweep_Ts, sweep_legs, window_micro):
 def run_precision_config(lanes, window_micro, target, prefix_events, sweep_Ts, sweep_legs):
     """The 65536-disk workload in both forms: the error of each form against
     the binary64 oracle over the legs that cover the first prefix_events
-    liftings, then timed legs up to `target` liftings, and the pressure."""
+    liftings, then timed legs up to `target` liftings, and the pressure.
+    FP32-mixed runs on the corridor scan, where its binary32 filter acts (the
+    graph path has no binary32 stage), beside FP64 on the same scan (a tenth
+    of the liftings) and FP64 on graph candidates (the default)."""
     import numpy as np
 
     import oracle
@@ -383,8 +394,9 @@ def run_precision_config(lanes, window_micro, target, prefix_events, sweep_Ts, s
         ref = oracle.run(s.x, s.y, s.sigma, s.L, s.active, s.leg_dirs(legs), s.T, log_cap=1 << 23)
         ref_ev = ref.n_events
     log(f"N=65536 oracle prefix: {legs} legs, {ref_ev} liftings, {time.perf_counter() - t0:.1f} s")
-    for form in ("fp64", "fp32"):
-        e = _make(s, form, lanes, window_micro, log_cap=1 << 14)
+    for key, form, nb, tgt in (("fp64", "fp64", "graph", target), ("fp32", "fp32", "cells", target),
+                               ("fp64_cells", "fp64", "cells", max(target // 10, prefix_events))):
+        e = _make(s, form, lanes, window_micro, log_cap=1 << 14, neighbours=nb)
         e.run(legs * s.T, s.T, 4)
         pos = e.positions()
         dx = np.abs((pos[:, 0] - ref.x + s.L / 2) % s.L - s.L / 2).max()
@@ -397,13 +409,14 @@ def run_precision_config(lanes, window_micro, target, prefix_events, sweep_Ts, s
                "max_abs_local_time_error": float(np.abs(e.stamps() - ref.stamps).max()),
                "max_abs_sum_b_error": float(np.abs(sb - ref.sum_b).max()),
                "active_set_equal": bool(np.array_equal(e.active(), ref.active))}
-        d, w = timed_legs(e, s, target_events=target, label=f"N=65536 {form}", chunk=20)
-        r = {"error_vs_fp64_oracle": err, **_summary(d, w, form), "overlaps": e.overlaps()}
-        if form == "fp64" and sweep_Ts:
+        d, w = timed_legs(e, s, target_events=tgt, label=f"N=65536 {key}", chunk=20)
+        r = {"error_vs_fp64_oracle": err, **_summary(d, w, form), "neighbours": nb, "overlaps": e.overlaps()}
+        if key == "fp64" and sweep_Ts:
             r["violation_sweep"] = violation_sweep(e, s, sweep_Ts, sweep_legs, window_micro)
-        out[form] = r
+        out[key] = r
         e.close()
-    out["fp32_over_fp64"] = out["fp32"]["events_per_s"] / out["fp64"]["events_per_s"]
+    out["fp32_over_fp64"] = out["fp32"]["events_per_s"] / out["fp64_cells"]["events_per_s"]
+    out["fp32_over_fp64_default"] = out["fp32"]["events_per_s"] / out["fp64"]["events_per_s"]
     return out
 
 
@@ -539,7 +552,7 @@ def save_state(path, lanes, window_micro):
 
     import workloads as W
     s = W.config(4)
-    e = _make(s, "fp64", lanes, window_micro)
+    e = _make(s, "fp64", lanes, window_micro, clock_period_ns=_clock_period_ns)
     legs = burn_in(e, s)
     np.savez(path, x=e.positions()[:, 0], y=e.positions()[:, 1], active=e.active(), legs=legs,
              liftings=e.stats()["events"])
@@ -560,7 +573,7 @@ def profile_run(legs, lanes, window_micro, form, state=None):
         z = np.load(state)
         s.x, s.y, s.active = z["x"], z["y"], z["active"].astype(np.int32)
         assert int(z["legs"]) % 2 == 0
-    e = _make(s, form, lanes, window_micro)
+    e = _make(s, form, lanes, window_micro, clock_period_ns=_clock_period_ns if _neighbours == "graph" else 0)
     st0 = e.stats()
     e.run(legs * s.T, s.T, 4)
     d = _stats_delta(st0, e.stats())
@@ -624,7 +637,8 @@ def trace_summary(trace_csv, bench_json, out_txt, command):
     out += [f"#   {c}" for c in command]
     out += [f"# source: paper_2004_11040_amd/csrc/ecmc_kernels.hip sha256[:16] = {_src_hash()}",
             f"# bench line: value {line['value'] / 1e6:.2f} M liftings/s ({line['config']['form']}, "
-            f"{line['config']['neighbours']}), lag {line['config']['window_sigma']:g} sigma", "",
+            f"{line['config']['neighbours']}), lag {line['config']['window_sigma']:g} sigma, clock period "
+            f"{line['config'].get('clock_period_ns', 0)} ns", "",
             f"{'kernel':58s} {'calls':>7s} {'total_ms':>10s} {'avg_us':>9s} {'pct':>6s}  {'ran':>6s} {'avg_us_ran':>10s}"]
     for name, (n, tot, nr, tr) in sorted(stats.items(), key=lambda kv: -kv[1][1])[:24]:
         out.append(f"{short(name)[:58]:58s} {n:7d} {tot / 1e3:10.3f} {tot / n:9.2f} {100 * tot / total:6.2f}"
@@ -730,8 +744,13 @@ def main():
     ap.add_argument("--lanes", type=int, default=64)
     ap.add_argument("--max-splits", type=int, default=0,
                     help="rollbacks without progress before a lockstep stretch (0: library default)")
-    ap.add_argument("--window-micro", type=int, default=160_000,
-                    help="bounded lag between chains, in 1e-6 sigma (0: free running)")
+    ap.add_argument("--window-micro", type=int, default=200_000,
+                    help="bounded lag between chains, in 1e-6 sigma (0: free running), for the headline "
+                         "form and the smaller workloads")
+    ap.add_argument("--clock-period-ns", type=int, default=4000,
+                    help="least time between two passes of the clock workgroup of the headline form")
+    ap.add_argument("--cells-window-micro", type=int, default=160_000,
+                    help="bounded lag of the two forms on the corridor scan at N=2^20 (clock unpaced)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--cpu-batch-events", type=int, default=20_000,
                     help="liftings per replica for the all-cores oracle run")
@@ -757,6 +776,7 @@ def main():
     args = ap.parse_args()
     globals()["_neighbours"] = args.neighbours
     globals()["_cooperative"] = args.cooperative_launch
+    globals()["_clock_period_ns"] = args.clock_period_ns
     if args.trace_summary:
         a = args.trace_summary
         trace_summary(a[0], a[1], a[2], a[3:])
@@ -802,17 +822,22 @@ def main():
     # the headline: FP64 with the default candidates (the constraint graph);
     # FP32-mixed on the corridor scan, where its binary32 filter acts, beside
     # FP64 on the same scan (the graph build has no binary32 stage)
+    # (the clock pacing pays on graph candidates only; the scan forms were
+    # measured best unpaced, at a smaller lag)
+    head = (args.window_micro, args.clock_period_ns)
+    cells = (args.cells_window_micro, 0)
     if args.form == "both":
-        plan = [("fp64", "fp64", args.neighbours), ("fp32", "fp32", "cells"), ("fp64_cells", "fp64", "cells")]
+        plan = [("fp64", "fp64", args.neighbours, head), ("fp32", "fp32", "cells", cells),
+                ("fp64_cells", "fp64", "cells", cells)]
     else:
-        plan = [(args.form, args.form, args.neighbours)]
+        plan = [(args.form, args.form, args.neighbours, head if args.neighbours == "graph" else cells)]
     # FP64 on the corridor scan is a like-for-like reference for the FP32-mixed
     # form: a tenth of the legs
     results = {key: run_form(form, args.steps if key != "fp64_cells" else max(args.steps // 10, 20),
-                             args.warmup, args.lanes, args.window_micro, args.max_splits,
+                             args.warmup, args.lanes, sched[0], args.max_splits,
                              sweep_Ts=sweep_Ts if key == "fp64" else (), sweep_legs=args.sweep_legs,
-                             neighbours=nb)
-               for key, form, nb in plan}
+                             neighbours=nb, clock_period_ns=sched[1])
+               for key, form, nb, sched in plan}
     main_key = plan[0][0]
     main_form = plan[0][1]
     r = results[main_key]
@@ -842,7 +867,8 @@ def main():
                                "untimed burn-in of >= 50 liftings per disk",
                    "form": main_form, "lanes_per_chain": args.lanes, "neighbours": plan[0][2],
                    "cooperative_launch": args.cooperative_launch,
-                   "window_sigma": args.window_micro * 1e-6, "parallelism": "1 GPU"},
+                   "window_sigma": plan[0][3][0] * 1e-6, "clock_period_ns": plan[0][3][1],
+                   "parallelism": "1 GPU"},
         "roofline": roof,
         "forms": results,
     }

@@ -147,6 +147,12 @@ extern "C" {
                                      expects this many workgroups beyond its
                                      grid (0..4; default 0) and checks at the
                                      first wait, so the fallback runs           */
+#define ECMC_OPT_CLOCK_PERIOD_NS 16 /* contexts: least time between two passes
+                                     of the clock workgroup that computes H, in
+                                     ns (0..100000; 0: back to back).  A pass
+                                     that ends early waits before it loads the
+                                     next-event times again.  Pure scheduling:
+                                     results do not depend on it.               */
 #define ECMC_OPT_CELL_PCT 12      /* batches: home-cell width in percent of 2 sigma,
                                      100..141 (cells of at most 4 disks), used
                                      where admissible for a replica (else its

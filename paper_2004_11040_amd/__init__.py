@@ -29,6 +29,7 @@ OPT_CELL_PCT = 12
 OPT_NEIGHBOURS = 13
 OPT_COOPERATIVE = 14
 OPT_TEST_NONRESIDENT = 15
+OPT_CLOCK_PERIOD_NS = 16
 NEIGHBOURS_CELLS, NEIGHBOURS_GRAPH = 0, 1
 FEAT_SCREEN, FEAT_RESERVE, FEAT_REREAD, FEAT_FRESH, FEAT_UNRESERVE, FEAT_ALL = 1, 2, 4, 8, 16, 31
 FEAT_DEFAULT = 30

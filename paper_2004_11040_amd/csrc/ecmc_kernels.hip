@@ -184,6 +184,7 @@ struct LegP {
   int32_t self_clock;  // 1: a chain waiting at the lag takes H from the chains' next-event
                        // times itself (no clock workgroup: the replica workgroups)
   int32_t resident_hook;  // test hook: arrivals the handshake expects beyond the grid (0)
+  int32_t clock_gap;      // least time between the clock workgroup's passes, device ticks (10 ns)
 };
 
 // One committed lifting, as needed to take it back (restart from the earliest
@@ -1309,7 +1310,10 @@ __device__ __forceinline__ void lds_barrier() {
 // grow within a launch, so values one pass old give a lower bound of H, as H
 // must be; the stop words are read one pass late as well).
 constexpr int CLOCK_PER_THREAD = 4;
-__device__ void clock_loop(const Dev &D, long long iter_cap, int expect) {
+// least time between two passes of the clock workgroup, in device ticks of
+// 10 ns (ECMC_OPT_CLOCK_PERIOD_NS)
+constexpr int32_t CLOCK_GAP_DEFAULT = 0;
+__device__ void clock_loop(const Dev &D, long long iter_cap, int expect, unsigned gap) {
   __shared__ double red[16];
   __shared__ int s_quit;
   double hc = ld_a(&D.ctl->clock);
@@ -1318,6 +1322,7 @@ __device__ void clock_loop(const Dev &D, long long iter_cap, int expect) {
   const bool pipe = D.k <= CLOCK_PER_THREAD * (int)blockDim.x;
   double nx[CLOCK_PER_THREAD];
   int done = 0, ab = 0, er = 0;
+  unsigned long long t_iss = t0;  // when the pending pass's loads were issued
   if (pipe) {
 #pragma unroll
     for (int j = 0; j < CLOCK_PER_THREAD; ++j) {
@@ -1331,6 +1336,9 @@ __device__ void clock_loop(const Dev &D, long long iter_cap, int expect) {
     if (pipe) {
 #pragma unroll
       for (int j = 0; j < CLOCK_PER_THREAD; ++j) m = fmin(m, nx[j]);
+      // pace the passes: the next loads go out `gap` after the last ones
+      while (__builtin_amdgcn_s_memrealtime() - t_iss < gap) __builtin_amdgcn_s_sleep(1);
+      t_iss = __builtin_amdgcn_s_memrealtime();
       if (threadIdx.x == 0) {
         done = __hip_atomic_load(&D.ctl->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         ab = __hip_atomic_load(&D.ctl->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -1342,6 +1350,8 @@ __device__ void clock_loop(const Dev &D, long long iter_cap, int expect) {
         nx[j] = c < D.k ? ld_a(&D.NEXT[c]) : INFINITY;
       }
     } else {
+      while (__builtin_amdgcn_s_memrealtime() - t_iss < gap) __builtin_amdgcn_s_sleep(1);
+      t_iss = __builtin_amdgcn_s_memrealtime();
 #pragma unroll 4
       for (int c = threadIdx.x; c < D.k; c += blockDim.x) m = fmin(m, ld_a(&D.NEXT[c]));
       if (threadIdx.x == 0) {
@@ -2275,7 +2285,7 @@ __global__ void __launch_bounds__(256) k_event(Dev D, Geo g, LegP lp, int32_t wa
     __hip_atomic_fetch_add(&D.ctl->arrived, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
   if (blockIdx.x == gridDim.x - 1) {  // the clock workgroup (idle without a bounded lag)
-    if (lp.window > 0.0) clock_loop(D, iter_cap, (int)gridDim.x + lp.resident_hook);
+    if (lp.window > 0.0) clock_loop(D, iter_cap, (int)gridDim.x + lp.resident_hook, (unsigned)lp.clock_gap);
   } else if (c < D.k && !D.ctl->error) {
     chain_events<G, F32, SCA, GR>(D, g, lp, wait_retries, iter_cap, c, lane);
   }
@@ -3329,6 +3339,7 @@ __device__ __noinline__ int replica_leg(const RepIn &ri, RepOut *rp, int dir) {
     lp.features = features;
     lp.self_clock = 1;
     lp.resident_hook = 0;
+    lp.clock_gap = 0;
     {
       // chains rotate over the lane groups from one attempt to the next: the
       // lanes of a wavefront issue their claims in one instruction with a fixed
@@ -3512,6 +3523,7 @@ struct ecmc_ctx {
   int32_t cooperative = 0;    // 1: event kernel launched cooperatively (co-residency guaranteed
                               // by the runtime); 0: plain launch checked by the arrival handshake
   int32_t resident_hook = 0;  // test hook: extra arrivals a plain launch's handshake expects
+  int32_t clock_gap = CLOCK_GAP_DEFAULT;  // least time between clock passes, device ticks
   int64_t nonresident = 0;    // plain launches whose handshake timed out
   int64_t clock_iters = 0;    // passes of the clock loop over all timed launches
   int64_t vkind[NVK] = {0, 0, 0, 0, 0};
@@ -3751,6 +3763,7 @@ int attempt(ecmc_ctx *ctx, int dir, double h, double tend, bool final, bool glob
   lp.window = window;
   lp.self_clock = 0;
   lp.resident_hook = 0;
+  lp.clock_gap = ctx->clock_gap;
   const bool timed = !global && ctx->kernel_timing && ctx->kevents_ok;
   k_count_delta<<<1, 256, 0, ctx->stream>>>(D, 0);
   HIPCHK(hipGetLastError());
@@ -3889,6 +3902,7 @@ int run_leg(ecmc_ctx *ctx, int dir, double T) {
     lp0.features = ctx->features;
     lp0.self_clock = 0;
     lp0.resident_hook = ctx->cooperative ? 0 : ctx->resident_hook;
+    lp0.clock_gap = ctx->clock_gap;
     Ctl hc;
     // the first batch covers as many rounds as the last leg along the same
     // direction took (the lattice is not isotropic: legs along +x take about
@@ -4425,6 +4439,10 @@ int ecmc_set_option(ecmc_ctx *ctx, int32_t key, int64_t value) {
     case ECMC_OPT_TEST_NONRESIDENT:
       if (value < 0 || value > 4) return ECMC_EINVAL;
       ctx->resident_hook = (int32_t)value;
+      return ECMC_OK;
+    case ECMC_OPT_CLOCK_PERIOD_NS:
+      if (value < 0 || value > 100000) return ECMC_EINVAL;
+      ctx->clock_gap = (int32_t)(value / 10);
       return ECMC_OK;
     default:
       return ECMC_EINVAL;

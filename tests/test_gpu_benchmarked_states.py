@@ -25,14 +25,18 @@ if not torch.cuda.is_available():
 import paper_2004_11040_amd as pkg  # noqa: E402
 from test_gpu_parity import check_parity  # noqa: E402
 
-FORMS = [(pkg.FP64, pkg.NEIGHBOURS_GRAPH, 160_000), (pkg.FP32_MIXED, pkg.NEIGHBOURS_CELLS, 160_000)]
+# (form, candidates, bounded lag in 1e-6 sigma, clock pacing in ns): the
+# benchmark's settings for each workload
+HEADLINE_FORMS = [(pkg.FP64, pkg.NEIGHBOURS_GRAPH, 200_000, 4000), (pkg.FP32_MIXED, pkg.NEIGHBOURS_CELLS, 160_000, 0)]
+PRECISION_FORMS = [(pkg.FP64, pkg.NEIGHBOURS_GRAPH, 200_000, 0), (pkg.FP32_MIXED, pkg.NEIGHBOURS_CELLS, 200_000, 0)]
 
 
-def _run(s, flags, neighbours, window_micro, legs, log_cap):
+def _run(s, flags, neighbours, window_micro, clock_ns, legs, log_cap):
     e = pkg.Ecmc(np.stack([s.x, s.y], 1), s.sigma, s.L, flags=flags, max_chains=s.k, log_cap=log_cap)
     e.set_option(pkg.OPT_LANES, 64)
     e.set_option(pkg.OPT_NEIGHBOURS, neighbours)
     e.set_option(pkg.OPT_WINDOW_MICRO, window_micro)
+    e.set_option(pkg.OPT_CLOCK_PERIOD_NS, clock_ns)
     e.set_active(s.active)
     e.run(legs * s.T, s.T, pkg.DIR_ALTERNATE)
     return e
@@ -45,11 +49,11 @@ def headline_ref():
     return s, oracle.run(s.x, s.y, s.sigma, s.L, s.active, s.leg_dirs(6), s.T, log_cap=1 << 24)
 
 
-@pytest.mark.parametrize("flags,neighbours,window_micro", FORMS)
-def test_headline_six_alternating_legs(headline_ref, flags, neighbours, window_micro):
+@pytest.mark.parametrize("flags,neighbours,window_micro,clock_ns", HEADLINE_FORMS)
+def test_headline_six_alternating_legs(headline_ref, flags, neighbours, window_micro, clock_ns):
     s, ref = headline_ref
     print(f"[states] N=2^20 flags={flags} neighbours={neighbours}", flush=True)
-    e = _run(s, flags, neighbours, window_micro, 6, 1 << 12)
+    e = _run(s, flags, neighbours, window_micro, clock_ns, 6, 1 << 12)
     st = check_parity(e, ref, s.L, s.k, f"headline 6 legs flags={flags}")
     assert st["legs_violated"] >= 3 and st["reruns"] > 0   # the race-heavy regime
     assert e.overlaps() == 0
@@ -70,11 +74,11 @@ def precision_ref():
     return s, legs, ref
 
 
-@pytest.mark.parametrize("flags,neighbours,window_micro", FORMS)
-def test_precision_workload_burned_in(precision_ref, flags, neighbours, window_micro):
+@pytest.mark.parametrize("flags,neighbours,window_micro,clock_ns", PRECISION_FORMS)
+def test_precision_workload_burned_in(precision_ref, flags, neighbours, window_micro, clock_ns):
     s, legs, ref = precision_ref
     assert ref.n_events >= 50 * s.n >= 1_000_000
-    e = _run(s, flags, neighbours, window_micro, legs, 1 << 15)
+    e = _run(s, flags, neighbours, window_micro, clock_ns, legs, 1 << 15)
     st = check_parity(e, ref, s.L, s.k, f"N=65536 {ref.n_events} liftings flags={flags}")
     assert e.overlaps() == 0
     print(f"[states] ok: {st['events']} liftings, {st['legs_violated']} violated legs, "

@@ -164,6 +164,23 @@ def test_bounded_lag_window_is_pure_scheduling(window_micro):
     print("window", window_micro, "attempts", st["attempts"], "reruns", st["reruns"])
 
 
+@pytest.mark.parametrize("clock_ns", [4000, 50_000])
+def test_paced_clock_is_pure_scheduling(clock_ns):
+    """A clock workgroup that waits between its passes (H goes stale for
+    longer) only delays commits: same liftings, same bits.  Out-of-range
+    periods are refused."""
+    s = W.config(1)
+    dirs = s.leg_dirs(3)
+    e = gpu_run(s.x, s.y, s.L, s.active, dirs, s.T, log_cap=1 << 14,
+                opts=((pkg.OPT_WINDOW_MICRO, 200_000), (pkg.OPT_CLOCK_PERIOD_NS, clock_ns)))
+    ref = oracle.run(s.x, s.y, 1.0, s.L, s.active, dirs, s.T)
+    st = check_parity(e, ref, s.L, s.k, f"clock period {clock_ns} ns")
+    print("clock period", clock_ns, "passes", st["clock_iters"], "reruns", st["reruns"])
+    for bad in (-1, 100_001):
+        with pytest.raises(pkg.EcmcError):
+            e.set_option(pkg.OPT_CLOCK_PERIOD_NS, bad)
+
+
 @pytest.mark.parametrize("window_micro", [200_000, 0])
 @pytest.mark.parametrize("lanes", [64, 32, 16])
 def test_window_with_many_chains(lanes, window_micro):
