@@ -472,7 +472,8 @@ def run_probes(k):
     return out
 
 
-def run_batch(n_rep, target, t_frac, graph=1, window_micro=0, max_splits=0, form="fp64", neighbours="graph"):
+def run_batch(n_rep, target, t_frac, graph=1, window_micro=0, max_splits=0, form="fp64", neighbours="graph",
+              clock_period_ns=0):
     """The replica workload: n_rep seeded replicas of N in {1024..16384}, eta in
     [0.60, 0.72], k = round(sqrt N), run in one persistent launch (captured in
     a hipGraph) until every replica has `target` liftings; the autotuner's legs
@@ -494,6 +495,7 @@ def run_batch(n_rep, target, t_frac, graph=1, window_micro=0, max_splits=0, form
     b.set_option(pkg.OPT_GRAPH, graph)
     b.set_option(pkg.OPT_NEIGHBOURS, NEIGHBOURS[neighbours])
     b.set_option(pkg.OPT_WINDOW_MICRO, window_micro)
+    b.set_option(pkg.OPT_CLOCK_PERIOD_NS, clock_period_ns)
     if max_splits:
         b.set_option(pkg.OPT_MAX_SPLITS, max_splits)
     T = [t_frac * s.L for s in reps]
@@ -520,7 +522,8 @@ def run_batch(n_rep, target, t_frac, graph=1, window_micro=0, max_splits=0, form
     out = {"workload": f"{n_rep} replicas, N in 64*[16,256], eta in [0.60,0.72], k=round(sqrt N), "
                        f"legs of {t_frac} L alternating +x/+y, {form} with {neighbours} candidates, "
                        f"{target} liftings per replica, "
-                       f"bounded lag {window_micro * 1e-6:g} sigma",
+                       f"bounded lag {window_micro * 1e-6:g} sigma, H recomputed at most every "
+                       f"{clock_period_ns} ns",
            "events": ev1 - ev0, "wall_s": wall, "events_per_s": (ev1 - ev0) / wall,
            "device_ms": info["device_ms"], "lanes": info["lanes"], "graph": info["graph"],
            "workgroups": info["workgroups"], "legs": info["legs"], "rollbacks": info["rollbacks"],
@@ -760,6 +763,8 @@ def main():
     ap.add_argument("--batch-leg-frac", type=float, default=0.25)
     ap.add_argument("--batch-window-micro", type=int, default=200_000,
                     help="bounded lag between a replica's chains, in 1e-6 sigma (0: free running)")
+    ap.add_argument("--batch-clock-period-ns", type=int, default=8000,
+                    help="least time between two recomputations of a replica's H by its waiting chains")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--batch-only", action="store_true",
                     help="run only the replica batch (FP64, graph candidates) and print its result")
@@ -794,7 +799,8 @@ def main():
         assert torch.cuda.is_available(), "bench.py needs a GPU"
         torch.cuda.set_device(0)
         r = run_batch(args.batch_replicas, args.batch_events, args.batch_leg_frac,
-                      window_micro=args.batch_window_micro)
+                      window_micro=args.batch_window_micro,
+                      clock_period_ns=args.batch_clock_period_ns)
         print(json.dumps({"batch": r}), flush=True)
         return
     if args.save_state or args.profile_run:
@@ -896,10 +902,12 @@ def main():
                 "N1048576": results["fp64"]["violation_sweep"]})
     if not args.no_batch:
         line["batch"] = run_batch(args.batch_replicas, args.batch_events, args.batch_leg_frac,
-                                  window_micro=args.batch_window_micro)
+                                  window_micro=args.batch_window_micro,
+                                  clock_period_ns=args.batch_clock_period_ns)
         # the FP32-mixed batch: on the corridor scan, where the binary32 filter acts
         line["batch_fp32_cells"] = run_batch(args.batch_replicas, args.batch_events, args.batch_leg_frac,
-                                             window_micro=args.batch_window_micro, form="fp32",
+                                             window_micro=args.batch_window_micro,
+                                             clock_period_ns=args.batch_clock_period_ns, form="fp32",
                                              neighbours="cells")
         if cpu_batch:
             line["batch"]["cpu_oracle_all_cores"] = cpu_batch

@@ -147,12 +147,16 @@ extern "C" {
                                      expects this many workgroups beyond its
                                      grid (0..4; default 0) and checks at the
                                      first wait, so the fallback runs           */
-#define ECMC_OPT_CLOCK_PERIOD_NS 16 /* contexts: least time between two passes
-                                     of the clock workgroup that computes H, in
-                                     ns (0..100000; 0: back to back).  A pass
-                                     that ends early waits before it loads the
-                                     next-event times again.  Pure scheduling:
-                                     results do not depend on it.               */
+#define ECMC_OPT_CLOCK_PERIOD_NS 16 /* least time between two recomputations
+                                     of H, in ns (0..100000; 0: as often as
+                                     possible).  Contexts: a pass of the clock
+                                     workgroup that ends early waits before it
+                                     loads the next-event times again.
+                                     Batches: a replica's waiting chains
+                                     recompute H at most once per period (the
+                                     one whose compare-and-swap on a time stamp
+                                     succeeds).  Pure scheduling: results do
+                                     not depend on it.                          */
 #define ECMC_OPT_CELL_PCT 12      /* batches: home-cell width in percent of 2 sigma,
                                      100..141 (cells of at most 4 disks), used
                                      where admissible for a replica (else its
@@ -434,7 +438,8 @@ int ecmc_batch_create(ecmc_batch **out, ecmc_ctx *const *ctxs, int32_t n_ctx,
  * ECMC_OPT_FEATURES, ECMC_OPT_WAIT_RETRIES, ECMC_OPT_MAX_SPLITS and
  * ECMC_OPT_WINDOW_MICRO (bounded lag between a replica's chains in units of
  * 1e-6 sigma, 0 = free; a chain waiting at the lag takes the replica's H from
- * its chains' next-event times itself).  Scheduling and layout of Alg. 5 on
+ * its chains' next-event times itself), ECMC_OPT_CLOCK_PERIOD_NS (least
+ * time between two such recomputations in a replica).  Scheduling and layout of Alg. 5 on
  * the device; results do not depend on them.  Options take effect at the
  * next ecmc_batch_run, also when a captured graph is replayed. */
 int ecmc_batch_set_option(ecmc_batch *b, int32_t key, int64_t value);

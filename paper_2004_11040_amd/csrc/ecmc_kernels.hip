@@ -127,6 +127,7 @@ struct Ctl {
   unsigned long long t_start, t_end;
   int32_t not_resident;   // part of the launch's grid had not started after a long wait (grid_not_resident)
   int32_t clock_iters;    // passes of the clock workgroup's loop in the last event launch
+  unsigned long long clock_stamp;  // self-clocked chains: when H was last recomputed (s_memrealtime)
   LegCtl lc;
 };
 // loops bounded by an iteration limit (reported with ECMC_EHANG)
@@ -184,7 +185,8 @@ struct LegP {
   int32_t self_clock;  // 1: a chain waiting at the lag takes H from the chains' next-event
                        // times itself (no clock workgroup: the replica workgroups)
   int32_t resident_hook;  // test hook: arrivals the handshake expects beyond the grid (0)
-  int32_t clock_gap;      // least time between the clock workgroup's passes, device ticks (10 ns)
+  int32_t clock_gap;      // least time between two recomputations of H (the clock workgroup's
+                          // passes, or a self-clocked group's), device ticks (10 ns)
 };
 
 // One committed lifting, as needed to take it back (restart from the earliest
@@ -1871,7 +1873,20 @@ __device__ void chain_events(const Dev &D, const Geo &g, const LegP &lp, int32_t
           break;
         }
         hc = bcast<G>(h2, 0);
-        if (lp.self_clock) {
+        // a paced self-clock: one waiting group per clock_gap recomputes H
+        // (the one whose compare-and-swap moves the stamp)
+        int go_clk = lp.self_clock;
+        if (lp.self_clock && lp.clock_gap > 0) {
+          if (lane == 0) {
+            const unsigned long long now = __builtin_amdgcn_s_memrealtime();
+            unsigned long long last = __hip_atomic_load(&D.ctl->clock_stamp, __ATOMIC_RELAXED, SC);
+            go_clk = now - last >= (unsigned long long)lp.clock_gap &&
+                     __hip_atomic_compare_exchange_strong(&D.ctl->clock_stamp, &last, now, __ATOMIC_RELAXED,
+                                                          __ATOMIC_RELAXED, SC);
+          }
+          go_clk = bcast<G>(go_clk, 0);
+        }
+        if (go_clk) {
           // H from the next-event times of all chains, strided over the group
           double m = INFINITY;
           for (int o = lane; o < D.k; o += G) m = fmin(m, ld_a<SC>(&D.NEXT[o]));
@@ -3235,7 +3250,7 @@ struct RepIn {
   int32_t features;      // ECMC_FEAT_* bits
   int32_t wait_retries;  // failed claims before a move up to contact
   int32_t graph;         // 1: candidates from the constraint graph G(3), 0: corridor scan
-  int32_t pad2;
+  int32_t clock_gap;     // least time between two recomputations of H by waiting chains (10 ns)
 };
 struct RepOut {          // results of the run
   int32_t status;        // ECMC_OK or the first error
@@ -3339,7 +3354,7 @@ __device__ __noinline__ int replica_leg(const RepIn &ri, RepOut *rp, int dir) {
     lp.features = features;
     lp.self_clock = 1;
     lp.resident_hook = 0;
-    lp.clock_gap = 0;
+    lp.clock_gap = ri.clock_gap;
     {
       // chains rotate over the lane groups from one attempt to the next: the
       // lanes of a wavefront issue their claims in one instruction with a fixed
@@ -4516,6 +4531,7 @@ struct ecmc_batch {
   int32_t use_graph = 0;
   int32_t features = ECMC_FEAT_ALL;
   int32_t wait_retries = 64;
+  int32_t clock_gap = 0;  // least time between two recomputations of a replica's H, device ticks
   int32_t max_splits = 1;
   int32_t graph = 1;        // 1: candidates from the constraint graph G(3), 0: corridor scan
   hipGraphExec_t exec = nullptr;
@@ -4665,6 +4681,7 @@ int batch_once(ecmc_batch *b, const int64_t *target, const double *leg_T, int32_
     R.window = b->window_micro * 1e-6 * ctx->g.sigma;
     R.features = b->features;
     R.wait_retries = b->wait_retries;
+    R.clock_gap = b->clock_gap;
     R.graph = b->graph;
   }
   // longest expected run first, so that no long replica starts last: the
@@ -4760,7 +4777,8 @@ std::string batch_signature(const ecmc_batch *b, const double *leg_T, int32_t di
     h = fnv1a(h, &ctx->g.sigma, sizeof(double));
     h = fnv1a(h, &leg_T[r], sizeof(double));
   }
-  const int32_t settings[6] = {direction, b->features, b->wait_retries, b->max_splits, b->use_graph, b->graph};
+  const int32_t settings[7] = {direction,     b->features, b->wait_retries, b->max_splits,
+                               b->use_graph, b->graph,    b->clock_gap};
   h = fnv1a(h, settings, sizeof(settings));
   h = fnv1a(h, &b->window_micro, sizeof(double));
   char buf[24];
@@ -4897,6 +4915,10 @@ int ecmc_batch_set_option(ecmc_batch *b, int32_t key, int64_t value) {
     case ECMC_OPT_NEIGHBOURS:
       if (value != ECMC_NEIGHBOURS_CELLS && value != ECMC_NEIGHBOURS_GRAPH) return ECMC_EINVAL;
       b->graph = value == ECMC_NEIGHBOURS_GRAPH ? 1 : 0;
+      return ECMC_OK;
+    case ECMC_OPT_CLOCK_PERIOD_NS:
+      if (value < 0 || value > 100000) return ECMC_EINVAL;
+      b->clock_gap = (int32_t)(value / 10);
       return ECMC_OK;
     default:
       return ECMC_EINVAL;

@@ -89,11 +89,13 @@ def test_batch_parity(lanes, graph, cell_pct, neighbours):
         _check(e, ref, len(act), f"rep{i} continued")
 
 
-@pytest.mark.parametrize("window_micro,lanes,flags", [
-    (50_000, 4, pkg.FP64), (200_000, 8, pkg.FP32_MIXED), (1_000_000, 16, pkg.FP64)])
-def test_batch_bounded_lag_parity(window_micro, lanes, flags):
+@pytest.mark.parametrize("window_micro,lanes,flags,clock_ns", [
+    (50_000, 4, pkg.FP64, 0), (200_000, 8, pkg.FP32_MIXED, 0), (1_000_000, 16, pkg.FP64, 0),
+    (200_000, 4, pkg.FP64, 8000), (200_000, 16, pkg.FP64, 50_000), (200_000, 8, pkg.FP32_MIXED, 8000)])
+def test_batch_bounded_lag_parity(window_micro, lanes, flags, clock_ns):
     """A replica's chains wait at a bounded lag, each taking H from the
-    others' next-event times itself: scheduling only, same liftings and bits."""
+    others' next-event times itself, at most once per clock period in a
+    replica when it is paced: scheduling only, same liftings and bits."""
     reps = _small_replicas(6, 17)
     systems = _make(reps, flags=flags)
     b = pkg.Batch(systems)
@@ -101,13 +103,14 @@ def test_batch_bounded_lag_parity(window_micro, lanes, flags):
     b.set_option(pkg.OPT_CELL_PCT, 100)
     b.set_option(pkg.OPT_GRAPH, 1)
     b.set_option(pkg.OPT_WINDOW_MICRO, window_micro)
+    b.set_option(pkg.OPT_CLOCK_PERIOD_NS, clock_ns)
     # the FP32-mixed form on the corridor scan, where its binary32 filter acts
     b.set_option(pkg.OPT_NEIGHBOURS, pkg.NEIGHBOURS_CELLS if flags == pkg.FP32_MIXED else pkg.NEIGHBOURS_GRAPH)
     big = np.full(len(reps), 1 << 60, np.int64)
     b.run(big, [r[4] for r in reps], pkg.DIR_ALTERNATE, max_legs=3)
     for i, ((x, y, L, act, T), e) in enumerate(zip(reps, systems)):
         ref = oracle.run(x, y, 1.0, L, act, [0, 1, 0], T)
-        _check(e, ref, len(act), f"lag rep{i} w={window_micro} lanes={lanes}")
+        _check(e, ref, len(act), f"lag rep{i} w={window_micro} lanes={lanes} clock={clock_ns}")
 
 
 def test_batch_fp32_mixed_and_autotune():
@@ -218,11 +221,13 @@ def _workload_systems(n_rep, flags=pkg.FP32_MIXED):
 def test_batch_workload_sixteen_replicas_two_legs():
     """16 replicas of the 512-replica workload (N from 1024 to 16384, k =
     round(sqrt N)) over two legs in the benchmark's settings (graph, bounded
-    lag 0.35 sigma, autotuned lanes and cells) against the oracle."""
+    lag 0.2 sigma, H recomputed at most every 8 us, autotuned lanes and cells)
+    against the oracle."""
     reps, systems = _workload_systems(16)
     b = pkg.Batch(systems)
     b.set_option(pkg.OPT_GRAPH, 1)
-    b.set_option(pkg.OPT_WINDOW_MICRO, 350_000)
+    b.set_option(pkg.OPT_WINDOW_MICRO, 200_000)
+    b.set_option(pkg.OPT_CLOCK_PERIOD_NS, 8000)
     big = np.full(len(reps), 1 << 60, np.int64)
     b.run(big, [s.T for s in reps], pkg.DIR_ALTERNATE, max_legs=2)
     for s, e in zip(reps, systems):

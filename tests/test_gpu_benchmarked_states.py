@@ -2,8 +2,9 @@
 
 * N = 2^20, k = 1024: six alternating legs from the lattice (+x and +y; the
   lattice disorders and violations become frequent), in the benchmark's
-  launch configuration for both forms: FP64 with graph candidates, and
-  FP32-mixed on the corridor scan with its binary32 filter.
+  launch configuration for both forms: FP64 with graph candidates (clock
+  paced), and FP32-mixed on the corridor scan with its binary32 filter; and
+  FP64 unpaced, where most of the six legs roll back.
 * N = 65536, k = 256 (the same density and k = sqrt N): the legs that take
   the lattice past 50 liftings per disk, the burn-in the benchmark times
   after (3.3e6 liftings, the first 10^6 among them), both forms, every
@@ -26,8 +27,11 @@ import paper_2004_11040_amd as pkg  # noqa: E402
 from test_gpu_parity import check_parity  # noqa: E402
 
 # (form, candidates, bounded lag in 1e-6 sigma, clock pacing in ns): the
-# benchmark's settings for each workload
-HEADLINE_FORMS = [(pkg.FP64, pkg.NEIGHBOURS_GRAPH, 200_000, 4000), (pkg.FP32_MIXED, pkg.NEIGHBOURS_CELLS, 160_000, 0)]
+# benchmark's settings for each workload.  At N = 2^20 the FP64 form also
+# runs unpaced at 0.16 sigma, where rollbacks come on most legs (the paced
+# clock makes them rarer in the first legs).
+HEADLINE_FORMS = [(pkg.FP64, pkg.NEIGHBOURS_GRAPH, 200_000, 4000), (pkg.FP32_MIXED, pkg.NEIGHBOURS_CELLS, 160_000, 0),
+                  (pkg.FP64, pkg.NEIGHBOURS_GRAPH, 160_000, 0)]
 PRECISION_FORMS = [(pkg.FP64, pkg.NEIGHBOURS_GRAPH, 200_000, 0), (pkg.FP32_MIXED, pkg.NEIGHBOURS_CELLS, 200_000, 0)]
 
 
@@ -54,8 +58,9 @@ def test_headline_six_alternating_legs(headline_ref, flags, neighbours, window_m
     s, ref = headline_ref
     print(f"[states] N=2^20 flags={flags} neighbours={neighbours}", flush=True)
     e = _run(s, flags, neighbours, window_micro, clock_ns, 6, 1 << 12)
-    st = check_parity(e, ref, s.L, s.k, f"headline 6 legs flags={flags}")
-    assert st["legs_violated"] >= 3 and st["reruns"] > 0   # the race-heavy regime
+    st = check_parity(e, ref, s.L, s.k, f"headline 6 legs flags={flags} clock={clock_ns}")
+    if clock_ns == 0:
+        assert st["legs_violated"] >= 3 and st["reruns"] > 0   # the race-heavy regime
     assert e.overlaps() == 0
     print(f"[states] ok: {st['events']} liftings, {st['legs_violated']} violated legs, "
           f"{st['reruns']} rollbacks", flush=True)
