@@ -82,3 +82,17 @@ def test_struct_layouts_agree_with_the_header(cname, pyclass, tmp_path):
     assert int(out["size"]) == ctypes.sizeof(pyclass)
     for f in fields:
         assert int(out[f]) == getattr(pyclass, f).offset, f
+
+
+def test_option_and_feature_constants_agree_with_the_header():
+    """Every ECMC_OPT_*, ECMC_FEAT_* and ECMC_NEIGHBOURS_* value the header
+    defines is the binding's constant of the same name, and the binding has
+    no option the header lacks."""
+    src = open(os.path.join(ROOT, "include", "ecmc.h")).read()
+    defs = {m.group(1): int(m.group(2)) for m in
+            re.finditer(r"#define\s+ECMC_((?:OPT|FEAT|NEIGHBOURS)_[A-Z0-9_]+)\s+(\d+)u?\b", src)}
+    assert len(defs) > 20
+    for name, value in defs.items():
+        assert getattr(pkg, name) == value, name
+    opts = {n for n in dir(pkg) if n.startswith("OPT_")}
+    assert opts == {n for n in defs if n.startswith("OPT_")}
