@@ -911,6 +911,9 @@ def main():
                                              neighbours="cells")
         if cpu_batch:
             line["batch"]["cpu_oracle_all_cores"] = cpu_batch
+        # the batched form against the plain FP64 form (different workloads:
+        # 512 replicas of 1024-16384 disks against one box of 2^20)
+        line["batch_over_fp64"] = line["batch"]["events_per_s"] / r["events_per_s"]
     if cpu:
         line["cpu_baseline"] = cpu
     line["paper_context"] = PAPER_CONTEXT
