@@ -1104,26 +1104,45 @@ __global__ void __launch_bounds__(256) k_graph_tile(Dev D, Geo g, double T, int 
         }
         if (m * g.c - u - g.d - STOP_MARGIN > lim) break;
       }
-      double aj[ROWS * CAP], pj[ROWS * CAP];
-      int idj[ROWS * CAP], slj[ROWS * CAP];
       int col = col0 + m;
       if (col >= nc) col -= nc;
       if (lc + m < GT_LC) {
+        // a lane visits only the occupied slots of its column (a bit each):
+        // the wavefront then iterates as often as its fullest lane needs, not
+        // once per slot.  The minima by (time, id) do not depend on the order.
+        unsigned occ = 0;
 #pragma unroll
-        for (int dr = 0; dr < ROWS; ++dr) {
+        for (int r = 0; r < ROWS * CAP; ++r) {
+          const int lj = (((lr + r / CAP - 1) * GT_LC) + lc + m) * CAP + r % CAP;
+          if (l_id[lj] >= 0) occ |= 1u << r;
+        }
+        while (occ) {
+          const int r = __builtin_ctz(occ);
+          occ &= occ - 1;
+          const int dr = r / CAP, q4 = r % CAP;
+          const int lj = (((lr + dr - 1) * GT_LC) + lc + m) * CAP + q4;
           int row = row0 + dr - 1;
           row = row < 0 ? row + nc : (row >= nc ? row - nc : row);
+          const int sl = ((row * nc + col) << 2) + q4;
+          if (sl == (int)s) continue;  // the staged tile may hold a cell twice in a small box
+          const int idr = l_id[lj];
+          double b, dp;
+          const double tau = tof(a, p, l_a[lj], l_p[lj], g, b, dp);
+          if (!(tau < T)) continue;
+          const int cls = lane_class(dp, g);
 #pragma unroll
-          for (int q4 = 0; q4 < CAP; ++q4) {
-            const int r = dr * CAP + q4;
-            const int lj = (((lr + dr - 1) * GT_LC) + lc + m) * CAP + q4;
-            aj[r] = l_a[lj];
-            pj[r] = l_p[lj];
-            idj[r] = l_id[lj];
-            slj[r] = ((row * nc + col) << 2) + q4;
-          }
+          for (int q = 0; q < 3; ++q)
+            if (q == cls && key_less(tau, idr, bt[q], bid[q])) {
+              bt[q] = tau;
+              bid[q] = idr;
+              bsl[q] = sl;
+            }
         }
-      } else {
+        continue;
+      }
+      double aj[ROWS * CAP], pj[ROWS * CAP];
+      int idj[ROWS * CAP], slj[ROWS * CAP];
+      {
 #pragma unroll
         for (int dr = 0; dr < ROWS; ++dr) {
           int row = row0 + dr - 1;
