@@ -428,8 +428,10 @@ int64_t ecmc_batch_scratch_bytes(int32_t n_ctx);
 /* Group n_ctx distinct contexts (HOST array of handles; the contexts must
  * outlive the batch) with a DEVICE scratch buffer of at least
  * ecmc_batch_scratch_bytes(n_ctx) bytes, 256-byte aligned, owned by the
- * caller.  Errors: ECMC_EINVAL (sizes, duplicates, mixed streams or forms),
- * ECMC_ESTATE (a context without an active set). */
+ * caller.  Each context stays one system of Sec. 2.1; the grouping is
+ * bookkeeping of the batch, no paper passage.  Errors: ECMC_EINVAL (sizes,
+ * duplicates, mixed streams or forms), ECMC_ESTATE (a context without an
+ * active set). */
 int ecmc_batch_create(ecmc_batch **out, ecmc_ctx *const *ctxs, int32_t n_ctx,
                       void *scratch, int64_t scratch_bytes);
 
@@ -460,8 +462,9 @@ int ecmc_batch_tune_cache(ecmc_batch *b, const char *path);
  * (and no cache entry), the autotuner first runs one leg per replica with
  * each lane cap that changes some replica's lanes, then with each cell width
  * that changes some replica's cells (those legs count), and keeps the
- * fastest.  Synchronises the stream.  Errors: ECMC_EINVAL, ECMC_ECELL,
- * ECMC_EHANG, ECMC_EDEVICE. */
+ * fastest.  Each replica runs the legs of ecmc_run: Alg. 5 between
+ * breakpoints with restart strategy 2 (Sec. 3.4), on its own.  Synchronises
+ * the stream.  Errors: ECMC_EINVAL, ECMC_ECELL, ECMC_EHANG, ECMC_EDEVICE. */
 int ecmc_batch_run(ecmc_batch *b, const int64_t *target_events,
                    const double *leg_T, int32_t direction, int32_t max_legs);
 
