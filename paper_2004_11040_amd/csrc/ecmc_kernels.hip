@@ -2331,17 +2331,17 @@ __global__ void __launch_bounds__(256) k_event(Dev D, Geo g, LegP lp, int32_t wa
 // a8: breakpoint.  If the attempt finished without a violation, write the
 // slot records back to the canonical arrays and commit per-chain results.
 // ------------------------------------------------------------------------
+// One thread per disk (most slots are empty): the slot the leg's build gave
+// it holds its record for the whole leg; the canonical arrays are written in
+// disk order.
 __global__ void k_writeback(Dev D, Geo g, int32_t dir) {
-  if (D.ctl->error) return;
-  int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (s < D.k) D.ACTIVE[s] = D.CST[D.CH_SLOT[s]].id;
-  int64_t ns = (int64_t)g.nc * g.nc * CAP;
-  if (s >= ns) return;
-  const int id = D.CST[s].id;
-  if (id < 0) return;
-  const MutRec m = D.MUT[s];
-  put_a(D, dir, id, m.a, g.L);
-  D.STAMP[id] = m.t;
+  if (D.ctl->error) return;  // a failed build leaves SLOT_OF unusable
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < D.k) D.ACTIVE[i] = D.CST[D.CH_SLOT[i]].id;
+  if (i >= D.n) return;
+  const MutRec m = D.MUT[D.SLOT_OF[i]];
+  put_a(D, dir, i, m.a, g.L);
+  D.STAMP[i] = m.t;
 }
 
 // Work counters summed over chains (one block), stored in pair `which`
@@ -4009,7 +4009,7 @@ int run_leg(ecmc_ctx *ctx, int dir, double T) {
   }
   k_chains_commit<<<blocks_for(D.k, 256), 256, 0, ctx->stream>>>(D);
   HIPCHK(hipGetLastError());
-  k_writeback<<<blocks_for(S, 256), 256, 0, ctx->stream>>>(D, ctx->g, dir);
+  k_writeback<<<blocks_for(D.n > D.k ? D.n : D.k, 256), 256, 0, ctx->stream>>>(D, ctx->g, dir);
   HIPCHK(hipGetLastError());
   return ECMC_OK;
 }
