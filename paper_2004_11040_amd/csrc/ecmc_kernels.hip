@@ -3070,14 +3070,16 @@ __device__ __forceinline__ void round_decide(Ctl &C, double H, long long ev_afte
       // the same race keeps coming back: a short stretch past R (T/1024: of
       // the lengths tried, T/32 ... T/2048, the fastest at N = 2^20 once
       // rounds cost ~20 us; T/512 was while they cost ~40) with a bounded
-      // lag well below the mean free time (divided by 8 after each
-      // violation), then in global-time order (Alg. 2)
+      // lag well below the mean free time (an eighth of the lag: with the
+      // clock paced, a half or a quarter rolled back more, a sixteenth held
+      // chains back; divided by 8 after each violation), then in global-time
+      // order (Alg. 2)
       lc.mode = MD_LOCKSTEP;
       lc.lvl = 0;
       lc.gend = fmin(lc.T, R + lc.T / 1024.0);
       lc.final_cur = lc.gend < lc.T ? 0 : 1;
       lc.tend_cur = lc.final_cur ? lc.T : lc.gend;
-      lc.lag_cur = lc.base_lag / 4.0;
+      lc.lag_cur = lc.base_lag / 8.0;
     }
   } else {
     lc.h = R;
