@@ -88,3 +88,39 @@ def test_precision_workload_burned_in(precision_ref, flags, neighbours, window_m
     assert e.overlaps() == 0
     print(f"[states] ok: {st['events']} liftings, {st['legs_violated']} violated legs, "
           f"{st['reruns']} rollbacks", flush=True)
+
+
+def test_headline_invariants_past_the_transient():
+    """N = 2^20 in the benchmark's launch configuration (FP64, graph
+    candidates, lag 0.2 sigma, clock paced at 4 us), run in blocks of 10
+    legs to at least 40 liftings per disk: past the lattice transient the
+    oracle's six legs cover, into the regime the benchmark times (about 200
+    legs, beyond what the oracle does in a test).  Properties that hold at
+    any size: k distinct active disks whose local time is the breakpoint,
+    static disks stamped before it (Remark on the meaning of local times),
+    no overlaps, a non-negative sum of lifting distances per chain, and
+    lifting logs of valid disk ids in which no disk lifts to itself."""
+    s = W.config(4)
+    e = _run(s, pkg.FP64, pkg.NEIGHBOURS_GRAPH, 200_000, 4000, 10, 1 << 12)
+    while e.stats()["events"] < 40 * s.n:
+        e.run(10 * s.T, s.T, pkg.DIR_ALTERNATE)
+    st = e.stats()
+    print(f"[states] N=2^20 invariants after {st['legs']} legs", flush=True)
+    assert st["legs"] % 10 == 0 and st["legs"] >= 100
+    act = e.active()
+    assert len(np.unique(act)) == s.k
+    stamps = e.stamps()
+    is_act = np.zeros(s.n, bool)
+    is_act[act] = True
+    assert np.all(stamps[is_act] == s.T)
+    assert np.all((stamps[~is_act] >= 0.0) & (stamps[~is_act] < s.T))
+    assert e.overlaps() == 0
+    sb, ev = e.chain_sums()
+    assert np.all(sb >= 0.0) and int(ev.sum()) == st["events"]
+    for c in range(0, s.k, 37):
+        lg = e.log(c)
+        assert lg.count == ev[c]
+        t = lg.targets
+        assert np.all((t >= 0) & (t < s.n))
+        assert np.all(t[1:] != t[:-1])
+    print(f"[states] ok: {st['events']} liftings, {st['reruns']} rollbacks", flush=True)
