@@ -290,3 +290,39 @@ def test_batch_tune_cache_round_trip(tmp_path):
         assert e.stats()["legs"] == 1
         ref = oracle.run(x, y, 1.0, L, act, [0], TT)
         _check(e, ref, len(act), "from cache")
+
+
+def test_batch_workload_all_replicas_invariants():
+    """All 512 replicas of the workload, six legs each in the benchmark's
+    settings (FP64, graph candidates, lag 0.2 sigma, H recomputed at most
+    every 8 us; lanes and cells fixed, no autotuning): properties that hold
+    at any size, on every replica (the oracle covers 16 of them): k distinct
+    active disks stamped with the breakpoint, static disks stamped before
+    it, no overlaps, non-negative sums of lifting distances."""
+    reps, systems = _workload_systems(512, flags=pkg.FP64)
+    b = pkg.Batch(systems)
+    b.set_option(pkg.OPT_GRAPH, 1)
+    b.set_option(pkg.OPT_NEIGHBOURS, pkg.NEIGHBOURS_GRAPH)
+    b.set_option(pkg.OPT_WINDOW_MICRO, 200_000)
+    b.set_option(pkg.OPT_CLOCK_PERIOD_NS, 8000)
+    b.set_option(pkg.OPT_LANES, 4)
+    b.set_option(pkg.OPT_CELL_PCT, 141)
+    big = np.full(len(reps), 1 << 60, np.int64)
+    b.run(big, [s.T for s in reps], pkg.DIR_ALTERNATE, max_legs=6)
+    bad = []
+    for s, e in zip(reps, systems):
+        st = e.stats()
+        act = e.active()
+        stamps = e.stamps()
+        is_act = np.zeros(s.n, bool)
+        is_act[act] = True
+        sb, ev = e.chain_sums()
+        ok = (st["legs"] == 6 and len(np.unique(act)) == s.k and np.all(stamps[is_act] == s.T)
+              and np.all((stamps[~is_act] >= 0.0) & (stamps[~is_act] < s.T)) and e.overlaps() == 0
+              and np.all(sb >= 0.0) and int(ev.sum()) == st["events"])
+        if not ok:
+            bad.append(s.name)
+    info = b.info()
+    print(f"512 replicas: {sum(e.stats()['events'] for e in systems)} liftings, "
+          f"{info['rollbacks']} rollbacks, {info['global_runs']} global stretches", flush=True)
+    assert not bad, bad[:8]
