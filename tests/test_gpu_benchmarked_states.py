@@ -90,9 +90,11 @@ def test_precision_workload_burned_in(precision_ref, flags, neighbours, window_m
           f"{st['reruns']} rollbacks", flush=True)
 
 
-def test_headline_invariants_past_the_transient():
-    """N = 2^20 in the benchmark's launch configuration (FP64, graph
-    candidates, lag 0.2 sigma, clock paced at 4 us), run in blocks of 10
+@pytest.mark.parametrize("flags,neighbours,window_micro,clock_ns", HEADLINE_FORMS[:2])
+def test_headline_invariants_past_the_transient(flags, neighbours, window_micro, clock_ns):
+    """N = 2^20 in the benchmark's launch configuration of each form (FP64 on
+    graph candidates, lag 0.2 sigma, clock paced at 4 us; FP32-mixed on the
+    corridor scan, lag 0.16 sigma, unpaced), run in blocks of 10
     legs to at least 40 liftings per disk: past the lattice transient the
     oracle's six legs cover, into the regime the benchmark times (about 200
     legs, beyond what the oracle does in a test).  Properties that hold at
@@ -101,11 +103,11 @@ def test_headline_invariants_past_the_transient():
     no overlaps, a non-negative sum of lifting distances per chain, and
     lifting logs of valid disk ids in which no disk lifts to itself."""
     s = W.config(4)
-    e = _run(s, pkg.FP64, pkg.NEIGHBOURS_GRAPH, 200_000, 4000, 10, 1 << 12)
+    e = _run(s, flags, neighbours, window_micro, clock_ns, 10, 1 << 12)
     while e.stats()["events"] < 40 * s.n:
         e.run(10 * s.T, s.T, pkg.DIR_ALTERNATE)
     st = e.stats()
-    print(f"[states] N=2^20 invariants after {st['legs']} legs", flush=True)
+    print(f"[states] N=2^20 flags={flags} invariants after {st['legs']} legs", flush=True)
     assert st["legs"] % 10 == 0 and st["legs"] >= 100
     act = e.active()
     assert len(np.unique(act)) == s.k
