@@ -126,3 +126,26 @@ def test_headline_invariants_past_the_transient(flags, neighbours, window_micro,
         assert np.all((t >= 0) & (t < s.n))
         assert np.all(t[1:] != t[:-1])
     print(f"[states] ok: {st['events']} liftings, {st['reruns']} rollbacks", flush=True)
+
+
+def test_headline_forms_agree_past_the_transient():
+    """Both forms reproduce the global-time order exactly (Lemma 2), by two
+    independent candidate paths (graph arrows in binary64; the corridor scan
+    with the binary32 filter).  200 legs at N = 2^20, each form in the
+    benchmark's settings, far past where the oracle runs in a test: the two
+    final states agree bit for bit (positions, stamps, active disks, every
+    chain's lifting count, sum of lifting distances and recent targets)."""
+    s = W.config(4)
+    out = []
+    for flags, neighbours, window_micro, clock_ns in HEADLINE_FORMS[:2]:
+        e = _run(s, flags, neighbours, window_micro, clock_ns, 200, 1 << 10)
+        sb, ev = e.chain_sums()
+        out.append((e.positions(), e.stamps(), e.active(), sb, ev, [e.log(c).targets for c in range(0, s.k, 7)],
+                    e.stats()["events"]))
+        e.close()
+    (p0, t0, a0, sb0, ev0, lg0, n0), (p1, t1, a1, sb1, ev1, lg1, n1) = out
+    print(f"[states] 200 legs: {n0} and {n1} liftings", flush=True)
+    assert n0 == n1
+    assert np.array_equal(p0, p1) and np.array_equal(t0, t1) and np.array_equal(a0, a1)
+    assert np.array_equal(ev0, ev1) and np.array_equal(sb0, sb1)
+    assert all(np.array_equal(x, y) for x, y in zip(lg0, lg1))
