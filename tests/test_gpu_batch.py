@@ -326,3 +326,37 @@ def test_batch_workload_all_replicas_invariants():
     print(f"512 replicas: {sum(e.stats()['events'] for e in systems)} liftings, "
           f"{info['rollbacks']} rollbacks, {info['global_runs']} global stretches", flush=True)
     assert not bad, bad[:8]
+
+
+@pytest.mark.xfail(strict=False, reason=(
+    "open issue: in the 512-replica batch (six legs) one to five replicas per run end in a state "
+    "that differs from the same replica in another run, in either candidate path (graph arrows "
+    "or the corridor scan), with or without the bounded lag; which replicas varies from run to "
+    "run (rep100, 111, 146, 163, 251, 342, 387, 471 seen).  The same replicas run as single-box "
+    "contexts, at 16, 32 and 64 lanes and with the per-chain rollback forced, match the oracle "
+    "exactly, and the checked replicas of the batch match it in most runs.  Cause not found."))
+def test_batch_forms_agree_on_all_replicas():
+    """The 512-replica workload, six legs, in the benchmark's two batch forms
+    (FP64 on graph candidates; FP32-mixed on the corridor scan, whose
+    binary32 filter decides nothing without a binary64 recomputation), lanes
+    and cells fixed: every replica ends in bit-identical states (positions,
+    stamps, active disks, per-chain lifting counts and sums)."""
+    out = []
+    for flags, nb in ((pkg.FP64, pkg.NEIGHBOURS_GRAPH), (pkg.FP32_MIXED, pkg.NEIGHBOURS_CELLS)):
+        reps, systems = _workload_systems(512, flags=flags)
+        b = pkg.Batch(systems)
+        b.set_option(pkg.OPT_GRAPH, 1)
+        b.set_option(pkg.OPT_NEIGHBOURS, nb)
+        b.set_option(pkg.OPT_WINDOW_MICRO, 200_000)
+        b.set_option(pkg.OPT_CLOCK_PERIOD_NS, 8000)
+        b.set_option(pkg.OPT_LANES, 4)
+        b.set_option(pkg.OPT_CELL_PCT, 141)
+        b.run(np.full(len(reps), 1 << 60, np.int64), [s.T for s in reps], pkg.DIR_ALTERNATE, max_legs=6)
+        out.append([(e.positions(), e.stamps(), e.active(), *e.chain_sums()) for e in systems])
+        b.close()
+        for e in systems:
+            e.close()
+    bad = [reps[r].name for r, (x, y) in enumerate(zip(*out))
+           if not all(np.array_equal(u, v) for u, v in zip(x, y))]
+    print(f"512 replicas, two forms: {len(bad)} differ", flush=True)
+    assert not bad, bad[:8]
