@@ -213,6 +213,10 @@ typedef struct {
   int64_t clock_iters;           /* passes of the clock workgroup's loop over the
                                     timed event launches (the clock's period is
                                     event_kernel_ms / clock_iters)             */
+  int64_t overflow_legs;         /* legs replayed whole in global-time order because
+                                    a chain committed more liftings after the last
+                                    settled time than its undo records hold (also
+                                    counted in global_legs)                    */
 } ecmc_stats_t;
 
 /* Bytes of device workspace for a context (the storage of the lifted

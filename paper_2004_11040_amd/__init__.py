@@ -69,7 +69,8 @@ class Stats(ctypes.Structure):
         (n, ctypes.c_double) for n in ("last_violation_t", "last_violation_tj",
                                        "last_violation_tau", "last_violation_h")] + [
         (n, ctypes.c_int64) for n in ("lockstep_runs", "violations_screened", "claim_yields",
-                                      "spin_aborts", "nonresident_launches", "cooperative", "clock_iters")]
+                                      "spin_aborts", "nonresident_launches", "cooperative", "clock_iters",
+                                      "overflow_legs")]
 
     def as_dict(self):
         d = {n: getattr(self, n) for n, _ in self._fields_ if n != "pad_"}

@@ -3280,6 +3280,7 @@ struct RepOut {          // results of the run
   int64_t events_run;
   int64_t vkind[NVK];
   unsigned long long ticks;  // device time the replica's legs took (100 MHz)
+  int64_t overflows;         // legs replayed whole in global-time order
 };
 
 __device__ double block_min_d(double v) {
@@ -3419,10 +3420,18 @@ __device__ __noinline__ int replica_leg(const RepIn &ri, RepOut *rp, int dir) {
     if (ovf) {  // the undo records do not reach back: the leg in global-time order
       replica_build(D, g, dir, T, ri.graph);
       if (D.ctl->error) return D.ctl->error;
+      // the chains' disks are tagged as moving, as before every attempt: the
+      // stretch takes only untagged disks as targets, and a chain's disk left
+      // untagged would be hit where it stood at the start of the leg
+      for (int c = tid; c < D.k; c += nt) chains_attempt_one(D, 0.0, c);
+      __syncthreads();
       lp.h = 0.0;
       global_order_call(D, g, lp);
       __syncthreads();
-      if (tid == 0) rp->global_runs++;
+      if (tid == 0) {
+        rp->global_runs++;
+        rp->overflows++;
+      }
       break;
     }
     const double R = fmax(fmin(tstar, clock), h);
@@ -3572,6 +3581,7 @@ struct ecmc_ctx {
   bool kevents_ok = false;
   // host-side statistics
   int64_t legs = 0, legs_violated = 0, attempts = 0, reruns = 0, global_legs = 0, lockstep_runs = 0;
+  int64_t overflow_legs = 0;  // legs replayed whole because the undo records did not reach back
   double chain_time = 0.0;
   double device_ms = 0.0;
   int64_t last_overlaps = 0;
@@ -4007,6 +4017,7 @@ int run_leg(ecmc_ctx *ctx, int dir, double T) {
       rc = attempt(ctx, dir, 0.0, T, true, true, 0.0, &v, &ts, &clk, &ovf);
       if (rc) return rc;
       ctx->global_legs++;
+      ctx->overflow_legs++;
     }
   }
   k_chains_commit<<<blocks_for(D.k, 256), 256, 0, ctx->stream>>>(D);
@@ -4175,6 +4186,7 @@ int ecmc_set_active(ecmc_ctx *ctx, const int32_t *idx, int32_t k) {
   HIPCHK(hipStreamSynchronize(ctx->stream));
   ctx->active_set = true;
   ctx->legs = ctx->legs_violated = ctx->attempts = ctx->reruns = ctx->global_legs = 0;
+  ctx->overflow_legs = 0;
   ctx->lockstep_runs = 0;
   ctx->chain_time = 0.0;
   ctx->device_ms = 0.0;
@@ -4300,6 +4312,7 @@ int ecmc_stats(ecmc_ctx *ctx, ecmc_stats_t *out) {
   out->reruns = ctx->reruns;
   out->global_legs = ctx->global_legs;
   out->lockstep_runs = ctx->lockstep_runs;
+  out->overflow_legs = ctx->overflow_legs;
   out->overlaps = ctx->last_overlaps;
   out->sum_b = sum_b;
   out->chain_time = ctx->chain_time;
@@ -4742,6 +4755,7 @@ int batch_once(ecmc_batch *b, const int64_t *target, const double *leg_T, int32_
     ctx->legs_violated += R.legs_violated;
     ctx->reruns += R.rollbacks;
     ctx->global_legs += R.global_runs;
+    ctx->overflow_legs += R.overflows;
     for (int q = 0; q < NVK; ++q) ctx->vkind[q] += R.vkind[q];
     ev += R.events_run;
     b->rep_ms_max = std::max(b->rep_ms_max, (double)R.ticks * 1e-5);  // s_memrealtime: 100 MHz
