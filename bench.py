@@ -510,6 +510,7 @@ def run_batch(n_rep, target, t_frac, graph=1, window_micro=0, max_splits=0, form
     b.run(big, T, pkg.DIR_ALTERNATE, max_legs=1)  # autotune (one leg per candidate)
     tune = b.info()
     ev0 = sum(e.stats()["events"] for e in systems)
+    ov0 = sum(e.stats()["overflow_legs"] for e in systems)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     b.run(np.full(n_rep, target, np.int64), T, pkg.DIR_ALTERNATE, max_legs=0)
@@ -517,7 +518,8 @@ def run_batch(n_rep, target, t_frac, graph=1, window_micro=0, max_splits=0, form
     wall = time.perf_counter() - t0
     info = b.info()
     ev1 = sum(e.stats()["events"] for e in systems)
-    log(f"batch: {ev1 - ev0} liftings in {wall:.2f} s")
+    ov1 = sum(e.stats()["overflow_legs"] for e in systems)
+    log(f"batch: {ev1 - ev0} liftings in {wall:.2f} s, {ov1 - ov0} legs replayed after an undo overflow")
     overlaps = sum(e.overlaps() for e in systems)
     out = {"workload": f"{n_rep} replicas, N in 64*[16,256], eta in [0.60,0.72], k=round(sqrt N), "
                        f"legs of {t_frac} L alternating +x/+y, {form} with {neighbours} candidates, "
@@ -528,6 +530,9 @@ def run_batch(n_rep, target, t_frac, graph=1, window_micro=0, max_splits=0, form
            "device_ms": info["device_ms"], "lanes": info["lanes"], "graph": info["graph"],
            "workgroups": info["workgroups"], "legs": info["legs"], "rollbacks": info["rollbacks"],
            "global_runs": info["global_runs"],
+           # legs replayed whole in global-time order: a chain outran its
+           # undo records (4096) after the last settled time, then a race
+           "overflow_replays": ov1 - ov0,
            "rollbacks_per_replica_leg": info["rollbacks"] / max(info["legs"], 1),
            "global_runs_per_replica_leg": info["global_runs"] / max(info["legs"], 1),
            # per-leg counts grow with the leg length; per lifting they do not
