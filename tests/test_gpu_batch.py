@@ -218,6 +218,52 @@ def _workload_systems(n_rep, flags=pkg.FP32_MIXED):
     return reps, systems
 
 
+def _oracle_final_state(task):
+    """The oracle's final state of one replica (a worker of a forked pool:
+    the oracle is C code on the host and touches no GPU)."""
+    x, y, L, act, dirs, T = task
+    r = oracle.run(x, y, 1.0, L, act, dirs, T, log=False)
+    return r.x, r.y, r.stamps, r.active, r.sum_b, r.n_events
+
+
+def test_batch_all_replicas_match_the_oracle():
+    """All 512 replicas of the workload, the first two legs from the lattice
+    (about 4e7 liftings; chains make some 10^4 liftings each in the first
+    leg, so undo-overflow replays occur), in the benchmark's FP64 settings
+    with lanes and cells fixed: every replica's positions, stamps, active
+    disks, lifting count and per-chain sums of b equal the oracle's bit for
+    bit.  The oracle runs in a forked pool of host processes, one per core
+    up to 16."""
+    import multiprocessing as mp
+    import os
+
+    reps, systems = _workload_systems(512, flags=pkg.FP64)
+    b = pkg.Batch(systems)
+    b.set_option(pkg.OPT_GRAPH, 1)
+    b.set_option(pkg.OPT_NEIGHBOURS, pkg.NEIGHBOURS_GRAPH)
+    b.set_option(pkg.OPT_WINDOW_MICRO, 200_000)
+    b.set_option(pkg.OPT_CLOCK_PERIOD_NS, 8000)
+    b.set_option(pkg.OPT_LANES, 4)
+    b.set_option(pkg.OPT_CELL_PCT, 141)
+    b.run(np.full(len(reps), 1 << 60, np.int64), [s.T for s in reps], pkg.DIR_ALTERNATE, max_legs=2)
+    tasks = [(s.x, s.y, s.L, s.active, s.leg_dirs(2), s.T) for s in reps]
+    procs = max(1, min(16, len(os.sched_getaffinity(0))))
+    with mp.get_context("fork").Pool(procs) as pool:
+        refs = pool.map(_oracle_final_state, tasks, chunksize=1)
+    bad = []
+    for s, e, (x, y, stamps, act, sb, nev) in zip(reps, systems, refs):
+        pos = e.positions()
+        ok = (e.stats()["events"] == nev and np.array_equal(pos[:, 0], x) and np.array_equal(pos[:, 1], y)
+              and np.array_equal(e.stamps(), stamps) and np.array_equal(e.active(), act)
+              and np.array_equal(e.chain_sums()[0], sb))
+        if not ok:
+            bad.append(s.name)
+    replays = sum(e.stats()["overflow_legs"] for e in systems)
+    print(f"512 replicas, two legs: {sum(e.stats()['events'] for e in systems)} liftings, "
+          f"{replays} overflow replays, {len(bad)} differ from the oracle", flush=True)
+    assert not bad, bad[:8]
+
+
 def test_batch_workload_sixteen_replicas_two_legs():
     """16 replicas of the 512-replica workload (N from 1024 to 16384, k =
     round(sqrt N)) over two legs in the benchmark's settings (graph, bounded
