@@ -380,8 +380,9 @@ void ecmc_free(ecmc_ctx *ctx);
  * of them at once is a systems pattern, not part of the paper), each a
  * context set up as usual
  * (ecmc_init, ecmc_set_active), run together in ONE persistent launch: a
- * workgroup takes a replica from a device queue and runs its legs, with the
- * breakpoint synchronisation, rollbacks (Sec. 3.4, strategy 2) and the
+ * workgroup claims a replica and runs its next two legs, largest expected
+ * remaining time first (a replica moves between workgroups from turn to
+ * turn, one at a time), with the breakpoint synchronisation, rollbacks (Sec. 3.4, strategy 2) and the
  * global-order fallback (Alg. 2) done on the device; its chains share the
  * workgroup's compute unit.  Results are read per replica with the
  * per-context calls
@@ -406,12 +407,12 @@ typedef struct {
   int64_t rollbacks;    /* rollbacks in the last call, all replicas        */
   int64_t global_runs;  /* global-order stretches in the last call         */
   double tune_events_per_ms[4]; /* autotuner: liftings per replica-ms (per ms
-                                   of summed replica device time, so that
-                                   the slowest replica does not decide) with
-                                   a lane cap
-                                   of 4, 8, 16, 32 (0: not tried, or the
-                                   same lanes for every replica as a smaller
-                                   cap)                                    */
+                                   of summed replica device time) in one leg
+                                   with a lane cap of 4, 8, 16, 32 (0: not
+                                   tried, or the same lanes for every replica
+                                   as a smaller cap); a larger cap is chosen
+                                   only if 3 % faster than the best smaller
+                                   one                                     */
   double tune_cell_events_per_ms[4]; /* autotuner: liftings per replica-ms with cells
                                    of 100, 115, 130, 141 % of 2 sigma at the
                                    chosen cap (0: not tried or no change)  */
@@ -423,9 +424,9 @@ typedef struct {
                              this gives the launch's load balance        */
 } ecmc_batch_info_t;
 
-/* Bytes of device scratch for a batch of n_ctx contexts (descriptors, the
- * work queue and its order, longest expected replica first; bookkeeping of
- * the batch, no paper passage).  Negative ECMC_EINVAL for n_ctx outside
+/* Bytes of device scratch for a batch of n_ctx contexts (each replica's
+ * descriptor, and its results with the state by which replicas are handed
+ * out; bookkeeping of the batch, no paper passage).  Negative ECMC_EINVAL for n_ctx outside
  * [1, 2^20]. */
 int64_t ecmc_batch_scratch_bytes(int32_t n_ctx);
 

@@ -3272,8 +3272,9 @@ struct RepIn {
   int32_t wait_retries;  // failed claims before a move up to contact
   int32_t graph;         // 1: candidates from the constraint graph G(3), 0: corridor scan
   int32_t clock_gap;     // least time between two recomputations of H by waiting chains (10 ns)
+  double cost_per_event;  // expected device time per lifting (any unit; only compared)
 };
-struct RepOut {          // results of the run
+struct RepOut {          // results of the run, and the replica's hand-out state
   int32_t status;        // ECMC_OK or the first error
   int32_t pad;
   int64_t legs_run, legs_violated, rollbacks, global_runs;
@@ -3281,6 +3282,9 @@ struct RepOut {          // results of the run
   int64_t vkind[NVK];
   unsigned long long ticks;  // device time the replica's legs took (100 MHz)
   int64_t overflows;         // legs replayed whole in global-time order
+  double cost;               // expected device time still to run (the host's estimate at the start)
+  int32_t owner;             // 1 while a workgroup runs the replica's legs
+  int32_t done;              // 1 once the replica has reached its target, its leg limit or an error
 };
 
 __device__ double block_min_d(double v) {
@@ -3493,21 +3497,73 @@ __device__ int replica_leg_g(const RepIn &ri, RepOut *rp, int dir) {
   }
 }
 
+// Replicas are handed out a few legs at a time, largest expected remaining
+// time first, so that a long replica that has not started yet displaces
+// one that has little left, and all of them end close together (a workgroup
+// that ran a replica to its end would start its second replica late).
+// A replica is run by one workgroup at a time: the workgroup claims it with
+// a compare-and-swap on its owner word, and the replica's state moves
+// between compute units, and XCDs, through an agent-scope release by the
+// last owner and an agent-scope acquire by the next one.
+constexpr int LEGS_PER_TURN = 2;
+
+// Wavefront 0: the replica that is neither finished nor owned with the
+// largest remaining cost (ties: the lower index), or -1 if there is none.
+__device__ int batch_pick(RepOut *outs, int n_rep) {
+  const int lane = threadIdx.x & 63;
+  double bc = -1.0;
+  int br = 0x7fffffff;
+  for (int q = lane; q < n_rep; q += 64) {
+    if (__hip_atomic_load(&outs[q].done, __ATOMIC_RELAXED, SCA)) continue;
+    if (__hip_atomic_load(&outs[q].owner, __ATOMIC_RELAXED, SCA)) continue;
+    const double c = ld_a<SCA>(&outs[q].cost);
+    if (c > bc || (c == bc && q < br)) {
+      bc = c;
+      br = q;
+    }
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    const double oc = __shfl_xor(bc, off, 64);
+    const int orr = __shfl_xor(br, off, 64);
+    if (oc > bc || (oc == bc && orr < br)) {
+      bc = oc;
+      br = orr;
+    }
+  }
+  return br == 0x7fffffff ? -1 : br;
+}
+
 template <bool F32>
-__global__ void __launch_bounds__(512) k_batch(const RepIn *__restrict__ reps, RepOut *outs, int32_t n_rep,
-                                               int32_t *queue, const int32_t *__restrict__ order) {
+__global__ void __launch_bounds__(512) k_batch(const RepIn *__restrict__ reps, RepOut *outs, int32_t n_rep) {
   __shared__ int s_rep;
   for (;;) {
     __syncthreads();
-    if (threadIdx.x == 0) {  // replicas in the order the host chose (longest expected first)
-      const int q = atomicAdd(queue, 1);
-      s_rep = q < n_rep ? order[q] : n_rep;
+    if (threadIdx.x < 64) {
+      int r = -1;
+      for (;;) {  // a lost race for a replica means another workgroup took it: look again
+        r = batch_pick(outs, n_rep);
+        if (r < 0) break;
+        int ok = 0;
+        if (threadIdx.x == 0) {
+          int z = 0;
+          ok = __hip_atomic_compare_exchange_strong(&outs[r].owner, &z, 1, __ATOMIC_ACQUIRE, __ATOMIC_RELAXED, SCA);
+          if (ok && __hip_atomic_load(&outs[r].done, __ATOMIC_RELAXED, SCA)) {  // finished in between
+            __hip_atomic_store(&outs[r].owner, 0, __ATOMIC_RELEASE, SCA);
+            ok = 0;
+          }
+        }
+        if (__shfl(ok, 0, 64)) break;
+      }
+      if (threadIdx.x == 0) s_rep = r;
     }
     __syncthreads();
     // the same value in every thread (the block leaves together); made a
     // scalar so that the replica's descriptor is read with scalar loads
     const int r = __builtin_amdgcn_readfirstlane(s_rep);
-    if (r >= n_rep) return;
+    // Nothing to claim: every unfinished replica is owned, and its owner
+    // looks again after each turn, so the workgroup may leave.
+    if (r < 0) return;
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");  // the state the last owner released
     const RepIn &ri = reps[r];
     RepOut *rp = &outs[r];
     const Dev &D = ri.D;
@@ -3516,25 +3572,31 @@ __global__ void __launch_bounds__(512) k_batch(const RepIn *__restrict__ reps, R
     for (int c = threadIdx.x; c < D.k; c += blockDim.x) ev0 += D.CNT_C[c * NCNT + C_EVENTS];
     ev0 = block_sum_ll(ev0);
     long long ev = ev0;
+    const int64_t legs0 = rp->legs_run;
     int64_t legs = 0;
-    while (ev < ri.target && (ri.max_legs == 0 || legs < ri.max_legs)) {
-      const int64_t ln = ri.legs_done + legs;
+    int rc = ECMC_OK;
+    while (legs < LEGS_PER_TURN && ev < ri.target && (ri.max_legs == 0 || legs0 + legs < ri.max_legs)) {
+      const int64_t ln = ri.legs_done + legs0 + legs;
       const int dir = ri.dir_mode == 4 ? (int)(ln & 1) : ri.dir_mode;
-      const int rc = replica_leg_g<F32>(ri, rp, dir);
-      if (rc) {
-        if (threadIdx.x == 0) rp->status = rc;
-        break;
-      }
+      rc = replica_leg_g<F32>(ri, rp, dir);
+      if (rc) break;
       ++legs;
       long long e = 0;
       for (int c = threadIdx.x; c < D.k; c += blockDim.x) e += D.CNT_C[c * NCNT + C_EVENTS];
       ev = block_sum_ll(e);
     }
+    const bool fin = rc != ECMC_OK || !(ev < ri.target && (ri.max_legs == 0 || legs0 + legs < ri.max_legs));
     if (threadIdx.x == 0) {
-      rp->legs_run = legs;
-      rp->events_run = ev - ev0;
-      rp->ticks = __builtin_amdgcn_s_memrealtime() - tk0;
+      if (rc) rp->status = rc;
+      rp->legs_run = legs0 + legs;
+      rp->events_run += ev - ev0;
+      rp->ticks += __builtin_amdgcn_s_memrealtime() - tk0;
+      st_a<SCA>(&rp->cost, fin ? 0.0 : (double)(ri.target - ev) * ri.cost_per_event);
+      if (fin) __hip_atomic_store(&rp->done, 1, __ATOMIC_RELAXED, SCA);
     }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");  // this turn's state, for the next owner
+    __syncthreads();
+    if (threadIdx.x == 0) __hip_atomic_store(&rp->owner, 0, __ATOMIC_RELEASE, SCA);
   }
 }
 
@@ -4552,8 +4614,6 @@ struct ecmc_batch {
   bool f32 = false;
   RepIn *d_in = nullptr;
   RepOut *d_out = nullptr;
-  int32_t *d_queue = nullptr;
-  int32_t *d_order = nullptr;  // queue position -> replica
   // per replica: liftings committed through this batch, device ticks per lifting (0: not measured)
   std::vector<int64_t> ev_seen;
   std::vector<double> ticks_per_event;
@@ -4637,13 +4697,10 @@ int batch_grid(ecmc_batch *b, int *grid) {
 }
 
 int batch_enqueue(ecmc_batch *b, int grid, hipStream_t st) {
-  k_fill<int32_t><<<1, 64, 0, st>>>(b->d_queue, 0, 1);
   if (b->f32)
-    k_batch<true><<<grid, BATCH_THREADS, 0, st>>>(b->d_in, b->d_out, (int32_t)b->ctxs.size(), b->d_queue,
-                                                  b->d_order);
+    k_batch<true><<<grid, BATCH_THREADS, 0, st>>>(b->d_in, b->d_out, (int32_t)b->ctxs.size());
   else
-    k_batch<false><<<grid, BATCH_THREADS, 0, st>>>(b->d_in, b->d_out, (int32_t)b->ctxs.size(), b->d_queue,
-                                                   b->d_order);
+    k_batch<false><<<grid, BATCH_THREADS, 0, st>>>(b->d_in, b->d_out, (int32_t)b->ctxs.size());
   BCHK(hipGetLastError());
   return ECMC_OK;
 }
@@ -4718,24 +4775,21 @@ int batch_once(ecmc_batch *b, const int64_t *target, const double *leg_T, int32_
     R.clock_gap = b->clock_gap;
     R.graph = b->graph;
   }
-  // longest expected run first, so that no long replica starts last: the
-  // remaining liftings times the measured device time per lifting, or per
-  // chain while a replica has not been measured
-  std::vector<int32_t> order((size_t)n);
+  // the expected device time still to run, by which the launch hands the
+  // replicas out (largest first): the remaining liftings times the measured
+  // device time per lifting, or per chain while a replica has not been measured
   {
     bool all = true;
     for (int r = 0; r < n; ++r) all = all && b->ticks_per_event[(size_t)r] > 0.0;
-    std::vector<double> cost((size_t)n);
     for (int r = 0; r < n; ++r) {
       const double rem = (double)std::max<int64_t>(target[r] - b->ev_seen[(size_t)r], 1);
-      cost[(size_t)r] = all ? rem * b->ticks_per_event[(size_t)r] : rem / (double)b->ctxs[(size_t)r]->D.k;
-      order[(size_t)r] = r;
+      const double cpe = all ? b->ticks_per_event[(size_t)r] : 1.0 / (double)b->ctxs[(size_t)r]->D.k;
+      h[(size_t)r].cost_per_event = cpe;
+      ho[(size_t)r].cost = rem * cpe;  // owner and done start at 0
     }
-    std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) { return cost[(size_t)x] > cost[(size_t)y]; });
   }
   BCHK(hipMemcpyAsync(b->d_in, h.data(), sizeof(RepIn) * (size_t)n, hipMemcpyHostToDevice, b->stream));
   BCHK(hipMemcpyAsync(b->d_out, ho.data(), sizeof(RepOut) * (size_t)n, hipMemcpyHostToDevice, b->stream));
-  BCHK(hipMemcpyAsync(b->d_order, order.data(), sizeof(int32_t) * (size_t)n, hipMemcpyHostToDevice, b->stream));
   b->rep_ms_max = b->rep_ms_sum = 0.0;
   BCHK(hipEventRecord(b->e0, b->stream));
   int rc = batch_launch(b);
@@ -4878,8 +4932,7 @@ extern "C" {
 
 int64_t ecmc_batch_scratch_bytes(int32_t n_ctx) {
   if (n_ctx < 1 || n_ctx > (1 << 20)) return ECMC_EINVAL;
-  return align_up((int64_t)n_ctx * (int64_t)sizeof(RepIn)) + align_up((int64_t)n_ctx * (int64_t)sizeof(RepOut)) +
-         ALIGN + align_up((int64_t)n_ctx * (int64_t)sizeof(int32_t));
+  return align_up((int64_t)n_ctx * (int64_t)sizeof(RepIn)) + align_up((int64_t)n_ctx * (int64_t)sizeof(RepOut));
 }
 
 int ecmc_batch_create(ecmc_batch **out, ecmc_ctx *const *ctxs, int32_t n_ctx, void *scratch,
@@ -4903,8 +4956,6 @@ int ecmc_batch_create(ecmc_batch **out, ecmc_ctx *const *ctxs, int32_t n_ctx, vo
   b->f32 = (ctxs[0]->flags & ECMC_FP32_MIXED) != 0;
   b->d_in = (RepIn *)scratch;
   b->d_out = (RepOut *)((char *)scratch + align_up((int64_t)n_ctx * (int64_t)sizeof(RepIn)));
-  b->d_queue = (int32_t *)((char *)b->d_out + align_up((int64_t)n_ctx * (int64_t)sizeof(RepOut)));
-  b->d_order = (int32_t *)((char *)b->d_queue + ALIGN);
   b->ev_seen.assign((size_t)n_ctx, 0);
   b->ticks_per_event.assign((size_t)n_ctx, 0.0);
   std::memset(&b->info, 0, sizeof(b->info));
@@ -5000,6 +5051,10 @@ int ecmc_batch_run(ecmc_batch *b, const int64_t *target_events, const double *le
       // chosen cap; candidates that give every replica the same setting as
       // an earlier one are skipped.
       const int caps[4] = {4, 8, 16, 32}, pcts[4] = {100, 115, 130, 141};
+      // liftings per replica-millisecond: the summed device time of the
+      // replicas, not the launch's (each candidate runs a different leg, and
+      // the slowest replica of one leg would decide)
+      auto replica_rate = [&](int64_t ev) { return b->rep_ms_sum > 0.0 ? (double)ev / b->rep_ms_sum : 0.0; };
       double best_rate = -1.0;
       const int pct0 = pct ? pct : 100;
       if (!lanes) {
@@ -5013,11 +5068,13 @@ int ecmc_batch_run(ecmc_batch *b, const int64_t *target_events, const double *le
           float ms = 0.f;
           int rc = batch_once(b, target_events, leg_T, direction, 1, caps[q], pct0, &ev, &ms);
           if (rc) return rc;
-          // liftings per replica-millisecond: the summed device time of the
-          // replicas, not the launch's, which the slowest replica sets
-          const double rate = b->rep_ms_sum > 0.0 ? (double)ev / b->rep_ms_sum : 0.0;
+          const double rate = replica_rate(ev);
           b->info.tune_events_per_ms[q] = rate;
-          if (rate > best_rate) {
+          // a larger cap must be 3 % faster: the longest replicas are the
+          // small ones, which a larger cap gives more lanes, and their runs
+          // set the launch's length (with caps 8 and 16 the longest replica
+          // took 4-7 % longer at the same summed rate)
+          if (rate > (best_rate < 0.0 ? best_rate : 1.03 * best_rate)) {
             best_rate = rate;
             lanes = caps[q];
           }
@@ -5035,7 +5092,7 @@ int ecmc_batch_run(ecmc_batch *b, const int64_t *target_events, const double *le
           float ms = 0.f;
           int rc = batch_once(b, target_events, leg_T, direction, 1, lanes, pcts[q], &ev, &ms);
           if (rc) return rc;
-          const double rate = b->rep_ms_sum > 0.0 ? (double)ev / b->rep_ms_sum : 0.0;
+          const double rate = replica_rate(ev);
           b->info.tune_cell_events_per_ms[q] = rate;
           if (rate > best_cell) {
             best_cell = rate;
