@@ -771,6 +771,9 @@ def main():
     ap.add_argument("--batch-clock-period-ns", type=int, default=8000,
                     help="least time between two recomputations of a replica's H by its waiting chains")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--batch-max-splits", type=int, default=0,
+                    help="batches: rollbacks without progress before a global-order stretch "
+                         "(0: library default)")
     ap.add_argument("--batch-only", action="store_true",
                     help="run only the replica batch (FP64, graph candidates) and print its result")
     ap.add_argument("--no-configs", action="store_true", help="skip the 256/4096/65536-disk workloads")
@@ -804,7 +807,7 @@ def main():
         assert torch.cuda.is_available(), "bench.py needs a GPU"
         torch.cuda.set_device(0)
         r = run_batch(args.batch_replicas, args.batch_events, args.batch_leg_frac,
-                      window_micro=args.batch_window_micro,
+                      window_micro=args.batch_window_micro, max_splits=args.batch_max_splits,
                       clock_period_ns=args.batch_clock_period_ns)
         print(json.dumps({"batch": r}), flush=True)
         return
@@ -907,7 +910,7 @@ def main():
                 "N1048576": results["fp64"]["violation_sweep"]})
     if not args.no_batch:
         line["batch"] = run_batch(args.batch_replicas, args.batch_events, args.batch_leg_frac,
-                                  window_micro=args.batch_window_micro,
+                                  window_micro=args.batch_window_micro, max_splits=args.batch_max_splits,
                                   clock_period_ns=args.batch_clock_period_ns)
         # the FP32-mixed batch: on the corridor scan, where the binary32 filter acts
         line["batch_fp32_cells"] = run_batch(args.batch_replicas, args.batch_events, args.batch_leg_frac,
