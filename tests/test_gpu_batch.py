@@ -227,13 +227,16 @@ def _oracle_final_state(task):
 
 
 def test_batch_all_replicas_match_the_oracle():
-    """All 512 replicas of the workload, the first two legs from the lattice
-    (about 4e7 liftings; chains make some 10^4 liftings each in the first
-    leg, so undo-overflow replays occur), in the benchmark's FP64 settings
-    with lanes and cells fixed: every replica's positions, stamps, active
-    disks, lifting count and per-chain sums of b equal the oracle's bit for
-    bit.  The oracle runs in a forked pool of host processes, one per core
-    up to 16."""
+    """All 512 replicas of the workload, the first four legs from the lattice
+    (about 6.6e7 liftings; chains make some 10^4 liftings each in the first
+    leg, so undo-overflow replays can occur), in the benchmark's FP64
+    settings with lanes and cells fixed: every replica's positions, stamps,
+    active disks, lifting count and per-chain sums of b equal the oracle's
+    bit for bit.  Replicas are handed out two legs at a time, and the 256
+    that have not started displace the first 256 after their first turn, so
+    most replicas run their second turn on another workgroup, often on
+    another XCD.  The oracle runs in a forked pool of host processes, one
+    per core up to 16."""
     import multiprocessing as mp
     import os
 
@@ -245,8 +248,8 @@ def test_batch_all_replicas_match_the_oracle():
     b.set_option(pkg.OPT_CLOCK_PERIOD_NS, 8000)
     b.set_option(pkg.OPT_LANES, 4)
     b.set_option(pkg.OPT_CELL_PCT, 141)
-    b.run(np.full(len(reps), 1 << 60, np.int64), [s.T for s in reps], pkg.DIR_ALTERNATE, max_legs=2)
-    tasks = [(s.x, s.y, s.L, s.active, s.leg_dirs(2), s.T) for s in reps]
+    b.run(np.full(len(reps), 1 << 60, np.int64), [s.T for s in reps], pkg.DIR_ALTERNATE, max_legs=4)
+    tasks = [(s.x, s.y, s.L, s.active, s.leg_dirs(4), s.T) for s in reps]
     procs = max(1, min(16, len(os.sched_getaffinity(0))))
     with mp.get_context("fork").Pool(procs) as pool:
         refs = pool.map(_oracle_final_state, tasks, chunksize=1)
@@ -259,7 +262,7 @@ def test_batch_all_replicas_match_the_oracle():
         if not ok:
             bad.append(s.name)
     replays = sum(e.stats()["overflow_legs"] for e in systems)
-    print(f"512 replicas, two legs: {sum(e.stats()['events'] for e in systems)} liftings, "
+    print(f"512 replicas, four legs: {sum(e.stats()['events'] for e in systems)} liftings, "
           f"{replays} overflow replays, {len(bad)} differ from the oracle", flush=True)
     assert not bad, bad[:8]
 
